@@ -1,0 +1,181 @@
+/*
+ * nnsemd.h -- C ABI of the MI355X (gfx950) NNS-EMD library.
+ *
+ * NNS-EMD approximates the Earth Mover's Distance (the transport LP of the
+ * paper's Eqs. (1)-(3)) by iterated nearest-neighbour search, Algorithm 1
+ * of the paper (Sec. III-A): in every round each active consumer (a point
+ * of C = (Y, b)) picks its nearest active supplier (a point of S = (X, a));
+ * every supplier serves its claimants nearest-first with
+ * f = min(s_i, c_j), adds f * D_ij to the cost R and records F_ij += f;
+ * points whose mass reached zero leave the active sets; the rounds repeat
+ * until one side is empty.  The method is not symmetric: X/a are always the
+ * suppliers that are searched, Y/b the consumers that search.
+ *
+ * Conventions shared by every call:
+ *  - Pointers marked "device" must be device memory of the handle's GPU
+ *    (any allocator: hipMalloc, torch, ...); "host" pointers are read during
+ *    the call only.  The library never frees caller memory.
+ *  - Point sets are row-major (rows x d), FP32 unless a call says
+ *    otherwise; masses are FP32 and are promoted exactly to FP64, in which
+ *    all mass arithmetic and the cost sum run.
+ *  - Calls enqueue work on `stream` (a hipStream_t; NULL = the default
+ *    stream) and return at once.  Argument checks that need no device data
+ *    happen before anything is enqueued and return a negative status.
+ *    Checks of the data itself (non-finite coordinates, negative or
+ *    non-finite masses, total masses that differ by more than 1e-5
+ *    relative, a plan buffer below m+n-1 entries, a round cap reached) are
+ *    reported per pair in nnsemd_stats_t.status once the stream has run;
+ *    such a pair's cost is NaN.
+ *  - Zero masses are allowed: those points never become active.
+ *  - Results are deterministic: identical inputs give bit-identical costs
+ *    and plans.  The search runs in FP32 with a proven error bound; any
+ *    consumer whose best and second-best FP32 keys are closer than that
+ *    bound is re-scored in FP64, so every nearest-neighbour decision and
+ *    the whole plan equal those of the FP64 definition (ties: smallest
+ *    supplier index; greedy order: (D_ij, j) ascending).
+ *  - A handle owns its workspace and must not be used by two host threads
+ *    at once; calls on one handle must be ordered on one stream.
+ *  - No C++ exception crosses this interface.
+ */
+#ifndef NNSEMD_H
+#define NNSEMD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nnsemd_handle* nnsemd_handle_t;
+
+typedef enum {
+    NNSEMD_OK = 0,
+    NNSEMD_ERR_INVALID_ARG = -1,   /* bad pointer, size, enum or data value */
+    NNSEMD_ERR_MASS_MISMATCH = -2, /* |sum a - sum b| > 1e-5 max(sum a, sum b) */
+    NNSEMD_ERR_CAPACITY = -3,      /* plan buffer smaller than m + n - 1 */
+    NNSEMD_ERR_OUT_OF_MEMORY = -4, /* workspace allocation failed */
+    NNSEMD_ERR_DEVICE = -5,        /* a HIP runtime call failed */
+    NNSEMD_ERR_NOT_CONVERGED = -6, /* the round cap was reached */
+    NNSEMD_ERR_UNSUPPORTED = -7    /* combination not implemented */
+} nnsemd_status_t;
+
+/* Ground distance D_ij (Sec. II-A uses L1 and L2; Table 8b compares them). */
+typedef enum {
+    NNSEMD_L2 = 0,          /* D = ||x - y||_2; search and order by ||x - y||^2 */
+    NNSEMD_SQEUCLIDEAN = 1, /* D = ||x - y||_2^2 */
+    NNSEMD_L1 = 2           /* D = ||x - y||_1 */
+} nnsemd_metric_t;
+
+typedef enum { NNSEMD_F32 = 0, NNSEMD_BF16 = 1 } nnsemd_dtype_t;
+
+/* Flow protocol of Sec. III-A: greedy serves claimants nearest-first (ties
+ * by consumer index); random serves them in the order of the SplitMix64
+ * output of the counter (seed, round, consumer), see nnsemd_options_t. */
+typedef enum { NNSEMD_GREEDY = 0, NNSEMD_RANDOM = 1 } nnsemd_protocol_t;
+
+/* Arithmetic of the distance search.  FP32: FP32 keys with FP64 re-scoring
+ * of near ties (exact decisions).  BF16_MFMA_REFINE (BF16 inputs, high d):
+ * distance tiles ||x||^2 + ||y||^2 - 2 x.y from BF16 matrix-core products
+ * with FP32 accumulation, candidate re-scoring in FP32. */
+typedef enum { NNSEMD_MODE_FP32 = 0, NNSEMD_MODE_BF16_MFMA_REFINE = 1 } nnsemd_mode_t;
+
+typedef struct {
+    int32_t protocol;   /* nnsemd_protocol_t, default NNSEMD_GREEDY */
+    int32_t mode;       /* nnsemd_mode_t, default NNSEMD_MODE_FP32 */
+    int64_t max_rounds; /* <= 0: m + n (never reached by valid input) */
+    uint64_t seed;      /* random protocol only */
+    int32_t threads;    /* workgroup size override (0 = tuned choice) */
+    int32_t reserved;
+} nnsemd_options_t;
+
+/* Per-pair results, written by the device (48 bytes). */
+typedef struct {
+    int32_t status;      /* nnsemd_status_t of this pair */
+    int32_t rounds;      /* NNS iterations t */
+    int64_t nnz;         /* plan entries (serves), <= m + n - 1 */
+    int64_t work;        /* sum over rounds of |active S| * |active C| */
+    int64_t near_ties;   /* consumers re-scored in FP64 (FP32 keys too close) */
+    double residual_src; /* supplier mass left when the rounds stopped */
+    double residual_dst; /* consumer mass left when the rounds stopped */
+} nnsemd_stats_t;
+
+/* Create a handle on HIP device `device` (its workspace grows on demand).
+ * Returns INVALID_ARG for a NULL `out` or a bad device index. */
+nnsemd_status_t nnsemd_create(nnsemd_handle_t* out, int32_t device);
+
+/* Free the handle and its workspace (waits for the device to be idle). */
+nnsemd_status_t nnsemd_destroy(nnsemd_handle_t h);
+
+/* Static description of a status code. */
+const char* nnsemd_status_string(nnsemd_status_t s);
+
+/* Text of the last host-side error on this handle ("" if none). */
+const char* nnsemd_last_error(nnsemd_handle_t h);
+
+/*
+ * emd_approx -- NNS-EMD of one pair (Algorithm 1; problem statement Sec. II-A).
+ *   X: device, m x d suppliers; a: device, m masses.
+ *   Y: device, n x d consumers; b: device, n masses.
+ *   d: 1..7 for the FP32 point path (dtype F32, mode FP32); any d >= 1 for
+ *      the BF16 path (dtype BF16, mode BF16_MFMA_REFINE).
+ *   opts: host, nullable (defaults above).
+ *   cost: device, 1 double: R = sum f * D_ij.
+ *   plan_src/plan_dst/plan_flow: device, nullable together; when given they
+ *      receive the plan F* as (supplier, consumer, flow) triples in
+ *      (round, supplier, serve) order; plan_capacity >= m + n - 1 entries.
+ *   stats: device, nullable; one nnsemd_stats_t.
+ * Errors: INVALID_ARG (NULL handle/pointers, negative sizes, bad enums),
+ * UNSUPPORTED (d or size beyond the implemented paths), OUT_OF_MEMORY,
+ * DEVICE.  Data errors go to stats->status.
+ */
+nnsemd_status_t emd_approx(nnsemd_handle_t h,
+                           const void* X, const float* a, int64_t m,
+                           const void* Y, const float* b, int64_t n,
+                           int32_t d, nnsemd_dtype_t dtype, nnsemd_metric_t metric,
+                           const nnsemd_options_t* opts,
+                           double* cost,
+                           int32_t* plan_src, int32_t* plan_dst, double* plan_flow,
+                           int64_t plan_capacity,
+                           nnsemd_stats_t* stats,
+                           void* stream);
+
+/*
+ * emd_approx_batched -- NNS-EMD of many independent ragged pairs in one
+ * persistent launch (the batching of Sec. III-D, done as a device-side pair
+ * queue instead of padded batches).
+ *   Xcat: device, sum_k |X_k| x d rows; acat: device masses; x_off: device,
+ *      num_x_sets + 1 int64 row offsets (set k = rows [x_off[k], x_off[k+1])).
+ *   Ycat, bcat, y_off, num_y_sets: the same for consumer sets.
+ *   pair_x, pair_y: device, num_pairs int32 set indices each, nullable
+ *      (NULL: pair p uses set p; one query against many candidates passes
+ *      pair_x = all zeros).
+ *   max_m, max_n: host upper bounds on any pair's set sizes (they size the
+ *      on-chip workspace); a pair above them fails with INVALID_ARG.
+ *   costs: device, num_pairs doubles.
+ *   plan_src/plan_dst/plan_flow: device, nullable together; pair p writes
+ *      at [plan_off[p], plan_off[p+1]) which must hold m_p + n_p - 1
+ *      entries (else that pair's status is CAPACITY); plan_off: device,
+ *      num_pairs + 1 int64, required with a plan.
+ *   stats: device, nullable; num_pairs entries.
+ * Errors as emd_approx.
+ */
+nnsemd_status_t emd_approx_batched(nnsemd_handle_t h, int64_t num_pairs,
+                                   const void* Xcat, const float* acat,
+                                   const int64_t* x_off, int64_t num_x_sets,
+                                   const void* Ycat, const float* bcat,
+                                   const int64_t* y_off, int64_t num_y_sets,
+                                   const int32_t* pair_x, const int32_t* pair_y,
+                                   int64_t max_m, int64_t max_n,
+                                   int32_t d, nnsemd_dtype_t dtype, nnsemd_metric_t metric,
+                                   const nnsemd_options_t* opts,
+                                   double* costs,
+                                   int32_t* plan_src, int32_t* plan_dst, double* plan_flow,
+                                   const int64_t* plan_off,
+                                   nnsemd_stats_t* stats,
+                                   void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NNSEMD_H */

@@ -1,0 +1,232 @@
+"""Thin ctypes binding of libnnsemd.so (include/nnsemd.h).
+
+Argument marshalling only: every step of NNS-EMD runs in the library's HIP
+kernels.  Tensors must already live on the GPU; PyTorch provides the device
+memory and the stream.  There is no CPU fallback: if the library or a GPU is
+missing the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libnnsemd.so")
+
+STATUS = {
+    0: "OK", -1: "INVALID_ARG", -2: "MASS_MISMATCH", -3: "CAPACITY", -4: "OUT_OF_MEMORY",
+    -5: "DEVICE", -6: "NOT_CONVERGED", -7: "UNSUPPORTED",
+}
+METRICS = {"l2": 0, "sqeuclidean": 1, "l1": 2}
+PROTOCOLS = {"greedy": 0, "random": 1}
+MODES = {"fp32": 0, "bf16_mfma_refine": 1}
+DTYPES = {"f32": 0, "bf16": 1}
+
+# nnsemd_stats_t as a numpy record (48 bytes, written by the device).
+STATS_DTYPE = np.dtype([("status", "<i4"), ("rounds", "<i4"), ("nnz", "<i8"), ("work", "<i8"),
+                        ("near_ties", "<i8"), ("residual_src", "<f8"), ("residual_dst", "<f8")])
+
+EXPORTS = ["nnsemd_create", "nnsemd_destroy", "nnsemd_status_string", "nnsemd_last_error",
+           "emd_approx", "emd_approx_batched"]
+
+
+class NNSEMDError(RuntimeError):
+    def __init__(self, status: int, msg: str = ""):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("protocol", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("max_rounds", ctypes.c_int64), ("seed", ctypes.c_uint64),
+                ("threads", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_lock = threading.Lock()
+_lib = None
+_handles: dict[int, ctypes.c_void_p] = {}
+
+
+def load_library():
+    """Load libnnsemd.so (raises if it was not built)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() (hipcc, gfx950) first")
+        lib = ctypes.CDLL(LIB_PATH)
+        P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        lib.nnsemd_create.argtypes = [ctypes.POINTER(P), I32]
+        lib.nnsemd_create.restype = I32
+        lib.nnsemd_destroy.argtypes = [P]
+        lib.nnsemd_destroy.restype = I32
+        lib.nnsemd_status_string.argtypes = [I32]
+        lib.nnsemd_status_string.restype = ctypes.c_char_p
+        lib.nnsemd_last_error.argtypes = [P]
+        lib.nnsemd_last_error.restype = ctypes.c_char_p
+        lib.emd_approx.argtypes = [P, P, P, I64, P, P, I64, I32, I32, I32, ctypes.POINTER(Options),
+                                   P, P, P, P, I64, P, P]
+        lib.emd_approx.restype = I32
+        lib.emd_approx_batched.argtypes = [P, I64, P, P, P, I64, P, P, P, I64, P, P, I64, I64, I32, I32,
+                                           I32, ctypes.POINTER(Options), P, P, P, P, P, P, P]
+        lib.emd_approx_batched.restype = I32
+        _lib = lib
+        return lib
+
+
+def handle(device: int = 0):
+    """Library handle for a device (created once per process)."""
+    lib = load_library()
+    with _lock:
+        h = _handles.get(device)
+        if h is None:
+            h = ctypes.c_void_p()
+            st = lib.nnsemd_create(ctypes.byref(h), device)
+            if st != 0:
+                raise NNSEMDError(st, "nnsemd_create failed")
+            _handles[device] = h
+        return h
+
+
+def _check(lib, h, st):
+    if st != 0:
+        raise NNSEMDError(st, lib.nnsemd_last_error(h).decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _options(protocol, mode, max_rounds, seed, threads):
+    return Options(PROTOCOLS[protocol], MODES[mode], int(max_rounds), int(seed) & (2**64 - 1),
+                   int(threads), 0)
+
+
+def _stream(torch, device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _require(t, dtype, name):
+    if t is None:
+        raise ValueError(f"{name} is required")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor (no CPU path exists)")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def stats_numpy(stats_tensor) -> np.ndarray:
+    """Copy a device stats buffer to host and view it as STATS_DTYPE records."""
+    return stats_tensor.cpu().numpy().view(STATS_DTYPE)
+
+
+def emd_approx(X, a, Y, b, metric: str = "l2", *, plan: bool = True, protocol: str = "greedy",
+               mode: str = "fp32", seed: int = 0, max_rounds: int = 0, threads: int = 0,
+               out: dict | None = None) -> dict:
+    """NNS-EMD of one pair on the GPU.  X (m x d) / a (m): suppliers; Y (n x d)
+    / b (n): consumers; FP32 CUDA tensors.  Returns device tensors: cost (1,),
+    stats (48 uint8), and with plan=True plan_src/plan_dst/plan_flow of
+    capacity m + n - 1 (the first stats.nnz entries are the plan).  Runs
+    asynchronously on the current stream."""
+    import torch
+    lib = load_library()
+    dev = X.device.index if X.device.index is not None else torch.cuda.current_device()
+    h = handle(dev)
+    dt = torch.bfloat16 if mode == "bf16_mfma_refine" else torch.float32
+    _require(X, dt, "X")
+    _require(Y, dt, "Y")
+    _require(a, torch.float32, "a")
+    _require(b, torch.float32, "b")
+    m, n = X.shape[0], Y.shape[0]
+    d = X.shape[1] if X.dim() == 2 else 1
+    o = out or {}
+    cost = o.get("cost")
+    if cost is None:
+        cost = torch.empty(1, dtype=torch.float64, device=X.device)
+    stats = o.get("stats")
+    if stats is None:
+        stats = torch.empty(STATS_DTYPE.itemsize, dtype=torch.uint8, device=X.device)
+    cap = max(m + n - 1, 1)
+    src = dst = flow = None
+    if plan:
+        src = o.get("plan_src") if o.get("plan_src") is not None else torch.empty(cap, dtype=torch.int32, device=X.device)
+        dst = o.get("plan_dst") if o.get("plan_dst") is not None else torch.empty(cap, dtype=torch.int32, device=X.device)
+        flow = o.get("plan_flow") if o.get("plan_flow") is not None else torch.empty(cap, dtype=torch.float64, device=X.device)
+        cap = src.numel()
+    opts = _options(protocol, mode, max_rounds, seed, threads)
+    st = lib.emd_approx(h, _ptr(X), _ptr(a), m, _ptr(Y), _ptr(b), n, d,
+                        DTYPES["bf16" if mode == "bf16_mfma_refine" else "f32"], METRICS[metric],
+                        ctypes.byref(opts), _ptr(cost), _ptr(src), _ptr(dst), _ptr(flow),
+                        cap if plan else 0, _ptr(stats), _stream(torch, dev))
+    _check(lib, h, st)
+    return {"cost": cost, "stats": stats, "plan_src": src, "plan_dst": dst, "plan_flow": flow}
+
+
+def plan_offsets(m_sizes, n_sizes) -> np.ndarray:
+    """Host helper: plan_off with capacity m_p + n_p - 1 per pair (int64)."""
+    cap = np.maximum(np.asarray(m_sizes, np.int64) + np.asarray(n_sizes, np.int64) - 1, 0)
+    off = np.zeros(len(cap) + 1, np.int64)
+    off[1:] = np.cumsum(cap)
+    return off
+
+
+def emd_approx_batched(Xcat, acat, x_off, Ycat, bcat, y_off, *, max_m: int, max_n: int,
+                       pair_x=None, pair_y=None, num_pairs: int | None = None, metric: str = "l2",
+                       plan_off=None, protocol: str = "greedy", mode: str = "fp32", seed: int = 0,
+                       max_rounds: int = 0, threads: int = 0, out: dict | None = None) -> dict:
+    """NNS-EMD of many ragged pairs in one persistent launch.  Offsets and
+    pair tables are int64/int32 CUDA tensors; max_m/max_n are host bounds on
+    the set sizes.  With plan_off (CUDA int64, num_pairs + 1) the plans are
+    written too.  Returns device tensors costs (num_pairs,), stats
+    (num_pairs * 48 uint8) and the plan buffers.  Asynchronous."""
+    import torch
+    lib = load_library()
+    dev = Xcat.device.index if Xcat.device.index is not None else torch.cuda.current_device()
+    h = handle(dev)
+    dt = torch.bfloat16 if mode == "bf16_mfma_refine" else torch.float32
+    _require(Xcat, dt, "Xcat")
+    _require(Ycat, dt, "Ycat")
+    _require(acat, torch.float32, "acat")
+    _require(bcat, torch.float32, "bcat")
+    _require(x_off, torch.int64, "x_off")
+    _require(y_off, torch.int64, "y_off")
+    if pair_x is not None:
+        _require(pair_x, torch.int32, "pair_x")
+    if pair_y is not None:
+        _require(pair_y, torch.int32, "pair_y")
+    nx, ny = x_off.numel() - 1, y_off.numel() - 1
+    if num_pairs is None:
+        num_pairs = pair_x.numel() if pair_x is not None else nx
+    d = Xcat.shape[1] if Xcat.dim() == 2 else 1
+    o = out or {}
+    costs = o.get("costs")
+    if costs is None:
+        costs = torch.empty(max(num_pairs, 1), dtype=torch.float64, device=Xcat.device)
+    stats = o.get("stats")
+    if stats is None:
+        stats = torch.empty(max(num_pairs, 1) * STATS_DTYPE.itemsize, dtype=torch.uint8, device=Xcat.device)
+    src = dst = flow = None
+    if plan_off is not None:
+        _require(plan_off, torch.int64, "plan_off")
+        total = o.get("plan_total")
+        if total is None:
+            total = int(plan_off[-1].item())
+        src = o.get("plan_src") if o.get("plan_src") is not None else torch.empty(max(total, 1), dtype=torch.int32, device=Xcat.device)
+        dst = o.get("plan_dst") if o.get("plan_dst") is not None else torch.empty(max(total, 1), dtype=torch.int32, device=Xcat.device)
+        flow = o.get("plan_flow") if o.get("plan_flow") is not None else torch.empty(max(total, 1), dtype=torch.float64, device=Xcat.device)
+    opts = _options(protocol, mode, max_rounds, seed, threads)
+    st = lib.emd_approx_batched(
+        h, num_pairs, _ptr(Xcat), _ptr(acat), _ptr(x_off), nx, _ptr(Ycat), _ptr(bcat), _ptr(y_off), ny,
+        _ptr(pair_x), _ptr(pair_y), int(max_m), int(max_n), d,
+        DTYPES["bf16" if mode == "bf16_mfma_refine" else "f32"], METRICS[metric], ctypes.byref(opts),
+        _ptr(costs), _ptr(src), _ptr(dst), _ptr(flow), _ptr(plan_off), _ptr(stats), _stream(torch, dev))
+    _check(lib, h, st)
+    return {"costs": costs, "stats": stats, "plan_src": src, "plan_dst": dst, "plan_flow": flow,
+            "plan_off": plan_off}

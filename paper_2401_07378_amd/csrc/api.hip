@@ -1,0 +1,248 @@
+// Host runtime of the NNS-EMD library: handles, argument checks, workspace
+// and dispatch to the kernels.  Implements include/nnsemd.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "internal.hpp"
+
+struct nnsemd_handle {
+    int device = 0;
+    int num_cus = 0;
+    size_t max_lds = 0;
+    std::string last_error;
+};
+
+namespace {
+
+using namespace nnsemd;
+
+nnsemd_status_t fail(nnsemd_handle_t h, nnsemd_status_t s, const char* msg) {
+    if (h) h->last_error = msg;
+    return s;
+}
+
+nnsemd_status_t device_fail(nnsemd_handle_t h, int err, const char* where) {
+    if (h) {
+        char buf[256];
+        std::snprintf(buf, sizeof(buf), "%s: %s", where, hipGetErrorString((hipError_t)err));
+        h->last_error = buf;
+    }
+    return NNSEMD_ERR_DEVICE;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+nnsemd_options_t default_options() {
+    nnsemd_options_t o;
+    std::memset(&o, 0, sizeof(o));
+    o.protocol = NNSEMD_GREEDY;
+    o.mode = NNSEMD_MODE_FP32;
+    return o;
+}
+
+// Common entry for one or many pairs of low-dimensional FP32 points.
+nnsemd_status_t run_pairs(nnsemd_handle_t h, PairSolverArgs& A, int d, int64_t max_m, int64_t max_n,
+                          const nnsemd_options_t& o, void* stream) {
+    if (d < 1 || d > 7) return fail(h, NNSEMD_ERR_UNSUPPORTED, "point path supports 1 <= d <= 7");
+    const int threads = o.threads > 0 ? o.threads : 256;
+    if (threads != 256 && threads != 512)
+        return fail(h, NNSEMD_ERR_UNSUPPORTED, "workgroup size must be 256 or 512");
+    const int64_t maxp = std::max<int64_t>({max_m, max_n, 1});
+    const int chunk = (int)((maxp + threads - 1) / threads);
+    const int chunk_cap = threads == 256 ? 16 : 8;
+    if (chunk > chunk_cap) return fail(h, NNSEMD_ERR_UNSUPPORTED, "set too large for the on-chip pair path");
+    const int mcap = (int)std::max<int64_t>(max_m, 1), ncap = (int)std::max<int64_t>(max_n, 1);
+    const PairLdsLayout lay = pair_lds_layout(mcap, ncap, record_stride(d));
+    if (lay.total + 8192 > h->max_lds)
+        return fail(h, NNSEMD_ERR_UNSUPPORTED, "set too large for the on-chip pair path (LDS)");
+    A.max_m = mcap;
+    A.max_n = ncap;
+    A.protocol = o.protocol;
+    A.seed = o.seed;
+    A.max_rounds = o.max_rounds;
+    int blocks = 0;
+    int err = pair_solver_blocks_per_cu(d, A.metric, threads, chunk, lay.total, &blocks);
+    if (err != 0) return device_fail(h, err, "occupancy query");
+    if (blocks < 1) return fail(h, NNSEMD_ERR_UNSUPPORTED, "pair workgroup does not fit on a compute unit");
+    const int64_t grid = A.num_pairs;
+    err = launch_pair_solver(A, d, threads, chunk, lay.total, (int)grid, stream);
+    if (err != 0) return device_fail(h, err, "solver launch");
+    return NNSEMD_OK;
+}
+
+nnsemd_status_t check_common(nnsemd_handle_t h, int32_t d, nnsemd_dtype_t dtype, nnsemd_metric_t metric,
+                             const nnsemd_options_t& o) {
+    if (d < 1) return fail(h, NNSEMD_ERR_INVALID_ARG, "d must be >= 1");
+    if (dtype != NNSEMD_F32 && dtype != NNSEMD_BF16) return fail(h, NNSEMD_ERR_INVALID_ARG, "bad dtype");
+    if (metric != NNSEMD_L2 && metric != NNSEMD_SQEUCLIDEAN && metric != NNSEMD_L1)
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "bad metric");
+    if (o.protocol != NNSEMD_GREEDY && o.protocol != NNSEMD_RANDOM)
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "bad protocol");
+    if (o.mode != NNSEMD_MODE_FP32 && o.mode != NNSEMD_MODE_BF16_MFMA_REFINE)
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "bad mode");
+    if (o.mode == NNSEMD_MODE_FP32 && dtype != NNSEMD_F32)
+        return fail(h, NNSEMD_ERR_UNSUPPORTED, "FP32 mode takes FP32 points");
+    if (o.mode == NNSEMD_MODE_BF16_MFMA_REFINE)
+        return fail(h, NNSEMD_ERR_UNSUPPORTED, "BF16 matrix-core mode is not available in this build");
+    return NNSEMD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+nnsemd_status_t nnsemd_create(nnsemd_handle_t* out, int32_t device) {
+    if (out == nullptr) return NNSEMD_ERR_INVALID_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+        return NNSEMD_ERR_INVALID_ARG;
+    nnsemd_handle* h = new (std::nothrow) nnsemd_handle();
+    if (h == nullptr) return NNSEMD_ERR_OUT_OF_MEMORY;
+    h->device = device;
+    DeviceGuard g(device);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        delete h;
+        return NNSEMD_ERR_DEVICE;
+    }
+    h->num_cus = prop.multiProcessorCount;
+    h->max_lds = prop.sharedMemPerBlock;
+    int optin = 0;
+    if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, device) == hipSuccess &&
+        optin > 0)
+        h->max_lds = std::max<size_t>(h->max_lds, (size_t)optin);
+    *out = h;
+    return NNSEMD_OK;
+}
+
+nnsemd_status_t nnsemd_destroy(nnsemd_handle_t h) {
+    if (h == nullptr) return NNSEMD_ERR_INVALID_ARG;
+    {
+        DeviceGuard g(h->device);
+        (void)hipDeviceSynchronize();
+    }
+    delete h;
+    return NNSEMD_OK;
+}
+
+const char* nnsemd_status_string(nnsemd_status_t s) {
+    switch (s) {
+        case NNSEMD_OK: return "ok";
+        case NNSEMD_ERR_INVALID_ARG: return "invalid argument";
+        case NNSEMD_ERR_MASS_MISMATCH: return "total masses differ by more than 1e-5 relative";
+        case NNSEMD_ERR_CAPACITY: return "plan buffer smaller than m + n - 1";
+        case NNSEMD_ERR_OUT_OF_MEMORY: return "out of memory";
+        case NNSEMD_ERR_DEVICE: return "device error";
+        case NNSEMD_ERR_NOT_CONVERGED: return "round cap reached";
+        case NNSEMD_ERR_UNSUPPORTED: return "unsupported combination";
+    }
+    return "unknown status";
+}
+
+const char* nnsemd_last_error(nnsemd_handle_t h) { return h ? h->last_error.c_str() : ""; }
+
+nnsemd_status_t emd_approx(nnsemd_handle_t h, const void* X, const float* a, int64_t m, const void* Y,
+                           const float* b, int64_t n, int32_t d, nnsemd_dtype_t dtype,
+                           nnsemd_metric_t metric, const nnsemd_options_t* opts, double* cost,
+                           int32_t* plan_src, int32_t* plan_dst, double* plan_flow, int64_t plan_capacity,
+                           nnsemd_stats_t* stats, void* stream) {
+    if (h == nullptr) return NNSEMD_ERR_INVALID_ARG;
+    h->last_error.clear();
+    const nnsemd_options_t o = opts ? *opts : default_options();
+    nnsemd_status_t s = check_common(h, d, dtype, metric, o);
+    if (s != NNSEMD_OK) return s;
+    if (m < 0 || n < 0) return fail(h, NNSEMD_ERR_INVALID_ARG, "negative size");
+    if (cost == nullptr) return fail(h, NNSEMD_ERR_INVALID_ARG, "cost must not be NULL");
+    if ((m > 0 && (X == nullptr || a == nullptr)) || (n > 0 && (Y == nullptr || b == nullptr)))
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "NULL point or mass array");
+    const bool plan = plan_src != nullptr || plan_dst != nullptr || plan_flow != nullptr;
+    if (plan && (plan_src == nullptr || plan_dst == nullptr || plan_flow == nullptr))
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "plan arrays must be all given or all NULL");
+    if (plan && m + n > 0 && plan_capacity < m + n - 1)
+        return fail(h, NNSEMD_ERR_CAPACITY, "plan capacity below m + n - 1");
+    DeviceGuard g(h->device);
+    PairSolverArgs A{};
+    A.num_pairs = 1;
+    A.X = static_cast<const float*>(X);
+    A.a = a;
+    A.Y = static_cast<const float*>(Y);
+    A.b = b;
+    A.single_m = m;
+    A.single_n = n;
+    A.metric = metric;
+    A.costs = cost;
+    A.plan_src = plan ? plan_src : nullptr;
+    A.plan_dst = plan ? plan_dst : nullptr;
+    A.plan_flow = plan ? plan_flow : nullptr;
+    A.single_plan_cap = plan_capacity;
+    A.stats = stats;
+    return run_pairs(h, A, d, m, n, o, stream);
+}
+
+nnsemd_status_t emd_approx_batched(nnsemd_handle_t h, int64_t num_pairs, const void* Xcat, const float* acat,
+                                   const int64_t* x_off, int64_t num_x_sets, const void* Ycat,
+                                   const float* bcat, const int64_t* y_off, int64_t num_y_sets,
+                                   const int32_t* pair_x, const int32_t* pair_y, int64_t max_m, int64_t max_n,
+                                   int32_t d, nnsemd_dtype_t dtype, nnsemd_metric_t metric,
+                                   const nnsemd_options_t* opts, double* costs, int32_t* plan_src,
+                                   int32_t* plan_dst, double* plan_flow, const int64_t* plan_off,
+                                   nnsemd_stats_t* stats, void* stream) {
+    if (h == nullptr) return NNSEMD_ERR_INVALID_ARG;
+    h->last_error.clear();
+    const nnsemd_options_t o = opts ? *opts : default_options();
+    nnsemd_status_t s = check_common(h, d, dtype, metric, o);
+    if (s != NNSEMD_OK) return s;
+    if (num_pairs < 0 || num_x_sets < 0 || num_y_sets < 0 || max_m < 0 || max_n < 0)
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "negative count");
+    if (num_pairs == 0) return NNSEMD_OK;
+    if (costs == nullptr || x_off == nullptr || y_off == nullptr || Xcat == nullptr || Ycat == nullptr ||
+        acat == nullptr || bcat == nullptr)
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "NULL required array");
+    if (num_x_sets == 0 || num_y_sets == 0) return fail(h, NNSEMD_ERR_INVALID_ARG, "no point sets");
+    if ((pair_x == nullptr && num_x_sets < num_pairs) || (pair_y == nullptr && num_y_sets < num_pairs))
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "fewer sets than pairs without a pair table");
+    const bool plan = plan_src != nullptr || plan_dst != nullptr || plan_flow != nullptr;
+    if (plan && (plan_src == nullptr || plan_dst == nullptr || plan_flow == nullptr || plan_off == nullptr))
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "plan arrays and plan_off must be all given or all NULL");
+    if (num_pairs > 0x7fffffffLL - (1LL << 20))
+        return fail(h, NNSEMD_ERR_UNSUPPORTED, "too many pairs for one call");
+    DeviceGuard g(h->device);
+    PairSolverArgs A{};
+    A.num_pairs = num_pairs;
+    A.X = static_cast<const float*>(Xcat);
+    A.a = acat;
+    A.x_off = x_off;
+    A.num_x_sets = num_x_sets;
+    A.Y = static_cast<const float*>(Ycat);
+    A.b = bcat;
+    A.y_off = y_off;
+    A.num_y_sets = num_y_sets;
+    A.pair_x = pair_x;
+    A.pair_y = pair_y;
+    A.metric = metric;
+    A.costs = costs;
+    A.plan_src = plan ? plan_src : nullptr;
+    A.plan_dst = plan ? plan_dst : nullptr;
+    A.plan_flow = plan ? plan_flow : nullptr;
+    A.plan_off = plan ? plan_off : nullptr;
+    A.stats = stats;
+    return run_pairs(h, A, d, max_m, max_n, o, stream);
+}
+
+}  // extern "C"

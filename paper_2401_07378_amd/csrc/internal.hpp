@@ -1,0 +1,82 @@
+// Internal declarations shared by the host runtime and the kernels of the
+// NNS-EMD library.  Not part of the public ABI (include/nnsemd.h is).
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "nnsemd.h"
+
+namespace nnsemd {
+
+// Unit roundoff of FP32 (2^-24).
+constexpr float kU32 = 5.9604644775390625e-08f;
+
+// Record stride (floats) of one active supplier in LDS for dimension d:
+// Euclidean metrics store (-2 x_0 .. -2 x_{d-1}, ||x||^2), L1 stores x.
+__host__ __device__ constexpr int record_stride(int d) { return d + 1 <= 4 ? 4 : 8; }
+
+// Arguments of the per-pair workgroup solver (low-dimensional FP32 points).
+struct PairSolverArgs {
+    int64_t num_pairs;
+    const float* X;
+    const float* a;
+    const int64_t* x_off;  // nullptr: single pair of single_m rows
+    int64_t num_x_sets;
+    const float* Y;
+    const float* b;
+    const int64_t* y_off;
+    int64_t num_y_sets;
+    const int32_t* pair_x;
+    const int32_t* pair_y;
+    int64_t single_m;
+    int64_t single_n;
+    int32_t max_m;  // LDS capacity of this launch
+    int32_t max_n;
+    int32_t metric;
+    int32_t protocol;
+    uint64_t seed;
+    int64_t max_rounds;  // <= 0: m + n
+    double* costs;
+    int32_t* plan_src;
+    int32_t* plan_dst;
+    double* plan_flow;
+    const int64_t* plan_off;  // nullptr with a plan: single pair, capacity below
+    int64_t single_plan_cap;
+    nnsemd_stats_t* stats;
+    const int32_t* order;  // nullable: workgroup b solves pair order[b]
+};
+
+// Byte layout of the dynamic LDS of one workgroup (one pair at a time).
+struct PairLdsLayout {
+    size_t smass, cmass, ckey, srec, sidx, scnt, soff, cact, cnn, list, total;
+};
+
+__host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+__host__ __device__ inline PairLdsLayout pair_lds_layout(int M, int N, int rs) {
+    PairLdsLayout L;
+    size_t o = 0;
+    L.smass = o; o += sizeof(double) * (size_t)M;
+    L.cmass = o; o += sizeof(double) * (size_t)N;
+    L.ckey = o;  o += sizeof(double) * (size_t)N;
+    o = align_up(o, 16);
+    L.srec = o;  o += sizeof(float) * (size_t)rs * (size_t)M;
+    L.sidx = o;  o += sizeof(int32_t) * (size_t)M;
+    L.scnt = o;  o += sizeof(int32_t) * (size_t)M;
+    L.soff = o;  o += sizeof(int32_t) * (size_t)M;
+    L.cact = o;  o += sizeof(int32_t) * (size_t)N;
+    L.cnn = o;   o += sizeof(int32_t) * (size_t)N;
+    L.list = o;  o += sizeof(int32_t) * (size_t)N;
+    L.total = align_up(o, 16);
+    return L;
+}
+
+// Launch entry points (defined in pair_solver.hip).
+// Returns hipSuccess-compatible int (0 on success).
+int launch_pair_solver(const PairSolverArgs& args, int d, int threads, int chunk_max,
+                       size_t lds_bytes, int grid, void* stream);
+int pair_solver_blocks_per_cu(int d, int metric, int threads, int chunk_max, size_t lds_bytes,
+                              int* blocks);
+
+}  // namespace nnsemd

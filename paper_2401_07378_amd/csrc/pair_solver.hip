@@ -1,0 +1,706 @@
+// Per-pair workgroup solver of NNS-EMD for low-dimensional FP32 points.
+//
+// One workgroup owns one pair at a time and keeps everything about it in
+// LDS: the compacted active suppliers (search records), per-point FP64
+// masses, the consumers' current picks and the claimant buckets.  The rounds
+// of Algorithm 1 (Sec. III-A) run as barrier-separated phases without ever
+// leaving the chip:
+//   1. NNS (Alg. 1 NNS step): every active consumer scans the active
+//      supplier records in FP32.  For the Euclidean metrics the record is
+//      (-2 x^, ||x^||^2) with x^ = x - centre, so one key costs d FMAs and
+//      equals ||x^ - y^||^2 - ||y^||^2 up to a rounding bound E_q; best and
+//      second-best keys are tracked and a consumer whose two keys are within
+//      that bound is re-scored in FP64 by a whole wavefront, so every pick
+//      equals the FP64 argmin with ties going to the smallest index.
+//   2. Claimant sets a_i: LDS-atomic counting sort of consumers by pick.
+//   3. Flow & cost (greedy or random protocol): one lane per claimed
+//      supplier selects its claimants in (D_ij, j) order (or the random
+//      protocol's key order) and serves f = min(s_i, c_j) in FP64 with the
+//      same operations as the definition, so flows are bit-identical to it.
+//   4. Weights update: plan entries and the surviving suppliers/consumers
+//      are compacted with one block-wide prefix scan (ballot-free: per-lane
+//      contiguous chunks, wavefront shuffles, one LDS hop).
+// One launch covers any number of ragged pairs, one workgroup each (the
+// batching of Sec. III-D without padding).
+#ifndef NNSEMD_CPU_EMULATION
+#include <hip/hip_runtime.h>
+#endif
+#include <math.h>
+#include <stdint.h>
+
+#include "internal.hpp"
+
+namespace nnsemd {
+namespace {
+
+constexpr int kWave = 64;
+
+struct Lds {
+    double* smass;  // [M] supplier mass by local index
+    double* cmass;  // [N] consumer mass by local index
+    double* ckey;   // [N] FP64 key of (pick, j); after the serve: flow (0 = unserved)
+    float* srec;    // [M * RS] active supplier records, compacted
+    int32_t* sidx;  // [M] local index of active supplier slot
+    int32_t* scnt;  // [M] claimant count by supplier
+    int32_t* soff;  // [M] bucket start, then bucket end
+    int32_t* cact;  // [N] active consumers, compacted, ascending
+    int32_t* cnn;   // [N] pick (local supplier index) by consumer
+    int32_t* list;  // [N] near-tie consumers during the search; claimant buckets after
+};
+
+struct Shared {
+    double red[16][24];
+    unsigned long long scan[16];
+    int32_t nflag;
+    int32_t pad;
+};
+
+__device__ inline Lds carve(char* base, int M, int N, int rs) {
+    PairLdsLayout L = pair_lds_layout(M, N, rs);
+    Lds s;
+    s.smass = reinterpret_cast<double*>(base + L.smass);
+    s.cmass = reinterpret_cast<double*>(base + L.cmass);
+    s.ckey = reinterpret_cast<double*>(base + L.ckey);
+    s.srec = reinterpret_cast<float*>(base + L.srec);
+    s.sidx = reinterpret_cast<int32_t*>(base + L.sidx);
+    s.scnt = reinterpret_cast<int32_t*>(base + L.scnt);
+    s.soff = reinterpret_cast<int32_t*>(base + L.soff);
+    s.cact = reinterpret_cast<int32_t*>(base + L.cact);
+    s.cnn = reinterpret_cast<int32_t*>(base + L.cnn);
+    s.list = reinterpret_cast<int32_t*>(base + L.list);
+    return s;
+}
+
+// Exact FP64 key in the definition's operation order (dimension order, no
+// fused multiply-add): squared Euclidean, or L1.
+template <int D, bool L1>
+__device__ inline double key64(const float* __restrict__ x, const float* __restrict__ y) {
+#pragma clang fp contract(off)
+    double acc = 0.0;
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+        double diff = (double)x[t] - (double)y[t];
+        if (L1)
+            acc = acc + fabs(diff);
+        else
+            acc = acc + diff * diff;
+    }
+    return acc;
+}
+
+__device__ inline double dist_of_key(double key, int metric) {
+    return metric == NNSEMD_L2 ? sqrt(key) : key;
+}
+
+// SplitMix64 output function of the counter (seed, round, consumer): the
+// random protocol's serve order key.
+__device__ inline uint64_t rp_key(uint64_t seed, int64_t round, int32_t j) {
+    uint64_t ctr = ((uint64_t)round << 32) ^ (uint64_t)(uint32_t)j;
+    uint64_t z = seed + (ctr + 1u) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Exclusive block scan of one 64-bit value per thread; *total = block sum.
+template <int T>
+__device__ inline unsigned long long block_scan_u64(unsigned long long v, unsigned long long* total,
+                                                    Shared& sh) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    unsigned long long x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        unsigned long long y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == kWave - 1) sh.scan[w] = x;
+    __syncthreads();
+    unsigned long long off = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < T / kWave; ++k) {
+        unsigned long long s = sh.scan[k];
+        off += (k < w) ? s : 0ull;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + x - v;
+}
+
+// Block-wide reduction of K values per thread (op 0 = sum, 1 = min, 2 = max),
+// deterministic (fixed butterfly + fixed wave order).  Results in out[].
+template <int T, int K>
+__device__ inline void block_reduce(double (&v)[K], const int (&op)[K], Shared& sh) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) {
+            double y = __shfl_xor(v[k], o);
+            v[k] = op[k] == 0 ? v[k] + y : (op[k] == 1 ? fmin(v[k], y) : fmax(v[k], y));
+        }
+        if (lane == 0) sh.red[w][k] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double r = sh.red[0][k];
+#pragma unroll
+        for (int q = 1; q < T / kWave; ++q) {
+            double y = sh.red[q][k];
+            r = op[k] == 0 ? r + y : (op[k] == 1 ? fmin(r, y) : fmax(r, y));
+        }
+        v[k] = r;
+    }
+    __syncthreads();
+}
+
+// FP32 search key of record `rec` for consumer y (see file comment).
+template <int D, int RS, bool L1>
+__device__ inline float key32(const float* __restrict__ rec, const float (&y)[D]) {
+    if (L1) {
+        float k = 0.f;
+#pragma unroll
+        for (int t = 0; t < D; ++t) k += fabsf(rec[t] - y[t]);
+        return k;
+    } else {
+        float k = rec[D];
+#pragma unroll
+        for (int t = D - 1; t >= 0; --t) k = fmaf(rec[t], y[t], k);
+        return k;
+    }
+}
+
+template <int RS>
+__device__ inline void load_rec(const float* __restrict__ base, int s, float (&r)[RS]) {
+    const float4* p = reinterpret_cast<const float4*>(base + (size_t)s * RS);
+#pragma unroll
+    for (int q = 0; q < RS / 4; ++q) {
+        float4 v = p[q];
+        r[4 * q + 0] = v.x;
+        r[4 * q + 1] = v.y;
+        r[4 * q + 2] = v.z;
+        r[4 * q + 3] = v.w;
+    }
+}
+
+template <int RS>
+__device__ inline void store_rec(float* __restrict__ base, int s, const float (&r)[RS]) {
+    float4* p = reinterpret_cast<float4*>(base + (size_t)s * RS);
+#pragma unroll
+    for (int q = 0; q < RS / 4; ++q)
+        p[q] = make_float4(r[4 * q + 0], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]);
+}
+
+template <int D, int T, int CSMAX, bool L1>
+__device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds& L, Shared& sh) {
+    constexpr int RS = record_stride(D);
+    constexpr int NW = T / kWave;
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = tid / kWave;
+
+    // ---------------------------------------------------------- pair geometry
+    int64_t x0 = 0, y0 = 0, m = A.single_m, n = A.single_n;
+    int status = NNSEMD_OK;
+    if (A.x_off != nullptr) {
+        int64_t px = A.pair_x ? (int64_t)A.pair_x[p] : p;
+        int64_t py = A.pair_y ? (int64_t)A.pair_y[p] : p;
+        if (px < 0 || px >= A.num_x_sets || py < 0 || py >= A.num_y_sets) {
+            status = NNSEMD_ERR_INVALID_ARG;
+            m = n = 0;
+        } else {
+            x0 = A.x_off[px];
+            m = A.x_off[px + 1] - x0;
+            y0 = A.y_off[py];
+            n = A.y_off[py + 1] - y0;
+        }
+    }
+    if (status == NNSEMD_OK && (m < 0 || n < 0 || m > A.max_m || n > A.max_n)) {
+        status = NNSEMD_ERR_INVALID_ARG;
+        m = n = 0;
+    }
+    int64_t plan_base = 0, plan_cap = 0;
+    const bool want_plan = A.plan_src != nullptr;
+    if (want_plan) {
+        if (A.plan_off != nullptr) {
+            plan_base = A.plan_off[p];
+            plan_cap = A.plan_off[p + 1] - plan_base;
+        } else {
+            plan_cap = A.single_plan_cap;
+        }
+        if (status == NNSEMD_OK && m + n > 0 && plan_cap < m + n - 1) {
+            status = NNSEMD_ERR_CAPACITY;
+            m = n = 0;
+        }
+    }
+    const float* __restrict__ X = A.X + x0 * D;
+    const float* __restrict__ Y = A.Y + y0 * D;
+    const int mi = (int)m, ni = (int)n;
+
+    // ------------------------------------- ingest: masses, checks, bounding box
+    double red[3 + 2 * D];
+    int rop[3 + 2 * D];
+    red[0] = 0.0; rop[0] = 0;  // sum a
+    red[1] = 0.0; rop[1] = 0;  // sum b
+    red[2] = 0.0; rop[2] = 2;  // bad value seen
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+        red[3 + t] = INFINITY;      rop[3 + t] = 1;
+        red[3 + D + t] = -INFINITY; rop[3 + D + t] = 2;
+    }
+    for (int i = tid; i < mi; i += T) {
+        float av = A.a[x0 + i];
+        if (!(av >= 0.f) || !isfinite(av)) red[2] = 1.0;
+        L.smass[i] = (double)av;
+        red[0] += (double)av;
+#pragma unroll
+        for (int t = 0; t < D; ++t) {
+            float xv = X[(size_t)i * D + t];
+            if (!isfinite(xv)) red[2] = 1.0;
+            red[3 + t] = fmin(red[3 + t], (double)xv);
+            red[3 + D + t] = fmax(red[3 + D + t], (double)xv);
+        }
+    }
+    for (int j = tid; j < ni; j += T) {
+        float bv = A.b[y0 + j];
+        if (!(bv >= 0.f) || !isfinite(bv)) red[2] = 1.0;
+        L.cmass[j] = (double)bv;
+        red[1] += (double)bv;
+#pragma unroll
+        for (int t = 0; t < D; ++t)
+            if (!isfinite(Y[(size_t)j * D + t])) red[2] = 1.0;
+    }
+    block_reduce<T, 3 + 2 * D>(red, rop, sh);
+    if (status == NNSEMD_OK && red[2] != 0.0) status = NNSEMD_ERR_INVALID_ARG;
+    if (status == NNSEMD_OK) {
+        double big = fmax(red[0], red[1]);
+        if (fabs(red[0] - red[1]) > 1e-5 * big) status = NNSEMD_ERR_MASS_MISMATCH;
+    }
+    float centre[D];
+#pragma unroll
+    for (int t = 0; t < D; ++t)
+        centre[t] = (L1 || mi == 0) ? 0.f : 0.5f * ((float)red[3 + t] + (float)red[3 + D + t]);
+
+    // ------------------- initial active sets (zero-mass points never enter)
+    int mact = 0, nact = 0;
+    float rhat = 0.f;
+    if (status == NNSEMD_OK) {
+        const int cs = (mi + T - 1) / T;
+        const int cc = (ni + T - 1) / T;
+        const int slo = min(tid * cs, mi), shi = min(slo + cs, mi);
+        const int clo = min(tid * cc, ni), chi = min(clo + cc, ni);
+        int ks = 0, kc = 0;
+        for (int i = slo; i < shi; ++i) ks += L.smass[i] > 0.0;
+        for (int j = clo; j < chi; ++j) kc += L.cmass[j] > 0.0;
+        unsigned long long tot;
+        unsigned long long pre = block_scan_u64<T>((unsigned long long)ks | ((unsigned long long)kc << 32), &tot, sh);
+        int ps = (int)(pre & 0xffffffffu), pc = (int)(pre >> 32);
+        mact = (int)(tot & 0xffffffffu);
+        nact = (int)(tot >> 32);
+        float rmax = 0.f;
+        for (int i = slo; i < shi; ++i) {
+            if (!(L.smass[i] > 0.0)) continue;
+            float r[RS];
+#pragma unroll
+            for (int q = 0; q < RS; ++q) r[q] = 0.f;
+            if (L1) {
+#pragma unroll
+                for (int t = 0; t < D; ++t) r[t] = X[(size_t)i * D + t];
+            } else {
+                float h = 0.f;
+#pragma unroll
+                for (int t = 0; t < D; ++t) {
+                    float xc = X[(size_t)i * D + t] - centre[t];
+                    r[t] = -2.f * xc;
+                    h = fmaf(xc, xc, h);
+                }
+                r[D] = h;
+                rmax = fmaxf(rmax, sqrtf(h));
+            }
+            store_rec<RS>(L.srec, ps, r);
+            L.sidx[ps] = i;
+            ++ps;
+        }
+        for (int j = clo; j < chi; ++j)
+            if (L.cmass[j] > 0.0) L.cact[pc++] = j;
+        double rr[1] = {(double)rmax};
+        const int ro[1] = {2};
+        block_reduce<T, 1>(rr, ro, sh);  // also orders the writes above
+        rhat = (float)rr[0] * (1.f + 1e-6f);
+        if (tid == 0) sh.nflag = 0;
+        __syncthreads();
+    }
+
+    // ------------------------------------------------------------- rounds
+    const int64_t max_rounds = A.max_rounds > 0 ? A.max_rounds : (int64_t)mi + ni;
+    int rounds = 0;
+    int64_t work = 0, nnz = 0, near = 0;
+    double cost = 0.0;  // this thread's part of R
+    while (status == NNSEMD_OK && mact > 0 && nact > 0) {
+        if (rounds >= max_rounds) {
+            status = NNSEMD_ERR_NOT_CONVERGED;
+            break;
+        }
+        work += (int64_t)mact * nact;
+
+        // ---- 1. NNS: FP32 scan, best + second best, near ties deferred
+        for (int s = tid; s < mact; s += T) L.scnt[L.sidx[s]] = 0;
+        int S = 1;
+        while (S < kWave && nact * S * 2 <= T) S <<= 1;
+        while (S > 1 && S > mact) S >>= 1;
+        const int r = tid & (S - 1);
+        const int g = tid / S;
+        const int G = T / S;
+        for (int q0 = 0; q0 < nact; q0 += G) {
+            const int q = q0 + g;
+            const bool valid = q < nact;
+            const int j = valid ? L.cact[q] : 0;
+            float y[D];
+            float yn2 = 0.f;
+#pragma unroll
+            for (int t = 0; t < D; ++t) {
+                float yv = valid ? Y[(size_t)j * D + t] - centre[t] : 0.f;
+                y[t] = yv;
+                yn2 = fmaf(yv, yv, yn2);
+            }
+            float b1 = INFINITY, b2 = INFINITY;
+            int bs = 0x7fffffff;
+            if (valid) {
+                for (int s = r; s < mact; s += S) {
+                    float rec[RS];
+                    load_rec<RS>(L.srec, s, rec);
+                    const float k = key32<D, RS, L1>(rec, y);
+                    b2 = fminf(b2, fmaxf(b1, k));
+                    if (k < b1) {
+                        b1 = k;
+                        bs = s;
+                    }
+                }
+            }
+            for (int o = 1; o < S; o <<= 1) {
+                const float c1 = __shfl_xor(b1, o);
+                const float c2 = __shfl_xor(b2, o);
+                const int cs2 = __shfl_xor(bs, o);
+                const float n2 = fminf(fmaxf(b1, c1), fminf(b2, c2));
+                const bool take = (c1 < b1) || (c1 == b1 && cs2 < bs);
+                b1 = take ? c1 : b1;
+                bs = take ? cs2 : bs;
+                b2 = n2;
+            }
+            if (valid && r == 0) {
+                float thr;
+                if (L1) {
+                    thr = 4.f * (float)(D + 1) * kU32 * b2 + 1e-30f;
+                } else {
+                    const float e = rhat + sqrtf(yn2);
+                    thr = 32.f * kU32 * e * e + 1e-30f;
+                }
+                if (!(b2 - b1 > thr)) {
+                    const int f = atomicAdd(&sh.nflag, 1);
+                    L.list[f] = j;
+                } else {
+                    const int i = L.sidx[bs];
+                    L.cnn[j] = i;
+                    L.ckey[j] = key64<D, L1>(X + (size_t)i * D, Y + (size_t)j * D);
+                }
+            }
+        }
+        __syncthreads();
+        const int nf = sh.nflag;
+        if (nf > 0) {
+            // FP64 re-score of near-tie consumers, one wavefront per consumer.
+            for (int f = wave; f < nf; f += NW) {
+                const int j = L.list[f];
+                const float* yp = Y + (size_t)j * D;
+                double best = INFINITY;
+                int bsl = 0x7fffffff;
+                for (int s = lane; s < mact; s += kWave) {
+                    const double k = key64<D, L1>(X + (size_t)L.sidx[s] * D, yp);
+                    if (k < best) {
+                        best = k;
+                        bsl = s;
+                    }
+                }
+#pragma unroll
+                for (int o = kWave / 2; o > 0; o >>= 1) {
+                    const double cb = __shfl_xor(best, o);
+                    const int cs2 = __shfl_xor(bsl, o);
+                    if (cb < best || (cb == best && cs2 < bsl)) {
+                        best = cb;
+                        bsl = cs2;
+                    }
+                }
+                if (lane == 0) {
+                    L.cnn[j] = L.sidx[bsl];
+                    L.ckey[j] = best;
+                }
+            }
+            near += nf;
+            __syncthreads();
+        }
+
+        // ---- 2. claimant sets: count, scan, scatter
+        for (int q = tid; q < nact; q += T) atomicAdd(&L.scnt[L.cnn[L.cact[q]]], 1);
+        __syncthreads();
+        {
+            const int cs = (mact + T - 1) / T;
+            const int lo = min(tid * cs, mact), hi = min(lo + cs, mact);
+            int sum = 0;
+            for (int s = lo; s < hi; ++s) sum += L.scnt[L.sidx[s]];
+            unsigned long long tot;
+            int run = (int)block_scan_u64<T>((unsigned long long)sum, &tot, sh);
+            for (int s = lo; s < hi; ++s) {
+                const int i = L.sidx[s];
+                L.soff[i] = run;
+                run += L.scnt[i];
+            }
+        }
+        __syncthreads();
+        for (int q = tid; q < nact; q += T) {
+            const int j = L.cact[q];
+            const int pos = atomicAdd(&L.soff[L.cnn[j]], 1);
+            L.list[pos] = j;
+        }
+        __syncthreads();
+
+        // ---- 3. flow & cost: one lane per claimed supplier
+        for (int s = tid; s < mact; s += T) {
+            const int i = L.sidx[s];
+            const int c = L.scnt[i];
+            if (c == 0) continue;
+            const int end = L.soff[i];
+            int pos = end - c;
+            double sm = L.smass[i];
+            while (pos < end && sm > 0.0) {
+                int best = pos;
+                int bj = L.list[pos];
+                if (A.protocol == NNSEMD_GREEDY) {
+                    double bk = L.ckey[bj];
+                    for (int e = pos + 1; e < end; ++e) {
+                        const int j2 = L.list[e];
+                        const double k2 = L.ckey[j2];
+                        if (k2 < bk || (k2 == bk && j2 < bj)) {
+                            best = e;
+                            bk = k2;
+                            bj = j2;
+                        }
+                    }
+                } else {
+                    uint64_t bk = rp_key(A.seed, rounds, bj);
+                    for (int e = pos + 1; e < end; ++e) {
+                        const int j2 = L.list[e];
+                        const uint64_t k2 = rp_key(A.seed, rounds, j2);
+                        if (k2 < bk || (k2 == bk && j2 < bj)) {
+                            best = e;
+                            bk = k2;
+                            bj = j2;
+                        }
+                    }
+                }
+                L.list[best] = L.list[pos];
+                L.list[pos] = bj;
+                const double cm = L.cmass[bj];
+                const double f = sm < cm ? sm : cm;
+                sm = sm - f;
+                L.cmass[bj] = cm - f;
+                cost = cost + f * dist_of_key(L.ckey[bj], A.metric);
+                L.ckey[bj] = f;
+                ++pos;
+            }
+            for (int e = pos; e < end; ++e) L.ckey[L.list[e]] = 0.0;
+            L.smass[i] = sm;
+        }
+        __syncthreads();
+
+        // ---- 4. weights update: plan append + compaction, one scan
+        {
+            const int pc = (nact + T - 1) / T;
+            const int plo = min(tid * pc, nact), phi = min(plo + pc, nact);
+            int kp = 0;
+            for (int k = plo; k < phi; ++k) kp += L.ckey[L.list[k]] > 0.0;
+            const int cs = (mact + T - 1) / T;
+            const int slo = min(tid * cs, mact);
+            const int cc = pc;
+            const int clo = plo;
+            float rec[CSMAX][RS];
+            int sid[CSMAX], cid[CSMAX];
+            int ks = 0, kc = 0;
+#pragma unroll
+            for (int u = 0; u < CSMAX; ++u) {
+                const int s = slo + u;
+                sid[u] = -1;
+                if (u < cs && s < mact) {
+                    const int i = L.sidx[s];
+                    if (L.smass[i] > 0.0) {
+                        sid[u] = i;
+                        load_rec<RS>(L.srec, s, rec[u]);
+                        ++ks;
+                    }
+                }
+                const int q = clo + u;
+                cid[u] = -1;
+                if (u < cc && q < nact) {
+                    const int j = L.cact[q];
+                    if (L.cmass[j] > 0.0) {
+                        cid[u] = j;
+                        ++kc;
+                    }
+                }
+            }
+            unsigned long long tot;
+            const unsigned long long pre = block_scan_u64<T>(
+                (unsigned long long)kp | ((unsigned long long)ks << 21) | ((unsigned long long)kc << 42),
+                &tot, sh);
+            const unsigned long long mask = (1ull << 21) - 1;
+            int wp = (int)(pre & mask), ws = (int)((pre >> 21) & mask), wc = (int)(pre >> 42);
+            if (want_plan) {
+                for (int k = plo; k < phi; ++k) {
+                    const int j = L.list[k];
+                    const double f = L.ckey[j];
+                    if (f > 0.0) {
+                        const int64_t e = plan_base + nnz + wp;
+                        A.plan_src[e] = L.cnn[j];
+                        A.plan_dst[e] = j;
+                        A.plan_flow[e] = f;
+                        ++wp;
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < CSMAX; ++u) {
+                if (sid[u] >= 0) {
+                    store_rec<RS>(L.srec, ws, rec[u]);
+                    L.sidx[ws] = sid[u];
+                    ++ws;
+                }
+                if (cid[u] >= 0) L.cact[wc++] = cid[u];
+            }
+            nnz += (int64_t)(tot & mask);
+            mact = (int)((tot >> 21) & mask);
+            nact = (int)(tot >> 42);
+            if (tid == 0) sh.nflag = 0;
+            __syncthreads();
+        }
+        ++rounds;
+    }
+
+    // ---------------------------------------------------------- results
+    double fin[3] = {cost, 0.0, 0.0};
+    const int fop[3] = {0, 0, 0};
+    if (status == NNSEMD_OK || status == NNSEMD_ERR_NOT_CONVERGED) {
+        for (int s = tid; s < mact; s += T) fin[1] += L.smass[L.sidx[s]];
+        for (int q = tid; q < nact; q += T) fin[2] += L.cmass[L.cact[q]];
+    }
+    block_reduce<T, 3>(fin, fop, sh);
+    if (tid == 0) {
+        A.costs[p] = status == NNSEMD_OK ? fin[0] : NAN;
+        if (A.stats != nullptr) {
+            nnsemd_stats_t st;
+            st.status = status;
+            st.rounds = rounds;
+            st.nnz = nnz;
+            st.work = work;
+            st.near_ties = near;
+            st.residual_src = fin[1];
+            st.residual_dst = fin[2];
+            A.stats[p] = st;
+        }
+    }
+}
+
+#ifndef NNSEMD_CPU_EMULATION
+// One workgroup per pair: the hardware dispatcher hands out workgroups as
+// earlier ones retire, which balances ragged pairs without a software queue.
+// (A persistent loop whose head is a thread-0-only queue fetch must not be
+// used here: its back-edge merges with the thread-0-only result write, and
+// the structurized code lets lanes 1-63 of wave 0 pass the following
+// barrier without the fetch, re-solving the same pair forever.)
+template <int D, int T, int CSMAX, bool L1>
+__global__ __launch_bounds__(T) void pair_solver_kernel(PairSolverArgs A) {
+    extern __shared__ __align__(16) char lds_dyn[];
+    __shared__ Shared sh;
+    const Lds L = carve(lds_dyn, A.max_m, A.max_n, record_stride(D));
+    const int64_t p = A.order != nullptr ? (int64_t)A.order[blockIdx.x] : (int64_t)blockIdx.x;
+    solve_pair<D, T, CSMAX, L1>(A, p, L, sh);
+}
+
+template <int D, int T, int CSMAX, bool L1>
+int launch_typed(const PairSolverArgs& A, size_t lds, int grid, hipStream_t st) {
+    if (lds > 48 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)pair_solver_kernel<D, T, CSMAX, L1>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return (int)e;
+    }
+    hipLaunchKernelGGL((pair_solver_kernel<D, T, CSMAX, L1>), dim3(grid), dim3(T), lds, st, A);
+    return (int)hipGetLastError();
+}
+
+template <int D, int T, int CSMAX, bool L1>
+int occupancy_typed(size_t lds, int* blocks) {
+    if (lds > 48 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)pair_solver_kernel<D, T, CSMAX, L1>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return (int)e;
+    }
+    return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, pair_solver_kernel<D, T, CSMAX, L1>, T, lds);
+}
+
+// Dispatch over (D, metric class, chunk class) for one workgroup size.
+template <int T, int CSMAX>
+int dispatch(bool run, const PairSolverArgs& A, int d, size_t lds, int grid, hipStream_t st,
+             int* blocks) {
+    const bool l1 = A.metric == NNSEMD_L1;
+#define NNSEMD_CASE(DD)                                                                      \
+    case DD:                                                                                 \
+        if (run)                                                                             \
+            return l1 ? launch_typed<DD, T, CSMAX, true>(A, lds, grid, st)                   \
+                      : launch_typed<DD, T, CSMAX, false>(A, lds, grid, st);                 \
+        return l1 ? occupancy_typed<DD, T, CSMAX, true>(lds, blocks)                         \
+                  : occupancy_typed<DD, T, CSMAX, false>(lds, blocks);
+    switch (d) {
+        NNSEMD_CASE(1)
+        NNSEMD_CASE(2)
+        NNSEMD_CASE(3)
+        NNSEMD_CASE(4)
+        NNSEMD_CASE(5)
+        NNSEMD_CASE(6)
+        NNSEMD_CASE(7)
+        default:
+            return (int)hipErrorInvalidValue;
+    }
+#undef NNSEMD_CASE
+}
+
+int dispatch_all(bool run, const PairSolverArgs& A, int d, int threads, int chunk_max, size_t lds,
+                 int grid, hipStream_t st, int* blocks) {
+    if (threads == 256) {
+        if (chunk_max <= 4) return dispatch<256, 4>(run, A, d, lds, grid, st, blocks);
+        if (chunk_max <= 16) return dispatch<256, 16>(run, A, d, lds, grid, st, blocks);
+    } else if (threads == 512) {
+        if (chunk_max <= 2) return dispatch<512, 2>(run, A, d, lds, grid, st, blocks);
+        if (chunk_max <= 8) return dispatch<512, 8>(run, A, d, lds, grid, st, blocks);
+    }
+    return (int)hipErrorInvalidValue;
+}
+
+#endif  // NNSEMD_CPU_EMULATION
+}  // namespace
+
+#ifndef NNSEMD_CPU_EMULATION
+int launch_pair_solver(const PairSolverArgs& args, int d, int threads, int chunk_max, size_t lds_bytes,
+                       int grid, void* stream) {
+    return dispatch_all(true, args, d, threads, chunk_max, lds_bytes, grid, (hipStream_t)stream, nullptr);
+}
+
+int pair_solver_blocks_per_cu(int d, int metric, int threads, int chunk_max, size_t lds_bytes, int* blocks) {
+    PairSolverArgs A{};
+    A.metric = metric;
+    return dispatch_all(false, A, d, threads, chunk_max, lds_bytes, 0, nullptr, blocks);
+}
+
+#endif  // NNSEMD_CPU_EMULATION
+
+}  // namespace nnsemd

@@ -1,0 +1,242 @@
+"""Parity of the HIP point path (one workgroup per pair) with the FP64 oracle.
+
+Every case runs the same seeded input through the C ABI and the oracle and
+requires: equal status, rounds, work and plan size; a bit-identical plan
+(supplier, consumer, flow) in the same order; and a cost within 1e-12
+relative (the two sum R in different orders).  The FP32 search is exact in
+its decisions because near ties are re-scored in FP64, so no tolerance is
+needed on the plan.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2401_07378_amd import workloads as W
+from tests.gpu_helpers import assert_pair_matches, gpu_batched, gpu_pair, oracle_pair
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "hand_examples.json")
+
+
+@pytest.mark.parametrize("ex", json.load(open(GOLDEN))["examples"], ids=lambda e: e["name"])
+def test_hand_examples(ex):
+    g = gpu_pair(ex["X"], ex["a"], ex["Y"], ex["b"], ex["metric"])
+    e = ex["expected"]
+    assert g["cost"] == pytest.approx(e["cost"], rel=1e-15)
+    assert int(g["stats"]["rounds"]) == e["rounds"]
+    assert int(g["stats"]["work"]) == e["work"]
+    plan = [[int(i), int(j), float(f)] for i, j, f in zip(g["src"], g["dst"], g["flow"])]
+    assert plan == e["plan"]
+
+
+CASES = []
+for seed in range(6):
+    for d in (1, 2, 3):
+        for metric in ("l2", "sqeuclidean", "l1"):
+            CASES.append((seed, d, metric))
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "s%d-d%d-%s" % c)
+def test_random_pairs(case):
+    seed, d, metric = case
+    rng = np.random.default_rng(seed * 31 + d)
+    m, n = int(rng.integers(1, 700)), int(rng.integers(1, 700))
+    masses = ["dirichlet", "integer", "uniform"][seed % 3]
+    X, a, Y, b = W.random_pair(seed + 10 * d, m, n, d, masses=masses)
+    assert_pair_matches(gpu_pair(X, a, Y, b, metric), oracle_pair(X, a, Y, b, metric),
+                        label=str(case))
+
+
+@pytest.mark.parametrize("d", [4, 5, 6, 7])
+def test_higher_point_dims(d):
+    X, a, Y, b = W.random_pair(40 + d, 300, 260, d)
+    for metric in ("l2", "l1"):
+        assert_pair_matches(gpu_pair(X, a, Y, b, metric), oracle_pair(X, a, Y, b, metric),
+                            label=f"d{d}-{metric}")
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_lattice_ties(seed):
+    """Integer coordinates: FP32 keys are exact, ties are real and the
+    FP64 re-score path decides them by the smallest index."""
+    X, a, Y, b = W.random_pair(60 + seed, 200, 240, 2, masses="integer", lattice=6)
+    g = gpu_pair(X, a, Y, b)
+    assert int(g["stats"]["near_ties"]) > 0
+    assert_pair_matches(g, oracle_pair(X, a, Y, b), label=f"lattice{seed}")
+
+
+def test_duplicate_points():
+    X, a, Y, b = W.random_pair(70, 64, 64, 3)
+    X = np.concatenate([X, X[:16]])
+    a = np.concatenate([a, a[:16]]).astype(np.float64)
+    a = (a / a.sum()).astype(np.float32)
+    assert_pair_matches(gpu_pair(X, a, Y, b), oracle_pair(X, a, Y, b), label="dups")
+
+
+def test_single_pair_2d_full_size():
+    ps = W.single_pair_2d()
+    g = gpu_pair(ps.X, ps.a, ps.Y, ps.b)
+    assert_pair_matches(g, oracle_pair(ps.X, ps.a, ps.Y, ps.b), label="256x256")
+    assert int(g["stats"]["nnz"]) == 256
+
+
+def test_maximum_size_pair():
+    X, a, Y, b = W.random_pair(71, 2048, 2048, 3)
+    assert_pair_matches(gpu_pair(X, a, Y, b), oracle_pair(X, a, Y, b), label="2048x2048")
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (1, 300), (300, 1), (2, 2), (63, 65), (257, 255)])
+def test_ragged_edges(m, n):
+    X, a, Y, b = W.random_pair(80 + m + n, m, n, 3)
+    assert_pair_matches(gpu_pair(X, a, Y, b), oracle_pair(X, a, Y, b), label=f"{m}x{n}")
+
+
+def test_empty_sides():
+    g = gpu_pair(np.zeros((0, 2)), np.zeros(0), np.zeros((0, 2)), np.zeros(0))
+    assert int(g["stats"]["status"]) == 0 and g["cost"] == 0.0 and int(g["stats"]["rounds"]) == 0
+
+
+def test_zero_masses():
+    X, a, Y, b = W.random_pair(90, 120, 150, 3)
+    a = a.copy()
+    b = b.copy()
+    a[::7] = 0
+    b[::5] = 0
+    a = (a / a.astype(np.float64).sum()).astype(np.float32)
+    b = (b / b.astype(np.float64).sum()).astype(np.float32)
+    assert_pair_matches(gpu_pair(X, a, Y, b), oracle_pair(X, a, Y, b), label="zeros")
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_random_protocol(seed):
+    X, a, Y, b = W.random_pair(95 + seed, 300, 350, 3)
+    kw = dict(protocol="random", seed=1234 + seed)
+    assert_pair_matches(gpu_pair(X, a, Y, b, **kw), oracle_pair(X, a, Y, b, **kw), label="rp")
+
+
+def test_translated_copy_one_round():
+    g = np.arange(20, dtype=np.float64)
+    X = np.stack(np.meshgrid(g, g), -1).reshape(-1, 2).astype(np.float32)
+    a = np.full(len(X), 1.0 / len(X), np.float32)
+    Y = (X.astype(np.float64) + np.array([0.125, -0.25])).astype(np.float32)
+    r = gpu_pair(X, a, Y, a)
+    assert int(r["stats"]["rounds"]) == 1
+    assert r["cost"] == pytest.approx(float(np.sqrt(0.125 ** 2 + 0.25 ** 2)) * a.astype(np.float64).sum(),
+                                      rel=1e-12)
+
+
+def test_status_codes():
+    X, a, Y, b = W.random_pair(99, 20, 30, 2)
+    Xn = X.copy()
+    Xn[3, 1] = np.inf
+    assert int(gpu_pair(Xn, a, Y, b)["stats"]["status"]) == -1
+    an = a.copy()
+    an[2] = -an[2]
+    assert int(gpu_pair(X, an, Y, b)["stats"]["status"]) == -1
+    assert int(gpu_pair(X, a * 2, Y, b)["stats"]["status"]) == -2
+    assert int(gpu_pair(X, a, Y, b, max_rounds=1)["stats"]["status"]) == -6
+    assert np.isnan(gpu_pair(X, a * 2, Y, b)["cost"])
+
+
+def test_host_side_errors():
+    import torch
+    from paper_2401_07378_amd import binding
+    X, a, Y, b = W.random_pair(98, 10, 10, 9)
+    t = lambda v: torch.from_numpy(np.ascontiguousarray(v)).cuda()
+    with pytest.raises(binding.NNSEMDError) as e:
+        binding.emd_approx(t(X), t(a), t(Y), t(b))
+    assert e.value.status == -7  # d = 9 is beyond the point path
+    with pytest.raises(binding.NNSEMDError) as e:
+        binding.emd_approx(t(X[:, :3]), t(a), t(Y[:, :3]), t(b), out={"plan_src": t(np.zeros(3, np.int32)),
+                                                                       "plan_dst": t(np.zeros(3, np.int32)),
+                                                                       "plan_flow": t(np.zeros(3))})
+    assert e.value.status == -3
+
+
+def test_determinism():
+    X, a, Y, b = W.random_pair(97, 900, 800, 3)
+    g1 = gpu_pair(X, a, Y, b)
+    g2 = gpu_pair(X, a, Y, b)
+    assert g1["cost"] == g2["cost"]
+    for k in ("src", "dst", "flow"):
+        assert np.array_equal(g1[k], g2[k])
+
+
+# ------------------------------------------------------------------ batched
+def test_batched_histograms_small_full_plans():
+    """64 pairs shaped like the batched workload (sizes 128..1024, 3-D,
+    Dirichlet masses): every pair's plan and stats against the oracle."""
+    ps = W.batched_hist_3d(64)
+    g = gpu_batched(ps, plan=True)
+    for p in range(ps.num_pairs):
+        X, a, Y, b = ps.pair(p)
+        ref = oracle_pair(X, a, Y, b)
+        lo, hi = g["plan_off"][p], g["plan_off"][p + 1]
+        k = int(g["stats"][p]["nnz"])
+        assert k <= hi - lo
+        gp = {"cost": float(g["costs"][p]), "stats": g["stats"][p], "src": g["src"][lo:lo + k],
+              "dst": g["dst"][lo:lo + k], "flow": g["flow"][lo:lo + k]}
+        assert_pair_matches(gp, ref, label=f"pair{p}")
+
+
+def test_batched_histograms_full_size_sampled():
+    """The full 4096-pair workload in the benchmark's launch configuration
+    (cost + stats, no plan); the oracle checks a seeded sample of pairs."""
+    ps = W.batched_hist_3d(4096)
+    g = gpu_batched(ps, plan=False)
+    assert np.all(g["stats"]["status"] == 0)
+    rng = np.random.default_rng(5)
+    sample = sorted(set(rng.choice(ps.num_pairs, 24, replace=False).tolist()) | {0, ps.num_pairs - 1})
+    for p in sample:
+        X, a, Y, b = ps.pair(p)
+        ref = oracle_pair(X, a, Y, b, with_plan=False)
+        gp = {"cost": float(g["costs"][p]), "stats": g["stats"][p]}
+        assert_pair_matches(gp, ref, plan=False, label=f"pair{p}")
+
+
+def test_batched_shared_query_pair_table():
+    """One supplier set against many consumer sets via pair_x/pair_y."""
+    ps = W.retrieval_3d(num_candidates=40, points=256)
+    g = gpu_batched(ps, plan=False)
+    for p in range(ps.num_pairs):
+        X, a, Y, b = ps.pair(p)
+        ref = oracle_pair(X, a, Y, b, with_plan=False)
+        assert_pair_matches({"cost": float(g["costs"][p]), "stats": g["stats"][p]}, ref, plan=False,
+                            label=f"cand{p}")
+
+
+def test_batched_bad_pair_entries():
+    """A pair above max sizes or with too small a plan slot fails alone."""
+    import torch
+    from paper_2401_07378_amd import binding
+    from tests.gpu_helpers import to_dev
+    ps = W.batched_hist_3d(6, lo=20, hi=60)
+    m_sizes, n_sizes = ps.sizes()
+    poff = binding.plan_offsets(m_sizes, n_sizes)
+    poff[3:] -= 1  # pair 2 gets one entry too few
+    r = binding.emd_approx_batched(to_dev(ps.X), to_dev(ps.a), to_dev(ps.x_off), to_dev(ps.Y), to_dev(ps.b),
+                                   to_dev(ps.y_off), max_m=int(m_sizes.max()), max_n=int(n_sizes.max()),
+                                   plan_off=to_dev(poff))
+    torch.cuda.synchronize()
+    st = binding.stats_numpy(r["stats"])
+    assert list(st["status"]) == [0, 0, -3, 0, 0, 0]
+    r = binding.emd_approx_batched(to_dev(ps.X), to_dev(ps.a), to_dev(ps.x_off), to_dev(ps.Y), to_dev(ps.b),
+                                   to_dev(ps.y_off), max_m=int(m_sizes.max()) - 1, max_n=int(n_sizes.max()))
+    torch.cuda.synchronize()
+    st = binding.stats_numpy(r["stats"])
+    big = m_sizes == m_sizes.max()
+    assert np.all(st["status"][big] == -1) and np.all(st["status"][~big] == 0)
+
+
+@pytest.mark.parametrize("threads", [256, 512])
+def test_batched_workgroup_sizes(threads):
+    ps = W.batched_hist_3d(16, lo=100, hi=900)
+    g = gpu_batched(ps, plan=False, threads=threads)
+    for p in range(ps.num_pairs):
+        X, a, Y, b = ps.pair(p)
+        ref = oracle_pair(X, a, Y, b, with_plan=False)
+        assert_pair_matches({"cost": float(g["costs"][p]), "stats": g["stats"][p]}, ref, plan=False,
+                            label=f"T{threads}-pair{p}")
