@@ -79,13 +79,17 @@ typedef enum { NNSEMD_GREEDY = 0, NNSEMD_RANDOM = 1 } nnsemd_protocol_t;
  * with FP32 accumulation, candidate re-scoring in FP32. */
 typedef enum { NNSEMD_MODE_FP32 = 0, NNSEMD_MODE_BF16_MFMA_REFINE = 1 } nnsemd_mode_t;
 
+/* Order in which a batched call starts its pairs (results do not depend on
+ * it): longest first by m * n, or as given. */
+typedef enum { NNSEMD_SCHEDULE_LONGEST_FIRST = 0, NNSEMD_SCHEDULE_AS_GIVEN = 1 } nnsemd_schedule_t;
+
 typedef struct {
     int32_t protocol;   /* nnsemd_protocol_t, default NNSEMD_GREEDY */
     int32_t mode;       /* nnsemd_mode_t, default NNSEMD_MODE_FP32 */
     int64_t max_rounds; /* <= 0: m + n (never reached by valid input) */
     uint64_t seed;      /* random protocol only */
     int32_t threads;    /* workgroup size override (0 = tuned choice) */
-    int32_t reserved;
+    int32_t schedule;   /* nnsemd_schedule_t, default longest first */
 } nnsemd_options_t;
 
 /* Per-pair results, written by the device (48 bytes). */
@@ -141,8 +145,9 @@ nnsemd_status_t emd_approx(nnsemd_handle_t h,
 
 /*
  * emd_approx_batched -- NNS-EMD of many independent ragged pairs in one
- * persistent launch (the batching of Sec. III-D, done as a device-side pair
- * queue instead of padded batches).
+ * launch (the batching of Sec. III-D without padding): one workgroup per
+ * pair, started longest-first unless opts->schedule says otherwise; each
+ * pair is solved exactly as by emd_approx.
  *   Xcat: device, sum_k |X_k| x d rows; acat: device masses; x_off: device,
  *      num_x_sets + 1 int64 row offsets (set k = rows [x_off[k], x_off[k+1])).
  *   Ycat, bcat, y_off, num_y_sets: the same for consumer sets.

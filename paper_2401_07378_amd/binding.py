@@ -14,7 +14,7 @@ import threading
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libnnsemd.so")
+LIB_PATH = os.environ.get("NNSEMD_LIB") or os.path.join(_PKG, "libnnsemd.so")
 
 STATUS = {
     0: "OK", -1: "INVALID_ARG", -2: "MASS_MISMATCH", -3: "CAPACITY", -4: "OUT_OF_MEMORY",
@@ -42,7 +42,7 @@ class NNSEMDError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("protocol", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("max_rounds", ctypes.c_int64), ("seed", ctypes.c_uint64),
-                ("threads", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("threads", ctypes.c_int32), ("schedule", ctypes.c_int32)]
 
 
 _lock = threading.Lock()
@@ -101,9 +101,12 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
-def _options(protocol, mode, max_rounds, seed, threads):
+SCHEDULES = {"longest_first": 0, "as_given": 1}
+
+
+def _options(protocol, mode, max_rounds, seed, threads, schedule="longest_first"):
     return Options(PROTOCOLS[protocol], MODES[mode], int(max_rounds), int(seed) & (2**64 - 1),
-                   int(threads), 0)
+                   int(threads), SCHEDULES[schedule])
 
 
 def _stream(torch, device):
@@ -180,7 +183,8 @@ def plan_offsets(m_sizes, n_sizes) -> np.ndarray:
 def emd_approx_batched(Xcat, acat, x_off, Ycat, bcat, y_off, *, max_m: int, max_n: int,
                        pair_x=None, pair_y=None, num_pairs: int | None = None, metric: str = "l2",
                        plan_off=None, protocol: str = "greedy", mode: str = "fp32", seed: int = 0,
-                       max_rounds: int = 0, threads: int = 0, out: dict | None = None) -> dict:
+                       max_rounds: int = 0, threads: int = 0, schedule: str = "longest_first",
+                       out: dict | None = None) -> dict:
     """NNS-EMD of many ragged pairs in one persistent launch.  Offsets and
     pair tables are int64/int32 CUDA tensors; max_m/max_n are host bounds on
     the set sizes.  With plan_off (CUDA int64, num_pairs + 1) the plans are
@@ -221,7 +225,7 @@ def emd_approx_batched(Xcat, acat, x_off, Ycat, bcat, y_off, *, max_m: int, max_
         src = o.get("plan_src") if o.get("plan_src") is not None else torch.empty(max(total, 1), dtype=torch.int32, device=Xcat.device)
         dst = o.get("plan_dst") if o.get("plan_dst") is not None else torch.empty(max(total, 1), dtype=torch.int32, device=Xcat.device)
         flow = o.get("plan_flow") if o.get("plan_flow") is not None else torch.empty(max(total, 1), dtype=torch.float64, device=Xcat.device)
-    opts = _options(protocol, mode, max_rounds, seed, threads)
+    opts = _options(protocol, mode, max_rounds, seed, threads, schedule)
     st = lib.emd_approx_batched(
         h, num_pairs, _ptr(Xcat), _ptr(acat), _ptr(x_off), nx, _ptr(Ycat), _ptr(bcat), _ptr(y_off), ny,
         _ptr(pair_x), _ptr(pair_y), int(max_m), int(max_n), d,

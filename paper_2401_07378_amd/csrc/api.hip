@@ -15,6 +15,9 @@ struct nnsemd_handle {
     int num_cus = 0;
     size_t max_lds = 0;
     std::string last_error;
+    unsigned long long* phase_cycles = nullptr;  // profiling builds only
+    int32_t* order = nullptr;                    // longest-first pair schedule (device)
+    int64_t order_cap = 0;
 };
 
 namespace {
@@ -75,11 +78,26 @@ nnsemd_status_t run_pairs(nnsemd_handle_t h, PairSolverArgs& A, int d, int64_t m
     A.protocol = o.protocol;
     A.seed = o.seed;
     A.max_rounds = o.max_rounds;
+    A.phase_cycles = h->phase_cycles;
     int blocks = 0;
     int err = pair_solver_blocks_per_cu(d, A.metric, threads, chunk, lay.total, &blocks);
     if (err != 0) return device_fail(h, err, "occupancy query");
     if (blocks < 1) return fail(h, NNSEMD_ERR_UNSUPPORTED, "pair workgroup does not fit on a compute unit");
     const int64_t grid = A.num_pairs;
+    if (A.x_off != nullptr && A.num_pairs > 1 && o.schedule == NNSEMD_SCHEDULE_LONGEST_FIRST) {
+        if (h->order_cap < A.num_pairs) {
+            if (h->order) (void)hipFree(h->order);
+            h->order = nullptr;
+            h->order_cap = 0;
+            if (hipMalloc((void**)&h->order, sizeof(int32_t) * (size_t)A.num_pairs) != hipSuccess)
+                return fail(h, NNSEMD_ERR_OUT_OF_MEMORY, "schedule workspace");
+            h->order_cap = A.num_pairs;
+        }
+        err = launch_order(A.x_off, A.y_off, A.pair_x, A.pair_y, A.num_pairs, A.num_x_sets, A.num_y_sets,
+                           h->order, stream);
+        if (err != 0) return device_fail(h, err, "schedule launch");
+        A.order = h->order;
+    }
     err = launch_pair_solver(A, d, threads, chunk, lay.total, (int)grid, stream);
     if (err != 0) return device_fail(h, err, "solver launch");
     return NNSEMD_OK;
@@ -93,6 +111,8 @@ nnsemd_status_t check_common(nnsemd_handle_t h, int32_t d, nnsemd_dtype_t dtype,
         return fail(h, NNSEMD_ERR_INVALID_ARG, "bad metric");
     if (o.protocol != NNSEMD_GREEDY && o.protocol != NNSEMD_RANDOM)
         return fail(h, NNSEMD_ERR_INVALID_ARG, "bad protocol");
+    if (o.schedule != NNSEMD_SCHEDULE_LONGEST_FIRST && o.schedule != NNSEMD_SCHEDULE_AS_GIVEN)
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "bad schedule");
     if (o.mode != NNSEMD_MODE_FP32 && o.mode != NNSEMD_MODE_BF16_MFMA_REFINE)
         return fail(h, NNSEMD_ERR_INVALID_ARG, "bad mode");
     if (o.mode == NNSEMD_MODE_FP32 && dtype != NNSEMD_F32)
@@ -136,6 +156,7 @@ nnsemd_status_t nnsemd_destroy(nnsemd_handle_t h) {
     {
         DeviceGuard g(h->device);
         (void)hipDeviceSynchronize();
+        if (h->order) (void)hipFree(h->order);
     }
     delete h;
     return NNSEMD_OK;
@@ -244,5 +265,15 @@ nnsemd_status_t emd_approx_batched(nnsemd_handle_t h, int64_t num_pairs, const v
     A.stats = stats;
     return run_pairs(h, A, d, max_m, max_n, o, stream);
 }
+
+#ifdef NNSEMD_PHASE_TIMING
+// Profiling builds only: device buffer of 9 unsigned 64-bit per-phase cycle
+// totals that every later launch on this handle adds to.
+nnsemd_status_t nnsemd_debug_phase_buffer(nnsemd_handle_t h, unsigned long long* cycles) {
+    if (h == nullptr) return NNSEMD_ERR_INVALID_ARG;
+    h->phase_cycles = cycles;
+    return NNSEMD_OK;
+}
+#endif
 
 }  // extern "C"

@@ -45,11 +45,12 @@ struct PairSolverArgs {
     int64_t single_plan_cap;
     nnsemd_stats_t* stats;
     const int32_t* order;  // nullable: workgroup b solves pair order[b]
+    unsigned long long* phase_cycles;  // profiling builds only: 9 per-phase cycle totals
 };
 
 // Byte layout of the dynamic LDS of one workgroup (one pair at a time).
 struct PairLdsLayout {
-    size_t smass, cmass, ckey, srec, sidx, scnt, soff, cact, cnn, list, total;
+    size_t smass, cmass, ckey, srec, sidx, scnt, soff, cact, cnn, list, sorted, total;
 };
 
 __host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -68,6 +69,7 @@ __host__ __device__ inline PairLdsLayout pair_lds_layout(int M, int N, int rs) {
     L.cact = o;  o += sizeof(int32_t) * (size_t)N;
     L.cnn = o;   o += sizeof(int32_t) * (size_t)N;
     L.list = o;  o += sizeof(int32_t) * (size_t)N;
+    L.sorted = o; o += sizeof(int32_t) * (size_t)N;
     L.total = align_up(o, 16);
     return L;
 }
@@ -76,6 +78,8 @@ __host__ __device__ inline PairLdsLayout pair_lds_layout(int M, int N, int rs) {
 // Returns hipSuccess-compatible int (0 on success).
 int launch_pair_solver(const PairSolverArgs& args, int d, int threads, int chunk_max,
                        size_t lds_bytes, int grid, void* stream);
+int launch_order(const int64_t* x_off, const int64_t* y_off, const int32_t* pair_x, const int32_t* pair_y,
+                 int64_t num_pairs, int64_t num_x_sets, int64_t num_y_sets, int32_t* order, void* stream);
 int pair_solver_blocks_per_cu(int d, int metric, int threads, int chunk_max, size_t lds_bytes,
                               int* blocks);
 

@@ -30,22 +30,35 @@
 
 #include "internal.hpp"
 
+// Optional per-phase cycle accounting for profiling builds only
+// (-DNNSEMD_PHASE_TIMING).  Every thread reads the clock (no divergent code);
+// thread 0 adds its totals to A.phase_cycles once, at the end of the pair.
+#ifdef NNSEMD_PHASE_TIMING
+#define NNSEMD_PH_DECL uint64_t ph[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}; uint64_t ph_t = clock64();
+#define NNSEMD_PH(k) { const uint64_t ph_n = clock64(); ph[k] += ph_n - ph_t; ph_t = ph_n; }
+#else
+#define NNSEMD_PH_DECL
+#define NNSEMD_PH(k)
+#endif
+
 namespace nnsemd {
 namespace {
 
 constexpr int kWave = 64;
+constexpr int kUnroll = 8;  // supplier records in flight per step of the search
 
 struct Lds {
-    double* smass;  // [M] supplier mass by local index
+    double* smass;  // [M] supplier mass (by local index while loading, then by active slot)
     double* cmass;  // [N] consumer mass by local index
     double* ckey;   // [N] FP64 key of (pick, j); after the serve: flow (0 = unserved)
     float* srec;    // [M * RS] active supplier records, compacted
     int32_t* sidx;  // [M] local index of active supplier slot
-    int32_t* scnt;  // [M] claimant count by supplier
-    int32_t* soff;  // [M] bucket start, then bucket end
+    int32_t* scnt;  // [M] claimant count by active slot
+    int32_t* soff;  // [M] bucket start, then bucket end, by active slot
     int32_t* cact;  // [N] active consumers, compacted, ascending
-    int32_t* cnn;   // [N] pick (local supplier index) by consumer
-    int32_t* list;  // [N] near-tie consumers during the search; claimant buckets after
+    int32_t* cnn;   // [N] pick (active slot) by consumer; after the serve: supplier local index
+    int32_t* list;    // [N] near-tie consumers during the search; claimant buckets after
+    int32_t* sorted;  // [N] claimant buckets in serve order
 };
 
 struct Shared {
@@ -68,6 +81,7 @@ __device__ inline Lds carve(char* base, int M, int N, int rs) {
     s.cact = reinterpret_cast<int32_t*>(base + L.cact);
     s.cnn = reinterpret_cast<int32_t*>(base + L.cnn);
     s.list = reinterpret_cast<int32_t*>(base + L.list);
+    s.sorted = reinterpret_cast<int32_t*>(base + L.sorted);
     return s;
 }
 
@@ -194,6 +208,115 @@ __device__ inline void store_rec(float* __restrict__ base, int s, const float (&
         p[q] = make_float4(r[4 * q + 0], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]);
 }
 
+// One pass of the search for the consumers q = qa + k*G (k < KC) of this
+// lane; S lanes share each consumer and scan every S-th active supplier.
+// Per consumer: FP32 best and second-best keys; if they are closer than the
+// rounding bound the consumer is queued for the FP64 re-score, otherwise its
+// pick and the exact FP64 key of the pick are stored.
+template <int D, int RS, bool L1, int KC>
+__device__ inline void nns_pass(const Lds& L, Shared& sh, const float* __restrict__ X,
+                                const float* __restrict__ Y, const float (&centre)[D], float rhat,
+                                int mact, int nact, int S, int qa, int G, int r) {
+    int jj[KC];
+    bool valid[KC];
+    float y[KC][D];
+    float yn2[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        const int q = qa + k * G;
+        valid[k] = q < nact;
+        jj[k] = L.cact[valid[k] ? q : 0];
+    }
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        yn2[k] = 0.f;
+#pragma unroll
+        for (int t = 0; t < D; ++t) {
+            const float yv = L1 ? Y[(size_t)jj[k] * D + t] : Y[(size_t)jj[k] * D + t] - centre[t];
+            y[k][t] = yv;
+            yn2[k] = fmaf(yv, yv, yn2[k]);
+        }
+    }
+    float b1[KC], b2[KC];
+    int bs[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        b1[k] = INFINITY;
+        b2[k] = INFINITY;
+        bs[k] = 0x7fffffff;
+    }
+    const int stride = S * kUnroll;
+    const int full = (mact / stride) * stride;
+    for (int s0 = r; s0 < full; s0 += stride) {
+        float rec[kUnroll][RS];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) load_rec<RS>(L.srec, s0 + u * S, rec[u]);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+                const float key = key32<D, RS, L1>(rec[u], y[k]);
+                const bool lt = key < b1[k];
+                bs[k] = lt ? s0 + u * S : bs[k];
+                b2[k] = __builtin_amdgcn_fmed3f(b1[k], key, b2[k]);
+                b1[k] = fminf(b1[k], key);
+            }
+        }
+    }
+    for (int s = full + r; s < mact; s += S) {
+        float rec[RS];
+        load_rec<RS>(L.srec, s, rec);
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            const float key = key32<D, RS, L1>(rec, y[k]);
+            const bool lt = key < b1[k];
+            bs[k] = lt ? s : bs[k];
+            b2[k] = __builtin_amdgcn_fmed3f(b1[k], key, b2[k]);
+            b1[k] = fminf(b1[k], key);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        for (int o = 1; o < S; o <<= 1) {
+            const float c1 = __shfl_xor(b1[k], o);
+            const float c2 = __shfl_xor(b2[k], o);
+            const int cs2 = __shfl_xor(bs[k], o);
+            const float n2 = fminf(fmaxf(b1[k], c1), fminf(b2[k], c2));
+            const bool take = (c1 < b1[k]) || (c1 == b1[k] && cs2 < bs[k]);
+            b1[k] = take ? c1 : b1[k];
+            bs[k] = take ? cs2 : bs[k];
+            b2[k] = n2;
+        }
+    }
+    if (r != 0) return;
+    bool flag[KC];
+    int pick[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        float thr;
+        if (L1) {
+            thr = 4.f * (float)(D + 1) * kU32 * b2[k] + 1e-30f;
+        } else {
+            const float e = rhat + sqrtf(yn2[k]);
+            thr = 32.f * kU32 * e * e + 1e-30f;
+        }
+        flag[k] = !(b2[k] - b1[k] > thr);
+        pick[k] = flag[k] ? 0 : bs[k];
+    }
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        if (!valid[k]) continue;
+        if (flag[k]) {
+            const int f = atomicAdd(&sh.nflag, 1);
+            L.list[f] = jj[k];
+        } else {
+            L.cnn[jj[k]] = pick[k];
+            L.ckey[jj[k]] = key64<D, L1>(X + (size_t)L.sidx[pick[k]] * D, Y + (size_t)jj[k] * D);
+            atomicAdd(&L.scnt[pick[k]], 1);
+        }
+    }
+}
+
 template <int D, int T, int CSMAX, bool L1>
 __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds& L, Shared& sh) {
     constexpr int RS = record_stride(D);
@@ -202,6 +325,7 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds& L, Sha
     const int lane = tid & (kWave - 1);
     const int wave = tid / kWave;
 
+    NNSEMD_PH_DECL
     // ---------------------------------------------------------- pair geometry
     int64_t x0 = 0, y0 = 0, m = A.single_m, n = A.single_n;
     int status = NNSEMD_OK;
@@ -285,6 +409,8 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds& L, Sha
         centre[t] = (L1 || mi == 0) ? 0.f : 0.5f * ((float)red[3 + t] + (float)red[3 + D + t]);
 
     // ------------------- initial active sets (zero-mass points never enter)
+    // Supplier state is kept by active slot from here on: records, local
+    // index, mass, claimant count and bucket offset are compacted together.
     int mact = 0, nact = 0;
     float rhat = 0.f;
     if (status == NNSEMD_OK) {
@@ -292,8 +418,14 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds& L, Sha
         const int cc = (ni + T - 1) / T;
         const int slo = min(tid * cs, mi), shi = min(slo + cs, mi);
         const int clo = min(tid * cc, ni), chi = min(clo + cc, ni);
+        double mv[CSMAX];
         int ks = 0, kc = 0;
-        for (int i = slo; i < shi; ++i) ks += L.smass[i] > 0.0;
+#pragma unroll
+        for (int u = 0; u < CSMAX; ++u) {
+            const int i = slo + u;
+            mv[u] = (u < cs && i < shi) ? L.smass[i] : 0.0;
+            ks += mv[u] > 0.0;
+        }
         for (int j = clo; j < chi; ++j) kc += L.cmass[j] > 0.0;
         unsigned long long tot;
         unsigned long long pre = block_scan_u64<T>((unsigned long long)ks | ((unsigned long long)kc << 32), &tot, sh);
@@ -301,8 +433,10 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds& L, Sha
         mact = (int)(tot & 0xffffffffu);
         nact = (int)(tot >> 32);
         float rmax = 0.f;
-        for (int i = slo; i < shi; ++i) {
-            if (!(L.smass[i] > 0.0)) continue;
+#pragma unroll
+        for (int u = 0; u < CSMAX; ++u) {
+            if (!(mv[u] > 0.0)) continue;
+            const int i = slo + u;
             float r[RS];
 #pragma unroll
             for (int q = 0; q < RS; ++q) r[q] = 0.f;
@@ -322,6 +456,8 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds& L, Sha
             }
             store_rec<RS>(L.srec, ps, r);
             L.sidx[ps] = i;
+            L.smass[ps] = mv[u];
+            L.scnt[ps] = 0;
             ++ps;
         }
         for (int j = clo; j < chi; ++j)
@@ -333,6 +469,7 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds& L, Sha
         if (tid == 0) sh.nflag = 0;
         __syncthreads();
     }
+    NNSEMD_PH(0)
 
     // ------------------------------------------------------------- rounds
     const int64_t max_rounds = A.max_rounds > 0 ? A.max_rounds : (int64_t)mi + ni;
@@ -346,69 +483,30 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds& L, Sha
         }
         work += (int64_t)mact * nact;
 
-        // ---- 1. NNS: FP32 scan, best + second best, near ties deferred
-        for (int s = tid; s < mact; s += T) L.scnt[L.sidx[s]] = 0;
+        // ---- 1. NNS: FP32 scan, best + second best, near ties deferred;
+        // each decided consumer also counts itself into its pick's bucket.
+        // S lanes share one consumer (each scans every S-th supplier) when
+        // there are too few consumers to fill the workgroup; otherwise each
+        // lane takes KC consumers so one record load feeds KC key chains.
         int S = 1;
         while (S < kWave && nact * S * 2 <= T) S <<= 1;
         while (S > 1 && S > mact) S >>= 1;
-        const int r = tid & (S - 1);
-        const int g = tid / S;
-        const int G = T / S;
-        for (int q0 = 0; q0 < nact; q0 += G) {
-            const int q = q0 + g;
-            const bool valid = q < nact;
-            const int j = valid ? L.cact[q] : 0;
-            float y[D];
-            float yn2 = 0.f;
-#pragma unroll
-            for (int t = 0; t < D; ++t) {
-                float yv = valid ? Y[(size_t)j * D + t] - centre[t] : 0.f;
-                y[t] = yv;
-                yn2 = fmaf(yv, yv, yn2);
-            }
-            float b1 = INFINITY, b2 = INFINITY;
-            int bs = 0x7fffffff;
-            if (valid) {
-                for (int s = r; s < mact; s += S) {
-                    float rec[RS];
-                    load_rec<RS>(L.srec, s, rec);
-                    const float k = key32<D, RS, L1>(rec, y);
-                    b2 = fminf(b2, fmaxf(b1, k));
-                    if (k < b1) {
-                        b1 = k;
-                        bs = s;
-                    }
-                }
-            }
-            for (int o = 1; o < S; o <<= 1) {
-                const float c1 = __shfl_xor(b1, o);
-                const float c2 = __shfl_xor(b2, o);
-                const int cs2 = __shfl_xor(bs, o);
-                const float n2 = fminf(fmaxf(b1, c1), fminf(b2, c2));
-                const bool take = (c1 < b1) || (c1 == b1 && cs2 < bs);
-                b1 = take ? c1 : b1;
-                bs = take ? cs2 : bs;
-                b2 = n2;
-            }
-            if (valid && r == 0) {
-                float thr;
-                if (L1) {
-                    thr = 4.f * (float)(D + 1) * kU32 * b2 + 1e-30f;
-                } else {
-                    const float e = rhat + sqrtf(yn2);
-                    thr = 32.f * kU32 * e * e + 1e-30f;
-                }
-                if (!(b2 - b1 > thr)) {
-                    const int f = atomicAdd(&sh.nflag, 1);
-                    L.list[f] = j;
-                } else {
-                    const int i = L.sidx[bs];
-                    L.cnn[j] = i;
-                    L.ckey[j] = key64<D, L1>(X + (size_t)i * D, Y + (size_t)j * D);
-                }
+        const int kc = S > 1 ? 1 : (nact > 2 * T ? 4 : (nact > T ? 2 : 1));
+        {
+            const int r = tid & (S - 1);
+            const int g = tid / S;
+            const int G = T / S;
+            for (int q0 = 0; q0 < nact; q0 += G * kc) {
+                if (kc == 4)
+                    nns_pass<D, RS, L1, 4>(L, sh, X, Y, centre, rhat, mact, nact, S, q0 + g, G, r);
+                else if (kc == 2)
+                    nns_pass<D, RS, L1, 2>(L, sh, X, Y, centre, rhat, mact, nact, S, q0 + g, G, r);
+                else
+                    nns_pass<D, RS, L1, 1>(L, sh, X, Y, centre, rhat, mact, nact, S, q0 + g, G, r);
             }
         }
         __syncthreads();
+        NNSEMD_PH(1)
         const int nf = sh.nflag;
         if (nf > 0) {
             // FP64 re-score of near-tie consumers, one wavefront per consumer.
@@ -434,131 +532,143 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds& L, Sha
                     }
                 }
                 if (lane == 0) {
-                    L.cnn[j] = L.sidx[bsl];
+                    L.cnn[j] = bsl;
                     L.ckey[j] = best;
+                    atomicAdd(&L.scnt[bsl], 1);
                 }
             }
             near += nf;
             __syncthreads();
         }
+        NNSEMD_PH(2)
 
-        // ---- 2. claimant sets: count, scan, scatter
-        for (int q = tid; q < nact; q += T) atomicAdd(&L.scnt[L.cnn[L.cact[q]]], 1);
-        __syncthreads();
+        // ---- 2. claimant sets a_i: scan the counts, scatter the claimants
         {
             const int cs = (mact + T - 1) / T;
             const int lo = min(tid * cs, mact), hi = min(lo + cs, mact);
             int sum = 0;
-            for (int s = lo; s < hi; ++s) sum += L.scnt[L.sidx[s]];
+            for (int s = lo; s < hi; ++s) sum += L.scnt[s];
             unsigned long long tot;
             int run = (int)block_scan_u64<T>((unsigned long long)sum, &tot, sh);
             for (int s = lo; s < hi; ++s) {
-                const int i = L.sidx[s];
-                L.soff[i] = run;
-                run += L.scnt[i];
+                L.soff[s] = run;
+                run += L.scnt[s];
             }
         }
         __syncthreads();
+        NNSEMD_PH(3)
         for (int q = tid; q < nact; q += T) {
             const int j = L.cact[q];
             const int pos = atomicAdd(&L.soff[L.cnn[j]], 1);
             L.list[pos] = j;
         }
         __syncthreads();
+        NNSEMD_PH(4)
 
-        // ---- 3. flow & cost: one lane per claimed supplier
-        for (int s = tid; s < mact; s += T) {
-            const int i = L.sidx[s];
-            const int c = L.scnt[i];
-            if (c == 0) continue;
-            const int end = L.soff[i];
-            int pos = end - c;
-            double sm = L.smass[i];
-            while (pos < end && sm > 0.0) {
-                int best = pos;
-                int bj = L.list[pos];
+        // ---- 3a. claimant order: each claimant counts the bucket members
+        // that precede it ((D_ij, j) for greedy, (random key, j) for random)
+        // and writes itself to that rank; no dependent chains.
+        for (int q = tid; q < nact; q += T) {
+            const int j = L.cact[q];
+            const int sl = L.cnn[j];
+            const int c = L.scnt[sl];
+            const int end = L.soff[sl];
+            const int start = end - c;
+            int rank = 0;
+            if (c > 1) {
                 if (A.protocol == NNSEMD_GREEDY) {
-                    double bk = L.ckey[bj];
-                    for (int e = pos + 1; e < end; ++e) {
+                    const double k = L.ckey[j];
+                    for (int e = start; e < end; ++e) {
                         const int j2 = L.list[e];
                         const double k2 = L.ckey[j2];
-                        if (k2 < bk || (k2 == bk && j2 < bj)) {
-                            best = e;
-                            bk = k2;
-                            bj = j2;
-                        }
+                        rank += (k2 < k) || (k2 == k && j2 < j);
                     }
                 } else {
-                    uint64_t bk = rp_key(A.seed, rounds, bj);
-                    for (int e = pos + 1; e < end; ++e) {
+                    const uint64_t k = rp_key(A.seed, rounds, j);
+                    for (int e = start; e < end; ++e) {
                         const int j2 = L.list[e];
                         const uint64_t k2 = rp_key(A.seed, rounds, j2);
-                        if (k2 < bk || (k2 == bk && j2 < bj)) {
-                            best = e;
-                            bk = k2;
-                            bj = j2;
-                        }
+                        rank += (k2 < k) || (k2 == k && j2 < j);
                     }
                 }
-                L.list[best] = L.list[pos];
-                L.list[pos] = bj;
-                const double cm = L.cmass[bj];
-                const double f = sm < cm ? sm : cm;
-                sm = sm - f;
-                L.cmass[bj] = cm - f;
-                cost = cost + f * dist_of_key(L.ckey[bj], A.metric);
-                L.ckey[bj] = f;
-                ++pos;
             }
-            for (int e = pos; e < end; ++e) L.ckey[L.list[e]] = 0.0;
-            L.smass[i] = sm;
+            L.sorted[start + rank] = j;
         }
         __syncthreads();
+        NNSEMD_PH(5)
+
+        // ---- 3b. flow & cost: one lane per claimed supplier walks its
+        // ordered claimants while it still holds mass.  A served claimant
+        // records the local index of its supplier (for the plan) and its
+        // flow in place of its key; an unserved one gets flow 0.
+        for (int s = tid; s < mact; s += T) {
+            const int c = L.scnt[s];
+            if (c == 0) continue;
+            const int end = L.soff[s];
+            const int isup = L.sidx[s];
+            int pos = end - c;
+            double sm = L.smass[s];
+            while (pos < end && sm > 0.0) {
+                const int j = L.sorted[pos];
+                const double cm = L.cmass[j];
+                const double f = sm < cm ? sm : cm;
+                sm = sm - f;
+                L.cmass[j] = cm - f;
+                cost = cost + f * dist_of_key(L.ckey[j], A.metric);
+                L.ckey[j] = f;
+                L.cnn[j] = isup;
+                ++pos;
+            }
+            for (int e = pos; e < end; ++e) L.ckey[L.sorted[e]] = 0.0;
+            L.smass[s] = sm;
+        }
+        __syncthreads();
+        NNSEMD_PH(6)
 
         // ---- 4. weights update: plan append + compaction, one scan
         {
             const int pc = (nact + T - 1) / T;
             const int plo = min(tid * pc, nact), phi = min(plo + pc, nact);
             int kp = 0;
-            for (int k = plo; k < phi; ++k) kp += L.ckey[L.list[k]] > 0.0;
+            for (int k = plo; k < phi; ++k) kp += L.ckey[L.sorted[k]] > 0.0;
             const int cs = (mact + T - 1) / T;
             const int slo = min(tid * cs, mact);
-            const int cc = pc;
-            const int clo = plo;
             float rec[CSMAX][RS];
+            double smv[CSMAX];
             int sid[CSMAX], cid[CSMAX];
-            int ks = 0, kc = 0;
+            int ks = 0, kc2 = 0;
 #pragma unroll
             for (int u = 0; u < CSMAX; ++u) {
                 const int s = slo + u;
                 sid[u] = -1;
+                smv[u] = 0.0;
                 if (u < cs && s < mact) {
-                    const int i = L.sidx[s];
-                    if (L.smass[i] > 0.0) {
-                        sid[u] = i;
+                    smv[u] = L.smass[s];
+                    if (smv[u] > 0.0) {
+                        sid[u] = L.sidx[s];
                         load_rec<RS>(L.srec, s, rec[u]);
                         ++ks;
                     }
                 }
-                const int q = clo + u;
+                const int q = plo + u;
                 cid[u] = -1;
-                if (u < cc && q < nact) {
+                if (u < pc && q < nact) {
                     const int j = L.cact[q];
                     if (L.cmass[j] > 0.0) {
                         cid[u] = j;
-                        ++kc;
+                        ++kc2;
                     }
                 }
             }
             unsigned long long tot;
             const unsigned long long pre = block_scan_u64<T>(
-                (unsigned long long)kp | ((unsigned long long)ks << 21) | ((unsigned long long)kc << 42),
+                (unsigned long long)kp | ((unsigned long long)ks << 21) | ((unsigned long long)kc2 << 42),
                 &tot, sh);
             const unsigned long long mask = (1ull << 21) - 1;
             int wp = (int)(pre & mask), ws = (int)((pre >> 21) & mask), wc = (int)(pre >> 42);
             if (want_plan) {
                 for (int k = plo; k < phi; ++k) {
-                    const int j = L.list[k];
+                    const int j = L.sorted[k];
                     const double f = L.ckey[j];
                     if (f > 0.0) {
                         const int64_t e = plan_base + nnz + wp;
@@ -574,6 +684,8 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds& L, Sha
                 if (sid[u] >= 0) {
                     store_rec<RS>(L.srec, ws, rec[u]);
                     L.sidx[ws] = sid[u];
+                    L.smass[ws] = smv[u];
+                    L.scnt[ws] = 0;
                     ++ws;
                 }
                 if (cid[u] >= 0) L.cact[wc++] = cid[u];
@@ -584,6 +696,7 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds& L, Sha
             if (tid == 0) sh.nflag = 0;
             __syncthreads();
         }
+        NNSEMD_PH(7)
         ++rounds;
     }
 
@@ -591,10 +704,15 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds& L, Sha
     double fin[3] = {cost, 0.0, 0.0};
     const int fop[3] = {0, 0, 0};
     if (status == NNSEMD_OK || status == NNSEMD_ERR_NOT_CONVERGED) {
-        for (int s = tid; s < mact; s += T) fin[1] += L.smass[L.sidx[s]];
+        for (int s = tid; s < mact; s += T) fin[1] += L.smass[s];
         for (int q = tid; q < nact; q += T) fin[2] += L.cmass[L.cact[q]];
     }
     block_reduce<T, 3>(fin, fop, sh);
+    NNSEMD_PH(8)
+#ifdef NNSEMD_PHASE_TIMING
+    if (tid == 0 && A.phase_cycles != nullptr)
+        for (int k = 0; k < 9; ++k) atomicAdd(&A.phase_cycles[k], (unsigned long long)ph[k]);
+#endif
     if (tid == 0) {
         A.costs[p] = status == NNSEMD_OK ? fin[0] : NAN;
         if (A.stats != nullptr) {
@@ -625,6 +743,51 @@ __global__ __launch_bounds__(T) void pair_solver_kernel(PairSolverArgs A) {
     const Lds L = carve(lds_dyn, A.max_m, A.max_n, record_stride(D));
     const int64_t p = A.order != nullptr ? (int64_t)A.order[blockIdx.x] : (int64_t)blockIdx.x;
     solve_pair<D, T, CSMAX, L1>(A, p, L, sh);
+}
+
+// Longest-first schedule: order[] lists the pairs by decreasing m * n (in
+// quarter-octave buckets; order inside a bucket is arbitrary and does not
+// affect any result), so the largest pairs start first and the short ones
+// fill the tail of the launch.  One workgroup of 1024 threads.
+constexpr int kOrderBuckets = 256;
+__global__ __launch_bounds__(1024) void order_kernel(const int64_t* __restrict__ x_off,
+                                                     const int64_t* __restrict__ y_off,
+                                                     const int32_t* __restrict__ pair_x,
+                                                     const int32_t* __restrict__ pair_y, int64_t num_pairs,
+                                                     int64_t num_x_sets, int64_t num_y_sets,
+                                                     int32_t* __restrict__ order) {
+    __shared__ int hist[kOrderBuckets];
+    __shared__ int cursor[kOrderBuckets];
+    const int tid = threadIdx.x;
+    for (int b = tid; b < kOrderBuckets; b += blockDim.x) hist[b] = 0;
+    __syncthreads();
+    auto bucket_of = [&](int64_t p) -> int {
+        const int64_t px = pair_x ? (int64_t)pair_x[p] : p;
+        const int64_t py = pair_y ? (int64_t)pair_y[p] : p;
+        if (px < 0 || px >= num_x_sets || py < 0 || py >= num_y_sets) return 0;
+        const int64_t m = x_off[px + 1] - x_off[px];
+        const int64_t n = y_off[py + 1] - y_off[py];
+        if (m <= 0 || n <= 0) return 0;
+        const unsigned long long w = (unsigned long long)m * (unsigned long long)n;
+        const int lg = 63 - __clzll(w);
+        const int frac = lg >= 2 ? (int)((w >> (lg - 2)) & 3ull) : 0;
+        const int b = 1 + 4 * lg + frac;
+        return b < kOrderBuckets ? b : kOrderBuckets - 1;
+    };
+    for (int64_t p = tid; p < num_pairs; p += blockDim.x) atomicAdd(&hist[bucket_of(p)], 1);
+    __syncthreads();
+    if (tid == 0) {
+        int run = 0;
+        for (int b = kOrderBuckets - 1; b >= 0; --b) {
+            cursor[b] = run;
+            run += hist[b];
+        }
+    }
+    __syncthreads();
+    for (int64_t p = tid; p < num_pairs; p += blockDim.x) {
+        const int pos = atomicAdd(&cursor[bucket_of(p)], 1);
+        order[pos] = (int32_t)p;
+    }
 }
 
 template <int D, int T, int CSMAX, bool L1>
@@ -693,6 +856,13 @@ int dispatch_all(bool run, const PairSolverArgs& A, int d, int threads, int chun
 int launch_pair_solver(const PairSolverArgs& args, int d, int threads, int chunk_max, size_t lds_bytes,
                        int grid, void* stream) {
     return dispatch_all(true, args, d, threads, chunk_max, lds_bytes, grid, (hipStream_t)stream, nullptr);
+}
+
+int launch_order(const int64_t* x_off, const int64_t* y_off, const int32_t* pair_x, const int32_t* pair_y,
+                 int64_t num_pairs, int64_t num_x_sets, int64_t num_y_sets, int32_t* order, void* stream) {
+    hipLaunchKernelGGL(order_kernel, dim3(1), dim3(1024), 0, (hipStream_t)stream, x_off, y_off, pair_x, pair_y,
+                       num_pairs, num_x_sets, num_y_sets, order);
+    return (int)hipGetLastError();
 }
 
 int pair_solver_blocks_per_cu(int d, int metric, int threads, int chunk_max, size_t lds_bytes, int* blocks) {
