@@ -83,6 +83,11 @@ typedef enum { NNSEMD_MODE_FP32 = 0, NNSEMD_MODE_BF16_MFMA_REFINE = 1 } nnsemd_m
  * it): longest first by m * n, or as given. */
 typedef enum { NNSEMD_SCHEDULE_LONGEST_FIRST = 0, NNSEMD_SCHEDULE_AS_GIVEN = 1 } nnsemd_schedule_t;
 
+/* Which implementation solves a single pair: automatic (on-chip whenever the
+ * pair fits one workgroup's LDS), the on-chip one-workgroup path, or the
+ * multi-workgroup path (any size; its host thread waits for the result). */
+typedef enum { NNSEMD_PATH_AUTO = 0, NNSEMD_PATH_ON_CHIP = 1, NNSEMD_PATH_MULTI = 2 } nnsemd_path_t;
+
 typedef struct {
     int32_t protocol;   /* nnsemd_protocol_t, default NNSEMD_GREEDY */
     int32_t mode;       /* nnsemd_mode_t, default NNSEMD_MODE_FP32 */
@@ -90,6 +95,8 @@ typedef struct {
     uint64_t seed;      /* random protocol only */
     int32_t threads;    /* workgroup size override (0 = tuned choice) */
     int32_t schedule;   /* nnsemd_schedule_t, default longest first */
+    int32_t path;       /* nnsemd_path_t (single pairs), default automatic */
+    int32_t reserved;   /* must be 0 */
 } nnsemd_options_t;
 
 /* Per-pair results, written by the device (48 bytes). */
@@ -142,6 +149,25 @@ nnsemd_status_t emd_approx(nnsemd_handle_t h,
                            int64_t plan_capacity,
                            nnsemd_stats_t* stats,
                            void* stream);
+
+/*
+ * emd_approx_map -- emd_approx plus the per-supplier barycentric transport
+ * map of the plan (colour transfer, Sec. IV-D): map[i*d + k] =
+ * sum_j F*_ij y_jk / sum_j F*_ij, accumulated in FP64 in plan order; rows of
+ * suppliers that sent nothing are NaN.  map: device, m x d doubles.  Uses
+ * the multi-workgroup path (the calling thread waits for the device).
+ * Plan arrays may be NULL as in emd_approx.
+ */
+nnsemd_status_t emd_approx_map(nnsemd_handle_t h,
+                               const void* X, const float* a, int64_t m,
+                               const void* Y, const float* b, int64_t n,
+                               int32_t d, nnsemd_dtype_t dtype, nnsemd_metric_t metric,
+                               const nnsemd_options_t* opts,
+                               double* cost, double* map,
+                               int32_t* plan_src, int32_t* plan_dst, double* plan_flow,
+                               int64_t plan_capacity,
+                               nnsemd_stats_t* stats,
+                               void* stream);
 
 /*
  * emd_approx_batched -- NNS-EMD of many independent ragged pairs in one

@@ -141,7 +141,7 @@ def solve(X, a, Y, b, metric: str = "l2", protocol: str = "greedy", seed: int = 
                             ctypes.byref(st))
     out = st.as_dict()
     out["status_name"] = STATUS.get(out["status"], str(out["status"]))
-    if with_plan and out["status"] == 0:
+    if with_plan and out["status"] in (0, -6):
         k = out["nnz"]
         out["src"], out["dst"], out["flow"] = src[:k].copy(), dst[:k].copy(), flow[:k].copy()
     return out

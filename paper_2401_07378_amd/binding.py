@@ -30,7 +30,7 @@ STATS_DTYPE = np.dtype([("status", "<i4"), ("rounds", "<i4"), ("nnz", "<i8"), ("
                         ("near_ties", "<i8"), ("residual_src", "<f8"), ("residual_dst", "<f8")])
 
 EXPORTS = ["nnsemd_create", "nnsemd_destroy", "nnsemd_status_string", "nnsemd_last_error",
-           "emd_approx", "emd_approx_batched"]
+           "emd_approx", "emd_approx_map", "emd_approx_batched"]
 
 
 class NNSEMDError(RuntimeError):
@@ -42,7 +42,8 @@ class NNSEMDError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("protocol", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("max_rounds", ctypes.c_int64), ("seed", ctypes.c_uint64),
-                ("threads", ctypes.c_int32), ("schedule", ctypes.c_int32)]
+                ("threads", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("path", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _lock = threading.Lock()
@@ -74,6 +75,9 @@ def load_library():
         lib.emd_approx_batched.argtypes = [P, I64, P, P, P, I64, P, P, P, I64, P, P, I64, I64, I32, I32,
                                            I32, ctypes.POINTER(Options), P, P, P, P, P, P, P]
         lib.emd_approx_batched.restype = I32
+        lib.emd_approx_map.argtypes = [P, P, P, I64, P, P, I64, I32, I32, I32, ctypes.POINTER(Options),
+                                       P, P, P, P, P, I64, P, P]
+        lib.emd_approx_map.restype = I32
         _lib = lib
         return lib
 
@@ -102,11 +106,12 @@ def _ptr(t):
 
 
 SCHEDULES = {"longest_first": 0, "as_given": 1}
+PATHS = {"auto": 0, "on_chip": 1, "multi": 2}
 
 
-def _options(protocol, mode, max_rounds, seed, threads, schedule="longest_first"):
+def _options(protocol, mode, max_rounds, seed, threads, schedule="longest_first", path="auto"):
     return Options(PROTOCOLS[protocol], MODES[mode], int(max_rounds), int(seed) & (2**64 - 1),
-                   int(threads), SCHEDULES[schedule])
+                   int(threads), SCHEDULES[schedule], PATHS[path], 0)
 
 
 def _stream(torch, device):
@@ -132,7 +137,7 @@ def stats_numpy(stats_tensor) -> np.ndarray:
 
 def emd_approx(X, a, Y, b, metric: str = "l2", *, plan: bool = True, protocol: str = "greedy",
                mode: str = "fp32", seed: int = 0, max_rounds: int = 0, threads: int = 0,
-               out: dict | None = None) -> dict:
+               path: str = "auto", out: dict | None = None) -> dict:
     """NNS-EMD of one pair on the GPU.  X (m x d) / a (m): suppliers; Y (n x d)
     / b (n): consumers; FP32 CUDA tensors.  Returns device tensors: cost (1,),
     stats (48 uint8), and with plan=True plan_src/plan_dst/plan_flow of
@@ -163,13 +168,42 @@ def emd_approx(X, a, Y, b, metric: str = "l2", *, plan: bool = True, protocol: s
         dst = o.get("plan_dst") if o.get("plan_dst") is not None else torch.empty(cap, dtype=torch.int32, device=X.device)
         flow = o.get("plan_flow") if o.get("plan_flow") is not None else torch.empty(cap, dtype=torch.float64, device=X.device)
         cap = src.numel()
-    opts = _options(protocol, mode, max_rounds, seed, threads)
+    opts = _options(protocol, mode, max_rounds, seed, threads, path=path)
     st = lib.emd_approx(h, _ptr(X), _ptr(a), m, _ptr(Y), _ptr(b), n, d,
                         DTYPES["bf16" if mode == "bf16_mfma_refine" else "f32"], METRICS[metric],
                         ctypes.byref(opts), _ptr(cost), _ptr(src), _ptr(dst), _ptr(flow),
                         cap if plan else 0, _ptr(stats), _stream(torch, dev))
     _check(lib, h, st)
     return {"cost": cost, "stats": stats, "plan_src": src, "plan_dst": dst, "plan_flow": flow}
+
+
+def emd_approx_map(X, a, Y, b, metric: str = "l2", *, plan: bool = True, protocol: str = "greedy",
+                   seed: int = 0, max_rounds: int = 0) -> dict:
+    """emd_approx plus the per-supplier barycentric map (m x d FP64 device
+    tensor 'map'); multi-workgroup path, returns when the device is done."""
+    import torch
+    lib = load_library()
+    dev = X.device.index if X.device.index is not None else torch.cuda.current_device()
+    h = handle(dev)
+    for t, nm in ((X, "X"), (Y, "Y"), (a, "a"), (b, "b")):
+        _require(t, torch.float32, nm)
+    m, n = X.shape[0], Y.shape[0]
+    d = X.shape[1] if X.dim() == 2 else 1
+    cost = torch.empty(1, dtype=torch.float64, device=X.device)
+    mp = torch.empty((max(m, 1), d), dtype=torch.float64, device=X.device)
+    stats = torch.empty(STATS_DTYPE.itemsize, dtype=torch.uint8, device=X.device)
+    cap = max(m + n - 1, 1)
+    src = dst = flow = None
+    if plan:
+        src = torch.empty(cap, dtype=torch.int32, device=X.device)
+        dst = torch.empty(cap, dtype=torch.int32, device=X.device)
+        flow = torch.empty(cap, dtype=torch.float64, device=X.device)
+    opts = _options(protocol, "fp32", max_rounds, seed, 0)
+    st = lib.emd_approx_map(h, _ptr(X), _ptr(a), m, _ptr(Y), _ptr(b), n, d, DTYPES["f32"], METRICS[metric],
+                            ctypes.byref(opts), _ptr(cost), _ptr(mp), _ptr(src), _ptr(dst), _ptr(flow),
+                            cap if plan else 0, _ptr(stats), _stream(torch, dev))
+    _check(lib, h, st)
+    return {"cost": cost, "map": mp[:m], "stats": stats, "plan_src": src, "plan_dst": dst, "plan_flow": flow}
 
 
 def plan_offsets(m_sizes, n_sizes) -> np.ndarray:

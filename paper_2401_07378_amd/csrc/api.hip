@@ -18,6 +18,9 @@ struct nnsemd_handle {
     unsigned long long* phase_cycles = nullptr;  // profiling builds only
     int32_t* order = nullptr;                    // longest-first pair schedule (device)
     int64_t order_cap = 0;
+    void* lp_base = nullptr;                     // multi-workgroup path workspace (device)
+    size_t lp_bytes = 0;
+    nnsemd::LPState* lp_host = nullptr;          // pinned copy of the round state
 };
 
 namespace {
@@ -87,6 +90,8 @@ nnsemd_status_t run_pairs(nnsemd_handle_t h, PairSolverArgs& A, int d, int64_t m
     if (A.x_off != nullptr && A.num_pairs > 1 && o.schedule == NNSEMD_SCHEDULE_LONGEST_FIRST) {
         if (h->order_cap < A.num_pairs) {
             if (h->order) (void)hipFree(h->order);
+        if (h->lp_base) (void)hipFree(h->lp_base);
+        if (h->lp_host) (void)hipHostFree(h->lp_host);
             h->order = nullptr;
             h->order_cap = 0;
             if (hipMalloc((void**)&h->order, sizeof(int32_t) * (size_t)A.num_pairs) != hipSuccess)
@@ -103,6 +108,98 @@ nnsemd_status_t run_pairs(nnsemd_handle_t h, PairSolverArgs& A, int d, int64_t m
     return NNSEMD_OK;
 }
 
+// Multi-workgroup path for one pair (any size).  Carves one device
+// allocation into the round state and per-point arrays, enqueues rounds and
+// reads the round state back every kChunk rounds to shrink the grids.
+nnsemd_status_t run_large(nnsemd_handle_t h, LPArgs& A, int d, void* stream) {
+    if (d < 1 || d > 7) return fail(h, NNSEMD_ERR_UNSUPPORTED, "point path supports 1 <= d <= 7");
+    if (A.m > (1ll << 20) || A.n > (1ll << 20))
+        return fail(h, NNSEMD_ERR_UNSUPPORTED, "multi-workgroup path supports up to 2^20 points per side");
+    const int rs = record_stride(d);
+    const int64_t mcap = std::max<int64_t>(A.m, 1), ncap = std::max<int64_t>(A.n, 1);
+    const int K = 3 + 2 * d;
+    const int64_t nb = (std::max(mcap, ncap) + 255) / 256;
+    const int64_t part_cap = std::max<int64_t>(ncap * 8, (int64_t)1 << 22);
+    const int64_t blk_cap = (std::max(mcap, ncap) + 1023) / 1024 + 1;
+    const bool want_map = A.map != nullptr;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = align_up(off, 256); off = o + bytes; return o; };
+    const size_t o_srec0 = take(sizeof(float) * rs * mcap), o_srec1 = take(sizeof(float) * rs * mcap);
+    const size_t o_sidx0 = take(4 * mcap), o_sidx1 = take(4 * mcap);
+    const size_t o_smass0 = take(8 * mcap), o_smass1 = take(8 * mcap);
+    const size_t o_scnt = take(4 * mcap), o_soff = take(4 * mcap);
+    const size_t o_cact0 = take(4 * ncap), o_cact1 = take(4 * ncap);
+    const size_t o_cmass = take(8 * ncap), o_cnn = take(4 * ncap), o_ckey = take(8 * ncap);
+    const size_t o_list = take(4 * ncap), o_sorted = take(4 * ncap), o_flag = take(4 * ncap);
+    const size_t o_part = take(16 * part_cap), o_blk = take(8 * blk_cap);
+    const size_t o_cost = take(8 * mcap);
+    const size_t o_wsum = want_map ? take(8 * mcap) : 0, o_bsum = want_map ? take(8 * mcap * d) : 0;
+    const size_t o_red = take(8 * nb * K), o_st = take(sizeof(LPState));
+    const size_t total = align_up(off, 256);
+    if (h->lp_bytes < total) {
+        if (h->lp_base) (void)hipFree(h->lp_base);
+        h->lp_base = nullptr;
+        h->lp_bytes = 0;
+        if (hipMalloc(&h->lp_base, total) != hipSuccess) return fail(h, NNSEMD_ERR_OUT_OF_MEMORY, "workspace");
+        h->lp_bytes = total;
+    }
+    if (h->lp_host == nullptr && hipHostMalloc((void**)&h->lp_host, sizeof(LPState)) != hipSuccess) {
+        h->lp_host = nullptr;
+        return fail(h, NNSEMD_ERR_OUT_OF_MEMORY, "pinned round state");
+    }
+    char* base = static_cast<char*>(h->lp_base);
+    LPWork& w = A.w;
+    w.srec[0] = reinterpret_cast<float*>(base + o_srec0);
+    w.srec[1] = reinterpret_cast<float*>(base + o_srec1);
+    w.sidx[0] = reinterpret_cast<int32_t*>(base + o_sidx0);
+    w.sidx[1] = reinterpret_cast<int32_t*>(base + o_sidx1);
+    w.smass[0] = reinterpret_cast<double*>(base + o_smass0);
+    w.smass[1] = reinterpret_cast<double*>(base + o_smass1);
+    w.scnt = reinterpret_cast<int32_t*>(base + o_scnt);
+    w.soff = reinterpret_cast<int32_t*>(base + o_soff);
+    w.cact[0] = reinterpret_cast<int32_t*>(base + o_cact0);
+    w.cact[1] = reinterpret_cast<int32_t*>(base + o_cact1);
+    w.cmass = reinterpret_cast<double*>(base + o_cmass);
+    w.cnn = reinterpret_cast<int32_t*>(base + o_cnn);
+    w.ckey = reinterpret_cast<double*>(base + o_ckey);
+    w.list = reinterpret_cast<int32_t*>(base + o_list);
+    w.sorted = reinterpret_cast<int32_t*>(base + o_sorted);
+    w.flagged = reinterpret_cast<int32_t*>(base + o_flag);
+    w.part = reinterpret_cast<float4*>(base + o_part);
+    w.ncap = ncap;
+    w.part_cap = part_cap;
+    w.blkcnt = reinterpret_cast<unsigned long long*>(base + o_blk);
+    w.blkcnt_cap = (int32_t)blk_cap;
+    w.costacc = reinterpret_cast<double*>(base + o_cost);
+    w.wsum = want_map ? reinterpret_cast<double*>(base + o_wsum) : nullptr;
+    w.bsum = want_map ? reinterpret_cast<double*>(base + o_bsum) : nullptr;
+    w.red = reinterpret_cast<double*>(base + o_red);
+    w.st = reinterpret_cast<LPState*>(base + o_st);
+    if (A.max_rounds <= 0) A.max_rounds = A.m + A.n;
+    int err = lp_launch_init(A, d, stream);
+    if (err != 0) return device_fail(h, err, "multi-workgroup init");
+    constexpr int kChunk = 16;
+    int mact_ub = (int)A.m, nact_ub = (int)A.n;
+    int64_t launched = 0;
+    for (;;) {
+        hipError_t e = hipMemcpyAsync(h->lp_host, w.st, sizeof(LPState), hipMemcpyDeviceToHost, (hipStream_t)stream);
+        if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+        if (e != hipSuccess) return device_fail(h, (int)e, "round state readback");
+        if (h->lp_host->done || h->lp_host->status != NNSEMD_OK) break;
+        if (launched > A.max_rounds + kChunk) break;  // unreachable: the device caps the rounds
+        mact_ub = h->lp_host->mact;
+        nact_ub = h->lp_host->nact;
+        for (int r = 0; r < kChunk; ++r) {
+            err = lp_launch_round(A, d, mact_ub, nact_ub, stream);
+            if (err != 0) return device_fail(h, err, "multi-workgroup round");
+            ++launched;
+        }
+    }
+    err = lp_launch_finish(A, d, stream);
+    if (err != 0) return device_fail(h, err, "multi-workgroup finish");
+    return NNSEMD_OK;
+}
+
 nnsemd_status_t check_common(nnsemd_handle_t h, int32_t d, nnsemd_dtype_t dtype, nnsemd_metric_t metric,
                              const nnsemd_options_t& o) {
     if (d < 1) return fail(h, NNSEMD_ERR_INVALID_ARG, "d must be >= 1");
@@ -113,6 +210,9 @@ nnsemd_status_t check_common(nnsemd_handle_t h, int32_t d, nnsemd_dtype_t dtype,
         return fail(h, NNSEMD_ERR_INVALID_ARG, "bad protocol");
     if (o.schedule != NNSEMD_SCHEDULE_LONGEST_FIRST && o.schedule != NNSEMD_SCHEDULE_AS_GIVEN)
         return fail(h, NNSEMD_ERR_INVALID_ARG, "bad schedule");
+    if (o.path != NNSEMD_PATH_AUTO && o.path != NNSEMD_PATH_ON_CHIP && o.path != NNSEMD_PATH_MULTI)
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "bad path");
+    if (o.reserved != 0) return fail(h, NNSEMD_ERR_INVALID_ARG, "reserved option field must be 0");
     if (o.mode != NNSEMD_MODE_FP32 && o.mode != NNSEMD_MODE_BF16_MFMA_REFINE)
         return fail(h, NNSEMD_ERR_INVALID_ARG, "bad mode");
     if (o.mode == NNSEMD_MODE_FP32 && dtype != NNSEMD_F32)
@@ -157,6 +257,8 @@ nnsemd_status_t nnsemd_destroy(nnsemd_handle_t h) {
         DeviceGuard g(h->device);
         (void)hipDeviceSynchronize();
         if (h->order) (void)hipFree(h->order);
+        if (h->lp_base) (void)hipFree(h->lp_base);
+        if (h->lp_host) (void)hipHostFree(h->lp_host);
     }
     delete h;
     return NNSEMD_OK;
@@ -198,6 +300,34 @@ nnsemd_status_t emd_approx(nnsemd_handle_t h, const void* X, const float* a, int
     if (plan && m + n > 0 && plan_capacity < m + n - 1)
         return fail(h, NNSEMD_ERR_CAPACITY, "plan capacity below m + n - 1");
     DeviceGuard g(h->device);
+    bool multi = o.path == NNSEMD_PATH_MULTI;
+    if (o.path == NNSEMD_PATH_AUTO) {
+        const int threads = o.threads > 0 ? o.threads : 256;
+        const int64_t maxp = std::max<int64_t>({m, n, 1});
+        const int chunk_cap = threads == 256 ? 16 : 8;
+        const PairLdsLayout lay = pair_lds_layout((int)std::max<int64_t>(m, 1), (int)std::max<int64_t>(n, 1),
+                                                  record_stride(std::max(1, std::min(d, 7))));
+        multi = (maxp + threads - 1) / threads > chunk_cap || lay.total + 8192 > h->max_lds;
+    }
+    if (multi) {
+        LPArgs L{};
+        L.m = m;
+        L.n = n;
+        L.X = static_cast<const float*>(X);
+        L.a = a;
+        L.Y = static_cast<const float*>(Y);
+        L.b = b;
+        L.metric = metric;
+        L.protocol = o.protocol;
+        L.seed = o.seed;
+        L.max_rounds = o.max_rounds;
+        L.cost = cost;
+        L.plan_src = plan ? plan_src : nullptr;
+        L.plan_dst = plan ? plan_dst : nullptr;
+        L.plan_flow = plan ? plan_flow : nullptr;
+        L.stats = stats;
+        return run_large(h, L, d, stream);
+    }
     PairSolverArgs A{};
     A.num_pairs = 1;
     A.X = static_cast<const float*>(X);
@@ -214,6 +344,46 @@ nnsemd_status_t emd_approx(nnsemd_handle_t h, const void* X, const float* a, int
     A.single_plan_cap = plan_capacity;
     A.stats = stats;
     return run_pairs(h, A, d, m, n, o, stream);
+}
+
+nnsemd_status_t emd_approx_map(nnsemd_handle_t h, const void* X, const float* a, int64_t m, const void* Y,
+                               const float* b, int64_t n, int32_t d, nnsemd_dtype_t dtype, nnsemd_metric_t metric,
+                               const nnsemd_options_t* opts, double* cost, double* map, int32_t* plan_src,
+                               int32_t* plan_dst, double* plan_flow, int64_t plan_capacity, nnsemd_stats_t* stats,
+                               void* stream) {
+    if (h == nullptr) return NNSEMD_ERR_INVALID_ARG;
+    h->last_error.clear();
+    const nnsemd_options_t o = opts ? *opts : default_options();
+    nnsemd_status_t s = check_common(h, d, dtype, metric, o);
+    if (s != NNSEMD_OK) return s;
+    if (m < 0 || n < 0) return fail(h, NNSEMD_ERR_INVALID_ARG, "negative size");
+    if (cost == nullptr || (map == nullptr && m > 0)) return fail(h, NNSEMD_ERR_INVALID_ARG, "cost and map must not be NULL");
+    if ((m > 0 && (X == nullptr || a == nullptr)) || (n > 0 && (Y == nullptr || b == nullptr)))
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "NULL point or mass array");
+    const bool plan = plan_src != nullptr || plan_dst != nullptr || plan_flow != nullptr;
+    if (plan && (plan_src == nullptr || plan_dst == nullptr || plan_flow == nullptr))
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "plan arrays must be all given or all NULL");
+    if (plan && m + n > 0 && plan_capacity < m + n - 1)
+        return fail(h, NNSEMD_ERR_CAPACITY, "plan capacity below m + n - 1");
+    DeviceGuard g(h->device);
+    LPArgs L{};
+    L.m = m;
+    L.n = n;
+    L.X = static_cast<const float*>(X);
+    L.a = a;
+    L.Y = static_cast<const float*>(Y);
+    L.b = b;
+    L.metric = metric;
+    L.protocol = o.protocol;
+    L.seed = o.seed;
+    L.max_rounds = o.max_rounds;
+    L.cost = cost;
+    L.plan_src = plan ? plan_src : nullptr;
+    L.plan_dst = plan ? plan_dst : nullptr;
+    L.plan_flow = plan ? plan_flow : nullptr;
+    L.stats = stats;
+    L.map = map;
+    return run_large(h, L, d, stream);
 }
 
 nnsemd_status_t emd_approx_batched(nnsemd_handle_t h, int64_t num_pairs, const void* Xcat, const float* acat,

@@ -74,6 +74,65 @@ __host__ __device__ inline PairLdsLayout pair_lds_layout(int M, int N, int rs) {
     return L;
 }
 
+// ---------------------------------------------------------------------
+// Multi-workgroup path for one pair of any size (large_pair.hip).
+struct LPState {
+    int32_t status, mact, nact, nflag;
+    int64_t nnz, work, near;
+    int32_t rounds, done, parity, pad0;
+    float centre[8];
+    float rhat, pad1;
+    double sum_a, sum_b;
+};
+
+struct LPWork {
+    float* srec[2];      // active supplier records by slot (ping-pong)
+    int32_t* sidx[2];    // slot -> local supplier index
+    double* smass[2];    // slot -> FP64 mass
+    int32_t* scnt;       // claimant count by slot
+    int32_t* soff;       // bucket start / end by slot
+    int32_t* cact[2];    // active consumers (ping-pong)
+    double* cmass;       // consumer FP64 mass by local index
+    int32_t* cnn;        // pick slot (then supplier local index after the serve)
+    double* ckey;        // FP64 key of the pick (then the flow)
+    int32_t* list;       // claimant buckets
+    int32_t* sorted;     // claimant buckets in serve order
+    int32_t* flagged;    // near-tie consumers of the round
+    float4* part;        // per (supplier chunk, consumer) FP32 best/second/slot
+    int64_t ncap;        // consumer capacity (row stride of part)
+    int64_t part_cap;    // entries of part
+    unsigned long long* blkcnt;  // per-block packed compaction counts
+    int32_t blkcnt_cap;
+    int32_t pad;
+    double* costacc;     // per supplier (local index) cost, serve order
+    double* wsum;        // per supplier outgoing flow (map only; may be null)
+    double* bsum;        // per supplier sum f * y (map only)
+    double* red;         // ingest partials
+    LPState* st;
+};
+
+struct LPArgs {
+    int64_t m, n;
+    const float* X;
+    const float* a;
+    const float* Y;
+    const float* b;
+    int32_t metric, protocol;
+    uint64_t seed;
+    int64_t max_rounds;
+    double* cost;
+    int32_t* plan_src;
+    int32_t* plan_dst;
+    double* plan_flow;
+    nnsemd_stats_t* stats;
+    double* map;  // m x d FP64 barycentric map, or null
+    LPWork w;
+};
+
+int lp_launch_init(const LPArgs& A, int d, void* stream);
+int lp_launch_round(const LPArgs& A, int d, int mact_ub, int nact_ub, void* stream);
+int lp_launch_finish(const LPArgs& A, int d, void* stream);
+
 // Launch entry points (defined in pair_solver.hip).
 // Returns hipSuccess-compatible int (0 on success).
 int launch_pair_solver(const PairSolverArgs& args, int d, int threads, int chunk_max,

@@ -1,0 +1,806 @@
+// Multi-workgroup NNS-EMD for one pair of any size (low-dimensional FP32
+// points), and the per-supplier barycentric transport map of its plan.
+//
+// Each round of Algorithm 1 (Sec. III-A) is a fixed sequence of kernels over
+// the whole device; the round state (active sizes, counters, the index of the
+// live ping-pong buffer) lives in a device struct, so the host enqueues
+// rounds without reading anything back and only synchronises every few
+// rounds to shrink the grids.
+//   search   consumer blocks x supplier chunks; supplier records staged in
+//            LDS tiles; FP32 best / second-best per (chunk, consumer)
+//   decide   merge the chunk partials; near ties (FP32 rounding bound) go to
+//            the FP64 re-score list, others store pick + exact FP64 key and
+//            count themselves into the pick's bucket
+//   rescore  FP64 argmin of near-tie consumers, one wavefront each
+//   offsets  exclusive scan of the bucket counts (one workgroup)
+//   scatter  claimants into buckets
+//   rank     each claimant's position in its bucket ((D, j) or random key)
+//   walk     one lane per claimed supplier serves in order, FP64
+//   compact  plan append + surviving suppliers / consumers: per-block counts,
+//            stable writes at the blocks' offsets, one-thread commit
+// Cost and map are accumulated per supplier (local index) in serve order, so
+// results are deterministic and the map equals the definition bit for bit.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "internal.hpp"
+
+namespace nnsemd {
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kLpThreads = 256;
+constexpr int kLpScanThreads = 1024;
+constexpr int kLpTile = 1024;   // supplier records per LDS tile in the search
+constexpr int kLpUnroll = 8;
+
+__device__ inline bool lp_live(const LPState* st) { return st->status == NNSEMD_OK && !st->done; }
+
+template <int D, bool L1>
+__device__ inline double lp_key64(const float* __restrict__ x, const float* __restrict__ y) {
+#pragma clang fp contract(off)
+    double acc = 0.0;
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+        double diff = (double)x[t] - (double)y[t];
+        if (L1)
+            acc = acc + fabs(diff);
+        else
+            acc = acc + diff * diff;
+    }
+    return acc;
+}
+
+__device__ inline uint64_t lp_rp_key(uint64_t seed, int64_t round, int32_t j) {
+    uint64_t ctr = ((uint64_t)round << 32) ^ (uint64_t)(uint32_t)j;
+    uint64_t z = seed + (ctr + 1u) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Exclusive scan of one 64-bit value per thread over a workgroup of T.
+template <int T>
+__device__ inline unsigned long long lp_block_scan(unsigned long long v, unsigned long long* total,
+                                                   unsigned long long* scratch) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    unsigned long long x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        unsigned long long y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == kWave - 1) scratch[w] = x;
+    __syncthreads();
+    unsigned long long off = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < T / kWave; ++k) {
+        unsigned long long s = scratch[k];
+        off += (k < w) ? s : 0ull;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + x - v;
+}
+
+template <int T>
+__device__ inline double lp_block_sum(double v, double* scratch) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) scratch[w] = v;
+    __syncthreads();
+    double r = scratch[0];
+#pragma unroll
+    for (int k = 1; k < T / kWave; ++k) r += scratch[k];
+    __syncthreads();
+    return r;
+}
+
+// ---------------------------------------------------------------- ingest
+// Per block: masses to FP64, validity, sums, bounding box partials.
+template <int D>
+__global__ __launch_bounds__(kLpThreads) void lp_ingest(LPArgs A) {
+    __shared__ double scratch[kLpThreads / kWave][3 + 2 * D];
+    const int tid = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * kLpThreads + tid;
+    double v[3 + 2 * D];
+    v[0] = 0.0;
+    v[1] = 0.0;
+    v[2] = 0.0;
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+        v[3 + t] = INFINITY;
+        v[3 + D + t] = -INFINITY;
+    }
+    if (i < A.m) {
+        const float av = A.a[i];
+        if (!(av >= 0.f) || !isfinite(av)) v[2] = 1.0;
+        v[0] = (double)av;
+        A.w.smass[0][i] = (double)av;
+#pragma unroll
+        for (int t = 0; t < D; ++t) {
+            const float xv = A.X[i * D + t];
+            if (!isfinite(xv)) v[2] = 1.0;
+            v[3 + t] = (double)xv;
+            v[3 + D + t] = (double)xv;
+        }
+        A.w.costacc[i] = 0.0;
+        if (A.w.wsum != nullptr) {
+            A.w.wsum[i] = 0.0;
+#pragma unroll
+            for (int t = 0; t < D; ++t) A.w.bsum[i * D + t] = 0.0;
+        }
+    }
+    if (i < A.n) {
+        const float bv = A.b[i];
+        if (!(bv >= 0.f) || !isfinite(bv)) v[2] = 1.0;
+        v[1] = (double)bv;
+        A.w.cmass[i] = (double)bv;
+#pragma unroll
+        for (int t = 0; t < D; ++t)
+            if (!isfinite(A.Y[i * D + t])) v[2] = 1.0;
+    }
+    const int lane = tid & (kWave - 1), w = tid / kWave;
+#pragma unroll
+    for (int k = 0; k < 3 + 2 * D; ++k) {
+        double x = v[k];
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) {
+            const double y = __shfl_xor(x, o);
+            x = (k < 2) ? x + y : (k < 3 + D && k >= 3) ? fmin(x, y) : fmax(x, y);
+        }
+        if (lane == 0) scratch[w][k] = x;
+    }
+    __syncthreads();
+    if (tid < 3 + 2 * D) {
+        const int k = tid;
+        double x = scratch[0][k];
+        for (int q = 1; q < kLpThreads / kWave; ++q) {
+            const double y = scratch[q][k];
+            x = (k < 2) ? x + y : (k < 3 + D && k >= 3) ? fmin(x, y) : fmax(x, y);
+        }
+        A.w.red[(size_t)blockIdx.x * (3 + 2 * D) + k] = x;
+    }
+}
+
+// ----------------------------------------------------------------- setup
+// One workgroup: reduce the ingest partials, check, centre, build the first
+// active sets (in buffer 1; buffer 0 holds the masses by local index) and the
+// radius that enters the FP32 rounding bound.
+template <int D, bool L1>
+__global__ __launch_bounds__(kLpScanThreads) void lp_setup(LPArgs A, int nblocks) {
+    constexpr int RS = record_stride(D);
+    constexpr int K = 3 + 2 * D;
+    __shared__ double red[K];
+    __shared__ unsigned long long scan_scratch[kLpScanThreads / kWave];
+    __shared__ double sum_scratch[kLpScanThreads / kWave];
+    const int tid = threadIdx.x;
+    LPState* st = A.w.st;
+    if (tid < K) {
+        const int k = tid;
+        double x = (k < 2) ? 0.0 : (k == 2 ? 0.0 : (k < 3 + D ? INFINITY : -INFINITY));
+        for (int b = 0; b < nblocks; ++b) {
+            const double y = A.w.red[(size_t)b * K + k];
+            x = (k < 2) ? x + y : (k == 2 ? fmax(x, y) : (k < 3 + D ? fmin(x, y) : fmax(x, y)));
+        }
+        red[k] = x;
+    }
+    __syncthreads();
+    int status = NNSEMD_OK;
+    if (red[2] != 0.0) status = NNSEMD_ERR_INVALID_ARG;
+    if (status == NNSEMD_OK) {
+        const double big = fmax(red[0], red[1]);
+        if (fabs(red[0] - red[1]) > 1e-5 * big) status = NNSEMD_ERR_MASS_MISMATCH;
+    }
+    float centre[D];
+#pragma unroll
+    for (int t = 0; t < D; ++t)
+        centre[t] = (L1 || A.m == 0) ? 0.f : 0.5f * ((float)red[3 + t] + (float)red[3 + D + t]);
+    const int m = (int)A.m, n = (int)A.n;
+    // initial compaction (zero masses never enter), chunked per thread
+    const int cs = (m + kLpScanThreads - 1) / kLpScanThreads;
+    const int cc = (n + kLpScanThreads - 1) / kLpScanThreads;
+    const int slo = min(tid * cs, m), shi = min(slo + cs, m);
+    const int clo = min(tid * cc, n), chi = min(clo + cc, n);
+    int ks = 0, kc = 0;
+    if (status == NNSEMD_OK) {
+        for (int i = slo; i < shi; ++i) ks += A.w.smass[0][i] > 0.0;
+        for (int j = clo; j < chi; ++j) kc += A.w.cmass[j] > 0.0;
+    }
+    unsigned long long tot;
+    const unsigned long long pre =
+        lp_block_scan<kLpScanThreads>((unsigned long long)ks | ((unsigned long long)kc << 32), &tot, scan_scratch);
+    int ps = (int)(pre & 0xffffffffu), pc = (int)(pre >> 32);
+    float rmax = 0.f;
+    if (status == NNSEMD_OK) {
+        // Records are written to buffer 1 first (buffer 0 still holds the
+        // masses by local index), then the masses follow.
+        for (int i = slo; i < shi; ++i) {
+            const double mv = A.w.smass[0][i];
+            if (!(mv > 0.0)) continue;
+            float r[RS];
+#pragma unroll
+            for (int q = 0; q < RS; ++q) r[q] = 0.f;
+            if (L1) {
+#pragma unroll
+                for (int t = 0; t < D; ++t) r[t] = A.X[(int64_t)i * D + t];
+            } else {
+                float h = 0.f;
+#pragma unroll
+                for (int t = 0; t < D; ++t) {
+                    const float xc = A.X[(int64_t)i * D + t] - centre[t];
+                    r[t] = -2.f * xc;
+                    h = fmaf(xc, xc, h);
+                }
+                r[D] = h;
+                rmax = fmaxf(rmax, sqrtf(h));
+            }
+            float4* dst = reinterpret_cast<float4*>(A.w.srec[1] + (size_t)ps * RS);
+#pragma unroll
+            for (int q = 0; q < RS / 4; ++q) dst[q] = make_float4(r[4 * q], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]);
+            A.w.sidx[1][ps] = i;
+            A.w.smass[1][ps] = mv;
+            A.w.scnt[ps] = 0;
+            ++ps;
+        }
+        for (int j = clo; j < chi; ++j)
+            if (A.w.cmass[j] > 0.0) A.w.cact[1][pc++] = j;
+    }
+    // max radius (positive floats order like their bit patterns)
+    __shared__ unsigned int rbits;
+    if (tid == 0) rbits = 0u;
+    __syncthreads();
+    atomicMax(&rbits, __float_as_uint(rmax));
+    (void)sum_scratch;
+    __syncthreads();
+    if (tid == 0) {
+        st->status = status;
+        st->mact = status == NNSEMD_OK ? (int)(tot & 0xffffffffu) : 0;
+        st->nact = status == NNSEMD_OK ? (int)(tot >> 32) : 0;
+        st->nflag = 0;
+        st->nnz = 0;
+        st->work = 0;
+        st->near = 0;
+        st->rounds = 0;
+        st->parity = 1;
+        st->done = (st->mact == 0 || st->nact == 0) ? 1 : 0;
+        st->rhat = __uint_as_float(rbits) * (1.f + 1e-6f);
+#pragma unroll
+        for (int t = 0; t < D; ++t) st->centre[t] = centre[t];
+        st->sum_a = red[0];
+        st->sum_b = red[1];
+    }
+}
+
+// ---------------------------------------------------------------- search
+template <int D, bool L1, int KC>
+__global__ __launch_bounds__(kLpThreads) void lp_search(LPArgs A, int split) {
+    constexpr int RS = record_stride(D);
+    __shared__ __align__(16) float tile[kLpTile * RS];
+    const LPState* st = A.w.st;
+    if (!lp_live(st)) return;
+    const int mact = st->mact, nact = st->nact, par = st->parity;
+    const int tid = threadIdx.x;
+    const int base = blockIdx.x * kLpThreads * KC;
+    if (base >= nact) return;
+    const int chunk = (mact + split - 1) / split;
+    const int s_lo = min((int)blockIdx.y * chunk, mact), s_hi = min(s_lo + chunk, mact);
+    const float* __restrict__ srec = A.w.srec[par];
+    const int* __restrict__ cact = A.w.cact[par];
+    float y[KC][D];
+    float b1[KC], b2[KC];
+    int bs[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        const int q = base + tid + k * kLpThreads;
+        const int j = cact[q < nact ? q : 0];
+#pragma unroll
+        for (int t = 0; t < D; ++t) y[k][t] = L1 ? A.Y[(int64_t)j * D + t] : A.Y[(int64_t)j * D + t] - st->centre[t];
+        b1[k] = INFINITY;
+        b2[k] = INFINITY;
+        bs[k] = 0x7fffffff;
+    }
+    for (int t0 = s_lo; t0 < s_hi; t0 += kLpTile) {
+        const int cnt = min(kLpTile, s_hi - t0);
+        const float4* src = reinterpret_cast<const float4*>(srec + (size_t)t0 * RS);
+        float4* dst = reinterpret_cast<float4*>(tile);
+        for (int e = tid; e < cnt * (RS / 4); e += kLpThreads) dst[e] = src[e];
+        __syncthreads();
+        const int full = (cnt / kLpUnroll) * kLpUnroll;
+        for (int s0 = 0; s0 < full; s0 += kLpUnroll) {
+            float rec[kLpUnroll][RS];
+#pragma unroll
+            for (int u = 0; u < kLpUnroll; ++u) {
+                const float4* p = reinterpret_cast<const float4*>(tile + (size_t)(s0 + u) * RS);
+#pragma unroll
+                for (int q = 0; q < RS / 4; ++q) {
+                    const float4 v = p[q];
+                    rec[u][4 * q] = v.x;
+                    rec[u][4 * q + 1] = v.y;
+                    rec[u][4 * q + 2] = v.z;
+                    rec[u][4 * q + 3] = v.w;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kLpUnroll; ++u) {
+#pragma unroll
+                for (int k = 0; k < KC; ++k) {
+                    float key;
+                    if (L1) {
+                        key = 0.f;
+#pragma unroll
+                        for (int t = 0; t < D; ++t) key += fabsf(rec[u][t] - y[k][t]);
+                    } else {
+                        key = rec[u][D];
+#pragma unroll
+                        for (int t = D - 1; t >= 0; --t) key = fmaf(rec[u][t], y[k][t], key);
+                    }
+                    const bool lt = key < b1[k];
+                    bs[k] = lt ? t0 + s0 + u : bs[k];
+                    b2[k] = __builtin_amdgcn_fmed3f(b1[k], key, b2[k]);
+                    b1[k] = fminf(b1[k], key);
+                }
+            }
+        }
+        for (int s = full; s < cnt; ++s) {
+            float rec[RS];
+#pragma unroll
+            for (int q = 0; q < RS; ++q) rec[q] = tile[(size_t)s * RS + q];
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+                float key;
+                if (L1) {
+                    key = 0.f;
+#pragma unroll
+                    for (int t = 0; t < D; ++t) key += fabsf(rec[t] - y[k][t]);
+                } else {
+                    key = rec[D];
+#pragma unroll
+                    for (int t = D - 1; t >= 0; --t) key = fmaf(rec[t], y[k][t], key);
+                }
+                const bool lt = key < b1[k];
+                bs[k] = lt ? t0 + s : bs[k];
+                b2[k] = __builtin_amdgcn_fmed3f(b1[k], key, b2[k]);
+                b1[k] = fminf(b1[k], key);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        const int q = base + tid + k * kLpThreads;
+        if (q < nact)
+            A.w.part[(size_t)blockIdx.y * A.w.ncap + q] = make_float4(b1[k], b2[k], __int_as_float(bs[k]), 0.f);
+    }
+}
+
+// ---------------------------------------------------------------- decide
+template <int D, bool L1>
+__global__ __launch_bounds__(kLpThreads) void lp_decide(LPArgs A, int split) {
+    LPState* st = A.w.st;
+    if (!lp_live(st)) return;
+    const int nact = st->nact, par = st->parity;
+    const int q = blockIdx.x * kLpThreads + threadIdx.x;
+    if (q >= nact) return;
+    float b1 = INFINITY, b2 = INFINITY;
+    int bs = 0x7fffffff;
+    for (int c = 0; c < split; ++c) {
+        const float4 v = A.w.part[(size_t)c * A.w.ncap + q];
+        const int cs = __float_as_int(v.z);
+        const float n2 = fminf(fmaxf(b1, v.x), fminf(b2, v.y));
+        const bool take = (v.x < b1) || (v.x == b1 && cs < bs);
+        b1 = take ? v.x : b1;
+        bs = take ? cs : bs;
+        b2 = n2;
+    }
+    const int j = A.w.cact[par][q];
+    float thr;
+    if (L1) {
+        thr = 4.f * (float)(D + 1) * kU32 * b2 + 1e-30f;
+    } else {
+        float yn2 = 0.f;
+#pragma unroll
+        for (int t = 0; t < D; ++t) {
+            const float yv = A.Y[(int64_t)j * D + t] - st->centre[t];
+            yn2 = fmaf(yv, yv, yn2);
+        }
+        const float e = st->rhat + sqrtf(yn2);
+        thr = 32.f * kU32 * e * e + 1e-30f;
+    }
+    if (!(b2 - b1 > thr)) {
+        const int f = atomicAdd(&st->nflag, 1);
+        A.w.flagged[f] = j;
+    } else {
+        const int i = A.w.sidx[par][bs];
+        A.w.cnn[j] = bs;
+        A.w.ckey[j] = lp_key64<D, L1>(A.X + (int64_t)i * D, A.Y + (int64_t)j * D);
+        atomicAdd(&A.w.scnt[bs], 1);
+    }
+}
+
+// --------------------------------------------------------------- rescore
+template <int D, bool L1>
+__global__ __launch_bounds__(kLpThreads) void lp_rescore(LPArgs A) {
+    LPState* st = A.w.st;
+    if (!lp_live(st)) return;
+    const int nf = st->nflag, mact = st->mact, par = st->parity;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int gw = blockIdx.x * (kLpThreads / kWave) + threadIdx.x / kWave;
+    const int nw = gridDim.x * (kLpThreads / kWave);
+    for (int f = gw; f < nf; f += nw) {
+        const int j = A.w.flagged[f];
+        const float* yp = A.Y + (int64_t)j * D;
+        double best = INFINITY;
+        int bsl = 0x7fffffff;
+        for (int s = lane; s < mact; s += kWave) {
+            const double k = lp_key64<D, L1>(A.X + (int64_t)A.w.sidx[par][s] * D, yp);
+            if (k < best) {
+                best = k;
+                bsl = s;
+            }
+        }
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) {
+            const double cb = __shfl_xor(best, o);
+            const int cs = __shfl_xor(bsl, o);
+            if (cb < best || (cb == best && cs < bsl)) {
+                best = cb;
+                bsl = cs;
+            }
+        }
+        if (lane == 0) {
+            A.w.cnn[j] = bsl;
+            A.w.ckey[j] = best;
+            atomicAdd(&A.w.scnt[bsl], 1);
+        }
+    }
+}
+
+// --------------------------------------------------------------- offsets
+__global__ __launch_bounds__(kLpScanThreads) void lp_offsets(LPArgs A) {
+    __shared__ unsigned long long scratch[kLpScanThreads / kWave];
+    LPState* st = A.w.st;
+    if (!lp_live(st)) return;
+    const int mact = st->mact;
+    const int tid = threadIdx.x;
+    const int cs = (mact + kLpScanThreads - 1) / kLpScanThreads;
+    const int lo = min(tid * cs, mact), hi = min(lo + cs, mact);
+    int sum = 0;
+    for (int s = lo; s < hi; ++s) sum += A.w.scnt[s];
+    unsigned long long tot;
+    int run = (int)lp_block_scan<kLpScanThreads>((unsigned long long)sum, &tot, scratch);
+    for (int s = lo; s < hi; ++s) {
+        A.w.soff[s] = run;
+        run += A.w.scnt[s];
+    }
+}
+
+// --------------------------------------------------------------- scatter
+__global__ __launch_bounds__(kLpThreads) void lp_scatter(LPArgs A) {
+    const LPState* st = A.w.st;
+    if (!lp_live(st)) return;
+    const int q = blockIdx.x * kLpThreads + threadIdx.x;
+    if (q >= st->nact) return;
+    const int j = A.w.cact[st->parity][q];
+    const int pos = atomicAdd(&A.w.soff[A.w.cnn[j]], 1);
+    A.w.list[pos] = j;
+}
+
+// ------------------------------------------------------------------ rank
+__global__ __launch_bounds__(kLpThreads) void lp_rank(LPArgs A) {
+    const LPState* st = A.w.st;
+    if (!lp_live(st)) return;
+    const int q = blockIdx.x * kLpThreads + threadIdx.x;
+    if (q >= st->nact) return;
+    const int j = A.w.cact[st->parity][q];
+    const int sl = A.w.cnn[j];
+    const int c = A.w.scnt[sl];
+    const int end = A.w.soff[sl];
+    const int start = end - c;
+    int rank = 0;
+    if (c > 1) {
+        if (A.protocol == NNSEMD_GREEDY) {
+            const double k = A.w.ckey[j];
+            for (int e = start; e < end; ++e) {
+                const int j2 = A.w.list[e];
+                const double k2 = A.w.ckey[j2];
+                rank += (k2 < k) || (k2 == k && j2 < j);
+            }
+        } else {
+            const uint64_t k = lp_rp_key(A.seed, st->rounds, j);
+            for (int e = start; e < end; ++e) {
+                const int j2 = A.w.list[e];
+                const uint64_t k2 = lp_rp_key(A.seed, st->rounds, j2);
+                rank += (k2 < k) || (k2 == k && j2 < j);
+            }
+        }
+    }
+    A.w.sorted[start + rank] = j;
+}
+
+// ------------------------------------------------------------------ walk
+template <int D>
+__global__ __launch_bounds__(kLpThreads) void lp_walk(LPArgs A) {
+#pragma clang fp contract(off)
+    const LPState* st = A.w.st;
+    if (!lp_live(st)) return;
+    const int s = blockIdx.x * kLpThreads + threadIdx.x;
+    const int par = st->parity;
+    if (s >= st->mact) return;
+    const int c = A.w.scnt[s];
+    if (c == 0) return;
+    const int end = A.w.soff[s];
+    const int isup = A.w.sidx[par][s];
+    int pos = end - c;
+    double sm = A.w.smass[par][s];
+    double acc = A.w.costacc[isup];
+    while (pos < end && sm > 0.0) {
+        const int j = A.w.sorted[pos];
+        const double cm = A.w.cmass[j];
+        const double f = sm < cm ? sm : cm;
+        sm = sm - f;
+        A.w.cmass[j] = cm - f;
+        const double key = A.w.ckey[j];
+        acc = acc + f * (A.metric == NNSEMD_L2 ? sqrt(key) : key);
+        if (A.w.wsum != nullptr) {
+            A.w.wsum[isup] = A.w.wsum[isup] + f;
+#pragma unroll
+            for (int t = 0; t < D; ++t)
+                A.w.bsum[(int64_t)isup * D + t] = A.w.bsum[(int64_t)isup * D + t] + f * (double)A.Y[(int64_t)j * D + t];
+        }
+        A.w.ckey[j] = f;
+        A.w.cnn[j] = isup;
+        ++pos;
+    }
+    for (int e = pos; e < end; ++e) A.w.ckey[A.w.sorted[e]] = 0.0;
+    A.w.smass[par][s] = sm;
+    A.w.costacc[isup] = acc;
+}
+
+// --------------------------------------------------------------- compact
+// Stable compaction of three streams in one pass structure: plan entries
+// (claimants in serve order with a positive flow), surviving suppliers
+// (records, index, mass; into the other buffer) and surviving consumers.
+// count: per-block counts; write: each block derives its offsets from the
+// counts of the blocks before it; commit: one thread updates the round state.
+constexpr int kLpCompactPer = 4;  // elements per thread and stream
+constexpr int kLpCompactBlock = kLpThreads * kLpCompactPer;
+
+__device__ inline void lp_flags(const LPArgs& A, int par, int mact, int nact, int e, bool& fp, bool& fs, bool& fc) {
+    fp = e < nact && A.w.ckey[A.w.sorted[e]] > 0.0;
+    fs = e < mact && A.w.smass[par][e] > 0.0;
+    fc = e < nact && A.w.cmass[A.w.cact[par][e]] > 0.0;
+}
+
+__global__ __launch_bounds__(kLpThreads) void lp_ccount(LPArgs A) {
+    __shared__ unsigned long long scratch[kLpThreads / kWave];
+    const LPState* st = A.w.st;
+    if (!lp_live(st)) return;
+    const int mact = st->mact, nact = st->nact, par = st->parity;
+    const int e0 = blockIdx.x * kLpCompactBlock + threadIdx.x * kLpCompactPer;
+    int kp = 0, ks = 0, kc = 0;
+#pragma unroll
+    for (int u = 0; u < kLpCompactPer; ++u) {
+        bool fp, fs, fc;
+        lp_flags(A, par, mact, nact, e0 + u, fp, fs, fc);
+        kp += fp;
+        ks += fs;
+        kc += fc;
+    }
+    unsigned long long tot;
+    (void)lp_block_scan<kLpThreads>((unsigned long long)kp | ((unsigned long long)ks << 21) |
+                                        ((unsigned long long)kc << 42), &tot, scratch);
+    if (threadIdx.x == 0) A.w.blkcnt[blockIdx.x] = tot;
+}
+
+template <int D>
+__global__ __launch_bounds__(kLpThreads) void lp_cwrite(LPArgs A) {
+    constexpr int RS = record_stride(D);
+    __shared__ unsigned long long scratch[kLpThreads / kWave];
+    __shared__ unsigned long long base_sh;
+    const LPState* st = A.w.st;
+    if (!lp_live(st)) return;
+    const int mact = st->mact, nact = st->nact, par = st->parity;
+    const int tid = threadIdx.x;
+    // offsets of this block: sum of the packed counts of earlier blocks
+    unsigned long long part = 0;
+    for (int b = tid; b < (int)blockIdx.x; b += kLpThreads) part += A.w.blkcnt[b];
+    unsigned long long btot;
+    (void)lp_block_scan<kLpThreads>(part, &btot, scratch);
+    if (tid == 0) base_sh = btot;
+    __syncthreads();
+    const unsigned long long base = base_sh;
+    const int e0 = blockIdx.x * kLpCompactBlock + tid * kLpCompactPer;
+    bool fp[kLpCompactPer], fs[kLpCompactPer], fc[kLpCompactPer];
+    int kp = 0, ks = 0, kc = 0;
+#pragma unroll
+    for (int u = 0; u < kLpCompactPer; ++u) {
+        lp_flags(A, par, mact, nact, e0 + u, fp[u], fs[u], fc[u]);
+        kp += fp[u];
+        ks += fs[u];
+        kc += fc[u];
+    }
+    unsigned long long tot;
+    const unsigned long long pre = base + lp_block_scan<kLpThreads>(
+        (unsigned long long)kp | ((unsigned long long)ks << 21) | ((unsigned long long)kc << 42), &tot, scratch);
+    const unsigned long long mask = (1ull << 21) - 1;
+    int wp = (int)(pre & mask), ws = (int)((pre >> 21) & mask), wc = (int)(pre >> 42);
+    const int64_t nnz0 = st->nnz;
+    const int np = 1 - par;
+#pragma unroll
+    for (int u = 0; u < kLpCompactPer; ++u) {
+        const int e = e0 + u;
+        if (fp[u] && A.plan_src != nullptr) {
+            const int j = A.w.sorted[e];
+            const int64_t o = nnz0 + wp;
+            A.plan_src[o] = A.w.cnn[j];
+            A.plan_dst[o] = j;
+            A.plan_flow[o] = A.w.ckey[j];
+        }
+        wp += fp[u];
+        if (fs[u]) {
+            const float4* src = reinterpret_cast<const float4*>(A.w.srec[par] + (size_t)e * RS);
+            float4* dst = reinterpret_cast<float4*>(A.w.srec[np] + (size_t)ws * RS);
+#pragma unroll
+            for (int q = 0; q < RS / 4; ++q) dst[q] = src[q];
+            A.w.sidx[np][ws] = A.w.sidx[par][e];
+            A.w.smass[np][ws] = A.w.smass[par][e];
+            A.w.scnt[ws] = 0;
+            ++ws;
+        }
+        if (fc[u]) A.w.cact[np][wc++] = A.w.cact[par][e];
+    }
+}
+
+__global__ void lp_commit(LPArgs A, int nblocks) {
+    LPState* st = A.w.st;
+    if (!lp_live(st)) return;
+    unsigned long long tot = 0;
+    for (int b = 0; b < nblocks; ++b) tot += A.w.blkcnt[b];
+    const unsigned long long mask = (1ull << 21) - 1;
+    const int m2 = (int)((tot >> 21) & mask), n2 = (int)(tot >> 42);
+    st->nnz += (int64_t)(tot & mask);
+    st->work += (int64_t)st->mact * st->nact;
+    st->near += st->nflag;
+    st->nflag = 0;
+    st->rounds += 1;
+    st->mact = m2;
+    st->nact = n2;
+    st->parity = 1 - st->parity;
+    if (m2 == 0 || n2 == 0) {
+        st->done = 1;
+    } else if (A.max_rounds > 0 && st->rounds >= A.max_rounds) {
+        st->status = NNSEMD_ERR_NOT_CONVERGED;
+        st->done = 1;
+    }
+}
+
+// ---------------------------------------------------------------- finish
+template <int D>
+__global__ __launch_bounds__(kLpScanThreads) void lp_finish(LPArgs A) {
+    __shared__ double scratch[kLpScanThreads / kWave];
+    LPState* st = A.w.st;
+    const int tid = threadIdx.x;
+    const int m = (int)A.m;
+    const bool ok = st->status == NNSEMD_OK || st->status == NNSEMD_ERR_NOT_CONVERGED;
+    const int cs = (m + kLpScanThreads - 1) / kLpScanThreads;
+    const int lo = min(tid * cs, m), hi = min(lo + cs, m);
+    double c = 0.0;
+    if (ok)
+        for (int i = lo; i < hi; ++i) c += A.w.costacc[i];
+    const double cost = lp_block_sum<kLpScanThreads>(c, scratch);
+    const int par = st->parity;
+    double rs = 0.0, rc = 0.0;
+    if (ok) {
+        for (int s = tid; s < st->mact; s += kLpScanThreads) rs += A.w.smass[par][s];
+        for (int q = tid; q < st->nact; q += kLpScanThreads) rc += A.w.cmass[A.w.cact[par][q]];
+    }
+    rs = lp_block_sum<kLpScanThreads>(rs, scratch);
+    rc = lp_block_sum<kLpScanThreads>(rc, scratch);
+    if (A.map != nullptr) {
+#pragma clang fp contract(off)
+        for (int64_t e = tid; e < (int64_t)m * D; e += kLpScanThreads) {
+            const int64_t i = e / D;
+            const double w = (ok && A.w.wsum != nullptr) ? A.w.wsum[i] : 0.0;
+            A.map[e] = w > 0.0 ? A.w.bsum[e] / w : NAN;
+        }
+    }
+    if (tid == 0) {
+        A.cost[0] = st->status == NNSEMD_OK ? cost : NAN;
+        if (A.stats != nullptr) {
+            nnsemd_stats_t out;
+            out.status = st->status;
+            out.rounds = st->rounds;
+            out.nnz = st->nnz;
+            out.work = st->work;
+            out.near_ties = st->near;
+            out.residual_src = rs;
+            out.residual_dst = rc;
+            A.stats[0] = out;
+        }
+    }
+}
+
+#define NNSEMD_LP_DISPATCH(D_, EXPR)                   \
+    switch (D_) {                                      \
+        case 1: { constexpr int DD = 1; EXPR; } break; \
+        case 2: { constexpr int DD = 2; EXPR; } break; \
+        case 3: { constexpr int DD = 3; EXPR; } break; \
+        case 4: { constexpr int DD = 4; EXPR; } break; \
+        case 5: { constexpr int DD = 5; EXPR; } break; \
+        case 6: { constexpr int DD = 6; EXPR; } break; \
+        case 7: { constexpr int DD = 7; EXPR; } break; \
+        default: return (int)hipErrorInvalidValue;     \
+    }
+
+}  // namespace
+
+int lp_launch_init(const LPArgs& A, int d, void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t pts = A.m > A.n ? A.m : A.n;
+    const int nblocks = (int)((pts + kLpThreads - 1) / kLpThreads);
+    const bool l1 = A.metric == NNSEMD_L1;
+    NNSEMD_LP_DISPATCH(d, {
+        if (nblocks > 0) hipLaunchKernelGGL(lp_ingest<DD>, dim3(nblocks), dim3(kLpThreads), 0, st, A);
+        if (l1)
+            hipLaunchKernelGGL((lp_setup<DD, true>), dim3(1), dim3(kLpScanThreads), 0, st, A, nblocks);
+        else
+            hipLaunchKernelGGL((lp_setup<DD, false>), dim3(1), dim3(kLpScanThreads), 0, st, A, nblocks);
+    })
+    return (int)hipGetLastError();
+}
+
+int lp_launch_round(const LPArgs& A, int d, int mact_ub, int nact_ub, void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    const bool l1 = A.metric == NNSEMD_L1;
+    const int kc = nact_ub > 4 * kLpThreads ? 4 : 1;
+    const int cblocks = (nact_ub + kLpThreads * kc - 1) / (kLpThreads * kc);
+    int split = (2048 + cblocks - 1) / cblocks;
+    const int max_split_by_work = mact_ub / 64 > 1 ? mact_ub / 64 : 1;
+    if (split > max_split_by_work) split = max_split_by_work;
+    if ((int64_t)split * A.w.ncap > A.w.part_cap) split = (int)(A.w.part_cap / A.w.ncap);
+    if (split < 1) split = 1;
+    const int qblocks = (nact_ub + kLpThreads - 1) / kLpThreads;
+    const int sblocks = (mact_ub + kLpThreads - 1) / kLpThreads;
+    const int cmax = mact_ub > nact_ub ? mact_ub : nact_ub;
+    const int cmblocks = (cmax + kLpCompactBlock - 1) / kLpCompactBlock;
+    if (qblocks == 0 || sblocks == 0) return 0;
+    if (cmblocks > A.w.blkcnt_cap) return (int)hipErrorInvalidValue;
+    NNSEMD_LP_DISPATCH(d, {
+        if (kc == 4) {
+            if (l1) hipLaunchKernelGGL((lp_search<DD, true, 4>), dim3(cblocks, split), dim3(kLpThreads), 0, st, A, split);
+            else hipLaunchKernelGGL((lp_search<DD, false, 4>), dim3(cblocks, split), dim3(kLpThreads), 0, st, A, split);
+        } else {
+            if (l1) hipLaunchKernelGGL((lp_search<DD, true, 1>), dim3(cblocks, split), dim3(kLpThreads), 0, st, A, split);
+            else hipLaunchKernelGGL((lp_search<DD, false, 1>), dim3(cblocks, split), dim3(kLpThreads), 0, st, A, split);
+        }
+        if (l1) {
+            hipLaunchKernelGGL((lp_decide<DD, true>), dim3(qblocks), dim3(kLpThreads), 0, st, A, split);
+            hipLaunchKernelGGL((lp_rescore<DD, true>), dim3(256), dim3(kLpThreads), 0, st, A);
+        } else {
+            hipLaunchKernelGGL((lp_decide<DD, false>), dim3(qblocks), dim3(kLpThreads), 0, st, A, split);
+            hipLaunchKernelGGL((lp_rescore<DD, false>), dim3(256), dim3(kLpThreads), 0, st, A);
+        }
+        hipLaunchKernelGGL(lp_offsets, dim3(1), dim3(kLpScanThreads), 0, st, A);
+        hipLaunchKernelGGL(lp_scatter, dim3(qblocks), dim3(kLpThreads), 0, st, A);
+        hipLaunchKernelGGL(lp_rank, dim3(qblocks), dim3(kLpThreads), 0, st, A);
+        hipLaunchKernelGGL(lp_walk<DD>, dim3(sblocks), dim3(kLpThreads), 0, st, A);
+        hipLaunchKernelGGL(lp_ccount, dim3(cmblocks), dim3(kLpThreads), 0, st, A);
+        hipLaunchKernelGGL(lp_cwrite<DD>, dim3(cmblocks), dim3(kLpThreads), 0, st, A);
+        hipLaunchKernelGGL(lp_commit, dim3(1), dim3(1), 0, st, A, cmblocks);
+    })
+    return (int)hipGetLastError();
+}
+
+int lp_launch_finish(const LPArgs& A, int d, void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    NNSEMD_LP_DISPATCH(d, { hipLaunchKernelGGL(lp_finish<DD>, dim3(1), dim3(kLpScanThreads), 0, st, A); })
+    return (int)hipGetLastError();
+}
+
+}  // namespace nnsemd

@@ -33,7 +33,7 @@ def gpu_pair(X, a, Y, b, metric="l2", plan=True, **kw):
     torch.cuda.synchronize()
     st = binding.stats_numpy(r["stats"])[0]
     out = {"cost": float(r["cost"].item()), "stats": st}
-    if plan and st["status"] == 0:
+    if plan and st["status"] in (0, -6):
         k = int(st["nnz"])
         out["src"] = r["plan_src"][:k].cpu().numpy()
         out["dst"] = r["plan_dst"][:k].cpu().numpy()
@@ -65,6 +65,25 @@ def gpu_batched(ps, plan=False, **kw):
         out["src"] = r["plan_src"].cpu().numpy()
         out["dst"] = r["plan_dst"].cpu().numpy()
         out["flow"] = r["plan_flow"].cpu().numpy()
+    return out
+
+
+def gpu_pair_map(X, a, Y, b, metric="l2", **kw):
+    """emd_approx_map on one pair: (cost, stats, plan arrays, map)."""
+    import torch
+    from paper_2401_07378_amd import binding
+    X = np.asarray(X, np.float32)
+    Y = np.asarray(Y, np.float32)
+    r = binding.emd_approx_map(to_dev(X), to_dev(np.asarray(a, np.float32)), to_dev(Y),
+                               to_dev(np.asarray(b, np.float32)), metric, **kw)
+    torch.cuda.synchronize()
+    st = binding.stats_numpy(r["stats"])[0]
+    out = {"cost": float(r["cost"].item()), "stats": st, "map": r["map"].cpu().numpy()}
+    if st["status"] in (0, -6):
+        k = int(st["nnz"])
+        out["src"] = r["plan_src"][:k].cpu().numpy()
+        out["dst"] = r["plan_dst"][:k].cpu().numpy()
+        out["flow"] = r["plan_flow"][:k].cpu().numpy()
     return out
 
 

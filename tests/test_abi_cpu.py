@@ -36,7 +36,7 @@ def test_stats_record_layout():
     # int32 status, int32 rounds, int64 nnz, work, near_ties, double x2
     assert binding.STATS_DTYPE.itemsize == 48
     assert binding.STATS_DTYPE.fields["residual_dst"][1] == 40
-    assert ctypes.sizeof(binding.Options) == 32
+    assert ctypes.sizeof(binding.Options) == 40
 
 
 def test_null_handle_is_rejected():

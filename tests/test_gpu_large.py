@@ -1,0 +1,128 @@
+"""Parity of the multi-workgroup path (one pair of any size) and of the
+barycentric transport map with the FP64 oracle.
+
+Small and medium pairs are forced onto the multi-workgroup path and compared
+in full: plan bit-identical, rounds/work/nnz equal, cost to 1e-12, map
+bit-identical to the oracle's map of its own plan.  The full 65536 x 65536
+colour-transfer pair is compared on its first rounds (the oracle stops at the
+same round cap) and checked in full on properties that hold at any size.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2401_07378_amd import workloads as W
+from tests.gpu_helpers import assert_pair_matches, gpu_pair, gpu_pair_map, oracle_pair
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    (1, 300, 280, 3, "dirichlet", "l2", "greedy"),
+    (2, 500, 700, 2, "uniform", "sqeuclidean", "greedy"),
+    (3, 700, 500, 1, "integer", "l1", "greedy"),
+    (4, 400, 400, 3, "dirichlet", "l2", "random"),
+    (5, 129, 1100, 5, "dirichlet", "l2", "greedy"),
+    (6, 1, 50, 3, "dirichlet", "l2", "greedy"),
+    (7, 50, 1, 3, "dirichlet", "l2", "greedy"),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "-".join(map(str, c[1:])))
+def test_multi_path_matches_oracle(case):
+    seed, m, n, d, masses, metric, protocol = case
+    X, a, Y, b = W.random_pair(700 + seed, m, n, d, masses=masses)
+    kw = dict(protocol=protocol, seed=99)
+    g = gpu_pair(X, a, Y, b, metric, path="multi", **kw)
+    assert_pair_matches(g, oracle_pair(X, a, Y, b, metric, **kw), label=str(case))
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_multi_path_lattice_ties(seed):
+    X, a, Y, b = W.random_pair(720 + seed, 400, 450, 2, masses="integer", lattice=7)
+    g = gpu_pair(X, a, Y, b, path="multi")
+    assert int(g["stats"]["near_ties"]) > 0
+    assert_pair_matches(g, oracle_pair(X, a, Y, b), label=f"lattice{seed}")
+
+
+def test_auto_path_routes_a_large_pair():
+    """3000 x 2600 does not fit one workgroup: emd_approx takes the
+    multi-workgroup path by itself."""
+    X, a, Y, b = W.random_pair(730, 3000, 2600, 3)
+    assert_pair_matches(gpu_pair(X, a, Y, b), oracle_pair(X, a, Y, b), label="3000x2600")
+
+
+@pytest.mark.parametrize("metric", ["l2", "sqeuclidean"])
+def test_barycentric_map_bit_identical(metric):
+    X, a, Y, b = W.random_pair(740, 350, 420, 3)
+    g = gpu_pair_map(X, a, Y, b, metric)
+    ref = oracle_pair(X, a, Y, b, metric)
+    assert_pair_matches(g, ref, label="map")
+    want = oracle.barycentric(ref["src"], ref["dst"], ref["flow"], Y, len(a))
+    got = g["map"]
+    assert np.array_equal(np.isnan(got), np.isnan(want))
+    assert np.array_equal(got[~np.isnan(got)], want[~np.isnan(want)])
+
+
+def test_barycentric_map_zero_mass_rows_are_nan():
+    X, a, Y, b = W.random_pair(741, 60, 70, 3)
+    a = a.copy()
+    a[[3, 9]] = 0
+    a = (a / a.astype(np.float64).sum()).astype(np.float32)
+    g = gpu_pair_map(X, a, Y, b)
+    assert np.all(np.isnan(g["map"][[3, 9]]))
+    assert not np.any(np.isnan(np.delete(g["map"], [3, 9], axis=0)))
+
+
+def test_multi_path_status_codes():
+    X, a, Y, b = W.random_pair(750, 40, 50, 3)
+    Xn = X.copy()
+    Xn[5, 2] = np.nan
+    assert int(gpu_pair(Xn, a, Y, b, path="multi")["stats"]["status"]) == -1
+    assert int(gpu_pair(X, a * 2, Y, b, path="multi")["stats"]["status"]) == -2
+    g = gpu_pair(X, a, Y, b, path="multi", max_rounds=2)
+    assert int(g["stats"]["status"]) == -6
+    ref = oracle_pair(X, a, Y, b, max_rounds=2)
+    assert ref["status"] == -6
+    np.testing.assert_array_equal(g["src"], ref["src"])
+    np.testing.assert_array_equal(g["flow"], ref["flow"])
+
+
+def test_multi_path_empty():
+    g = gpu_pair(np.zeros((0, 3)), np.zeros(0), np.zeros((0, 3)), np.zeros(0), path="multi")
+    assert int(g["stats"]["status"]) == 0 and g["cost"] == 0.0
+
+
+def test_colour_transfer_full_size_first_rounds():
+    """65536 x 65536 clipped Gaussian mixtures, squared Euclidean: the first
+    two rounds (about 7e9 pair evaluations) against the oracle capped at the
+    same round."""
+    ps = W.colour_transfer_3d()
+    g = gpu_pair(ps.X, ps.a, ps.Y, ps.b, "sqeuclidean", max_rounds=2)
+    ref = oracle_pair(ps.X, ps.a, ps.Y, ps.b, "sqeuclidean", max_rounds=2)
+    assert int(g["stats"]["status"]) == -6 and ref["status"] == -6
+    assert int(g["stats"]["work"]) == ref["work"]
+    assert int(g["stats"]["nnz"]) == ref["nnz"]
+    np.testing.assert_array_equal(g["src"], ref["src"])
+    np.testing.assert_array_equal(g["dst"], ref["dst"])
+    np.testing.assert_array_equal(g["flow"], ref["flow"])
+    assert float(g["stats"]["residual_src"]) == ref["residual_src"]
+
+
+def test_colour_transfer_full_size_properties():
+    """The whole 65536 x 65536 run with its map: uniform dyadic masses make
+    the plan a permutation, every point is matched, R is the sum of f * D
+    over the plan, and the map sends x_i exactly to its partner y."""
+    ps = W.colour_transfer_3d()
+    g = gpu_pair_map(ps.X, ps.a, ps.Y, ps.b, "sqeuclidean")
+    st = g["stats"]
+    n = len(ps.a)
+    assert int(st["status"]) == 0
+    assert int(st["nnz"]) == n
+    assert float(st["residual_src"]) == 0.0 and float(st["residual_dst"]) == 0.0
+    assert np.array_equal(np.sort(g["src"]), np.arange(n)) and np.array_equal(np.sort(g["dst"]), np.arange(n))
+    assert np.all(g["flow"] == 2.0 ** -16)
+    X64, Y64 = ps.X.astype(np.float64), ps.Y.astype(np.float64)
+    d2 = ((X64[g["src"]] - Y64[g["dst"]]) ** 2).sum(1)
+    assert g["cost"] == pytest.approx(float((g["flow"] * d2).sum()), rel=1e-12)
+    np.testing.assert_array_equal(g["map"][g["src"]], Y64[g["dst"]])
+    assert int(st["rounds"]) > 100 and int(st["work"]) > 10 * n * n

@@ -63,13 +63,14 @@ def test_scanner_flags_the_bad_shape():
 
 
 @pytest.mark.skipif(not shutil.which(HIPCC) and not os.path.exists(HIPCC), reason="hipcc not available")
-def test_solver_kernels_have_no_divergent_back_edge_into_a_barrier(tmp_path):
-    out = tmp_path / "pair_solver.s"
+@pytest.mark.parametrize("src", ["pair_solver.hip", "large_pair.hip"])
+def test_solver_kernels_have_no_divergent_back_edge_into_a_barrier(tmp_path, src):
+    out = tmp_path / (src + ".s")
     cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "--offload-device-only", "-S",
            "-I" + os.path.join(ROOT, "include"), "-I" + os.path.join(ROOT, "paper_2401_07378_amd", "csrc"),
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           os.path.join(ROOT, "paper_2401_07378_amd", "csrc", "pair_solver.hip"), "-o", str(out)]
+           os.path.join(ROOT, "paper_2401_07378_amd", "csrc", src), "-o", str(out)]
     subprocess.run(cmd, check=True, capture_output=True)
     asm = out.read_text()
-    assert asm.count("pair_solver_kernel") > 0
+    assert asm.count("s_barrier") > 0
     assert scan(asm) == []
