@@ -33,9 +33,11 @@ sys.path.insert(0, ROOT)
 # lane-operations per second (half the 157.3 TFLOP/s FP32 figure, which counts
 # a packed FMA as four flops; packed FP32 is not used by these kernels).
 PEAK_VALU_LANE_OPS = 256 * 64 * 2.4e9
+# Dense BF16 matrix-core peak of MI355X (2.5 PFLOP/s, no sparsity).
+PEAK_BF16_MFMA = 2.5e15
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pair_solver_batched_hist_3d_traffic.json")
 SOURCES = [os.path.join(ROOT, "paper_2401_07378_amd", "csrc", f)
-           for f in ("pair_solver.hip", "api.hip", "internal.hpp")]
+           for f in ("pair_solver.hip", "round_common.hpp", "api.hip", "internal.hpp")]
 
 
 def log(msg):
@@ -76,8 +78,9 @@ def main():
     ap.add_argument("--no-single-pair", action="store_true")
     ap.add_argument("--single-pair-sample", type=int, default=512)
     ap.add_argument("--workload", default="batched_hist_3d",
-                    choices=["batched_hist_3d", "colour_transfer_3d"],
-                    help="batched_hist_3d is the headline line; colour_transfer_3d times the 65536 x 65536 pair")
+                    choices=["batched_hist_3d", "colour_transfer_3d", "documents_300d"],
+                    help="batched_hist_3d is the headline line; colour_transfer_3d times the 65536 x 65536 "
+                         "pair; documents_300d times 8192 BF16 300-d document pairs")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -107,6 +110,8 @@ def main():
 
     if args.workload == "colour_transfer_3d":
         return bench_colour_transfer(args, dev)
+    if args.workload == "documents_300d":
+        return bench_documents(args, dev)
 
     log(f"generating workload ({args.pairs} pairs)")
     ps = W.batched_hist_3d(args.pairs)
@@ -294,6 +299,144 @@ def bench_colour_transfer(args, dev):
                                    "clipped to [0,1]^3, uniform masses, squared Euclidean, cost + barycentric map",
                        "rounds": int(st["rounds"]), "near_tie_rescored": int(st["near_ties"])},
             "roofline": roofline, "cpu_baseline": cpu}
+    print(json.dumps(line), flush=True)
+
+
+def bench_documents(args, dev):
+    """One 300-d BF16 query against 8192 ragged candidates (20..500 points,
+    Zipf(1.1) masses, L2) through the high-dimensional path: key tiles on the
+    matrix cores.  Compared on the same values with the batched FP32 vector
+    path and the plain single-pair FP32 path (one emd_approx per pair)."""
+    import numpy as np
+    import torch
+
+    from paper_2401_07378_amd import binding
+    from paper_2401_07378_amd import workloads as W
+
+    log("generating documents_300d (8192 candidates)")
+    ps = W.documents_300d()
+    P, d = ps.num_pairs, ps.d
+    m_sizes, n_sizes = ps.sizes()
+    t = lambda v: torch.from_numpy(np.ascontiguousarray(v)).to(dev)
+    bf = lambda bits: torch.from_numpy(np.ascontiguousarray(bits).view(np.int16)).view(torch.bfloat16).to(dev)
+    Xb, Yb = bf(ps.X_bits), bf(ps.Y_bits)
+    Xf, Yf = t(ps.X), t(ps.Y)
+    a, b, xo, yo, px, py = t(ps.a), t(ps.b), t(ps.x_off), t(ps.y_off), t(ps.pair_x), t(ps.pair_y)
+    plan_off_np = binding.plan_offsets(m_sizes, n_sizes)
+    want_plan = not args.no_plan
+    max_m, max_n = int(m_sizes.max()), int(n_sizes.max())
+
+    def buffers():
+        o = {"costs": torch.empty(P, dtype=torch.float64, device=dev),
+             "stats": torch.empty(P * binding.STATS_DTYPE.itemsize, dtype=torch.uint8, device=dev)}
+        if want_plan:
+            total = int(plan_off_np[-1])
+            o.update(plan_src=torch.empty(total, dtype=torch.int32, device=dev),
+                     plan_dst=torch.empty(total, dtype=torch.int32, device=dev),
+                     plan_flow=torch.empty(total, dtype=torch.float64, device=dev), plan_total=total)
+        return o
+
+    plan_off = t(plan_off_np) if want_plan else None
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(X, Y, mode, out, steps):
+        def step():
+            binding.emd_approx_batched(X, a, xo, Y, b, yo, pair_x=px, pair_y=py, max_m=max_m, max_n=max_n,
+                                       metric="l2", plan_off=plan_off, mode=mode, schedule=args.schedule,
+                                       out=out)
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    out = buffers()
+    log(f"timing {args.steps} steps (BF16 matrix-core path)")
+    ms = timed(Xb, Yb, "bf16_mfma_refine", out, args.steps)
+    value = P / (ms / 1e3)
+    log(f"{ms:.3f} ms/step, {value:.1f} pairs/s")
+    st = binding.stats_numpy(out["stats"])[:P]
+    costs = out["costs"].cpu().numpy()[:P]
+    assert np.all(st["status"] == 0), "some pair failed"
+
+    out_v = buffers()
+    vsteps = max(1, min(args.steps, 5))
+    ms_v = timed(Xf, Yf, "fp32", out_v, vsteps)
+    same_bits = bool(np.array_equal(out_v["costs"].cpu().numpy()[:P], costs))
+    log(f"batched FP32 vector path {ms_v:.3f} ms/step; identical costs: {same_bits}")
+
+    single = None
+    if not args.no_single_pair:
+        S = min(args.single_pair_sample, P)
+        views = []
+        for p in range(S):
+            xs, xe = ps.x_off[ps.pair_x[p]], ps.x_off[ps.pair_x[p] + 1]
+            ys, ye = ps.y_off[ps.pair_y[p]], ps.y_off[ps.pair_y[p] + 1]
+            views.append((Xf[xs:xe], a[xs:xe], Yf[ys:ye], b[ys:ye]))
+        outs = [{"cost": torch.empty(1, dtype=torch.float64, device=dev),
+                 "stats": torch.empty(48, dtype=torch.uint8, device=dev)} for _ in range(S)]
+        for p in range(min(S, 8)):
+            binding.emd_approx(*views[p], "l2", plan=False, out=outs[p])
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for p in range(S):
+            binding.emd_approx(*views[p], "l2", plan=False, out=outs[p])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        sms = e0.elapsed_time(e1)
+        single = {"value": S / (sms / 1e3), "unit": "pairs/s",
+                  "sample": f"first {S} pairs, FP32 values of the same BF16 points, one launch each",
+                  "speedup_batched": value / (S / (sms / 1e3))}
+        log(f"single-pair FP32 path {single['value']:.1f} pairs/s")
+
+    flops = float(2.0 * (m_sizes * n_sizes).sum() * d)
+    work = int(st["work"].sum())
+    alg_bytes = int(ps.X_bits.nbytes + ps.a.nbytes + ps.Y_bits.nbytes + ps.b.nbytes + ps.x_off.nbytes
+                    + ps.y_off.nbytes + 8 * P + P * (8 + 48)
+                    + (int(st["nnz"].sum()) * 16 if want_plan else 0))
+    roofline = {"bound": "mfma", "achieved": flops / (ms / 1e3) / 1e12, "peak": PEAK_BF16_MFMA / 1e12,
+                "unit": "TFLOP/s", "frac": flops / (ms / 1e3) / PEAK_BF16_MFMA, "traffic": None,
+                "kernel": "doc_pair_kernel<bf16, mfma, 256, 4>", "flops_per_launch": flops,
+                "work_evals": work, "algorithmic_bytes": alg_bytes,
+                "hbm_gbs_algorithmic": alg_bytes / (ms / 1e3) / 1e9}
+
+    cpu = parity = None
+    if not args.no_cpu_baseline:
+        import oracle
+        S = min(P, 1024)
+        log(f"oracle on the first {S} pairs (CPU, OpenMP over pairs)")
+        t0 = time.perf_counter()
+        ref, threads = oracle.solve_batched(ps.X, ps.a, ps.x_off, ps.Y, ps.b, ps.y_off,
+                                            pair_x=ps.pair_x[:S], pair_y=ps.pair_y[:S])
+        dt = time.perf_counter() - t0
+        cpu = {"value": S / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+               "sample": f"first {S} of the {P} pairs, cost only, FP64, {threads} OpenMP threads", "seconds": dt}
+        rc = np.array([r["cost"] for r in ref])
+        rel = np.abs(costs[:S] - rc) / np.abs(rc)
+        same = (np.array([r["rounds"] for r in ref]) == st["rounds"][:S]) & \
+               (np.array([r["work"] for r in ref]) == st["work"][:S]) & \
+               (np.array([r["nnz"] for r in ref]) == st["nnz"][:S])
+        parity = {"max_rel_err": float(rel.max()), "pairs_checked": S, "stats_identical": int(same.sum()),
+                  "near_tie_rescored_consumers": int(st["near_ties"].sum()), "tolerance": 1e-3,
+                  "fp32_vector_path_identical_costs": same_bits}
+        log(f"oracle {cpu['value']:.1f} pairs/s; max rel err {rel.max():.3g}")
+
+    line = {"metric": "EMD pairs/sec at stated rel. error vs FP64 oracle; batched/MFMA vs plain FP32",
+            "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "bf16", "data": "synthetic",
+            "config": {"workload": "documents_300d: 1 query vs 8192 candidates, sizes U{20..500}, 300-d "
+                                   "N(0,1)/sqrt(300) stored BF16, Zipf(1.1) masses, L2, cost+plan+stats",
+                       "num_pairs": P, "plan": want_plan, "seed": ps.meta["seed"],
+                       "rounds_mean": float(st["rounds"].mean())},
+            "roofline": roofline, "cpu_baseline": cpu, "single_pair_fp32": single,
+            "batched_fp32_vector": {"value": P / (ms_v / 1e3), "unit": "pairs/s", "ms_per_step": ms_v},
+            "parity": parity}
     print(json.dumps(line), flush=True)
 
 

@@ -73,10 +73,13 @@ typedef enum { NNSEMD_F32 = 0, NNSEMD_BF16 = 1 } nnsemd_dtype_t;
  * output of the counter (seed, round, consumer), see nnsemd_options_t. */
 typedef enum { NNSEMD_GREEDY = 0, NNSEMD_RANDOM = 1 } nnsemd_protocol_t;
 
-/* Arithmetic of the distance search.  FP32: FP32 keys with FP64 re-scoring
- * of near ties (exact decisions).  BF16_MFMA_REFINE (BF16 inputs, high d):
- * distance tiles ||x||^2 + ||y||^2 - 2 x.y from BF16 matrix-core products
- * with FP32 accumulation, candidate re-scoring in FP32. */
+/* Arithmetic of the distance search.  FP32 (FP32 points): FP32 keys on the
+ * vector ALUs.  BF16_MFMA_REFINE (BF16 points): the key tile
+ * ||x||^2 - 2 x.y of a pair from BF16 matrix-core products with FP32
+ * accumulation.  In both modes a consumer whose two best FP32 keys are
+ * closer than the proven FP32 error bound is re-scored in FP64 from the
+ * inputs, so every argmin and every serve order is the one of the FP64
+ * definition (ties to the smallest index) and the cost is summed in FP64. */
 typedef enum { NNSEMD_MODE_FP32 = 0, NNSEMD_MODE_BF16_MFMA_REFINE = 1 } nnsemd_mode_t;
 
 /* Order in which a batched call starts its pairs (results do not depend on
@@ -127,8 +130,14 @@ const char* nnsemd_last_error(nnsemd_handle_t h);
  * emd_approx -- NNS-EMD of one pair (Algorithm 1; problem statement Sec. II-A).
  *   X: device, m x d suppliers; a: device, m masses.
  *   Y: device, n x d consumers; b: device, n masses.
- *   d: 1..7 for the FP32 point path (dtype F32, mode FP32); any d >= 1 for
- *      the BF16 path (dtype BF16, mode BF16_MFMA_REFINE).
+ *   dtype: F32 (points are float) with mode FP32, or BF16 (points are
+ *      bfloat16 bit patterns, uint16 per coordinate) with mode
+ *      BF16_MFMA_REFINE.
+ *   d: F32 with 1 <= d <= 7 takes the low-dimensional point path (any m, n;
+ *      pairs beyond one workgroup's LDS run on the multi-workgroup path);
+ *      BF16 with any d, or F32 with d > 7, takes the high-dimensional path
+ *      (d <= 65536, m, n <= 4096, metrics L2 and SQEUCLIDEAN; the pair's
+ *      m x n FP32 key tile is kept in library-owned device scratch).
  *   opts: host, nullable (defaults above).
  *   cost: device, 1 double: R = sum f * D_ij.
  *   plan_src/plan_dst/plan_flow: device, nullable together; when given they
@@ -155,7 +164,8 @@ nnsemd_status_t emd_approx(nnsemd_handle_t h,
  * map of the plan (colour transfer, Sec. IV-D): map[i*d + k] =
  * sum_j F*_ij y_jk / sum_j F*_ij, accumulated in FP64 in plan order; rows of
  * suppliers that sent nothing are NaN.  map: device, m x d doubles.  Uses
- * the multi-workgroup path (the calling thread waits for the device).
+ * the multi-workgroup path (the calling thread waits for the device); FP32
+ * points with 1 <= d <= 7 only (else UNSUPPORTED).
  * Plan arrays may be NULL as in emd_approx.
  */
 nnsemd_status_t emd_approx_map(nnsemd_handle_t h,

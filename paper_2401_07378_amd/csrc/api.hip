@@ -21,6 +21,8 @@ struct nnsemd_handle {
     void* lp_base = nullptr;                     // multi-workgroup path workspace (device)
     size_t lp_bytes = 0;
     nnsemd::LPState* lp_host = nullptr;          // pinned copy of the round state
+    float* doc_tiles = nullptr;                  // key-tile scratch of the high-dimensional path
+    size_t doc_bytes = 0;
 };
 
 namespace {
@@ -61,6 +63,23 @@ nnsemd_options_t default_options() {
     return o;
 }
 
+// Longest-first schedule of a batch into h->order (device).
+nnsemd_status_t schedule(nnsemd_handle_t h, const int64_t* x_off, const int64_t* y_off, const int32_t* pair_x,
+                         const int32_t* pair_y, int64_t num_pairs, int64_t num_x_sets, int64_t num_y_sets,
+                         void* stream) {
+    if (h->order_cap < num_pairs) {
+        if (h->order) (void)hipFree(h->order);
+        h->order = nullptr;
+        h->order_cap = 0;
+        if (hipMalloc((void**)&h->order, sizeof(int32_t) * (size_t)num_pairs) != hipSuccess)
+            return fail(h, NNSEMD_ERR_OUT_OF_MEMORY, "schedule workspace");
+        h->order_cap = num_pairs;
+    }
+    int err = launch_order(x_off, y_off, pair_x, pair_y, num_pairs, num_x_sets, num_y_sets, h->order, stream);
+    if (err != 0) return device_fail(h, err, "schedule launch");
+    return NNSEMD_OK;
+}
+
 // Common entry for one or many pairs of low-dimensional FP32 points.
 nnsemd_status_t run_pairs(nnsemd_handle_t h, PairSolverArgs& A, int d, int64_t max_m, int64_t max_n,
                           const nnsemd_options_t& o, void* stream) {
@@ -88,19 +107,9 @@ nnsemd_status_t run_pairs(nnsemd_handle_t h, PairSolverArgs& A, int d, int64_t m
     if (blocks < 1) return fail(h, NNSEMD_ERR_UNSUPPORTED, "pair workgroup does not fit on a compute unit");
     const int64_t grid = A.num_pairs;
     if (A.x_off != nullptr && A.num_pairs > 1 && o.schedule == NNSEMD_SCHEDULE_LONGEST_FIRST) {
-        if (h->order_cap < A.num_pairs) {
-            if (h->order) (void)hipFree(h->order);
-        if (h->lp_base) (void)hipFree(h->lp_base);
-        if (h->lp_host) (void)hipHostFree(h->lp_host);
-            h->order = nullptr;
-            h->order_cap = 0;
-            if (hipMalloc((void**)&h->order, sizeof(int32_t) * (size_t)A.num_pairs) != hipSuccess)
-                return fail(h, NNSEMD_ERR_OUT_OF_MEMORY, "schedule workspace");
-            h->order_cap = A.num_pairs;
-        }
-        err = launch_order(A.x_off, A.y_off, A.pair_x, A.pair_y, A.num_pairs, A.num_x_sets, A.num_y_sets,
-                           h->order, stream);
-        if (err != 0) return device_fail(h, err, "schedule launch");
+        nnsemd_status_t s = schedule(h, A.x_off, A.y_off, A.pair_x, A.pair_y, A.num_pairs, A.num_x_sets,
+                                     A.num_y_sets, stream);
+        if (s != NNSEMD_OK) return s;
         A.order = h->order;
     }
     err = launch_pair_solver(A, d, threads, chunk, lay.total, (int)grid, stream);
@@ -200,6 +209,69 @@ nnsemd_status_t run_large(nnsemd_handle_t h, LPArgs& A, int d, void* stream) {
     return NNSEMD_OK;
 }
 
+// High-dimensional path: BF16 points on the matrix cores, or FP32 points
+// with d > 7 on the vector ALUs.  Pairs are launched in chunks whose key
+// tiles fit the scratch budget.
+constexpr size_t kDocTileBudget = (size_t)4 << 30;
+constexpr int kDocMaxSide = 4096;
+constexpr int kDocMaxDim = 65536;
+
+nnsemd_status_t run_docs(nnsemd_handle_t h, DocArgs& A, int64_t max_m, int64_t max_n, nnsemd_dtype_t dtype,
+                         const nnsemd_options_t& o, void* stream) {
+    if (A.metric == NNSEMD_L1)
+        return fail(h, NNSEMD_ERR_UNSUPPORTED, "high-dimensional path supports the L2 and squared Euclidean metrics");
+    if (A.d > kDocMaxDim) return fail(h, NNSEMD_ERR_UNSUPPORTED, "d above 65536");
+    if (o.threads != 0 && o.threads != 256)
+        return fail(h, NNSEMD_ERR_UNSUPPORTED, "high-dimensional path runs 256-thread workgroups");
+    if (max_m > kDocMaxSide || max_n > kDocMaxSide)
+        return fail(h, NNSEMD_ERR_UNSUPPORTED, "high-dimensional path supports up to 4096 points per side");
+    const int mcap = (int)std::max<int64_t>(max_m, 1), ncap = (int)std::max<int64_t>(max_n, 1);
+    const int chunk = (std::max(mcap, ncap) + 255) / 256;
+    const size_t lds = doc_lds_bytes(mcap, ncap);
+    if (lds + 8192 > h->max_lds) return fail(h, NNSEMD_ERR_UNSUPPORTED, "pair does not fit in LDS");
+    A.max_m = mcap;
+    A.max_n = ncap;
+    A.protocol = o.protocol;
+    A.seed = o.seed;
+    A.max_rounds = o.max_rounds;
+    const bool mfma = dtype == NNSEMD_BF16;
+    int blocks = 0;
+    int err = launch_doc_solver(A, mfma, chunk, lds, 0, stream, &blocks);
+    if (err != 0) return device_fail(h, err, "occupancy query");
+    if (blocks < 1) return fail(h, NNSEMD_ERR_UNSUPPORTED, "pair workgroup does not fit on a compute unit");
+    const int64_t stride = align_up((size_t)mcap * (size_t)ncap, 64);
+    const int64_t per_launch =
+        std::max<int64_t>(1, std::min<int64_t>(A.num_pairs, (int64_t)(kDocTileBudget / (sizeof(float) * stride))));
+    const size_t need = sizeof(float) * (size_t)stride * (size_t)per_launch;
+    if (h->doc_bytes < need) {
+        if (h->doc_tiles) (void)hipFree(h->doc_tiles);
+        h->doc_tiles = nullptr;
+        h->doc_bytes = 0;
+        if (hipMalloc((void**)&h->doc_tiles, need) != hipSuccess)
+            return fail(h, NNSEMD_ERR_OUT_OF_MEMORY, "key-tile scratch");
+        h->doc_bytes = need;
+    }
+    A.tiles = h->doc_tiles;
+    A.tile_stride = stride;
+    if (A.x_off != nullptr && A.num_pairs > 1 && o.schedule == NNSEMD_SCHEDULE_LONGEST_FIRST) {
+        nnsemd_status_t s = schedule(h, A.x_off, A.y_off, A.pair_x, A.pair_y, A.num_pairs, A.num_x_sets,
+                                     A.num_y_sets, stream);
+        if (s != NNSEMD_OK) return s;
+        A.order = h->order;
+    }
+    for (int64_t base = 0; base < A.num_pairs; base += per_launch) {
+        A.pair_base = base;
+        const int grid = (int)std::min<int64_t>(per_launch, A.num_pairs - base);
+        err = launch_doc_solver(A, mfma, chunk, lds, grid, stream, nullptr);
+        if (err != 0) return device_fail(h, err, "high-dimensional solver launch");
+    }
+    return NNSEMD_OK;
+}
+
+// FP32 points with d <= 7 take the point path; BF16 points (matrix-core
+// mode) and FP32 points with d > 7 take the high-dimensional path.
+bool use_doc_path(int32_t d, nnsemd_dtype_t dtype) { return dtype == NNSEMD_BF16 || d > 7; }
+
 nnsemd_status_t check_common(nnsemd_handle_t h, int32_t d, nnsemd_dtype_t dtype, nnsemd_metric_t metric,
                              const nnsemd_options_t& o) {
     if (d < 1) return fail(h, NNSEMD_ERR_INVALID_ARG, "d must be >= 1");
@@ -217,8 +289,8 @@ nnsemd_status_t check_common(nnsemd_handle_t h, int32_t d, nnsemd_dtype_t dtype,
         return fail(h, NNSEMD_ERR_INVALID_ARG, "bad mode");
     if (o.mode == NNSEMD_MODE_FP32 && dtype != NNSEMD_F32)
         return fail(h, NNSEMD_ERR_UNSUPPORTED, "FP32 mode takes FP32 points");
-    if (o.mode == NNSEMD_MODE_BF16_MFMA_REFINE)
-        return fail(h, NNSEMD_ERR_UNSUPPORTED, "BF16 matrix-core mode is not available in this build");
+    if (o.mode == NNSEMD_MODE_BF16_MFMA_REFINE && dtype != NNSEMD_BF16)
+        return fail(h, NNSEMD_ERR_UNSUPPORTED, "BF16 matrix-core mode takes BF16 points");
     return NNSEMD_OK;
 }
 
@@ -259,6 +331,7 @@ nnsemd_status_t nnsemd_destroy(nnsemd_handle_t h) {
         if (h->order) (void)hipFree(h->order);
         if (h->lp_base) (void)hipFree(h->lp_base);
         if (h->lp_host) (void)hipHostFree(h->lp_host);
+        if (h->doc_tiles) (void)hipFree(h->doc_tiles);
     }
     delete h;
     return NNSEMD_OK;
@@ -300,6 +373,27 @@ nnsemd_status_t emd_approx(nnsemd_handle_t h, const void* X, const float* a, int
     if (plan && m + n > 0 && plan_capacity < m + n - 1)
         return fail(h, NNSEMD_ERR_CAPACITY, "plan capacity below m + n - 1");
     DeviceGuard g(h->device);
+    if (use_doc_path(d, dtype)) {
+        if (o.path == NNSEMD_PATH_MULTI)
+            return fail(h, NNSEMD_ERR_UNSUPPORTED, "multi-workgroup path supports FP32 points with d <= 7");
+        DocArgs A{};
+        A.num_pairs = 1;
+        A.X = X;
+        A.a = a;
+        A.Y = Y;
+        A.b = b;
+        A.single_m = m;
+        A.single_n = n;
+        A.d = d;
+        A.metric = metric;
+        A.costs = cost;
+        A.plan_src = plan ? plan_src : nullptr;
+        A.plan_dst = plan ? plan_dst : nullptr;
+        A.plan_flow = plan ? plan_flow : nullptr;
+        A.single_plan_cap = plan_capacity;
+        A.stats = stats;
+        return run_docs(h, A, m, n, dtype, o, stream);
+    }
     bool multi = o.path == NNSEMD_PATH_MULTI;
     if (o.path == NNSEMD_PATH_AUTO) {
         const int threads = o.threads > 0 ? o.threads : 256;
@@ -365,6 +459,8 @@ nnsemd_status_t emd_approx_map(nnsemd_handle_t h, const void* X, const float* a,
         return fail(h, NNSEMD_ERR_INVALID_ARG, "plan arrays must be all given or all NULL");
     if (plan && m + n > 0 && plan_capacity < m + n - 1)
         return fail(h, NNSEMD_ERR_CAPACITY, "plan capacity below m + n - 1");
+    if (use_doc_path(d, dtype))
+        return fail(h, NNSEMD_ERR_UNSUPPORTED, "the transport map is computed for FP32 points with d <= 7");
     DeviceGuard g(h->device);
     LPArgs L{};
     L.m = m;
@@ -414,6 +510,29 @@ nnsemd_status_t emd_approx_batched(nnsemd_handle_t h, int64_t num_pairs, const v
     if (num_pairs > 0x7fffffffLL - (1LL << 20))
         return fail(h, NNSEMD_ERR_UNSUPPORTED, "too many pairs for one call");
     DeviceGuard g(h->device);
+    if (use_doc_path(d, dtype)) {
+        DocArgs A{};
+        A.num_pairs = num_pairs;
+        A.X = Xcat;
+        A.a = acat;
+        A.x_off = x_off;
+        A.num_x_sets = num_x_sets;
+        A.Y = Ycat;
+        A.b = bcat;
+        A.y_off = y_off;
+        A.num_y_sets = num_y_sets;
+        A.pair_x = pair_x;
+        A.pair_y = pair_y;
+        A.d = d;
+        A.metric = metric;
+        A.costs = costs;
+        A.plan_src = plan ? plan_src : nullptr;
+        A.plan_dst = plan ? plan_dst : nullptr;
+        A.plan_flow = plan ? plan_flow : nullptr;
+        A.plan_off = plan ? plan_off : nullptr;
+        A.stats = stats;
+        return run_docs(h, A, max_m, max_n, dtype, o, stream);
+    }
     PairSolverArgs A{};
     A.num_pairs = num_pairs;
     A.X = static_cast<const float*>(Xcat);

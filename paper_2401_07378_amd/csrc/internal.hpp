@@ -133,6 +133,49 @@ int lp_launch_init(const LPArgs& A, int d, void* stream);
 int lp_launch_round(const LPArgs& A, int d, int mact_ub, int nact_ub, void* stream);
 int lp_launch_finish(const LPArgs& A, int d, void* stream);
 
+// ---------------------------------------------------------------------
+// High-dimensional path (doc_solver.hip): one workgroup per pair, the key
+// tile of the pair in a per-workgroup global scratch slot.
+struct DocArgs {
+    int64_t num_pairs;
+    const void* X;  // BF16 bits (uint16) or FP32, row-major, d per point
+    const float* a;
+    const int64_t* x_off;  // nullptr: single pair of single_m rows
+    int64_t num_x_sets;
+    const void* Y;
+    const float* b;
+    const int64_t* y_off;
+    int64_t num_y_sets;
+    const int32_t* pair_x;
+    const int32_t* pair_y;
+    int64_t single_m;
+    int64_t single_n;
+    int32_t max_m;
+    int32_t max_n;
+    int32_t d;
+    int32_t metric;
+    int32_t protocol;
+    int32_t pad;
+    uint64_t seed;
+    int64_t max_rounds;
+    double* costs;
+    int32_t* plan_src;
+    int32_t* plan_dst;
+    double* plan_flow;
+    const int64_t* plan_off;
+    int64_t single_plan_cap;
+    nnsemd_stats_t* stats;
+    const int32_t* order;  // nullable: workgroup b solves pair order[pair_base + b]
+    int64_t pair_base;     // first schedule position of this launch
+    float* tiles;          // grid * tile_stride floats of key-tile scratch
+    int64_t tile_stride;   // >= max_m * max_n
+};
+
+size_t doc_lds_bytes(int max_m, int max_n);
+// blocks == nullptr: launch; else query resident workgroups per CU.
+int launch_doc_solver(const DocArgs& A, bool bf16_mfma, int chunk_max, size_t lds, int grid, void* stream,
+                      int* blocks);
+
 // Launch entry points (defined in pair_solver.hip).
 // Returns hipSuccess-compatible int (0 on success).
 int launch_pair_solver(const PairSolverArgs& args, int d, int threads, int chunk_max,

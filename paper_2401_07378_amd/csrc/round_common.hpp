@@ -1,0 +1,319 @@
+// Pieces shared by the one-workgroup-per-pair solvers (point path and the
+// BF16 document path): LDS layout of a pair, workgroup scans and reductions,
+// and the generic phases of one round of Algorithm 1 (Sec. III-A) that run
+// after the search has stored every active consumer's pick (active supplier
+// slot in cnn[j], exact FP64 key in ckey[j]) and counted it into scnt[slot]:
+//   round_buckets  claimant sets a_i: scan of the counts, scatter
+//   round_rank     each claimant's place in its bucket: (D_ij, j) order for
+//                  the greedy protocol, (random key, j) for the random one
+//   round_walk     one lane per claimed supplier serves in that order (FP64)
+//   round_compact  plan append + surviving suppliers / consumers
+// Every function ends with a workgroup barrier; all of them must be called
+// by every thread of the workgroup with block-uniform arguments.
+#pragma once
+
+#include <stdint.h>
+
+#include "internal.hpp"
+
+namespace nnsemd {
+namespace rc {
+
+constexpr int kWave = 64;
+
+struct Lds {
+    double* smass;  // [M] supplier mass (by local index while loading, then by active slot)
+    double* cmass;  // [N] consumer mass by local index
+    double* ckey;   // [N] FP64 key of (pick, j); after the serve: flow (0 = unserved)
+    float* srec;    // [M * RS] active supplier records, compacted
+    int32_t* sidx;  // [M] local index of active supplier slot
+    int32_t* scnt;  // [M] claimant count by active slot
+    int32_t* soff;  // [M] bucket start, then bucket end, by active slot
+    int32_t* cact;  // [N] active consumers, compacted, ascending
+    int32_t* cnn;   // [N] pick (active slot) by consumer; after the serve: supplier local index
+    int32_t* list;    // [N] near-tie consumers during the search; claimant buckets after
+    int32_t* sorted;  // [N] claimant buckets in serve order
+};
+
+struct Shared {
+    double red[16][24];
+    unsigned long long scan[16];
+    int32_t nflag;
+    int32_t pad;
+};
+
+__device__ inline Lds carve(char* base, int M, int N, int rs) {
+    PairLdsLayout L = pair_lds_layout(M, N, rs);
+    Lds s;
+    s.smass = reinterpret_cast<double*>(base + L.smass);
+    s.cmass = reinterpret_cast<double*>(base + L.cmass);
+    s.ckey = reinterpret_cast<double*>(base + L.ckey);
+    s.srec = reinterpret_cast<float*>(base + L.srec);
+    s.sidx = reinterpret_cast<int32_t*>(base + L.sidx);
+    s.scnt = reinterpret_cast<int32_t*>(base + L.scnt);
+    s.soff = reinterpret_cast<int32_t*>(base + L.soff);
+    s.cact = reinterpret_cast<int32_t*>(base + L.cact);
+    s.cnn = reinterpret_cast<int32_t*>(base + L.cnn);
+    s.list = reinterpret_cast<int32_t*>(base + L.list);
+    s.sorted = reinterpret_cast<int32_t*>(base + L.sorted);
+    return s;
+}
+
+__device__ inline double dist_of_key(double key, int metric) {
+    return metric == NNSEMD_L2 ? sqrt(key) : key;
+}
+
+// SplitMix64 output function of the counter (seed, round, consumer): the
+// random protocol's serve order key.
+__device__ inline uint64_t rp_key(uint64_t seed, int64_t round, int32_t j) {
+    uint64_t ctr = ((uint64_t)round << 32) ^ (uint64_t)(uint32_t)j;
+    uint64_t z = seed + (ctr + 1u) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Exclusive block scan of one 64-bit value per thread; *total = block sum.
+template <int T>
+__device__ inline unsigned long long block_scan_u64(unsigned long long v, unsigned long long* total,
+                                                    Shared& sh) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    unsigned long long x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        unsigned long long y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == kWave - 1) sh.scan[w] = x;
+    __syncthreads();
+    unsigned long long off = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < T / kWave; ++k) {
+        unsigned long long s = sh.scan[k];
+        off += (k < w) ? s : 0ull;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + x - v;
+}
+
+// Block-wide reduction of K values per thread (op 0 = sum, 1 = min, 2 = max),
+// deterministic (fixed butterfly + fixed wave order).  Results in out[].
+template <int T, int K>
+__device__ inline void block_reduce(double (&v)[K], const int (&op)[K], Shared& sh) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) {
+            double y = __shfl_xor(v[k], o);
+            v[k] = op[k] == 0 ? v[k] + y : (op[k] == 1 ? fmin(v[k], y) : fmax(v[k], y));
+        }
+        if (lane == 0) sh.red[w][k] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double r = sh.red[0][k];
+#pragma unroll
+        for (int q = 1; q < T / kWave; ++q) {
+            double y = sh.red[q][k];
+            r = op[k] == 0 ? r + y : (op[k] == 1 ? fmin(r, y) : fmax(r, y));
+        }
+        v[k] = r;
+    }
+    __syncthreads();
+}
+
+// FP32 search key of record `rec` for consumer y (see file comment).
+template <int RS>
+__device__ inline void load_rec(const float* __restrict__ base, int s, float (&r)[RS]) {
+    const float4* p = reinterpret_cast<const float4*>(base + (size_t)s * RS);
+#pragma unroll
+    for (int q = 0; q < RS / 4; ++q) {
+        float4 v = p[q];
+        r[4 * q + 0] = v.x;
+        r[4 * q + 1] = v.y;
+        r[4 * q + 2] = v.z;
+        r[4 * q + 3] = v.w;
+    }
+}
+
+template <int RS>
+__device__ inline void store_rec(float* __restrict__ base, int s, const float (&r)[RS]) {
+    float4* p = reinterpret_cast<float4*>(base + (size_t)s * RS);
+#pragma unroll
+    for (int q = 0; q < RS / 4; ++q)
+        p[q] = make_float4(r[4 * q + 0], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]);
+}
+
+
+// ---- claimant sets a_i: scan the counts, scatter the claimants
+template <int T>
+__device__ inline void round_buckets(const Lds& L, Shared& sh, int mact, int nact) {
+    const int tid = threadIdx.x;
+    {
+        const int cs = (mact + T - 1) / T;
+        const int lo = min(tid * cs, mact), hi = min(lo + cs, mact);
+        int sum = 0;
+        for (int s = lo; s < hi; ++s) sum += L.scnt[s];
+        unsigned long long tot;
+        int run = (int)block_scan_u64<T>((unsigned long long)sum, &tot, sh);
+        for (int s = lo; s < hi; ++s) {
+            L.soff[s] = run;
+            run += L.scnt[s];
+        }
+    }
+    __syncthreads();
+    for (int q = tid; q < nact; q += T) {
+        const int j = L.cact[q];
+        const int pos = atomicAdd(&L.soff[L.cnn[j]], 1);
+        L.list[pos] = j;
+    }
+    __syncthreads();
+}
+
+// ---- claimant order: each claimant counts the bucket members that precede
+// it and writes itself to that rank; no dependent chains.
+template <int T>
+__device__ inline void round_rank(const Lds& L, int nact, int protocol, uint64_t seed, int rounds) {
+    for (int q = threadIdx.x; q < nact; q += T) {
+        const int j = L.cact[q];
+        const int sl = L.cnn[j];
+        const int c = L.scnt[sl];
+        const int end = L.soff[sl];
+        const int start = end - c;
+        int rank = 0;
+        if (c > 1) {
+            if (protocol == NNSEMD_GREEDY) {
+                const double k = L.ckey[j];
+                for (int e = start; e < end; ++e) {
+                    const int j2 = L.list[e];
+                    const double k2 = L.ckey[j2];
+                    rank += (k2 < k) || (k2 == k && j2 < j);
+                }
+            } else {
+                const uint64_t k = rp_key(seed, rounds, j);
+                for (int e = start; e < end; ++e) {
+                    const int j2 = L.list[e];
+                    const uint64_t k2 = rp_key(seed, rounds, j2);
+                    rank += (k2 < k) || (k2 == k && j2 < j);
+                }
+            }
+        }
+        L.sorted[start + rank] = j;
+    }
+    __syncthreads();
+}
+
+// ---- flow & cost: one lane per claimed supplier walks its ordered
+// claimants while it still holds mass.  A served claimant records the local
+// index of its supplier (for the plan) and its flow in place of its key; an
+// unserved one gets flow 0.  `cost` is this thread's part of R.
+template <int T>
+__device__ inline void round_walk(const Lds& L, int mact, int metric, double& cost) {
+    for (int s = threadIdx.x; s < mact; s += T) {
+        const int c = L.scnt[s];
+        if (c == 0) continue;
+        const int end = L.soff[s];
+        const int isup = L.sidx[s];
+        int pos = end - c;
+        double sm = L.smass[s];
+        while (pos < end && sm > 0.0) {
+            const int j = L.sorted[pos];
+            const double cm = L.cmass[j];
+            const double f = sm < cm ? sm : cm;
+            sm = sm - f;
+            L.cmass[j] = cm - f;
+            cost = cost + f * dist_of_key(L.ckey[j], metric);
+            L.ckey[j] = f;
+            L.cnn[j] = isup;
+            ++pos;
+        }
+        for (int e = pos; e < end; ++e) L.ckey[L.sorted[e]] = 0.0;
+        L.smass[s] = sm;
+    }
+    __syncthreads();
+}
+
+// ---- weights update: plan append + compaction of the active sets (and of
+// the RS-float search records when RS > 0), one scan for all three streams.
+template <int T, int CSMAX, int RS>
+__device__ inline void round_compact(const Lds& L, Shared& sh, int& mact, int& nact, int64_t& nnz,
+                                     int32_t* plan_src, int32_t* plan_dst, double* plan_flow, int64_t plan_base) {
+    constexpr int RSA = RS > 0 ? RS : 4;
+    const int tid = threadIdx.x;
+    const int pc = (nact + T - 1) / T;
+    const int plo = min(tid * pc, nact), phi = min(plo + pc, nact);
+    int kp = 0;
+    for (int k = plo; k < phi; ++k) kp += L.ckey[L.sorted[k]] > 0.0;
+    const int cs = (mact + T - 1) / T;
+    const int slo = min(tid * cs, mact);
+    float rec[CSMAX][RSA];
+    double smv[CSMAX];
+    int sid[CSMAX], cid[CSMAX];
+    int ks = 0, kc2 = 0;
+#pragma unroll
+    for (int u = 0; u < CSMAX; ++u) {
+        const int s = slo + u;
+        sid[u] = -1;
+        smv[u] = 0.0;
+        if (u < cs && s < mact) {
+            smv[u] = L.smass[s];
+            if (smv[u] > 0.0) {
+                sid[u] = L.sidx[s];
+                if constexpr (RS > 0) load_rec<RS>(L.srec, s, rec[u]);
+                ++ks;
+            }
+        }
+        const int q = plo + u;
+        cid[u] = -1;
+        if (u < pc && q < nact) {
+            const int j = L.cact[q];
+            if (L.cmass[j] > 0.0) {
+                cid[u] = j;
+                ++kc2;
+            }
+        }
+    }
+    unsigned long long tot;
+    const unsigned long long pre = block_scan_u64<T>(
+        (unsigned long long)kp | ((unsigned long long)ks << 21) | ((unsigned long long)kc2 << 42), &tot, sh);
+    const unsigned long long mask = (1ull << 21) - 1;
+    int wp = (int)(pre & mask), ws = (int)((pre >> 21) & mask), wc = (int)(pre >> 42);
+    if (plan_src != nullptr) {
+        for (int k = plo; k < phi; ++k) {
+            const int j = L.sorted[k];
+            const double f = L.ckey[j];
+            if (f > 0.0) {
+                const int64_t e = plan_base + nnz + wp;
+                plan_src[e] = L.cnn[j];
+                plan_dst[e] = j;
+                plan_flow[e] = f;
+                ++wp;
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < CSMAX; ++u) {
+        if (sid[u] >= 0) {
+            if constexpr (RS > 0) store_rec<RS>(L.srec, ws, rec[u]);
+            L.sidx[ws] = sid[u];
+            L.smass[ws] = smv[u];
+            L.scnt[ws] = 0;
+            ++ws;
+        }
+        if (cid[u] >= 0) L.cact[wc++] = cid[u];
+    }
+    nnz += (int64_t)(tot & mask);
+    mact = (int)((tot >> 21) & mask);
+    nact = (int)(tot >> 42);
+    if (tid == 0) sh.nflag = 0;
+    __syncthreads();
+}
+
+}  // namespace rc
+}  // namespace nnsemd

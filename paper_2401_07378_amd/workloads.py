@@ -258,3 +258,24 @@ def random_pair(seed: int, m: int, n: int, d: int, masses: str = "dirichlet",
     else:
         a, b = dirichlet_masses(r, m), dirichlet_masses(r, n)
     return X, a, Y, b
+
+
+def random_doc_pair(seed: int, m: int, n: int, d: int, masses: str = "zipf", lattice: int = 0) -> tuple:
+    """Small seeded high-dimensional pair for tests, as BF16 bits:
+    (X_bits m x d, a, Y_bits n x d, b).  Coordinates N(0,1)/sqrt(d) rounded
+    to BF16, or integers in [0, lattice) (exact in BF16 up to 256, so ties
+    are real).  masses: 'zipf', 'dirichlet' or 'uniform'."""
+    r = rng_for(seed, 0)
+    if lattice > 0:
+        X = f32_to_bf16_bits(to_f32(r.integers(0, lattice, size=(m, d))))
+        Y = f32_to_bf16_bits(to_f32(r.integers(0, lattice, size=(n, d))))
+    else:
+        X = f32_to_bf16_bits(to_f32(r.standard_normal((m, d)) / np.sqrt(d)))
+        Y = f32_to_bf16_bits(to_f32(r.standard_normal((n, d)) / np.sqrt(d)))
+    if masses == "uniform":
+        a, b = uniform_masses(m), uniform_masses(n)
+    elif masses == "dirichlet":
+        a, b = dirichlet_masses(r, m), dirichlet_masses(r, n)
+    else:
+        a, b = zipf_masses(r, m), zipf_masses(r, n)
+    return X.reshape(m, d), a, Y.reshape(n, d), b

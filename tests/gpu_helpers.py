@@ -18,6 +18,35 @@ def to_dev(x, dtype=None):
     return t.to(dev())
 
 
+def to_dev_bf16(bits):
+    """uint16 BF16 bit patterns -> torch.bfloat16 device tensor (same bits)."""
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(bits, dtype=np.uint16).view(np.int16)).view(torch.bfloat16)
+    return t.to(dev())
+
+
+def gpu_pair_bf16(Xbits, a, Ybits, b, metric="l2", plan=True, **kw):
+    """emd_approx on BF16 points (matrix-core mode)."""
+    import torch
+    from paper_2401_07378_amd import binding
+    r = binding.emd_approx(to_dev_bf16(Xbits), to_dev(np.asarray(a, np.float32)), to_dev_bf16(Ybits),
+                           to_dev(np.asarray(b, np.float32)), metric, plan=plan, mode="bf16_mfma_refine", **kw)
+    torch.cuda.synchronize()
+    return _collect(r, plan)
+
+
+def _collect(r, plan):
+    from paper_2401_07378_amd import binding
+    st = binding.stats_numpy(r["stats"])[0]
+    out = {"cost": float(r["cost"].item()), "stats": st}
+    if plan and st["status"] in (0, -6):
+        k = int(st["nnz"])
+        out["src"] = r["plan_src"][:k].cpu().numpy()
+        out["dst"] = r["plan_dst"][:k].cpu().numpy()
+        out["flow"] = r["plan_flow"][:k].cpu().numpy()
+    return out
+
+
 def gpu_pair(X, a, Y, b, metric="l2", plan=True, **kw):
     """Run emd_approx on one pair; returns (cost, stats record, plan arrays)."""
     import torch
@@ -31,14 +60,7 @@ def gpu_pair(X, a, Y, b, metric="l2", plan=True, **kw):
     r = binding.emd_approx(to_dev(X), to_dev(np.asarray(a, np.float32)), to_dev(Y),
                            to_dev(np.asarray(b, np.float32)), metric, plan=plan, **kw)
     torch.cuda.synchronize()
-    st = binding.stats_numpy(r["stats"])[0]
-    out = {"cost": float(r["cost"].item()), "stats": st}
-    if plan and st["status"] in (0, -6):
-        k = int(st["nnz"])
-        out["src"] = r["plan_src"][:k].cpu().numpy()
-        out["dst"] = r["plan_dst"][:k].cpu().numpy()
-        out["flow"] = r["plan_flow"][:k].cpu().numpy()
-    return out
+    return _collect(r, plan)
 
 
 def gpu_batched(ps, plan=False, **kw):
@@ -54,7 +76,11 @@ def gpu_batched(ps, plan=False, **kw):
     if plan:
         poff_np = binding.plan_offsets(m_sizes, n_sizes)
         poff = to_dev(poff_np)
-    r = binding.emd_approx_batched(to_dev(ps.X), to_dev(ps.a), to_dev(ps.x_off), to_dev(ps.Y),
+    if kw.get("mode") == "bf16_mfma_refine":
+        Xd, Yd = to_dev_bf16(ps.X_bits), to_dev_bf16(ps.Y_bits)
+    else:
+        Xd, Yd = to_dev(ps.X), to_dev(ps.Y)
+    r = binding.emd_approx_batched(Xd, to_dev(ps.a), to_dev(ps.x_off), Yd,
                                    to_dev(ps.b), to_dev(ps.y_off), pair_x=px, pair_y=py,
                                    num_pairs=ps.num_pairs, plan_off=poff, **args, **kw)
     torch.cuda.synchronize()

@@ -1,0 +1,172 @@
+"""Parity of the high-dimensional path with the FP64 oracle.
+
+BF16 points run the key tile on the matrix cores (FP32 accumulation); FP32
+points with d > 7 run it on the vector ALUs.  Both re-score near ties in FP64,
+so the plan must be bit-identical to the oracle's on the same values (the
+oracle receives the exact FP32 values of the BF16 numbers) and the cost equal
+to 1e-12 relative -- far inside the 1e-3 allowed for BF16 matrix-core mode.
+The full 8192-candidate document workload is checked on sampled pairs against
+the oracle and, on every pair, against the FP32 vector path, which must give
+the same bits (both take the exact decisions, with the same FP64 summation).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2401_07378_amd import workloads as W
+from tests.gpu_helpers import assert_pair_matches, gpu_batched, gpu_pair, gpu_pair_bf16, oracle_pair
+
+pytestmark = pytest.mark.gpu
+
+f32 = W.bf16_bits_to_f32
+
+CASES = [
+    # seed, m, n, d, masses, metric, protocol
+    (1, 40, 60, 300, "zipf", "l2", "greedy"),
+    (2, 500, 500, 300, "zipf", "l2", "greedy"),
+    (3, 20, 500, 300, "zipf", "l2", "greedy"),
+    (4, 500, 20, 300, "zipf", "l2", "greedy"),
+    (5, 1, 77, 300, "zipf", "l2", "greedy"),
+    (6, 77, 1, 300, "zipf", "l2", "greedy"),
+    (7, 130, 170, 33, "dirichlet", "l2", "greedy"),
+    (8, 64, 64, 8, "uniform", "sqeuclidean", "greedy"),
+    (9, 100, 90, 1, "dirichlet", "l2", "greedy"),
+    (10, 257, 129, 300, "dirichlet", "sqeuclidean", "random"),
+    (11, 96, 96, 1024, "zipf", "l2", "greedy"),
+    (12, 700, 650, 50, "zipf", "l2", "greedy"),
+]
+
+
+def _ids(c):
+    return "-".join(map(str, c[1:]))
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_bf16_matrix_core_pair_matches_oracle(case):
+    seed, m, n, d, masses, metric, protocol = case
+    Xb, a, Yb, b = W.random_doc_pair(800 + seed, m, n, d, masses=masses)
+    kw = dict(protocol=protocol, seed=5)
+    g = gpu_pair_bf16(Xb, a, Yb, b, metric, **kw)
+    assert_pair_matches(g, oracle_pair(f32(Xb), a, f32(Yb), b, metric, **kw), label=str(case))
+
+
+@pytest.mark.parametrize("case", CASES[:8] + CASES[9:], ids=_ids)
+def test_fp32_high_dim_pair_matches_oracle(case):
+    seed, m, n, d, masses, metric, protocol = case
+    d = max(d, 8)  # d <= 7 is the point path
+    r = W.rng_for(850 + seed, 0)
+    X = W.to_f32(r.standard_normal((m, d)) / np.sqrt(d))
+    Y = W.to_f32(r.standard_normal((n, d)) / np.sqrt(d))
+    _, a, _, b = W.random_doc_pair(850 + seed, m, n, 1, masses=masses)
+    kw = dict(protocol=protocol, seed=5)
+    g = gpu_pair(X, a, Y, b, metric, **kw)
+    assert_pair_matches(g, oracle_pair(X, a, Y, b, metric, **kw), label=str(case))
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_bf16_lattice_ties_are_rescored(seed):
+    """Integer coordinates make exact key ties: every one must resolve to the
+    smallest supplier index, as in the oracle."""
+    Xb, a, Yb, b = W.random_doc_pair(870 + seed, 150, 180, 40, masses="uniform", lattice=3)
+    g = gpu_pair_bf16(Xb, a, Yb, b)
+    assert int(g["stats"]["near_ties"]) > 0
+    assert_pair_matches(g, oracle_pair(f32(Xb), a, f32(Yb), b), label=f"lattice{seed}")
+
+
+def test_bf16_zero_mass_points_and_status_codes():
+    Xb, a, Yb, b = W.random_doc_pair(880, 60, 70, 300)
+    a = a.copy()
+    a[[0, 7]] = 0
+    a = (a / a.astype(np.float64).sum()).astype(np.float32)
+    assert_pair_matches(gpu_pair_bf16(Xb, a, Yb, b), oracle_pair(f32(Xb), a, f32(Yb), b), label="zero mass")
+    Xn = Xb.copy()
+    Xn[3, 100] = 0x7FC0  # NaN
+    assert int(gpu_pair_bf16(Xn, a, Yb, b)["stats"]["status"]) == -1
+    Xi = Xb.copy()
+    Xi[3, 100] = 0x7F80  # +inf
+    assert int(gpu_pair_bf16(Xi, a, Yb, b)["stats"]["status"]) == -1
+    neg = a.copy()
+    neg[2] = -neg[2]
+    assert int(gpu_pair_bf16(Xb, neg, Yb, b)["stats"]["status"]) == -1
+    assert int(gpu_pair_bf16(Xb, a * 2, Yb, b)["stats"]["status"]) == -2
+    g = gpu_pair_bf16(Xb, a, Yb, b, max_rounds=2)
+    ref = oracle_pair(f32(Xb), a, f32(Yb), b, max_rounds=2)
+    assert int(g["stats"]["status"]) == -6 and ref["status"] == -6
+    np.testing.assert_array_equal(g["src"], ref["src"])
+    np.testing.assert_array_equal(g["dst"], ref["dst"])
+    np.testing.assert_array_equal(g["flow"], ref["flow"])
+
+
+def test_bf16_empty_sides():
+    z = np.zeros((0, 300), np.uint16)
+    Xb, a, Yb, b = W.random_doc_pair(881, 5, 5, 300)
+    g = gpu_pair_bf16(z, np.zeros(0, np.float32), z, np.zeros(0, np.float32))
+    assert int(g["stats"]["status"]) == 0 and g["cost"] == 0.0
+    g = gpu_pair_bf16(Xb, a, z, np.zeros(0, np.float32))
+    assert int(g["stats"]["status"]) == -2
+
+
+def test_unsupported_combinations_raise():
+    import torch
+    from paper_2401_07378_amd import binding
+    from tests.gpu_helpers import to_dev, to_dev_bf16
+    Xb, a, Yb, b = W.random_doc_pair(882, 10, 10, 300)
+    with pytest.raises(binding.NNSEMDError) as e:
+        binding.emd_approx(to_dev_bf16(Xb), to_dev(a), to_dev_bf16(Yb), to_dev(b), "l1", mode="bf16_mfma_refine")
+    assert e.value.status == -7
+    Xb, a, Yb, b = W.random_doc_pair(883, 4097, 3, 16)
+    with pytest.raises(binding.NNSEMDError) as e:
+        binding.emd_approx(to_dev_bf16(Xb), to_dev(a), to_dev_bf16(Yb), to_dev(b), mode="bf16_mfma_refine")
+    assert e.value.status == -7
+    torch.cuda.synchronize()
+
+
+def _small_docs(num, seed=890):
+    return W.documents_300d(num_candidates=num, seed=seed)
+
+
+@pytest.mark.parametrize("mode", ["bf16_mfma_refine", "fp32"])
+def test_document_batch_matches_oracle(mode):
+    """One query against 48 ragged candidates, plans included."""
+    ps = _small_docs(48)
+    g = gpu_batched(ps, plan=True, mode=mode)
+    m_sizes, n_sizes = ps.sizes()
+    for p in range(ps.num_pairs):
+        X, a, Y, b = ps.pair(p)
+        ref = oracle_pair(X, a, Y, b)
+        lo = g["plan_off"][p]
+        k = int(g["stats"][p]["nnz"])
+        gp = {"cost": float(g["costs"][p]), "stats": g["stats"][p], "src": g["src"][lo:lo + k],
+              "dst": g["dst"][lo:lo + k], "flow": g["flow"][lo:lo + k]}
+        assert_pair_matches(gp, ref, label=f"pair{p}")
+
+
+def test_document_batch_as_given_schedule_same_bits():
+    ps = _small_docs(32, seed=891)
+    g1 = gpu_batched(ps, mode="bf16_mfma_refine")
+    g2 = gpu_batched(ps, mode="bf16_mfma_refine", schedule="as_given")
+    np.testing.assert_array_equal(g1["costs"], g2["costs"])
+    np.testing.assert_array_equal(g1["stats"], g2["stats"])
+
+
+def test_documents_full_size_sampled():
+    """The 8192-candidate document workload: sampled pairs against the
+    oracle; every pair against the FP32 vector path (identical bits)."""
+    ps = W.documents_300d()
+    g = gpu_batched(ps, mode="bf16_mfma_refine")
+    assert np.all(g["stats"]["status"] == 0)
+    v = gpu_batched(ps, mode="fp32")
+    np.testing.assert_array_equal(g["costs"], v["costs"])
+    np.testing.assert_array_equal(g["stats"]["rounds"], v["stats"]["rounds"])
+    np.testing.assert_array_equal(g["stats"]["nnz"], v["stats"]["nnz"])
+    np.testing.assert_array_equal(g["stats"]["work"], v["stats"]["work"])
+    m_sizes, n_sizes = ps.sizes()
+    big = int(np.argmax(m_sizes * n_sizes))
+    sample = sorted(set(W.rng_for(892, 0).choice(ps.num_pairs, 14, replace=False).tolist()) | {0, big})
+    refs, _ = oracle.solve_batched(ps.X, ps.a, ps.x_off, ps.Y, ps.b, ps.y_off,
+                                   pair_x=ps.pair_x[sample], pair_y=ps.pair_y[sample])
+    for p, ref in zip(sample, refs):
+        st = g["stats"][p]
+        assert int(st["rounds"]) == ref["rounds"] and int(st["work"]) == ref["work"], p
+        assert int(st["nnz"]) == ref["nnz"], p
+        assert abs(float(g["costs"][p]) - ref["cost"]) <= 1e-12 * ref["cost"], p

@@ -126,3 +126,16 @@ def test_colour_transfer_full_size_properties():
     assert g["cost"] == pytest.approx(float((g["flow"] * d2).sum()), rel=1e-12)
     np.testing.assert_array_equal(g["map"][g["src"]], Y64[g["dst"]])
     assert int(st["rounds"]) > 100 and int(st["work"]) > 10 * n * n
+
+
+def test_workspaces_survive_schedule_growth():
+    """Growing the batched schedule buffer must leave the multi-workgroup
+    workspace alone: large pair, a bigger batch than any before, large pair."""
+    from tests.gpu_helpers import gpu_batched
+    X, a, Y, b = W.random_pair(760, 300, 280, 3)
+    ref = oracle_pair(X, a, Y, b)
+    assert_pair_matches(gpu_pair(X, a, Y, b, path="multi"), ref, label="before")
+    ps = W.batched_hist_3d(num_pairs=9000, lo=2, hi=6, seed=761)
+    g = gpu_batched(ps)
+    assert np.all(g["stats"]["status"] == 0)
+    assert_pair_matches(gpu_pair(X, a, Y, b, path="multi"), ref, label="after")

@@ -147,8 +147,11 @@ def test_host_side_errors():
     X, a, Y, b = W.random_pair(98, 10, 10, 9)
     t = lambda v: torch.from_numpy(np.ascontiguousarray(v)).cuda()
     with pytest.raises(binding.NNSEMDError) as e:
-        binding.emd_approx(t(X), t(a), t(Y), t(b))
-    assert e.value.status == -7  # d = 9 is beyond the point path
+        binding.emd_approx(t(X), t(a), t(Y), t(b), "l1")
+    assert e.value.status == -7  # L1 at d = 9: beyond the point path, not on the high-dimensional one
+    with pytest.raises(binding.NNSEMDError) as e:
+        binding.emd_approx(t(X), t(a), t(Y), t(b), path="multi")
+    assert e.value.status == -7  # the multi-workgroup path is for d <= 7
     with pytest.raises(binding.NNSEMDError) as e:
         binding.emd_approx(t(X[:, :3]), t(a), t(Y[:, :3]), t(b), out={"plan_src": t(np.zeros(3, np.int32)),
                                                                        "plan_dst": t(np.zeros(3, np.int32)),
