@@ -21,7 +21,7 @@ struct nnsemd_handle {
     void* lp_base = nullptr;                     // multi-workgroup path workspace (device)
     size_t lp_bytes = 0;
     nnsemd::LPState* lp_host = nullptr;          // pinned copy of the round state
-    float* doc_tiles = nullptr;                  // key-tile scratch of the high-dimensional path
+    char* doc_tiles = nullptr;                   // key-tile scratch of the high-dimensional path
     size_t doc_bytes = 0;
 };
 
@@ -239,10 +239,10 @@ nnsemd_status_t run_docs(nnsemd_handle_t h, DocArgs& A, int64_t max_m, int64_t m
     int err = launch_doc_solver(A, mfma, chunk, lds, 0, stream, &blocks);
     if (err != 0) return device_fail(h, err, "occupancy query");
     if (blocks < 1) return fail(h, NNSEMD_ERR_UNSUPPORTED, "pair workgroup does not fit on a compute unit");
-    const int64_t stride = align_up((size_t)mcap * (size_t)ncap, 64);
+    const int64_t slot = (int64_t)doc_slot_bytes(mcap, ncap);
     const int64_t per_launch =
-        std::max<int64_t>(1, std::min<int64_t>(A.num_pairs, (int64_t)(kDocTileBudget / (sizeof(float) * stride))));
-    const size_t need = sizeof(float) * (size_t)stride * (size_t)per_launch;
+        std::max<int64_t>(1, std::min<int64_t>(A.num_pairs, (int64_t)(kDocTileBudget / (size_t)slot)));
+    const size_t need = (size_t)slot * (size_t)per_launch;
     if (h->doc_bytes < need) {
         if (h->doc_tiles) (void)hipFree(h->doc_tiles);
         h->doc_tiles = nullptr;
@@ -251,8 +251,9 @@ nnsemd_status_t run_docs(nnsemd_handle_t h, DocArgs& A, int64_t max_m, int64_t m
             return fail(h, NNSEMD_ERR_OUT_OF_MEMORY, "key-tile scratch");
         h->doc_bytes = need;
     }
-    A.tiles = h->doc_tiles;
-    A.tile_stride = stride;
+    A.scratch = h->doc_tiles;
+    A.slot_bytes = slot;
+    A.phase_cycles = h->phase_cycles;
     if (A.x_off != nullptr && A.num_pairs > 1 && o.schedule == NNSEMD_SCHEDULE_LONGEST_FIRST) {
         nnsemd_status_t s = schedule(h, A.x_off, A.y_off, A.pair_x, A.pair_y, A.num_pairs, A.num_x_sets,
                                      A.num_y_sets, stream);

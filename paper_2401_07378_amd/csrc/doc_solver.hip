@@ -6,19 +6,24 @@
 // m x n dot products run on the matrix cores (v_mfma_f32_16x16x32_bf16, FP32
 // accumulation; each wavefront computes 32 x 32 output tiles from 2 x 2
 // MFMA blocks); with FP32 inputs they run on the vector ALUs.  The tile goes
-// to a per-workgroup global scratch area (it stays in L2 / MALL while the
-// workgroup runs its rounds).
+// to a per-workgroup global scratch slot that the rounds read.
 //
-// Exactness: an FP32 key differs from the exact one by at most
+// Exactness.  An FP32 key differs from the exact one by at most
 // E = 2 (d + 1) u (||x|| + ||y||)^2 (u = 2^-24) for any accumulation order of
-// the d products, even if every addition rounded with error 2u; a consumer
-// whose best and second-best keys are closer than 4E (twice the worst
-// disagreement of two keys, with R = max ||x|| in place of ||x||) is re-scored
-// over all active suppliers in FP64 from the inputs, in the definition's
-// operation order.  Every pick is then
-// the exact argmin (ties to the smallest index) and carries its exact FP64
-// key, so the plan equals the FP64 definition's.  After the search the
-// round continues with the phases shared with the point path.
+// the d products, even if every addition rounded with error 2u.
+//  * Search: a consumer whose two best FP32 keys are closer than
+//    8 (d + 2) u (R + ||y||)^2 (R = max ||x||; twice the worst disagreement of
+//    two keys) is re-scored in FP64 on the suppliers whose FP32 key lies
+//    within that bound of the best, in the definition's operation order.
+//    Every pick is therefore the FP64 argmin, ties to the smallest index.
+//  * Serve order (greedy protocol): claimants of one supplier are ordered by
+//    their full FP32 keys (tile + ||y||^2), whose error is at most
+//    t_j = 4 (d + 2) u (R + ||y_j||)^2; two claimants closer than t_a + t_b get
+//    exact FP64 keys and are compared on those.
+//  * Cost: R = sum f * D over the plan, with every D recomputed in FP64 from
+//    the inputs after the rounds (all lanes busy, one pass).
+// The plan is thus the one of the FP64 definition, and R agrees with the
+// sequential FP64 sum up to the summation order.
 #ifndef NNSEMD_CPU_EMULATION
 #include <hip/hip_runtime.h>
 #endif
@@ -48,6 +53,9 @@ __device__ inline bool finite_in(float v) { return isfinite(v); }
 
 __device__ inline float bf_lo(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ inline float bf_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+__device__ inline bool finite_pair(uint32_t w) {
+    return (w & 0x7F80u) != 0x7F80u && (w & 0x7F800000u) != 0x7F800000u;
+}
 
 // Exact FP64 squared Euclidean key of two points: the sum of the squared
 // coordinate differences in dimension order, no fused multiply-add.  Loads
@@ -103,20 +111,61 @@ __device__ inline double dkey64(const TIn* __restrict__ x, const TIn* __restrict
     return acc;
 }
 
+// This lane's part (lane gl of G sharing the row) of the FP32 squared norm
+// of one row, and whether any coordinate is not finite.  Any summation
+// order is covered by the error bounds above.
+template <int G, typename TIn>
+__device__ inline float norm2_part(const TIn* __restrict__ row, int d, int gl, bool& bad) {
+    float s2 = 0.f;
+    int k0 = 0;
+    if constexpr (sizeof(TIn) == 2) {
+        if (((d & 3) == 0) && ((reinterpret_cast<uintptr_t>(row) & 7u) == 0)) {
+            for (int c = gl; c < d / 4; c += G) {
+                const uint2 v = *reinterpret_cast<const uint2*>(row + 4 * c);
+                bad |= !finite_pair(v.x) || !finite_pair(v.y);
+                const float f0 = bf_lo(v.x), f1 = bf_hi(v.x), f2 = bf_lo(v.y), f3 = bf_hi(v.y);
+                s2 = fmaf(f0, f0, s2);
+                s2 = fmaf(f1, f1, s2);
+                s2 = fmaf(f2, f2, s2);
+                s2 = fmaf(f3, f3, s2);
+            }
+            k0 = d;
+        }
+    } else {
+        if (((d & 3) == 0) && ((reinterpret_cast<uintptr_t>(row) & 15u) == 0)) {
+            for (int c = gl; c < d / 4; c += G) {
+                const float4 v = *reinterpret_cast<const float4*>(row + 4 * c);
+                bad |= !isfinite(v.x) || !isfinite(v.y) || !isfinite(v.z) || !isfinite(v.w);
+                s2 = fmaf(v.x, v.x, s2);
+                s2 = fmaf(v.y, v.y, s2);
+                s2 = fmaf(v.z, v.z, s2);
+                s2 = fmaf(v.w, v.w, s2);
+            }
+            k0 = d;
+        }
+    }
+    for (int k = k0 + gl; k < d; k += G) {
+        const TIn v = row[k];
+        bad |= !finite_in(v);
+        const float f = to_f32(v);
+        s2 = fmaf(f, f, s2);
+    }
+    return s2;
+}
+
 // 8 consecutive BF16 values of row r starting at column k0 (zeros beyond d
 // or for rows >= rows), as an MFMA fragment.
 __device__ inline bf16x8 frag8(const uint16_t* __restrict__ base, int r, int rows, int k0, int d) {
     union {
-        uint32_t w[4];
+        uint2 w[2];
+        uint32_t s[4];
         bf16x8 v;
     } u;
     if (r < rows && k0 + 8 <= d) {
-        const uint32_t* p = reinterpret_cast<const uint32_t*>(base + (size_t)r * d + k0);
-        if (((uintptr_t)p & 3u) == 0) {
-            u.w[0] = p[0];
-            u.w[1] = p[1];
-            u.w[2] = p[2];
-            u.w[3] = p[3];
+        const uint16_t* p = base + (size_t)r * d + k0;
+        if ((reinterpret_cast<uintptr_t>(p) & 7u) == 0) {
+            u.w[0] = reinterpret_cast<const uint2*>(p)[0];
+            u.w[1] = reinterpret_cast<const uint2*>(p)[1];
             return u.v;
         }
     }
@@ -124,11 +173,12 @@ __device__ inline bf16x8 frag8(const uint16_t* __restrict__ base, int r, int row
 #pragma unroll
     for (int e = 0; e < 8; ++e) h[e] = (r < rows && k0 + e < d) ? base[(size_t)r * d + k0 + e] : (uint16_t)0;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) u.w[e] = (uint32_t)h[2 * e] | ((uint32_t)h[2 * e + 1] << 16);
+    for (int e = 0; e < 4; ++e) u.s[e] = (uint32_t)h[2 * e] | ((uint32_t)h[2 * e + 1] << 16);
     return u.v;
 }
 
-// Key tile with matrix cores: each wavefront owns 32 x 32 output tiles.
+// Key tile with matrix cores: each wavefront owns 32 x 32 output tiles; the
+// fragments of the next K step are loaded while the current one multiplies.
 // MFMA 16x16x32 lane layout (checked on gfx950): A lane l holds row l%16,
 // k = 8(l/16)..+8; B lane l holds column l%16, the same k; C lane l
 // register r is row 4(l/16)+r, column l%16.
@@ -147,16 +197,27 @@ __device__ void key_tile_mfma(const uint16_t* __restrict__ X, const uint16_t* __
         for (int a = 0; a < 2; ++a)
 #pragma unroll
             for (int b = 0; b < 2; ++b) acc[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        bf16x8 a0 = frag8(X, i0 + r16, m, kq, d);
+        bf16x8 a1 = frag8(X, i0 + 16 + r16, m, kq, d);
+        bf16x8 b0 = frag8(Y, j0 + r16, n, kq, d);
+        bf16x8 b1 = frag8(Y, j0 + 16 + r16, n, kq, d);
         for (int ks = 0; ks < ksteps; ++ks) {
-            const int k0 = ks * 32 + kq;
-            const bf16x8 a0 = frag8(X, i0 + r16, m, k0, d);
-            const bf16x8 a1 = frag8(X, i0 + 16 + r16, m, k0, d);
-            const bf16x8 b0 = frag8(Y, j0 + r16, n, k0, d);
-            const bf16x8 b1 = frag8(Y, j0 + 16 + r16, n, k0, d);
+            bf16x8 na0 = a0, na1 = a1, nb0 = b0, nb1 = b1;
+            if (ks + 1 < ksteps) {
+                const int k1 = (ks + 1) * 32 + kq;
+                na0 = frag8(X, i0 + r16, m, k1, d);
+                na1 = frag8(X, i0 + 16 + r16, m, k1, d);
+                nb0 = frag8(Y, j0 + r16, n, k1, d);
+                nb1 = frag8(Y, j0 + 16 + r16, n, k1, d);
+            }
             acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
             acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[0][1], 0, 0, 0);
             acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
             acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
+            a0 = na0;
+            a1 = na1;
+            b0 = nb0;
+            b1 = nb1;
         }
 #pragma unroll
         for (int a = 0; a < 2; ++a)
@@ -232,14 +293,79 @@ __device__ void key_tile_valu(const float* __restrict__ X, const float* __restri
     }
 }
 
+// Greedy serve order of the claimants (see the file comment): rank of each
+// claimant in its bucket from the full FP32 keys; claimants with an
+// undecided comparison get exact keys and are ranked again.
+template <int T, typename TIn>
+__device__ inline void rank_greedy_doc(const Lds& L, Shared& sh, int nact, const float* __restrict__ kap,
+                                       const float* __restrict__ yn, float rhat, float tscale,
+                                       int32_t* __restrict__ amb, const TIn* __restrict__ X,
+                                       const TIn* __restrict__ Y, int d, int64_t& near) {
+    for (int pass = 0; pass < 2; ++pass) {
+        const int cnt = pass == 0 ? nact : sh.namb;
+        for (int q = threadIdx.x; q < cnt; q += T) {
+            const int j = pass == 0 ? L.cact[q] : amb[q];
+            const int sl = L.cnn[j];
+            const int c = L.scnt[sl];
+            const int end = L.soff[sl];
+            const int start = end - c;
+            int rank = 0;
+            bool undecided = false;
+            if (c > 1) {
+                const float a = kap[j];
+                const float ea = rhat + yn[j];
+                const float ta = tscale * ea * ea;
+                const double ka = L.ckey[j];
+                for (int e = start; e < end; ++e) {
+                    const int j2 = L.list[e];
+                    if (j2 == j) continue;
+                    const float b = kap[j2];
+                    const float eb = rhat + yn[j2];
+                    const float tol = ta + tscale * eb * eb;
+                    if (b < a - tol) {
+                        ++rank;
+                    } else if (!(b > a + tol)) {
+                        const double kb = L.ckey[j2];
+                        if (ka >= 0.0 && kb >= 0.0)
+                            rank += (kb < ka) || (kb == ka && j2 < j);
+                        else
+                            undecided = true;
+                    }
+                }
+            }
+            // (No comparison is undecided in the second pass: both sides of
+            // each undecided one now carry exact keys.)
+            if (undecided && pass == 0)
+                amb[atomicAdd(&sh.namb, 1)] = j;
+            else
+                L.sorted[start + rank] = j;
+        }
+        __syncthreads();
+        const int na = sh.namb;
+        if (pass == 1 || na == 0) break;
+        // Undecided comparisons are symmetric, so both claimants of each one
+        // are listed; their exact keys decide the second pass.
+        for (int f = threadIdx.x; f < na; f += T) {
+            const int j = amb[f];
+            L.ckey[j] = dkey64<TIn>(X + (size_t)L.sidx[L.cnn[j]] * d, Y + (size_t)j * d, d);
+        }
+        near += na;
+        __syncthreads();
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) sh.namb = 0;
+}
+
 template <typename TIn, bool MFMA, int T, int CSMAX>
-__device__ void solve_doc_pair(const DocArgs& A, int64_t p, float* __restrict__ tile, const Lds& L,
-                               float* __restrict__ xx, float* __restrict__ yn, Shared& sh) {
+__device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ slot, const Lds& L,
+                               float* __restrict__ xx, float* __restrict__ yy, float* __restrict__ yn,
+                               float* __restrict__ kap, int32_t* __restrict__ amb, Shared& sh) {
     constexpr int NW = T / 64;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid / 64;
     const int d = A.d;
+    NNSEMD_PH_DECL
 
     int64_t x0 = 0, y0 = 0, m = A.single_m, n = A.single_n;
     int status = NNSEMD_OK;
@@ -274,11 +400,25 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, float* __restrict__ 
             m = n = 0;
         }
     }
+    // Plan destination: the caller's arrays, or the scratch slot (the cost
+    // pass reads the plan back either way).
+    float* __restrict__ tile = reinterpret_cast<float*>(slot);
+    int32_t* psrc = A.plan_src;
+    int32_t* pdst = A.plan_dst;
+    double* pflow = A.plan_flow;
+    if (!want_plan) {
+        const size_t tb = doc_tile_bytes(A.max_m, A.max_n);
+        const int64_t cap = (int64_t)A.max_m + A.max_n;
+        pflow = reinterpret_cast<double*>(slot + tb);
+        psrc = reinterpret_cast<int32_t*>(pflow + cap);
+        pdst = psrc + cap;
+        plan_base = 0;
+    }
     const TIn* __restrict__ X = reinterpret_cast<const TIn*>(A.X) + x0 * d;
     const TIn* __restrict__ Y = reinterpret_cast<const TIn*>(A.Y) + y0 * d;
     const int mi = (int)m, ni = (int)n;
 
-    // ---- ingest: masses, validity, norms
+    // ---- ingest: masses, validity, norms (16 lanes per row)
     double red[4] = {0.0, 0.0, 0.0, 0.0};  // sum a, sum b, bad, max ||x||^2
     const int rop[4] = {0, 0, 2, 2};
     for (int i = tid; i < mi; i += T) {
@@ -286,29 +426,42 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, float* __restrict__ 
         if (!(av >= 0.f) || !isfinite(av)) red[2] = 1.0;
         L.smass[i] = (double)av;
         red[0] += (double)av;
-        float s2 = 0.f;
-        for (int k = 0; k < d; ++k) {
-            const TIn v = X[(size_t)i * d + k];
-            if (!finite_in(v)) red[2] = 1.0;
-            const float f = to_f32(v);
-            s2 = fmaf(f, f, s2);
-        }
-        xx[i] = s2;
-        red[3] = fmax(red[3], (double)s2);
     }
     for (int j = tid; j < ni; j += T) {
         const float bv = A.b[y0 + j];
         if (!(bv >= 0.f) || !isfinite(bv)) red[2] = 1.0;
         L.cmass[j] = (double)bv;
         red[1] += (double)bv;
-        float s2 = 0.f;
-        for (int k = 0; k < d; ++k) {
-            const TIn v = Y[(size_t)j * d + k];
-            if (!finite_in(v)) red[2] = 1.0;
-            const float f = to_f32(v);
-            s2 = fmaf(f, f, s2);
+    }
+    const float infl = 1.f + (float)(d + 2) * kU32;  // covers the FP32 norms' own rounding
+    {
+        constexpr int G = 16;
+        const int gl = tid & (G - 1);
+        for (int r0 = 0; r0 < mi + ni; r0 += T / G) {
+            const int row = r0 + tid / G;
+            bool bad = false;
+            float s2 = 0.f;
+            if (row < mi + ni) {
+                const TIn* pr = row < mi ? X + (size_t)row * d : Y + (size_t)(row - mi) * d;
+                s2 = norm2_part<G, TIn>(pr, d, gl, bad);
+            }
+            int bi = bad ? 1 : 0;
+#pragma unroll
+            for (int o = G / 2; o > 0; o >>= 1) {
+                s2 += __shfl_xor(s2, o);
+                bi |= __shfl_xor(bi, o);
+            }
+            if (gl == 0 && row < mi + ni) {
+                if (bi) red[2] = 1.0;
+                if (row < mi) {
+                    xx[row] = s2;
+                    red[3] = fmax(red[3], (double)s2);
+                } else {
+                    yy[row - mi] = s2;
+                    yn[row - mi] = sqrtf(s2) * infl;
+                }
+            }
         }
-        yn[j] = sqrtf(s2);
     }
     block_reduce<T, 4>(red, rop, sh);
     if (status == NNSEMD_OK && red[2] != 0.0) status = NNSEMD_ERR_INVALID_ARG;
@@ -316,11 +469,11 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, float* __restrict__ 
         const double big = fmax(red[0], red[1]);
         if (fabs(red[0] - red[1]) > 1e-5 * big) status = NNSEMD_ERR_MASS_MISMATCH;
     }
-    // R >= max ||x|| despite the FP32 norms' own rounding; gap threshold
-    // 8 (d + 2) u (R + ||y||)^2.
-    const float rhat = sqrtf((float)red[3]) * (1.f + (float)(d + 2) * kU32);
-    const float thr_scale = 8.f * (float)(d + 2) * kU32;
+    const float rhat = sqrtf((float)red[3]) * infl;
+    // Key error bound t = tscale (R + ||y||)^2; the search gap threshold is 2t.
+    const float tscale = 4.f * (float)(d + 2) * kU32;
 
+    NNSEMD_PH(0)
     // ---- key tile
     if (status == NNSEMD_OK) {
         if constexpr (MFMA)
@@ -331,6 +484,7 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, float* __restrict__ 
                              tile);
     }
     __syncthreads();
+    NNSEMD_PH(1)
 
     // ---- initial active sets (zero-mass points never enter)
     int mact = 0, nact = 0;
@@ -364,7 +518,10 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, float* __restrict__ 
         }
         for (int j = clo; j < chi; ++j)
             if (L.cmass[j] > 0.0) L.cact[pc++] = j;
-        if (tid == 0) sh.nflag = 0;
+        if (tid == 0) {
+            sh.nflag = 0;
+            sh.namb = 0;
+        }
         __syncthreads();
     }
 
@@ -372,7 +529,6 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, float* __restrict__ 
     const int64_t max_rounds = A.max_rounds > 0 ? A.max_rounds : (int64_t)mi + ni;
     int rounds = 0;
     int64_t work = 0, nnz = 0, near = 0;
-    double cost = 0.0;
     float* flag_b1 = reinterpret_cast<float*>(L.sorted);  // best FP32 key of each flagged consumer
     while (status == NNSEMD_OK && mact > 0 && nact > 0) {
         if (rounds >= max_rounds) {
@@ -427,20 +583,21 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, float* __restrict__ 
             }
             if (valid && r == 0) {
                 const float e = rhat + yn[j];
-                const float thr = thr_scale * e * e + 1e-30f;
+                const float thr = 2.f * tscale * e * e + 1e-30f;
                 if (!(b2 - b1 > thr)) {
                     const int f = atomicAdd(&sh.nflag, 1);
                     L.list[f] = j;
                     flag_b1[f] = b1;
-                    L.ckey[j] = 0.0;  // set by the re-scoring wave; skipped by the pass below
                 } else {
                     L.cnn[j] = bs;
-                    L.ckey[j] = -1.0;  // exact key computed below
+                    kap[j] = b1 + yy[j];
+                    L.ckey[j] = -1.0;  // exact key not known
                     atomicAdd(&L.scnt[bs], 1);
                 }
             }
         }
         __syncthreads();
+        NNSEMD_PH(2)
         const int nf = sh.nflag;
         if (nf > 0) {
             // Near ties: the FP64 argmin is among the suppliers whose FP32
@@ -449,7 +606,7 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, float* __restrict__ 
             for (int f = wave; f < nf; f += NW) {
                 const int j = L.list[f];
                 const float e = rhat + yn[j];
-                const float lim = flag_b1[f] + (thr_scale * e * e + 1e-30f);
+                const float lim = flag_b1[f] + (2.f * tscale * e * e + 1e-30f);
                 double best = INFINITY;
                 int bsl = 0x7fffffff;
                 for (int s = lane; s < mact; s += 64) {
@@ -473,27 +630,39 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, float* __restrict__ 
                 if (lane == 0) {
                     L.cnn[j] = bsl;
                     L.ckey[j] = best;
+                    kap[j] = tile[(size_t)L.sidx[bsl] * ni + j] + yy[j];
                     atomicAdd(&L.scnt[bsl], 1);
                 }
             }
             near += nf;
+            __syncthreads();
         }
-        // Exact FP64 key of every other pick (for the serve order and R).
-        for (int q = tid; q < nact; q += T) {
-            const int j = L.cact[q];
-            if (L.ckey[j] < 0.0) L.ckey[j] = dkey64<TIn>(X + (size_t)L.sidx[L.cnn[j]] * d, Y + (size_t)j * d, d);
-        }
-        __syncthreads();
+        NNSEMD_PH(3)
         round_buckets<T>(L, sh, mact, nact);
-        round_rank<T>(L, nact, A.protocol, A.seed, rounds);
-        round_walk<T>(L, mact, A.metric, cost);
-        round_compact<T, CSMAX, 0>(L, sh, mact, nact, nnz, want_plan ? A.plan_src : nullptr, A.plan_dst,
-                                   A.plan_flow, plan_base);
+        if (A.protocol == NNSEMD_GREEDY)
+            rank_greedy_doc<T, TIn>(L, sh, nact, kap, yn, rhat, tscale, amb, X, Y, d, near);
+        else
+            round_rank<T>(L, nact, A.protocol, A.seed, rounds);
+        NNSEMD_PH(4)
+        double unused = 0.0;
+        round_walk<T, false>(L, mact, A.metric, unused);
+        NNSEMD_PH(5)
+        round_compact<T, CSMAX, 0>(L, sh, mact, nact, nnz, psrc, pdst, pflow, plan_base);
+        NNSEMD_PH(6)
         ++rounds;
     }
 
-    double fin[3] = {cost, 0.0, 0.0};
+    // ---- R = sum f * D over the plan, D from exact FP64 keys
+    double fin[3] = {0.0, 0.0, 0.0};
     const int fop[3] = {0, 0, 0};
+    if (status == NNSEMD_OK) {
+        for (int64_t e = tid; e < nnz; e += T) {
+            const int64_t at = plan_base + e;
+            const int i = psrc[at], j = pdst[at];
+            fin[0] += pflow[at] * dist_of_key(dkey64<TIn>(X + (size_t)i * d, Y + (size_t)j * d, d), A.metric);
+        }
+    }
+    NNSEMD_PH(7)
     if (status == NNSEMD_OK || status == NNSEMD_ERR_NOT_CONVERGED) {
         for (int s = tid; s < mact; s += T) fin[1] += L.smass[s];
         for (int q = tid; q < nact; q += T) fin[2] += L.cmass[L.cact[q]];
@@ -513,6 +682,8 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, float* __restrict__ 
             A.stats[p] = st;
         }
     }
+    NNSEMD_PH(8)
+    NNSEMD_PH_FLUSH(A.phase_cycles)
 }
 
 #ifndef NNSEMD_CPU_EMULATION
@@ -523,11 +694,14 @@ __global__ __launch_bounds__(T) void doc_pair_kernel(DocArgs A) {
     const PairLdsLayout lay = pair_lds_layout(A.max_m, A.max_n, 0);
     const Lds L = carve(lds_dyn, A.max_m, A.max_n, 0);
     float* xx = reinterpret_cast<float*>(lds_dyn + lay.total);
-    float* yn = xx + A.max_m;
+    float* yy = xx + A.max_m;
+    float* yn = yy + A.max_n;
+    float* kap = yn + A.max_n;
+    int32_t* amb = reinterpret_cast<int32_t*>(kap + A.max_n);
     const int64_t b = A.pair_base + (int64_t)blockIdx.x;
     const int64_t p = A.order != nullptr ? (int64_t)A.order[b] : b;
-    float* tile = A.tiles + (size_t)blockIdx.x * (size_t)A.tile_stride;
-    solve_doc_pair<TIn, MFMA, T, CSMAX>(A, p, tile, L, xx, yn, sh);
+    char* slot = A.scratch + (size_t)blockIdx.x * (size_t)A.slot_bytes;
+    solve_doc_pair<TIn, MFMA, T, CSMAX>(A, p, slot, L, xx, yy, yn, kap, amb, sh);
 }
 
 template <typename TIn, bool MFMA, int CSMAX>
@@ -546,8 +720,9 @@ int doc_launch_typed(const DocArgs& A, size_t lds, int grid, hipStream_t st, boo
 
 }  // namespace
 
+// Pair layout (no records) + xx[M], yy[N], yn[N], kap[N] (float), amb[N] (int32).
 size_t doc_lds_bytes(int max_m, int max_n) {
-    return pair_lds_layout(max_m, max_n, 0).total + sizeof(float) * ((size_t)max_m + (size_t)max_n);
+    return pair_lds_layout(max_m, max_n, 0).total + sizeof(float) * ((size_t)max_m + 4 * (size_t)max_n);
 }
 
 #ifndef NNSEMD_CPU_EMULATION

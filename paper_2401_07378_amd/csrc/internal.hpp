@@ -167,11 +167,20 @@ struct DocArgs {
     nnsemd_stats_t* stats;
     const int32_t* order;  // nullable: workgroup b solves pair order[pair_base + b]
     int64_t pair_base;     // first schedule position of this launch
-    float* tiles;          // grid * tile_stride floats of key-tile scratch
-    int64_t tile_stride;   // >= max_m * max_n
+    char* scratch;         // grid * slot_bytes: per-workgroup key tile, then the plan when none is requested
+    int64_t slot_bytes;    // doc_slot_bytes(max_m, max_n)
+    unsigned long long* phase_cycles;  // profiling builds only: 9 per-phase cycle totals
 };
 
 size_t doc_lds_bytes(int max_m, int max_n);
+// Scratch slot of one workgroup: the m x n FP32 key tile (256-byte aligned)
+// followed by m + n plan entries (int32 src, int32 dst, double flow).
+__host__ __device__ inline size_t doc_tile_bytes(int max_m, int max_n) {
+    return align_up(sizeof(float) * (size_t)max_m * (size_t)max_n, 256);
+}
+__host__ __device__ inline size_t doc_slot_bytes(int max_m, int max_n) {
+    return doc_tile_bytes(max_m, max_n) + align_up(16 * ((size_t)max_m + (size_t)max_n), 256);
+}
 // blocks == nullptr: launch; else query resident workgroups per CU.
 int launch_doc_solver(const DocArgs& A, bool bf16_mfma, int chunk_max, size_t lds, int grid, void* stream,
                       int* blocks);

@@ -31,17 +31,6 @@
 #include "internal.hpp"
 #include "round_common.hpp"
 
-// Optional per-phase cycle accounting for profiling builds only
-// (-DNNSEMD_PHASE_TIMING).  Every thread reads the clock (no divergent code);
-// thread 0 adds its totals to A.phase_cycles once, at the end of the pair.
-#ifdef NNSEMD_PHASE_TIMING
-#define NNSEMD_PH_DECL uint64_t ph[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}; uint64_t ph_t = clock64();
-#define NNSEMD_PH(k) { const uint64_t ph_n = clock64(); ph[k] += ph_n - ph_t; ph_t = ph_n; }
-#else
-#define NNSEMD_PH_DECL
-#define NNSEMD_PH(k)
-#endif
-
 namespace nnsemd {
 namespace {
 
@@ -439,10 +428,7 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds& L, Sha
     }
     block_reduce<T, 3>(fin, fop, sh);
     NNSEMD_PH(8)
-#ifdef NNSEMD_PHASE_TIMING
-    if (tid == 0 && A.phase_cycles != nullptr)
-        for (int k = 0; k < 9; ++k) atomicAdd(&A.phase_cycles[k], (unsigned long long)ph[k]);
-#endif
+    NNSEMD_PH_FLUSH(A.phase_cycles)
     if (tid == 0) {
         A.costs[p] = status == NNSEMD_OK ? fin[0] : NAN;
         if (A.stats != nullptr) {

@@ -16,6 +16,21 @@
 
 #include "internal.hpp"
 
+// Optional per-phase cycle accounting for profiling builds only
+// (-DNNSEMD_PHASE_TIMING).  Every thread reads the clock (no divergent code);
+// thread 0 adds its totals to the phase buffer once, at the end of the pair.
+#ifdef NNSEMD_PHASE_TIMING
+#define NNSEMD_PH_DECL uint64_t ph[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}; uint64_t ph_t = clock64();
+#define NNSEMD_PH(k) { const uint64_t ph_n = clock64(); ph[k] += ph_n - ph_t; ph_t = ph_n; }
+#define NNSEMD_PH_FLUSH(buf)                                                              \
+    if (threadIdx.x == 0 && (buf) != nullptr)                                             \
+        for (int k = 0; k < 9; ++k) atomicAdd(&(buf)[k], (unsigned long long)ph[k]);
+#else
+#define NNSEMD_PH_DECL
+#define NNSEMD_PH(k)
+#define NNSEMD_PH_FLUSH(buf)
+#endif
+
 namespace nnsemd {
 namespace rc {
 
@@ -38,8 +53,8 @@ struct Lds {
 struct Shared {
     double red[16][24];
     unsigned long long scan[16];
-    int32_t nflag;
-    int32_t pad;
+    int32_t nflag;  // near-tie consumers of the search
+    int32_t namb;   // claimants whose serve order needs exact keys (high-dimensional path)
 };
 
 __device__ inline Lds carve(char* base, int M, int N, int rs) {
@@ -212,8 +227,9 @@ __device__ inline void round_rank(const Lds& L, int nact, int protocol, uint64_t
 // ---- flow & cost: one lane per claimed supplier walks its ordered
 // claimants while it still holds mass.  A served claimant records the local
 // index of its supplier (for the plan) and its flow in place of its key; an
-// unserved one gets flow 0.  `cost` is this thread's part of R.
-template <int T>
+// unserved one gets flow 0.  With COST, `cost` accumulates this thread's part
+// of R from the exact keys; without, R is left to the caller.
+template <int T, bool COST = true>
 __device__ inline void round_walk(const Lds& L, int mact, int metric, double& cost) {
     for (int s = threadIdx.x; s < mact; s += T) {
         const int c = L.scnt[s];
@@ -228,7 +244,7 @@ __device__ inline void round_walk(const Lds& L, int mact, int metric, double& co
             const double f = sm < cm ? sm : cm;
             sm = sm - f;
             L.cmass[j] = cm - f;
-            cost = cost + f * dist_of_key(L.ckey[j], metric);
+            if constexpr (COST) cost = cost + f * dist_of_key(L.ckey[j], metric);
             L.ckey[j] = f;
             L.cnn[j] = isup;
             ++pos;
