@@ -215,6 +215,81 @@ nnsemd_status_t emd_approx_batched(nnsemd_handle_t h, int64_t num_pairs,
                                    nnsemd_stats_t* stats,
                                    void* stream);
 
+/* ------------------------------------------------------------------------
+ * Learned surrogate for retrieval (not part of the paper, which treats
+ * NNS-EMD as a non-differentiable procedure): a deep-sets network predicts
+ * the EMD of two 3-D point sets from pooled per-point features, a retrieval
+ * keeps the candidates it ranks best, and NNS-EMD (Algorithm 1) re-ranks
+ * them.  It never replaces an NNS-EMD value in a result.
+ *
+ *   phi(x)  = relu(W2 relu(W1 x + b1) + b2)            3 -> 256 -> 256
+ *   E(X, a) = sum_i a_i phi(x_i)                        (mass-weighted pooling)
+ *   pred    = softplus(w4 . relu(W3 [E_q, E_c, |E_q - E_c|] + b3) + b4)
+ *   loss    = mean_b (log pred_b - log y_b)^2           (labels y_b > 0)
+ *
+ * theta: device, nnsemd_sg_num_params() FP32 master parameters, in the order
+ * W1 (256 x 3), b1 (256), W2 (256 x 256), b2 (256), W3 (256 x 768), b3 (256),
+ * w4 (256), b4 (1), matrices row-major [out][in].  The kernels use the
+ * weights rounded to BF16, with FP32 accumulation; every call re-derives the
+ * BF16 copies from theta.  Point sets are concatenated FP32 rows (x, y, z)
+ * with masses and int64 offsets (set s = rows [off[s], off[s+1])).  All
+ * arrays are caller-owned device memory; calls are asynchronous on stream.
+ * ------------------------------------------------------------------------ */
+int64_t nnsemd_sg_num_params(void);
+
+/* Pooled embeddings E (num_sets x 256 FP32) of point sets.  num_points: the
+ * rows of X (offsets are clamped to it; bad offsets never read outside X). */
+nnsemd_status_t nnsemd_sg_embed(nnsemd_handle_t h, const float* theta, const float* X, const float* a,
+                                const int64_t* set_off, int64_t num_sets, int64_t num_points, float* E,
+                                void* stream);
+
+/* pred[b] for pairs (Eq[q_idx[b]], Ec[c_idx[b]]); q_idx NULL = row 0 for all,
+ * c_idx NULL = row b.  num_q / num_c: rows of the tables; an index outside
+ * them gives pred NaN. */
+nnsemd_status_t nnsemd_sg_predict(nnsemd_handle_t h, const float* theta, const float* Eq, int64_t num_q,
+                                  const float* Ec, int64_t num_c, const int32_t* q_idx, const int32_t* c_idx,
+                                  int64_t num_pairs, float* pred, void* stream);
+
+/* Loss (1 float) and gradient (nnsemd_sg_num_params floats, master layout;
+ * the gradient of each rounded weight is that of its master value) of one
+ * training batch: pair b compares set 2b with set 2b+1 (set_off has
+ * 2 num_pairs + 1 entries, set_off[2 num_pairs] = num_points); labels: the
+ * NNS-EMD values, > 0.  Offsets that are not a partition of the points make
+ * the loss NaN.  1 <= num_pairs <= 2^20, 1 <= num_points <= 2^26. */
+nnsemd_status_t nnsemd_sg_loss_grad(nnsemd_handle_t h, const float* theta, const float* X, const float* a,
+                                    const int64_t* set_off, int64_t num_pairs, int64_t num_points,
+                                    const float* labels, float* loss, float* grad, void* stream);
+
+/* nnsemd_sg_loss_grad, then one Adam step on theta (beta1 0.9, beta2 0.999,
+ * eps 1e-8, bias-corrected with step >= 1; adam_m / adam_v: device FP32
+ * moments, zero before step 1).  grad: device output, or NULL for library
+ * workspace. */
+nnsemd_status_t nnsemd_sg_train_step(nnsemd_handle_t h, float* theta, float* adam_m, float* adam_v, int64_t step,
+                                     float lr, const float* X, const float* a, const int64_t* set_off,
+                                     int64_t num_pairs, int64_t num_points, const float* labels, float* loss,
+                                     float* grad, void* stream);
+
+/* Indices of the k smallest of n values, ascending by (value, index), NaN
+ * last; 1 <= k <= min(n, 1024). */
+nnsemd_status_t nnsemd_topk_smallest_f32(nnsemd_handle_t h, const float* values, int64_t n, int32_t k,
+                                         int32_t* idx, void* stream);
+nnsemd_status_t nnsemd_topk_smallest_f64(nnsemd_handle_t h, const double* values, int64_t n, int32_t k,
+                                         int32_t* idx, void* stream);
+
+/* Surrogate-pruned retrieval of one query (Xq, aq: mq points, suppliers)
+ * among num_candidates candidate sets (Ycat, bcat, y_off: consumers; their
+ * embeddings index_E from nnsemd_sg_embed): the keep candidates of smallest
+ * pred are re-ranked by NNS-EMD (greedy, L2, exactly as emd_approx_batched);
+ * out_idx / out_cost receive the top of them by NNS-EMD (ascending, ties by
+ * index).  kept_idx (keep int32) and kept_stats (keep records), nullable,
+ * receive the kept candidates and their NNS-EMD stats.  max_n: host bound
+ * on the candidate sizes.  1 <= top <= keep <= min(num_candidates, 1024). */
+nnsemd_status_t nnsemd_sg_retrieve(nnsemd_handle_t h, const float* theta, const float* index_E,
+                                   int64_t num_candidates, const float* Xq, const float* aq, int64_t mq,
+                                   const float* Ycat, const float* bcat, const int64_t* y_off, int64_t max_n,
+                                   int32_t keep, int32_t top, int32_t* out_idx, double* out_cost,
+                                   int32_t* kept_idx, nnsemd_stats_t* kept_stats, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -30,7 +30,10 @@ STATS_DTYPE = np.dtype([("status", "<i4"), ("rounds", "<i4"), ("nnz", "<i8"), ("
                         ("near_ties", "<i8"), ("residual_src", "<f8"), ("residual_dst", "<f8")])
 
 EXPORTS = ["nnsemd_create", "nnsemd_destroy", "nnsemd_status_string", "nnsemd_last_error",
-           "emd_approx", "emd_approx_map", "emd_approx_batched"]
+           "emd_approx", "emd_approx_map", "emd_approx_batched",
+           "nnsemd_sg_num_params", "nnsemd_sg_embed", "nnsemd_sg_predict", "nnsemd_sg_loss_grad",
+           "nnsemd_sg_train_step", "nnsemd_topk_smallest_f32", "nnsemd_topk_smallest_f64", "nnsemd_sg_retrieve"]
+SG_HIDDEN = 256
 
 
 class NNSEMDError(RuntimeError):
@@ -78,6 +81,19 @@ def load_library():
         lib.emd_approx_map.argtypes = [P, P, P, I64, P, P, I64, I32, I32, I32, ctypes.POINTER(Options),
                                        P, P, P, P, P, I64, P, P]
         lib.emd_approx_map.restype = I32
+        F32 = ctypes.c_float
+        lib.nnsemd_sg_num_params.argtypes = []
+        lib.nnsemd_sg_num_params.restype = I64
+        lib.nnsemd_sg_embed.argtypes = [P, P, P, P, P, I64, I64, P, P]
+        lib.nnsemd_sg_predict.argtypes = [P, P, P, I64, P, I64, P, P, I64, P, P]
+        lib.nnsemd_sg_loss_grad.argtypes = [P, P, P, P, P, I64, I64, P, P, P, P]
+        lib.nnsemd_sg_train_step.argtypes = [P, P, P, P, I64, F32, P, P, P, I64, I64, P, P, P, P]
+        lib.nnsemd_topk_smallest_f32.argtypes = [P, P, I64, I32, P, P]
+        lib.nnsemd_topk_smallest_f64.argtypes = [P, P, I64, I32, P, P]
+        lib.nnsemd_sg_retrieve.argtypes = [P, P, P, I64, P, P, I64, P, P, P, I64, I32, I32, P, P, P, P, P]
+        for fn in ("nnsemd_sg_embed", "nnsemd_sg_predict", "nnsemd_sg_loss_grad", "nnsemd_sg_train_step",
+                   "nnsemd_topk_smallest_f32", "nnsemd_topk_smallest_f64", "nnsemd_sg_retrieve"):
+            getattr(lib, fn).restype = I32
         _lib = lib
         return lib
 
@@ -268,3 +284,118 @@ def emd_approx_batched(Xcat, acat, x_off, Ycat, bcat, y_off, *, max_m: int, max_
     _check(lib, h, st)
     return {"costs": costs, "stats": stats, "plan_src": src, "plan_dst": dst, "plan_flow": flow,
             "plan_off": plan_off}
+
+
+# ---------------------------------------------------------------- surrogate
+def _dev_of(t):
+    import torch
+    return t.device.index if t.device.index is not None else torch.cuda.current_device()
+
+
+def sg_num_params() -> int:
+    return int(load_library().nnsemd_sg_num_params())
+
+
+def sg_embed(theta, X, a, set_off, out=None):
+    """Pooled embeddings (num_sets x 256 FP32) of concatenated 3-D point sets."""
+    import torch
+    lib = load_library()
+    dev = _dev_of(X)
+    h = handle(dev)
+    _require(theta, torch.float32, "theta")
+    _require(X, torch.float32, "X")
+    _require(a, torch.float32, "a")
+    _require(set_off, torch.int64, "set_off")
+    S = set_off.numel() - 1
+    E = out if out is not None else torch.empty((max(S, 1), SG_HIDDEN), dtype=torch.float32, device=X.device)
+    st = lib.nnsemd_sg_embed(h, _ptr(theta), _ptr(X), _ptr(a), _ptr(set_off), S, X.shape[0], _ptr(E),
+                             _stream(torch, dev))
+    _check(lib, h, st)
+    return E[:S]
+
+
+def sg_predict(theta, Eq, Ec, q_idx=None, c_idx=None, num_pairs=None, out=None):
+    """Surrogate EMD of pairs of embedding rows."""
+    import torch
+    lib = load_library()
+    dev = _dev_of(Eq)
+    h = handle(dev)
+    for t, nm in ((theta, "theta"), (Eq, "Eq"), (Ec, "Ec")):
+        _require(t, torch.float32, nm)
+    if num_pairs is None:
+        num_pairs = c_idx.numel() if c_idx is not None else Ec.shape[0]
+    pred = out if out is not None else torch.empty(max(num_pairs, 1), dtype=torch.float32, device=Eq.device)
+    st = lib.nnsemd_sg_predict(h, _ptr(theta), _ptr(Eq), Eq.shape[0], _ptr(Ec), Ec.shape[0], _ptr(q_idx),
+                               _ptr(c_idx), num_pairs, _ptr(pred), _stream(torch, dev))
+    _check(lib, h, st)
+    return pred[:num_pairs]
+
+
+def sg_loss_grad(theta, X, a, set_off, labels, grad=None):
+    """(loss (1,), grad (num_params,)) of one training batch (pair b = sets 2b, 2b+1)."""
+    import torch
+    lib = load_library()
+    dev = _dev_of(X)
+    h = handle(dev)
+    loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    if grad is None:
+        grad = torch.empty(sg_num_params(), dtype=torch.float32, device=X.device)
+    st = lib.nnsemd_sg_loss_grad(h, _ptr(theta), _ptr(X), _ptr(a), _ptr(set_off), labels.numel(), X.shape[0],
+                                 _ptr(labels), _ptr(loss), _ptr(grad), _stream(torch, dev))
+    _check(lib, h, st)
+    return loss, grad
+
+
+def sg_train_step(theta, m, v, step, lr, X, a, set_off, labels, loss=None, grad=None):
+    """One Adam step on theta (in place); returns the batch loss tensor (1,)."""
+    import torch
+    lib = load_library()
+    dev = _dev_of(X)
+    h = handle(dev)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    st = lib.nnsemd_sg_train_step(h, _ptr(theta), _ptr(m), _ptr(v), int(step), float(lr), _ptr(X), _ptr(a),
+                                  _ptr(set_off), labels.numel(), X.shape[0], _ptr(labels), _ptr(loss), _ptr(grad),
+                                  _stream(torch, dev))
+    _check(lib, h, st)
+    return loss
+
+
+def topk_smallest(values, k: int, out=None):
+    """Indices (int32) of the k smallest values, ascending by (value, index)."""
+    import torch
+    lib = load_library()
+    dev = _dev_of(values)
+    h = handle(dev)
+    idx = out if out is not None else torch.empty(k, dtype=torch.int32, device=values.device)
+    if values.dtype == torch.float32:
+        st = lib.nnsemd_topk_smallest_f32(h, _ptr(values), values.numel(), k, _ptr(idx), _stream(torch, dev))
+    elif values.dtype == torch.float64:
+        st = lib.nnsemd_topk_smallest_f64(h, _ptr(values), values.numel(), k, _ptr(idx), _stream(torch, dev))
+    else:
+        raise ValueError("values must be float32 or float64")
+    _check(lib, h, st)
+    return idx
+
+
+def sg_retrieve(theta, index_E, Xq, aq, Ycat, bcat, y_off, max_n: int, keep: int = 1000, top: int = 10,
+                out: dict | None = None) -> dict:
+    """Surrogate-pruned retrieval: keep the `keep` candidates of smallest
+    predicted EMD, re-rank them with NNS-EMD, return the `top` best
+    (idx int32, cost float64) plus the kept indices and their stats."""
+    import torch
+    lib = load_library()
+    dev = _dev_of(Xq)
+    h = handle(dev)
+    o = out or {}
+    d = Xq.device
+    idx = o.get("idx") if o.get("idx") is not None else torch.empty(top, dtype=torch.int32, device=d)
+    cost = o.get("cost") if o.get("cost") is not None else torch.empty(top, dtype=torch.float64, device=d)
+    kept = o.get("kept") if o.get("kept") is not None else torch.empty(keep, dtype=torch.int32, device=d)
+    kst = o.get("kept_stats") if o.get("kept_stats") is not None else \
+        torch.empty(keep * STATS_DTYPE.itemsize, dtype=torch.uint8, device=d)
+    st = lib.nnsemd_sg_retrieve(h, _ptr(theta), _ptr(index_E), index_E.shape[0], _ptr(Xq), _ptr(aq), Xq.shape[0],
+                                _ptr(Ycat), _ptr(bcat), _ptr(y_off), int(max_n), keep, top, _ptr(idx), _ptr(cost),
+                                _ptr(kept), _ptr(kst), _stream(torch, dev))
+    _check(lib, h, st)
+    return {"idx": idx, "cost": cost, "kept": kept, "kept_stats": kst}

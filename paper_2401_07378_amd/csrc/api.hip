@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -23,6 +24,9 @@ struct nnsemd_handle {
     nnsemd::LPState* lp_host = nullptr;          // pinned copy of the round state
     char* doc_tiles = nullptr;                   // key-tile scratch of the high-dimensional path
     size_t doc_bytes = 0;
+    char* sg_quant = nullptr;                    // BF16 weight copies of the surrogate
+    char* sg_ws = nullptr;                       // surrogate workspace
+    size_t sg_bytes = 0;
 };
 
 namespace {
@@ -273,6 +277,63 @@ nnsemd_status_t run_docs(nnsemd_handle_t h, DocArgs& A, int64_t max_m, int64_t m
 // mode) and FP32 points with d > 7 take the high-dimensional path.
 bool use_doc_path(int32_t d, nnsemd_dtype_t dtype) { return dtype == NNSEMD_BF16 || d > 7; }
 
+// ---- surrogate helpers
+struct Carver {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        const size_t o = align_up(off, 256);
+        off = o + bytes;
+        return o;
+    }
+};
+
+nnsemd_status_t sg_workspace(nnsemd_handle_t h, size_t bytes) {
+    if (h->sg_bytes >= bytes) return NNSEMD_OK;
+    if (h->sg_ws) (void)hipFree(h->sg_ws);
+    h->sg_ws = nullptr;
+    h->sg_bytes = 0;
+    if (hipMalloc((void**)&h->sg_ws, bytes) != hipSuccess) return fail(h, NNSEMD_ERR_OUT_OF_MEMORY, "surrogate workspace");
+    h->sg_bytes = bytes;
+    return NNSEMD_OK;
+}
+
+// BF16 weight copies from the FP32 master parameters (enqueued on stream).
+nnsemd_status_t sg_quantize(nnsemd_handle_t h, const float* theta, sg::SgQuant& q, void* stream) {
+    constexpr int64_t Hd = kSgHidden;
+    Carver c;
+    const size_t oW1 = c.take(sizeof(float) * 3 * Hd), ow4 = c.take(sizeof(float) * Hd);
+    const size_t oW2 = c.take(2 * Hd * Hd), oW2T = c.take(2 * Hd * Hd);
+    const size_t oW3 = c.take(2 * Hd * 3 * Hd), oW3T = c.take(2 * Hd * 3 * Hd);
+    if (h->sg_quant == nullptr && hipMalloc((void**)&h->sg_quant, align_up(c.off, 256)) != hipSuccess) {
+        h->sg_quant = nullptr;
+        return fail(h, NNSEMD_ERR_OUT_OF_MEMORY, "surrogate weights");
+    }
+    char* b = h->sg_quant;
+    q.W1 = reinterpret_cast<float*>(b + oW1);
+    q.w4 = reinterpret_cast<float*>(b + ow4);
+    q.W2 = reinterpret_cast<uint16_t*>(b + oW2);
+    q.W2T = reinterpret_cast<uint16_t*>(b + oW2T);
+    q.W3 = reinterpret_cast<uint16_t*>(b + oW3);
+    q.W3T = reinterpret_cast<uint16_t*>(b + oW3T);
+    const int err = sg::launch_prepare(theta, q, stream);
+    if (err != 0) return device_fail(h, err, "surrogate weight conversion");
+    return NNSEMD_OK;
+}
+
+size_t sg_predict_bytes(int64_t B) {
+    const int64_t Bpad = (B + 63) / 64 * 64;
+    return align_up(2 * (size_t)Bpad * 3 * kSgHidden, 256) + align_up(4 * (size_t)Bpad * kSgHidden, 256) + 256;
+}
+
+sg::SgPredictWork sg_predict_carve(char* base, int64_t B) {
+    const int64_t Bpad = (B + 63) / 64 * 64;
+    Carver c;
+    const size_t oZ = c.take(2 * (size_t)Bpad * 3 * kSgHidden), oP = c.take(4 * (size_t)Bpad * kSgHidden);
+    return sg::SgPredictWork{reinterpret_cast<uint16_t*>(base + oZ), reinterpret_cast<float*>(base + oP)};
+}
+
+constexpr int64_t kSgMaxRows = (int64_t)1 << 30;
+
 nnsemd_status_t check_common(nnsemd_handle_t h, int32_t d, nnsemd_dtype_t dtype, nnsemd_metric_t metric,
                              const nnsemd_options_t& o) {
     if (d < 1) return fail(h, NNSEMD_ERR_INVALID_ARG, "d must be >= 1");
@@ -333,6 +394,8 @@ nnsemd_status_t nnsemd_destroy(nnsemd_handle_t h) {
         if (h->lp_base) (void)hipFree(h->lp_base);
         if (h->lp_host) (void)hipHostFree(h->lp_host);
         if (h->doc_tiles) (void)hipFree(h->doc_tiles);
+        if (h->sg_quant) (void)hipFree(h->sg_quant);
+        if (h->sg_ws) (void)hipFree(h->sg_ws);
     }
     delete h;
     return NNSEMD_OK;
@@ -554,6 +617,244 @@ nnsemd_status_t emd_approx_batched(nnsemd_handle_t h, int64_t num_pairs, const v
     A.plan_off = plan ? plan_off : nullptr;
     A.stats = stats;
     return run_pairs(h, A, d, max_m, max_n, o, stream);
+}
+
+int64_t nnsemd_sg_num_params(void) { return kSgParams; }
+
+nnsemd_status_t nnsemd_sg_embed(nnsemd_handle_t h, const float* theta, const float* X, const float* a,
+                                const int64_t* set_off, int64_t num_sets, int64_t num_points, float* E,
+                                void* stream) {
+    if (h == nullptr) return NNSEMD_ERR_INVALID_ARG;
+    h->last_error.clear();
+    if (num_sets < 0 || num_points < 0 || num_sets > 0x7fffffffLL || num_points > kSgMaxRows)
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "bad set or point count");
+    if (num_sets == 0) return NNSEMD_OK;
+    if (theta == nullptr || set_off == nullptr || E == nullptr || (num_points > 0 && (X == nullptr || a == nullptr)))
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "NULL array");
+    DeviceGuard g(h->device);
+    sg::SgQuant q;
+    nnsemd_status_t s = sg_quantize(h, theta, q, stream);
+    if (s != NNSEMD_OK) return s;
+    const int err = sg::launch_embed(theta, q, X, a, set_off, num_sets, num_points, E, stream);
+    if (err != 0) return device_fail(h, err, "surrogate embedding");
+    return NNSEMD_OK;
+}
+
+nnsemd_status_t nnsemd_sg_predict(nnsemd_handle_t h, const float* theta, const float* Eq, int64_t num_q,
+                                  const float* Ec, int64_t num_c, const int32_t* q_idx, const int32_t* c_idx,
+                                  int64_t num_pairs, float* pred, void* stream) {
+    if (h == nullptr) return NNSEMD_ERR_INVALID_ARG;
+    h->last_error.clear();
+    if (num_pairs < 0 || num_pairs > kSgMaxRows) return fail(h, NNSEMD_ERR_INVALID_ARG, "bad pair count");
+    if (num_q < 1 || num_c < 1) return fail(h, NNSEMD_ERR_INVALID_ARG, "empty embedding table");
+    if (q_idx == nullptr && c_idx == nullptr && num_c < num_pairs)
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "fewer candidate rows than pairs without an index table");
+    if (num_pairs == 0) return NNSEMD_OK;
+    if (theta == nullptr || Eq == nullptr || Ec == nullptr || pred == nullptr)
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "NULL array");
+    DeviceGuard g(h->device);
+    sg::SgQuant q;
+    nnsemd_status_t s = sg_quantize(h, theta, q, stream);
+    if (s != NNSEMD_OK) return s;
+    if ((s = sg_workspace(h, sg_predict_bytes(num_pairs))) != NNSEMD_OK) return s;
+    const sg::SgPredictWork w = sg_predict_carve(h->sg_ws, num_pairs);
+    const int err =
+        sg::launch_predict(theta, q, Eq, num_q, Ec, num_c, q_idx, c_idx, 0, num_pairs, w, nullptr, pred, stream);
+    if (err != 0) return device_fail(h, err, "surrogate prediction");
+    return NNSEMD_OK;
+}
+
+namespace {
+// Carve the training workspace for B pairs and P points; returns bytes
+// needed (base == nullptr: size only).
+size_t sg_train_carve(char* base, int64_t B, int64_t P, bool own_grad, sg::SgTrainWork& w, float** grad) {
+    constexpr int64_t Hd = kSgHidden;
+    const int64_t Ppad = (P + 63) / 64 * 64, Bpad = (B + 63) / 64 * 64, S = 2 * B;
+    const int64_t nblk = std::max<int64_t>(1, (P + 511) / 512);
+    Carver c;
+    const size_t oH1 = c.take(2 * Ppad * Hd), oH1T = c.take(2 * Ppad * Hd);
+    const size_t odP = c.take(2 * Ppad * Hd), odPT = c.take(2 * Ppad * Hd);
+    const size_t oPRE2 = c.take(4 * Ppad * Hd), odH1 = c.take(4 * Ppad * Hd);
+    const size_t oE = c.take(4 * S * Hd), odE = c.take(4 * S * Hd);
+    const size_t oZ = c.take(2 * Bpad * 3 * Hd), oZT = c.take(2 * Bpad * 3 * Hd);
+    const size_t odG = c.take(2 * Bpad * Hd), odGT = c.take(2 * Bpad * Hd);
+    const size_t oPRE3 = c.take(4 * Bpad * Hd), odZ = c.take(4 * Bpad * 3 * Hd);
+    const size_t oHB = c.take(4 * Bpad * kSgHbCols), ohs = c.take(4 * kSgHbCols);
+    const size_t ot = c.take(4 * Bpad), opred = c.take(4 * Bpad), odb2 = c.take(4 * S * Hd);
+    const size_t osplit = c.take(4 * 64 * Hd * Hd), ol1p = c.take(4 * nblk * 4 * Hd), ol1s = c.take(4 * 4 * Hd);
+    const size_t obad = c.take(64);
+    const size_t ograd = own_grad ? c.take(4 * kSgParams) : 0;
+    if (base != nullptr) {
+        auto F = [&](size_t o) { return reinterpret_cast<float*>(base + o); };
+        auto U = [&](size_t o) { return reinterpret_cast<uint16_t*>(base + o); };
+        w.H1q = U(oH1);
+        w.H1qT = U(oH1T);
+        w.dP2q = U(odP);
+        w.dP2qT = U(odPT);
+        w.PRE2 = F(oPRE2);
+        w.dH1 = F(odH1);
+        w.E = F(oE);
+        w.dE = F(odE);
+        w.Z = U(oZ);
+        w.ZT = U(oZT);
+        w.dGq = U(odG);
+        w.dGqT = U(odGT);
+        w.PRE3 = F(oPRE3);
+        w.dZ = F(odZ);
+        w.HB = F(oHB);
+        w.hsum = F(ohs);
+        w.t = F(ot);
+        w.pred = F(opred);
+        w.db2p = F(odb2);
+        w.split = F(osplit);
+        w.l1p = F(ol1p);
+        w.l1s = F(ol1s);
+        w.bad = reinterpret_cast<int*>(base + obad);
+        if (own_grad) *grad = F(ograd);
+    }
+    return align_up(c.off, 256);
+}
+
+nnsemd_status_t sg_loss_grad_common(nnsemd_handle_t h, const float* theta, const float* X, const float* a,
+                                    const int64_t* set_off, int64_t num_pairs, int64_t num_points,
+                                    const float* labels, float* loss, float** grad, sg::SgQuant& q, void* stream) {
+    if (num_pairs < 1 || num_pairs > (1 << 20) || num_points < 1 || num_points > (int64_t)1 << 26)
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "training batch: 1 <= pairs <= 2^20, 1 <= points <= 2^26");
+    if (theta == nullptr || X == nullptr || a == nullptr || set_off == nullptr || labels == nullptr)
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "NULL array");
+    nnsemd_status_t s = sg_quantize(h, theta, q, stream);
+    if (s != NNSEMD_OK) return s;
+    sg::SgTrainWork w;
+    const bool own = *grad == nullptr;
+    const size_t need = sg_train_carve(nullptr, num_pairs, num_points, own, w, grad);
+    if ((s = sg_workspace(h, need)) != NNSEMD_OK) return s;
+    sg_train_carve(h->sg_ws, num_pairs, num_points, own, w, grad);
+    const int err = sg::launch_loss_grad(theta, q, X, a, set_off, num_pairs, num_points, labels, w, loss, *grad, stream);
+    if (err != 0) return device_fail(h, err, "surrogate backward");
+    return NNSEMD_OK;
+}
+}  // namespace
+
+nnsemd_status_t nnsemd_sg_loss_grad(nnsemd_handle_t h, const float* theta, const float* X, const float* a,
+                                    const int64_t* set_off, int64_t num_pairs, int64_t num_points,
+                                    const float* labels, float* loss, float* grad, void* stream) {
+    if (h == nullptr) return NNSEMD_ERR_INVALID_ARG;
+    h->last_error.clear();
+    if (grad == nullptr) return fail(h, NNSEMD_ERR_INVALID_ARG, "grad must not be NULL");
+    DeviceGuard g(h->device);
+    sg::SgQuant q;
+    return sg_loss_grad_common(h, theta, X, a, set_off, num_pairs, num_points, labels, loss, &grad, q, stream);
+}
+
+nnsemd_status_t nnsemd_sg_train_step(nnsemd_handle_t h, float* theta, float* adam_m, float* adam_v, int64_t step,
+                                     float lr, const float* X, const float* a, const int64_t* set_off,
+                                     int64_t num_pairs, int64_t num_points, const float* labels, float* loss,
+                                     float* grad, void* stream) {
+    if (h == nullptr) return NNSEMD_ERR_INVALID_ARG;
+    h->last_error.clear();
+    if (adam_m == nullptr || adam_v == nullptr || step < 1 || !(lr > 0.f))
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "Adam state, step >= 1 and lr > 0 required");
+    DeviceGuard g(h->device);
+    sg::SgQuant q;
+    nnsemd_status_t s =
+        sg_loss_grad_common(h, theta, X, a, set_off, num_pairs, num_points, labels, loss, &grad, q, stream);
+    if (s != NNSEMD_OK) return s;
+    const double beta1 = 0.9, beta2 = 0.999;
+    const float bc1 = (float)(1.0 - std::pow(beta1, (double)step));
+    const float bc2 = (float)(1.0 - std::pow(beta2, (double)step));
+    const int err = sg::launch_adam(theta, adam_m, adam_v, grad, lr, beta1, beta2, 1e-8f, bc1, bc2, stream);
+    if (err != 0) return device_fail(h, err, "Adam update");
+    return NNSEMD_OK;
+}
+
+nnsemd_status_t nnsemd_topk_smallest_f32(nnsemd_handle_t h, const float* values, int64_t n, int32_t k, int32_t* idx,
+                                         void* stream) {
+    if (h == nullptr) return NNSEMD_ERR_INVALID_ARG;
+    h->last_error.clear();
+    if (values == nullptr || idx == nullptr || k < 1 || k > kSgTopkMax || n < k || n > 0x7fffffffLL)
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "top-k needs 1 <= k <= min(n, 1024), n < 2^31");
+    DeviceGuard g(h->device);
+    const int err = sg::launch_topk_f32(values, n, k, idx, stream);
+    if (err != 0) return device_fail(h, err, "top-k");
+    return NNSEMD_OK;
+}
+
+nnsemd_status_t nnsemd_topk_smallest_f64(nnsemd_handle_t h, const double* values, int64_t n, int32_t k, int32_t* idx,
+                                         void* stream) {
+    if (h == nullptr) return NNSEMD_ERR_INVALID_ARG;
+    h->last_error.clear();
+    if (values == nullptr || idx == nullptr || k < 1 || k > kSgTopkMax || n < k || n > 0x7fffffffLL)
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "top-k needs 1 <= k <= min(n, 1024), n < 2^31");
+    DeviceGuard g(h->device);
+    const int err = sg::launch_topk_f64(values, n, k, idx, stream);
+    if (err != 0) return device_fail(h, err, "top-k");
+    return NNSEMD_OK;
+}
+
+nnsemd_status_t nnsemd_sg_retrieve(nnsemd_handle_t h, const float* theta, const float* index_E, int64_t num_candidates,
+                                   const float* Xq, const float* aq, int64_t mq, const float* Ycat, const float* bcat,
+                                   const int64_t* y_off, int64_t max_n, int32_t keep, int32_t top, int32_t* out_idx,
+                                   double* out_cost, int32_t* kept_idx, nnsemd_stats_t* kept_stats, void* stream) {
+    if (h == nullptr) return NNSEMD_ERR_INVALID_ARG;
+    h->last_error.clear();
+    if (theta == nullptr || index_E == nullptr || Xq == nullptr || aq == nullptr || Ycat == nullptr ||
+        bcat == nullptr || y_off == nullptr || out_idx == nullptr || out_cost == nullptr)
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "NULL array");
+    if (num_candidates < 1 || num_candidates > kSgMaxRows || mq < 1 || max_n < 1 || keep < 1 ||
+        keep > kSgTopkMax || keep > num_candidates || top < 1 || top > keep)
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "need 1 <= top <= keep <= min(candidates, 1024), mq, max_n >= 1");
+    DeviceGuard g(h->device);
+    sg::SgQuant q;
+    nnsemd_status_t s = sg_quantize(h, theta, q, stream);
+    if (s != NNSEMD_OK) return s;
+    Carver c;
+    const size_t oEq = c.take(4 * kSgHidden), oqoff = c.take(2 * 8), opred = c.take(4 * (size_t)num_candidates);
+    const size_t osel = c.take(4 * (size_t)keep), ozero = c.take(4 * (size_t)keep), oxoff = c.take(16);
+    const size_t ocost = c.take(8 * (size_t)keep), opos = c.take(4 * (size_t)top);
+    const size_t ostats = c.take(sizeof(nnsemd_stats_t) * (size_t)keep);
+    const size_t opw = c.take(sg_predict_bytes(num_candidates));
+    if ((s = sg_workspace(h, align_up(c.off, 256))) != NNSEMD_OK) return s;
+    char* b = h->sg_ws;
+    float* Eq = reinterpret_cast<float*>(b + oEq);
+    int64_t* qoff = reinterpret_cast<int64_t*>(b + oqoff);
+    float* pred = reinterpret_cast<float*>(b + opred);
+    int32_t* sel = kept_idx ? kept_idx : reinterpret_cast<int32_t*>(b + osel);
+    int32_t* zeros = reinterpret_cast<int32_t*>(b + ozero);
+    int64_t* xoff = reinterpret_cast<int64_t*>(b + oxoff);
+    double* costs = reinterpret_cast<double*>(b + ocost);
+    int32_t* pos = reinterpret_cast<int32_t*>(b + opos);
+    nnsemd_stats_t* st = kept_stats ? kept_stats : reinterpret_cast<nnsemd_stats_t*>(b + ostats);
+    const sg::SgPredictWork pw = sg_predict_carve(b + opw, num_candidates);
+    int err = sg::launch_two_offsets(qoff, mq, stream);
+    if (err == 0) err = sg::launch_embed(theta, q, Xq, aq, qoff, 1, mq, Eq, stream);
+    if (err == 0)
+        err = sg::launch_predict(theta, q, Eq, 1, index_E, num_candidates, nullptr, nullptr, 0, num_candidates, pw,
+                                 nullptr, pred, stream);
+    if (err == 0) err = sg::launch_topk_f32(pred, num_candidates, keep, sel, stream);
+    if (err == 0) err = sg::launch_fill_i32(zeros, keep, 0, stream);
+    if (err == 0) err = sg::launch_two_offsets(xoff, mq, stream);
+    if (err != 0) return device_fail(h, err, "surrogate retrieval");
+    PairSolverArgs A{};
+    A.num_pairs = keep;
+    A.X = Xq;
+    A.a = aq;
+    A.x_off = xoff;
+    A.num_x_sets = 1;
+    A.Y = Ycat;
+    A.b = bcat;
+    A.y_off = y_off;
+    A.num_y_sets = num_candidates;
+    A.pair_x = zeros;
+    A.pair_y = sel;
+    A.metric = NNSEMD_L2;
+    A.costs = costs;
+    A.stats = st;
+    const nnsemd_options_t o = default_options();
+    if ((s = run_pairs(h, A, 3, mq, max_n, o, stream)) != NNSEMD_OK) return s;
+    err = sg::launch_topk_f64(costs, keep, top, pos, stream);
+    if (err == 0) err = sg::launch_gather_ranked(pos, sel, costs, top, out_idx, out_cost, stream);
+    if (err != 0) return device_fail(h, err, "re-rank selection");
+    return NNSEMD_OK;
 }
 
 #ifdef NNSEMD_PHASE_TIMING

@@ -185,6 +185,63 @@ __host__ __device__ inline size_t doc_slot_bytes(int max_m, int max_n) {
 int launch_doc_solver(const DocArgs& A, bool bf16_mfma, int chunk_max, size_t lds, int grid, void* stream,
                       int* blocks);
 
+// ---------------------------------------------------------------------
+// Deep-sets EMD surrogate (surrogate.hip).  Flat FP32 parameter layout:
+// W1 (H x 3), b1 (H), W2 (H x H), b2 (H), W3 (H x 3H), b3 (H), w4 (H), b4.
+constexpr int kSgHidden = 256;
+constexpr int64_t kSgW1 = 0;
+constexpr int64_t kSgB1 = kSgW1 + 3 * kSgHidden;
+constexpr int64_t kSgW2 = kSgB1 + kSgHidden;
+constexpr int64_t kSgB2 = kSgW2 + (int64_t)kSgHidden * kSgHidden;
+constexpr int64_t kSgW3 = kSgB2 + kSgHidden;
+constexpr int64_t kSgB3 = kSgW3 + (int64_t)kSgHidden * 3 * kSgHidden;
+constexpr int64_t kSgW4 = kSgB3 + kSgHidden;
+constexpr int64_t kSgB4 = kSgW4 + kSgHidden;
+constexpr int64_t kSgParams = kSgB4 + 1;
+constexpr int kSgHbCols = 2 * kSgHidden + 8;  // head-backward row: dg | dt*g | dt | r^2/B | pad
+constexpr int kSgTopkMax = 1024;
+
+namespace sg {
+// BF16 (and BF16-rounded FP32) copies of the weights used by the kernels.
+struct SgQuant {
+    float* W1;      // H x 3, rounded
+    float* w4;      // H, rounded
+    uint16_t* W2;   // H x H   [out][in]
+    uint16_t* W2T;  // H x H   [in][out]
+    uint16_t* W3;   // H x 3H  [out][in]
+    uint16_t* W3T;  // 3H x H  [in][out]
+};
+struct SgPredictWork {
+    uint16_t* Z;  // Bpad x 3H
+    float* PRE3;  // B x H
+};
+struct SgTrainWork {
+    uint16_t *H1q, *H1qT, *dP2q, *dP2qT;  // Ppad x H and H x Ppad
+    float *PRE2, *dH1;                    // P x H
+    float *E, *dE;                        // 2B x H
+    uint16_t *Z, *ZT, *dGq, *dGqT;        // Bpad x 3H, 3H x Bpad, Bpad x H, H x Bpad
+    float *PRE3, *dZ, *HB, *hsum, *t, *pred, *db2p, *split, *l1p, *l1s;
+    int* bad;  // offsets check
+};
+int launch_prepare(const float* theta, const SgQuant& q, void* stream);
+int launch_embed(const float* theta, const SgQuant& q, const float* X, const float* a, const int64_t* set_off,
+                 int64_t num_sets, int64_t num_points, float* E, void* stream);
+int launch_predict(const float* theta, const SgQuant& q, const float* Eq, int64_t nq, const float* Ec, int64_t nc,
+                   const int32_t* qi, const int32_t* ci, int train_layout, int64_t B, const SgPredictWork& w,
+                   float* t_out, float* pred, void* stream);
+int launch_loss_grad(const float* theta, const SgQuant& q, const float* X, const float* a, const int64_t* set_off,
+                     int64_t B, int64_t P, const float* labels, const SgTrainWork& w, float* loss, float* grad,
+                     void* stream);
+int launch_adam(float* theta, float* m, float* v, const float* grad, float lr, double beta1, double beta2, float eps,
+                float bc1, float bc2, void* stream);
+int launch_topk_f32(const float* vals, int64_t n, int k, int32_t* out, void* stream);
+int launch_topk_f64(const double* vals, int64_t n, int k, int32_t* out, void* stream);
+int launch_gather_ranked(const int32_t* pos, const int32_t* sel, const double* vals, int k, int32_t* out_idx,
+                         double* out_val, void* stream);
+int launch_fill_i32(int32_t* p, int64_t n, int32_t v, void* stream);
+int launch_two_offsets(int64_t* off, int64_t m, void* stream);
+}  // namespace sg
+
 // Launch entry points (defined in pair_solver.hip).
 // Returns hipSuccess-compatible int (0 on success).
 int launch_pair_solver(const PairSolverArgs& args, int d, int threads, int chunk_max,

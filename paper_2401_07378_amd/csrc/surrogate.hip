@@ -1,0 +1,780 @@
+// Deep-sets EMD surrogate: kernels and their host launchers.
+//
+// The surrogate is a learned pre-filter for retrieval (not part of the
+// paper, whose method it serves): NNS-EMD re-ranks what it keeps.
+//   phi(x)  = relu(W2 relu(W1 x + b1) + b2)          per point, 3 -> 256 -> 256
+//   E(X, a) = sum_i a_i phi(x_i)                      mass-weighted pooling
+//   z       = [E_q, E_c, |E_q - E_c|]                 768
+//   pred    = softplus(w4 . relu(W3 z + b3) + b4)
+//   loss    = mean_b (log pred_b - log y_b)^2
+// Weights are used rounded to BF16 (FP32 master copies are optimised); the
+// operands of the matrix-core products (layer-1 activations, pair features,
+// back-propagated layer-2 and head gradients) are BF16; accumulation, biases,
+// activations, pooling and the optimiser are FP32.
+//
+// Kernels: a generic BF16 "NT" GEMM on v_mfma_f32_16x16x32_bf16 (C = A B^T,
+// both operands K-contiguous, optional split-K), a fused phi + pooling
+// kernel for inference (one workgroup per set, no workspace), unfused layer
+// kernels for training, LDS transposes, deterministic column sums, Adam, and
+// a radix top-k.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "internal.hpp"
+
+namespace nnsemd {
+namespace sg {
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+constexpr int H = kSgHidden;
+
+__device__ inline uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;  // NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ inline float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ inline float bfround(float f) { return bf2f(f2bf(f)); }
+
+__device__ inline float softplusf(float t) { return t > 20.f ? t : log1pf(expf(t)); }
+// ReLU that keeps NaN (fmaxf would return 0 for it).
+__device__ inline float relu_nan(float v) { return v != v ? v : fmaxf(v, 0.f); }
+__device__ inline float sigmoidf(float t) { return 1.f / (1.f + expf(-t)); }
+
+// 16-byte fragment of 8 consecutive BF16 values (zeros outside the matrix).
+__device__ inline bf16x8 frag16(const uint16_t* __restrict__ base, int64_t ld, int r, int rows, int k) {
+    union {
+        uint4 q;
+        bf16x8 v;
+    } u;
+    if (r < rows) {
+        u.q = *reinterpret_cast<const uint4*>(base + (int64_t)r * ld + k);
+    } else {
+        u.q = make_uint4(0u, 0u, 0u, 0u);
+    }
+    return u.v;
+}
+
+// ---------------------------------------------------------------- weights
+__global__ void prepare_kernel(const float* __restrict__ theta, SgQuant q) {
+    const int64_t n = (int64_t)H * H + (int64_t)H * 3 * H + H * 3 + H;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        if (e < (int64_t)H * H) {
+            const int o = (int)(e / H), i = (int)(e % H);
+            const uint16_t b = f2bf(theta[kSgW2 + e]);
+            q.W2[(int64_t)o * H + i] = b;
+            q.W2T[(int64_t)i * H + o] = b;
+            continue;
+        }
+        int64_t f = e - (int64_t)H * H;
+        if (f < (int64_t)H * 3 * H) {
+            const int o = (int)(f / (3 * H)), i = (int)(f % (3 * H));
+            const uint16_t b = f2bf(theta[kSgW3 + f]);
+            q.W3[(int64_t)o * 3 * H + i] = b;
+            q.W3T[(int64_t)i * H + o] = b;
+            continue;
+        }
+        f -= (int64_t)H * 3 * H;
+        if (f < H * 3) {
+            q.W1[f] = bfround(theta[kSgW1 + f]);
+            continue;
+        }
+        f -= H * 3;
+        q.w4[f] = bfround(theta[kSgW4 + f]);
+    }
+}
+
+// ---------------------------------------------------------------- GEMM
+// C[M x N] (+ split z * c_split) = A[M x K] B[N x K]^T over K range of split z.
+// Workgroup tile 64 x 64, four wavefronts of 32 x 32 (2 x 2 MFMA blocks).
+// Requires lda, ldb multiples of 8, K multiple of 32, 16-byte aligned bases.
+__global__ __launch_bounds__(256) void gemm_nt_kernel(const uint16_t* __restrict__ A, int64_t lda,
+                                                      const uint16_t* __restrict__ B, int64_t ldb,
+                                                      float* __restrict__ C, int64_t ldc, int M, int N, int K,
+                                                      int kchunk, int64_t c_split) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int m0 = blockIdx.x * 64 + (wave >> 1) * 32;
+    const int n0 = blockIdx.y * 64 + (wave & 1) * 32;
+    const int kb = blockIdx.z * kchunk;
+    const int ke = min(K, kb + kchunk);
+    const int r16 = lane & 15, kq = 8 * (lane >> 4);
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    if (kb < ke) {
+        bf16x8 a0 = frag16(A, lda, m0 + r16, M, kb + kq);
+        bf16x8 a1 = frag16(A, lda, m0 + 16 + r16, M, kb + kq);
+        bf16x8 b0 = frag16(B, ldb, n0 + r16, N, kb + kq);
+        bf16x8 b1 = frag16(B, ldb, n0 + 16 + r16, N, kb + kq);
+        for (int k = kb; k < ke; k += 32) {
+            bf16x8 na0 = a0, na1 = a1, nb0 = b0, nb1 = b1;
+            if (k + 32 < ke) {
+                na0 = frag16(A, lda, m0 + r16, M, k + 32 + kq);
+                na1 = frag16(A, lda, m0 + 16 + r16, M, k + 32 + kq);
+                nb0 = frag16(B, ldb, n0 + r16, N, k + 32 + kq);
+                nb1 = frag16(B, ldb, n0 + 16 + r16, N, k + 32 + kq);
+            }
+            acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
+            a0 = na0;
+            a1 = na1;
+            b0 = nb0;
+            b1 = nb1;
+        }
+    }
+    float* Cz = C + (int64_t)blockIdx.z * c_split;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = m0 + 16 * a + 4 * (lane >> 4) + r;
+                const int j = n0 + 16 * b + r16;
+                if (i < M && j < N) Cz[(int64_t)i * ldc + j] = acc[a][b][r];
+            }
+}
+
+// out[i] = sum_z parts[z * stride + i], z ascending.
+__global__ void sum_splits_kernel(const float* __restrict__ parts, int splits, int64_t stride, float* __restrict__ out,
+                                  int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        float s = 0.f;
+        for (int z = 0; z < splits; ++z) s += parts[(int64_t)z * stride + i];
+        out[i] = s;
+    }
+}
+
+// out[j] (+)= sum over rows r of in[r * ld + j], r ascending (j < cols).
+__global__ void colsum_kernel(const float* __restrict__ in, int64_t rows, int64_t ld, int cols, float* __restrict__ out,
+                              int accumulate) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= cols) return;
+    float s = 0.f;
+    for (int64_t r = 0; r < rows; ++r) s += in[r * ld + j];
+    out[j] = accumulate ? out[j] + s : s;
+}
+
+// out[c * ldo + r] = in[r * ldi + c] for r < R (zeros for R <= r < Rpad), c < C.
+__global__ __launch_bounds__(256) void transpose_kernel(const uint16_t* __restrict__ in, int64_t ldi, int R, int Rpad,
+                                                        int Cc, uint16_t* __restrict__ out, int64_t ldo) {
+    __shared__ uint16_t t[64][66];
+    const int r0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int rr = e / 64, cc = e % 64;
+        const int r = r0 + rr, c = c0 + cc;
+        t[rr][cc] = (r < R && c < Cc) ? in[(int64_t)r * ldi + c] : (uint16_t)0;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int cc = e / 64, rr = e % 64;
+        const int r = r0 + rr, c = c0 + cc;
+        if (r < Rpad && c < Cc) out[(int64_t)c * ldo + r] = t[rr][cc];
+    }
+}
+
+// ---------------------------------------------------------------- phi
+__device__ inline float layer1_pre(const float* __restrict__ x, const float* __restrict__ W1q,
+                                   const float* __restrict__ b1, int j) {
+    return fmaf(x[2], W1q[3 * j + 2], fmaf(x[1], W1q[3 * j + 1], fmaf(x[0], W1q[3 * j], b1[j])));
+}
+
+// H1q[p][j] = bf16(relu(W1 x_p + b1)) for p < P, zero rows up to Ppad.
+__global__ __launch_bounds__(256) void layer1_kernel(const float* __restrict__ X, int64_t P, int64_t Ppad,
+                                                     const float* __restrict__ W1q, const float* __restrict__ b1,
+                                                     uint16_t* __restrict__ H1q) {
+    const int j = threadIdx.x;
+    for (int64_t p = blockIdx.x; p < Ppad; p += gridDim.x) {
+        float h = 0.f;
+        if (p < P) h = fmaxf(layer1_pre(X + 3 * p, W1q, b1, j), 0.f);
+        H1q[p * H + j] = f2bf(h);
+    }
+}
+
+// Point range of set s clamped to [0, P) (offsets are caller data; bad
+// offsets make the loss NaN, never an access outside the buffers).
+__device__ inline void set_range(const int64_t* __restrict__ off, int64_t s, int64_t P, int64_t& lo, int64_t& hi) {
+    lo = min<int64_t>(max<int64_t>(off[s], 0), P);
+    hi = min<int64_t>(max<int64_t>(off[s + 1], lo), P);
+}
+
+// flag = 1 unless off[0] == 0, off is non-decreasing and off[S] == P.
+__global__ void check_offsets_kernel(const int64_t* __restrict__ off, int64_t S, int64_t P, int* __restrict__ flag) {
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = (off[0] != 0 || off[S] != P) ? 1 : 0;
+    __syncthreads();
+    for (int64_t s = threadIdx.x; s < S; s += blockDim.x)
+        if (off[s + 1] < off[s]) bad = 1;
+    __syncthreads();
+    if (threadIdx.x == 0) *flag = bad;
+}
+
+// E[s][j] = sum_{p in s} a_p relu(PRE2[p][j] + b2[j]), p ascending.
+__global__ __launch_bounds__(256) void pool_kernel(const float* __restrict__ PRE2, const float* __restrict__ b2,
+                                                   const float* __restrict__ a, const int64_t* __restrict__ off,
+                                                   int64_t P, float* __restrict__ E) {
+    const int s = blockIdx.x, j = threadIdx.x;
+    const float bj = b2[j];
+    int64_t lo, hi;
+    set_range(off, s, P, lo, hi);
+    float acc = 0.f;
+    for (int64_t p = lo; p < hi; ++p) acc = fmaf(a[p], fmaxf(PRE2[p * H + j] + bj, 0.f), acc);
+    E[(int64_t)s * H + j] = acc;
+}
+
+// Fused inference: one workgroup per set, 64 points at a time: layer 1 into
+// LDS (BF16), layer 2 on the matrix cores (each wavefront 64 points x 64
+// outputs), bias + ReLU + mass weighting, column sums kept in registers.
+__global__ __launch_bounds__(256) void embed_fused_kernel(const float* __restrict__ X, const float* __restrict__ a,
+                                                          const int64_t* __restrict__ off, int64_t P, SgQuant q,
+                                                          const float* __restrict__ theta, float* __restrict__ E) {
+    constexpr int LD = H + 8;  // padded row (elements) against bank conflicts
+    __shared__ __align__(16) uint16_t h1[64 * LD];
+    __shared__ float am[64];
+    const int s = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r16 = lane & 15, kq = 8 * (lane >> 4);
+    const float* b1 = theta + kSgB1;
+    const float* b2 = theta + kSgB2;
+    int64_t lo, hi;
+    set_range(off, s, P, lo, hi);
+    float colsum[4] = {0.f, 0.f, 0.f, 0.f};  // column 64 wave + 16 b + r16, after the lane reduction
+    for (int64_t p0 = lo; p0 < hi; p0 += 64) {
+        const int np = (int)min<int64_t>(64, hi - p0);
+        for (int e = tid; e < 64 * H; e += 256) {
+            const int pr = e / H, j = e % H;
+            float h = 0.f;
+            if (pr < np) h = fmaxf(layer1_pre(X + 3 * (p0 + pr), q.W1, b1, j), 0.f);
+            h1[pr * LD + j] = f2bf(h);
+        }
+        if (tid < 64) am[tid] = tid < np ? a[p0 + tid] : 0.f;
+        __syncthreads();
+        f32x4 acc[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[i][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < H; k0 += 32) {
+            bf16x8 bfr[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) bfr[b] = frag16(q.W2, H, wave * 64 + 16 * b + r16, H, k0 + kq);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                union {
+                    uint4 u;
+                    bf16x8 v;
+                } af;
+                af.u = *reinterpret_cast<const uint4*>(&h1[(16 * i + r16) * LD + k0 + kq]);
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    acc[i][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af.v, bfr[b], acc[i][b], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const float bj = b2[wave * 64 + 16 * b + r16];
+            float part = 0.f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int pr = 16 * i + 4 * (lane >> 4) + r;
+                    part = fmaf(am[pr], fmaxf(acc[i][b][r] + bj, 0.f), part);
+                }
+            part += __shfl_xor(part, 16);
+            part += __shfl_xor(part, 32);
+            colsum[b] += part;
+        }
+        __syncthreads();
+    }
+    if (lane < 16) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) E[(int64_t)s * H + wave * 64 + 16 * b + lane] = colsum[b];
+    }
+}
+
+// ---------------------------------------------------------------- head
+// Zq[b] = bf16([Eq, Ec, |Eq - Ec|]) for b < B, zero rows up to Bpad.
+// Rows outside the tables (nq, nc rows) give NaN features, hence NaN pred.
+__global__ __launch_bounds__(256) void build_z_kernel(const float* __restrict__ Eq_tab, const float* __restrict__ Ec_tab,
+                                                      const int32_t* __restrict__ qi, const int32_t* __restrict__ ci,
+                                                      int64_t nq, int64_t nc, int train_layout, int64_t B,
+                                                      int64_t Bpad, uint16_t* __restrict__ Z) {
+    const int j = threadIdx.x;
+    for (int64_t b = blockIdx.x; b < Bpad; b += gridDim.x) {
+        float vq = 0.f, vc = 0.f;
+        if (b < B) {
+            const int64_t sq = train_layout ? 2 * b : (qi ? (int64_t)qi[b] : 0);
+            const int64_t sc = train_layout ? 2 * b + 1 : (ci ? (int64_t)ci[b] : b);
+            vq = (sq >= 0 && sq < nq) ? Eq_tab[sq * H + j] : NAN;
+            vc = (sc >= 0 && sc < nc) ? Ec_tab[sc * H + j] : NAN;
+        }
+        uint16_t* zr = Z + b * 3 * H;
+        zr[j] = f2bf(vq);
+        zr[H + j] = f2bf(vc);
+        zr[2 * H + j] = f2bf(fabsf(vq - vc));
+    }
+}
+
+// One wavefront per pair: t = w4 . relu(PRE3 + b3) + b4, pred = softplus(t).
+__global__ __launch_bounds__(256) void head_fwd_kernel(const float* __restrict__ PRE3, const float* __restrict__ theta,
+                                                       const float* __restrict__ w4q, int64_t B,
+                                                       float* __restrict__ t_out, float* __restrict__ pred) {
+    const int lane = threadIdx.x & 63;
+    const int64_t b = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (b >= B) return;
+    const float* b3 = theta + kSgB3;
+    float s = 0.f;
+#pragma unroll
+    for (int u = 0; u < H / 64; ++u) {
+        const int j = lane + 64 * u;
+        s = fmaf(relu_nan(PRE3[b * H + j] + b3[j]), w4q[j], s);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) {
+        const float t = s + theta[kSgB4];
+        if (t_out) t_out[b] = t;
+        pred[b] = softplusf(t);
+    }
+}
+
+// Head backward, one wavefront per pair.  Row b of HB (ld kSgHbCols):
+// [dg (H) | dt * g (H) | dt | r^2 / B]; dGq[b] = bf16(dg).
+__global__ __launch_bounds__(256) void head_bwd_kernel(const float* __restrict__ PRE3, const float* __restrict__ theta,
+                                                       const float* __restrict__ w4q, const float* __restrict__ t_in,
+                                                       const float* __restrict__ pred, const float* __restrict__ y,
+                                                       int64_t B, float* __restrict__ HB, uint16_t* __restrict__ dGq) {
+    const int lane = threadIdx.x & 63;
+    const int64_t b = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (b >= B) return;
+    const float* b3 = theta + kSgB3;
+    const float pv = pred[b];
+    const float r = logf(pv) - logf(y[b]);
+    const float dpred = 2.f * r / ((float)B * pv);
+    const float dt = dpred * sigmoidf(t_in[b]);
+    float* row = HB + b * kSgHbCols;
+#pragma unroll
+    for (int u = 0; u < H / 64; ++u) {
+        const int j = lane + 64 * u;
+        const float pre = PRE3[b * H + j] + b3[j];
+        const float g = relu_nan(pre);
+        const float dg = pre > 0.f ? dt * w4q[j] : 0.f;
+        row[j] = dg;
+        row[H + j] = dt * g;
+        dGq[b * H + j] = f2bf(dg);
+    }
+    if (lane == 0) {
+        row[2 * H] = dt;
+        row[2 * H + 1] = r * r / (float)B;
+    }
+}
+
+// dE of the two sets of pair b from dZ (B x 3H).
+__global__ void dz_to_de_kernel(const float* __restrict__ dZ, const float* __restrict__ E, int64_t B,
+                                float* __restrict__ dE) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < B * H; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = e / H;
+        const int j = (int)(e % H);
+        const float q = E[2 * b * H + j], c = E[(2 * b + 1) * H + j];
+        const float sg = (float)((q > c) - (q < c));
+        const float* dz = dZ + b * 3 * H;
+        dE[2 * b * H + j] = fmaf(dz[2 * H + j], sg, dz[j]);
+        dE[(2 * b + 1) * H + j] = dz[H + j] - dz[2 * H + j] * sg;
+    }
+}
+
+// dPRE2[p][j] = a_p dE[s][j] where PRE2 + b2 > 0 (BF16), and the per-set
+// column sums (FP32, p ascending) for db2.
+__global__ __launch_bounds__(256) void pool_bwd_kernel(const float* __restrict__ PRE2, const float* __restrict__ b2,
+                                                       const float* __restrict__ a, const int64_t* __restrict__ off,
+                                                       int64_t P, const float* __restrict__ dE,
+                                                       uint16_t* __restrict__ dP2q, float* __restrict__ db2_part) {
+    const int s = blockIdx.x, j = threadIdx.x;
+    const float bj = b2[j];
+    const float de = dE[(int64_t)s * H + j];
+    int64_t lo, hi;
+    set_range(off, s, P, lo, hi);
+    float acc = 0.f;
+    for (int64_t p = lo; p < hi; ++p) {
+        const float v = PRE2[p * H + j] + bj > 0.f ? a[p] * de : 0.f;
+        acc += v;
+        dP2q[p * H + j] = f2bf(v);
+    }
+    db2_part[(int64_t)s * H + j] = acc;
+}
+
+// Partial sums over a chunk of points of dpre1 * [x, 1] (dW1, db1).
+__global__ __launch_bounds__(256) void layer1_bwd_kernel(const float* __restrict__ dH1, const float* __restrict__ X,
+                                                         const float* __restrict__ W1q, const float* __restrict__ b1,
+                                                         int64_t P, int64_t chunk, float* __restrict__ part) {
+    const int j = threadIdx.x;
+    const int64_t lo = blockIdx.x * chunk, hi = min<int64_t>(P, lo + chunk);
+    float gw0 = 0.f, gw1 = 0.f, gw2 = 0.f, gb = 0.f;
+    for (int64_t p = lo; p < hi; ++p) {
+        const float* x = X + 3 * p;
+        if (layer1_pre(x, W1q, b1, j) > 0.f) {
+            const float g = dH1[p * H + j];
+            gb += g;
+            gw0 = fmaf(g, x[0], gw0);
+            gw1 = fmaf(g, x[1], gw1);
+            gw2 = fmaf(g, x[2], gw2);
+        }
+    }
+    float* o = part + (int64_t)blockIdx.x * 4 * H;
+    o[3 * j] = gw0;
+    o[3 * j + 1] = gw1;
+    o[3 * j + 2] = gw2;
+    o[3 * H + j] = gb;
+}
+
+// Scatter of the head column sums into the flat gradient.
+__global__ void head_grad_scatter_kernel(const float* __restrict__ hsum, const int* __restrict__ bad,
+                                         float* __restrict__ grad, float* __restrict__ loss) {
+    const int j = threadIdx.x;
+    grad[kSgB3 + j] = hsum[j];
+    grad[kSgW4 + j] = hsum[H + j];
+    if (j == 0) {
+        grad[kSgB4] = hsum[2 * H];
+        if (loss) *loss = *bad ? NAN : hsum[2 * H + 1];
+    }
+}
+
+__global__ void layer1_grad_scatter_kernel(const float* __restrict__ s, float* __restrict__ grad) {
+    const int j = threadIdx.x;
+    grad[kSgW1 + 3 * j] = s[3 * j];
+    grad[kSgW1 + 3 * j + 1] = s[3 * j + 1];
+    grad[kSgW1 + 3 * j + 2] = s[3 * j + 2];
+    grad[kSgB1 + j] = s[3 * H + j];
+}
+
+// Adam with host-rounded coefficients (beta, 1 - beta each rounded once).
+__global__ void adam_kernel(float* __restrict__ theta, float* __restrict__ m, float* __restrict__ v,
+                            const float* __restrict__ g, int64_t n, float lr, float beta1, float omb1, float beta2,
+                            float omb2, float eps, float bc1, float bc2) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = beta1 * m[i] + omb1 * gi;
+        const float vi = beta2 * v[i] + omb2 * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        theta[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    }
+}
+
+// ---------------------------------------------------------------- top-k
+// Order-preserving unsigned keys: -0 == +0, NaN after everything.
+__device__ inline uint32_t ord_key(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return 0xffffffffu;
+    if ((u & 0x7fffffffu) == 0u) u = 0u;
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ inline uint64_t ord_key(double f) {
+    uint64_t u = (uint64_t)__double_as_longlong(f);
+    if ((u & 0x7fffffffffffffffull) > 0x7ff0000000000000ull) return ~0ull;
+    if ((u & 0x7fffffffffffffffull) == 0ull) u = 0ull;
+    return (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
+}
+
+constexpr int kTopkThreads = 1024;
+
+// The k smallest of n values, ascending by (value, index), in one workgroup:
+// radix select of the k-th key, stable collection, bitonic sort.
+template <typename V, typename K>
+__global__ __launch_bounds__(kTopkThreads) void topk_kernel(const V* __restrict__ vals, int64_t n, int k,
+                                                            int32_t* __restrict__ out) {
+    constexpr int T = kTopkThreads;
+    constexpr int NB = (int)sizeof(K) * 8;
+    __shared__ unsigned int hist[256];
+    __shared__ K skey[kSgTopkMax];
+    __shared__ int32_t sidx[kSgTopkMax];
+    __shared__ int64_t scan[T];
+    __shared__ K s_prefix;
+    __shared__ int64_t s_need;
+    const int tid = threadIdx.x;
+    const int64_t per = (n + T - 1) / T;
+    const int64_t lo = min<int64_t>(n, tid * per), hi = min<int64_t>(n, lo + per);
+    K prefix = 0, mask = 0;
+    int64_t need = k;
+    for (int shift = NB - 8; shift >= 0; shift -= 8) {
+        for (int b = tid; b < 256; b += T) hist[b] = 0u;
+        __syncthreads();
+        for (int64_t i = lo; i < hi; ++i) {
+            const K key = ord_key(vals[i]);
+            if ((key & mask) == prefix) atomicAdd(&hist[(int)((key >> shift) & 0xff)], 1u);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int64_t c = 0;
+            int b = 0;
+            for (; b < 255; ++b) {
+                if (c + (int64_t)hist[b] >= need) break;
+                c += hist[b];
+            }
+            s_prefix = prefix | ((K)b << shift);
+            s_need = need - c;
+        }
+        __syncthreads();
+        prefix = s_prefix;
+        need = s_need;
+        mask |= (K)0xff << shift;
+        __syncthreads();
+    }
+    // prefix = key of the k-th smallest; need = how many of that key to take.
+    int64_t cl = 0, ce = 0;
+    for (int64_t i = lo; i < hi; ++i) {
+        const K key = ord_key(vals[i]);
+        cl += key < prefix;
+        ce += key == prefix;
+    }
+    scan[tid] = cl;
+    __syncthreads();
+    if (tid == 0) {
+        int64_t run = 0;
+        for (int t = 0; t < T; ++t) {
+            const int64_t v = scan[t];
+            scan[t] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    int64_t wl = scan[tid];
+    __syncthreads();
+    scan[tid] = ce;
+    __syncthreads();
+    if (tid == 0) {
+        int64_t run = 0;
+        for (int t = 0; t < T; ++t) {
+            const int64_t v = scan[t];
+            scan[t] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    const int64_t nless = k - need;
+    int64_t we = scan[tid];
+    for (int64_t i = lo; i < hi; ++i) {
+        const K key = ord_key(vals[i]);
+        if (key < prefix) {
+            skey[wl] = key;
+            sidx[wl] = (int32_t)i;
+            ++wl;
+        } else if (key == prefix) {
+            if (we < need) {
+                skey[nless + we] = key;
+                sidx[nless + we] = (int32_t)i;
+            }
+            ++we;
+        }
+    }
+    for (int e = k + tid; e < kSgTopkMax; e += T) {
+        skey[e] = ~(K)0;
+        sidx[e] = 0x7fffffff;
+    }
+    __syncthreads();
+    // bitonic sort of kSgTopkMax entries by (key, index)
+    for (int size = 2; size <= kSgTopkMax; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int e = tid; e < kSgTopkMax; e += T) {
+                const int o = e ^ stride;
+                if (o > e) {
+                    const bool up = (e & size) == 0;
+                    const bool gt = skey[e] > skey[o] || (skey[e] == skey[o] && sidx[e] > sidx[o]);
+                    if (gt == up) {
+                        const K tk = skey[e];
+                        skey[e] = skey[o];
+                        skey[o] = tk;
+                        const int32_t ti = sidx[e];
+                        sidx[e] = sidx[o];
+                        sidx[o] = ti;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int e = tid; e < k; e += T) out[e] = sidx[e];
+}
+
+// out_idx[r] = sel[pos[r]], out_val[r] = vals[pos[r]].
+__global__ void gather_ranked_kernel(const int32_t* __restrict__ pos, const int32_t* __restrict__ sel,
+                                     const double* __restrict__ vals, int k, int32_t* __restrict__ out_idx,
+                                     double* __restrict__ out_val) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= k) return;
+    const int p = pos[r];
+    out_idx[r] = sel[p];
+    if (out_val) out_val[r] = vals[p];
+}
+
+__global__ void fill_i32_kernel(int32_t* __restrict__ p, int64_t n, int32_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void two_offsets_kernel(int64_t* __restrict__ off, int64_t m) {
+    if (threadIdx.x == 0) {
+        off[0] = 0;
+        off[1] = m;
+    }
+}
+
+inline int grid_for(int64_t n, int per_block = 256, int cap = 65536) {
+    return (int)std::max<int64_t>(1, std::min<int64_t>((n + per_block - 1) / per_block, cap));
+}
+
+inline int gemm_nt(const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, float* C, int64_t ldc, int M,
+                   int N, int K, int splits, int64_t c_split, hipStream_t st) {
+    const int kchunk = ((K / splits + 31) / 32) * 32;
+    dim3 grid((M + 63) / 64, (N + 63) / 64, splits);
+    hipLaunchKernelGGL(gemm_nt_kernel, grid, dim3(256), 0, st, A, lda, B, ldb, C, ldc, M, N, K, kchunk, c_split);
+    return (int)hipGetLastError();
+}
+
+inline int transpose(const uint16_t* in, int64_t ldi, int R, int Rpad, int C, uint16_t* out, int64_t ldo,
+                     hipStream_t st) {
+    dim3 grid((Rpad + 63) / 64, (C + 63) / 64);
+    hipLaunchKernelGGL(transpose_kernel, grid, dim3(256), 0, st, in, ldi, R, Rpad, C, out, ldo);
+    return (int)hipGetLastError();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+int launch_prepare(const float* theta, const SgQuant& q, void* stream) {
+    hipLaunchKernelGGL(prepare_kernel, dim3(512), dim3(256), 0, (hipStream_t)stream, theta, q);
+    return (int)hipGetLastError();
+}
+
+int launch_embed(const float* theta, const SgQuant& q, const float* X, const float* a, const int64_t* set_off,
+                 int64_t num_sets, int64_t num_points, float* E, void* stream) {
+    if (num_sets == 0) return 0;
+    hipLaunchKernelGGL(embed_fused_kernel, dim3((unsigned)num_sets), dim3(256), 0, (hipStream_t)stream, X, a, set_off,
+                       num_points, q, theta, E);
+    return (int)hipGetLastError();
+}
+
+int launch_predict(const float* theta, const SgQuant& q, const float* Eq, int64_t nq, const float* Ec, int64_t nc,
+                   const int32_t* qi, const int32_t* ci, int train_layout, int64_t B, const SgPredictWork& w,
+                   float* t_out, float* pred, void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    if (B == 0) return 0;
+    const int64_t Bpad = (B + 63) / 64 * 64;
+    hipLaunchKernelGGL(build_z_kernel, dim3(grid_for(Bpad, 1)), dim3(256), 0, st, Eq, Ec, qi, ci, nq, nc, train_layout,
+                       B, Bpad, w.Z);
+    int err = (int)hipGetLastError();
+    if (err) return err;
+    err = gemm_nt(w.Z, 3 * H, q.W3, 3 * H, w.PRE3, H, (int)B, H, 3 * H, 1, 0, st);
+    if (err) return err;
+    hipLaunchKernelGGL(head_fwd_kernel, dim3((unsigned)((B + 3) / 4)), dim3(256), 0, st, w.PRE3, theta, q.w4, B, t_out,
+                       pred);
+    return (int)hipGetLastError();
+}
+
+int launch_loss_grad(const float* theta, const SgQuant& q, const float* X, const float* a, const int64_t* set_off,
+                     int64_t B, int64_t P, const float* labels, const SgTrainWork& w, float* loss, float* grad,
+                     void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t S = 2 * B;
+    const int64_t Ppad = (P + 63) / 64 * 64;
+    const int64_t Bpad = (B + 63) / 64 * 64;
+    int err;
+    hipLaunchKernelGGL(check_offsets_kernel, dim3(1), dim3(256), 0, st, set_off, S, P, w.bad);
+    // forward
+    hipLaunchKernelGGL(layer1_kernel, dim3(grid_for(Ppad, 1)), dim3(256), 0, st, X, P, Ppad, q.W1, theta + kSgB1,
+                       w.H1q);
+    if ((err = (int)hipGetLastError())) return err;
+    if ((err = gemm_nt(w.H1q, H, q.W2, H, w.PRE2, H, (int)P, H, H, 1, 0, st))) return err;
+    hipLaunchKernelGGL(pool_kernel, dim3((unsigned)S), dim3(256), 0, st, w.PRE2, theta + kSgB2, a, set_off, P, w.E);
+    if ((err = (int)hipGetLastError())) return err;
+    SgPredictWork pw{w.Z, w.PRE3};
+    if ((err = launch_predict(theta, q, w.E, S, w.E, S, nullptr, nullptr, 1, B, pw, w.t, w.pred, stream))) return err;
+    // head backward
+    hipLaunchKernelGGL(head_bwd_kernel, dim3((unsigned)((B + 3) / 4)), dim3(256), 0, st, w.PRE3, theta, q.w4, w.t,
+                       w.pred, labels, B, w.HB, w.dGq);
+    if ((err = (int)hipGetLastError())) return err;
+    hipLaunchKernelGGL(colsum_kernel, dim3((kSgHbCols + 255) / 256), dim3(256), 0, st, w.HB, B, (int64_t)kSgHbCols,
+                       kSgHbCols, w.hsum, 0);
+    hipLaunchKernelGGL(head_grad_scatter_kernel, dim3(1), dim3(256), 0, st, w.hsum, w.bad, grad, loss);
+    // dW3 = dG^T Z: both transposed to K = pair index
+    if ((err = transpose(w.dGq, H, (int)B, (int)Bpad, H, w.dGqT, Bpad, st))) return err;
+    if ((err = transpose(w.Z, 3 * H, (int)B, (int)Bpad, 3 * H, w.ZT, Bpad, st))) return err;
+    if ((err = gemm_nt(w.dGqT, Bpad, w.ZT, Bpad, grad + kSgW3, 3 * H, H, 3 * H, (int)Bpad, 1, 0, st))) return err;
+    // dZ = dG W3
+    if ((err = gemm_nt(w.dGq, H, q.W3T, H, w.dZ, 3 * H, (int)B, 3 * H, H, 1, 0, st))) return err;
+    hipLaunchKernelGGL(dz_to_de_kernel, dim3(grid_for(B * H)), dim3(256), 0, st, w.dZ, w.E, B, w.dE);
+    if ((err = (int)hipGetLastError())) return err;
+    // pooling and layer-2 backward
+    hipLaunchKernelGGL(pool_bwd_kernel, dim3((unsigned)S), dim3(256), 0, st, w.PRE2, theta + kSgB2, a, set_off, P,
+                       w.dE, w.dP2q, w.db2p);
+    if ((err = (int)hipGetLastError())) return err;
+    hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(256), 0, st, w.db2p, S, (int64_t)H, H, grad + kSgB2, 0);
+    if ((err = transpose(w.dP2q, H, (int)P, (int)Ppad, H, w.dP2qT, Ppad, st))) return err;
+    if ((err = transpose(w.H1q, H, (int)P, (int)Ppad, H, w.H1qT, Ppad, st))) return err;
+    const int splits = (int)std::max<int64_t>(1, std::min<int64_t>(64, Ppad / 2048));
+    if ((err = gemm_nt(w.dP2qT, Ppad, w.H1qT, Ppad, w.split, H, H, H, (int)Ppad, splits, (int64_t)H * H, st)))
+        return err;
+    hipLaunchKernelGGL(sum_splits_kernel, dim3(grid_for((int64_t)H * H)), dim3(256), 0, st, w.split, splits,
+                       (int64_t)H * H, grad + kSgW2, (int64_t)H * H);
+    // dH1 = dP2 W2
+    if ((err = gemm_nt(w.dP2q, H, q.W2T, H, w.dH1, H, (int)P, H, H, 1, 0, st))) return err;
+    const int64_t chunk = 512;
+    const int64_t nblk = std::max<int64_t>(1, (P + chunk - 1) / chunk);
+    hipLaunchKernelGGL(layer1_bwd_kernel, dim3((unsigned)nblk), dim3(256), 0, st, w.dH1, X, q.W1, theta + kSgB1, P,
+                       chunk, w.l1p);
+    if ((err = (int)hipGetLastError())) return err;
+    hipLaunchKernelGGL(colsum_kernel, dim3(4), dim3(256), 0, st, w.l1p, nblk, (int64_t)4 * H, 4 * H, w.l1s, 0);
+    hipLaunchKernelGGL(layer1_grad_scatter_kernel, dim3(1), dim3(256), 0, st, w.l1s, grad);
+    return (int)hipGetLastError();
+}
+
+int launch_adam(float* theta, float* m, float* v, const float* grad, float lr, double beta1, double beta2, float eps,
+                float bc1, float bc2, void* stream) {
+    hipLaunchKernelGGL(adam_kernel, dim3(grid_for(kSgParams)), dim3(256), 0, (hipStream_t)stream, theta, m, v, grad,
+                       (int64_t)kSgParams, lr, (float)beta1, (float)(1.0 - beta1), (float)beta2, (float)(1.0 - beta2),
+                       eps, bc1, bc2);
+    return (int)hipGetLastError();
+}
+
+int launch_topk_f32(const float* vals, int64_t n, int k, int32_t* out, void* stream) {
+    hipLaunchKernelGGL((topk_kernel<float, uint32_t>), dim3(1), dim3(kTopkThreads), 0, (hipStream_t)stream, vals, n, k,
+                       out);
+    return (int)hipGetLastError();
+}
+
+int launch_topk_f64(const double* vals, int64_t n, int k, int32_t* out, void* stream) {
+    hipLaunchKernelGGL((topk_kernel<double, uint64_t>), dim3(1), dim3(kTopkThreads), 0, (hipStream_t)stream, vals, n, k,
+                       out);
+    return (int)hipGetLastError();
+}
+
+int launch_gather_ranked(const int32_t* pos, const int32_t* sel, const double* vals, int k, int32_t* out_idx,
+                         double* out_val, void* stream) {
+    hipLaunchKernelGGL(gather_ranked_kernel, dim3((k + 255) / 256), dim3(256), 0, (hipStream_t)stream, pos, sel, vals, k,
+                       out_idx, out_val);
+    return (int)hipGetLastError();
+}
+
+int launch_fill_i32(int32_t* p, int64_t n, int32_t v, void* stream) {
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, p, n, v);
+    return (int)hipGetLastError();
+}
+
+int launch_two_offsets(int64_t* off, int64_t m, void* stream) {
+    hipLaunchKernelGGL(two_offsets_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, off, m);
+    return (int)hipGetLastError();
+}
+
+}  // namespace sg
+}  // namespace nnsemd

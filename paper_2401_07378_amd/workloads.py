@@ -212,29 +212,58 @@ def colour_transfer_3d(n: int = 65536, seed: int = SEEDS["colour_transfer_3d"]) 
                    meta={"n": n, "seed": seed})
 
 
-def retrieval_cloud(r, n: int = 256) -> np.ndarray:
-    """K ~ U{1..8} components, means U[0,1]^3, sigma U[0.02,0.2],
+def retrieval_clouds(r, count: int, n: int = 256) -> np.ndarray:
+    """count Gaussian-mixture clouds of n 3-D points, shape (count, n, 3):
+    K ~ U{1..8} components, means U[0,1]^3, isotropic sigma U[0.02,0.2],
     Dirichlet(1) component weights, no clipping."""
-    k = int(r.integers(1, 9))
-    w = r.standard_exponential(k)
-    w = w / w.sum()
-    return _gmm_cloud(r, n, k, 0.0, 1.0, 0.02, 0.2, w, False)
+    K = r.integers(1, 9, size=count)
+    means = r.uniform(0.0, 1.0, size=(count, 8, 3))
+    sig = r.uniform(0.02, 0.2, size=(count, 8))
+    w = r.standard_exponential((count, 8)) * (np.arange(8)[None, :] < K[:, None])
+    w = w / w.sum(axis=1, keepdims=True)
+    cw = np.cumsum(w, axis=1)
+    u = r.random((count, n))
+    comp = np.minimum((u[:, :, None] >= cw[:, None, :]).sum(axis=2), K[:, None] - 1)
+    rows = np.arange(count)[:, None]
+    pts = means[rows, comp] + r.standard_normal((count, n, 3)) * sig[rows, comp][..., None]
+    return to_f32(pts)
 
 
 def retrieval_3d(num_candidates: int = 100000, points: int = 256, query: int = 0,
                  seed: int = SEEDS["retrieval_3d"]) -> PairSet:
-    """Query q (suppliers) against every candidate (consumers).  Candidate c
-    draws from stream 1_000_000 + c; query q from stream q."""
-    qx = retrieval_cloud(rng_for(seed, query), points)
-    cands = [(retrieval_cloud(rng_for(seed, 1_000_000 + c), points), uniform_masses(points))
-             for c in range(num_candidates)]
+    """Query q (suppliers) against every candidate (consumers).  Candidates
+    come in blocks of 4096 drawn from stream 1_000_000 + block; query q from
+    stream q.  Uniform masses."""
+    qx = retrieval_clouds(rng_for(seed, query), 1, points)[0]
+    blocks = [retrieval_clouds(rng_for(seed, 1_000_000 + k), min(4096, num_candidates - 4096 * k), points)
+              for k in range((num_candidates + 4095) // 4096)]
+    Y = np.concatenate(blocks).reshape(-1, 3) if blocks else np.zeros((0, 3), np.float32)
+    b = np.tile(uniform_masses(points), num_candidates)
+    y_off = np.arange(num_candidates + 1, dtype=np.int64) * points
     Xc, ac, xo = _concat([(qx, uniform_masses(points))], 3)
-    Yc, bc, yo = _concat(cands, 3)
-    return PairSet("retrieval_3d", 3, Xc, ac, xo, Yc, bc, yo,
+    return PairSet("retrieval_3d", 3, Xc, ac, xo, np.ascontiguousarray(Y), b, y_off,
                    pair_x=np.zeros(num_candidates, np.int32),
                    pair_y=np.arange(num_candidates, dtype=np.int32), metric="l2",
                    meta={"num_candidates": num_candidates, "points": points, "query": query,
                          "seed": seed})
+
+
+def retrieval_query(query: int, points: int = 256, seed: int = SEEDS["retrieval_3d"]) -> np.ndarray:
+    """The query cloud q of retrieval_3d (stream q)."""
+    return retrieval_clouds(rng_for(seed, query), 1, points)[0]
+
+
+def surrogate_training_pairs(num_pairs: int, points: int = 256, seed: int = SEEDS["retrieval_3d"]):
+    """Training pairs for the surrogate, drawn like the retrieval clouds from
+    streams 2_000_000 + block (disjoint from queries and candidates):
+    returns (X, a, set_off) with pair b = (set 2b, set 2b+1)."""
+    sets = 2 * num_pairs
+    blocks = [retrieval_clouds(rng_for(seed, 2_000_000 + k), min(4096, sets - 4096 * k), points)
+              for k in range((sets + 4095) // 4096)]
+    X = np.concatenate(blocks).reshape(-1, 3) if blocks else np.zeros((0, 3), np.float32)
+    a = np.tile(uniform_masses(points), sets)
+    off = np.arange(sets + 1, dtype=np.int64) * points
+    return np.ascontiguousarray(X), a, off
 
 
 def random_pair(seed: int, m: int, n: int, d: int, masses: str = "dirichlet",
