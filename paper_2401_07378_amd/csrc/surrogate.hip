@@ -155,14 +155,25 @@ __global__ void sum_splits_kernel(const float* __restrict__ parts, int splits, i
     }
 }
 
-// out[j] (+)= sum over rows r of in[r * ld + j], r ascending (j < cols).
-__global__ void colsum_kernel(const float* __restrict__ in, int64_t rows, int64_t ld, int cols, float* __restrict__ out,
-                              int accumulate) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= cols) return;
+// out[j] (+)= sum over rows r of in[r * ld + j] (j < cols): 16 row slices
+// per column (rows r = slice mod 16, ascending), then the slices in order.
+constexpr int kColsumThreads = 1024;
+__global__ __launch_bounds__(kColsumThreads) void colsum_kernel(const float* __restrict__ in, int64_t rows, int64_t ld,
+                                                                int cols, float* __restrict__ out, int accumulate) {
+    __shared__ float part[16][64];
+    const int c = threadIdx.x & 63, slice = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + c;
     float s = 0.f;
-    for (int64_t r = 0; r < rows; ++r) s += in[r * ld + j];
-    out[j] = accumulate ? out[j] + s : s;
+    if (j < cols)
+        for (int64_t r = slice; r < rows; r += 16) s += in[r * ld + j];
+    part[slice][c] = s;
+    __syncthreads();
+    if (slice == 0 && j < cols) {
+        float t = 0.f;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) t += part[q][c];
+        out[j] = accumulate ? out[j] + t : t;
+    }
 }
 
 // out[c * ldo + r] = in[r * ldi + c] for r < R (zeros for R <= r < Rpad), c < C.
@@ -323,6 +334,97 @@ __global__ __launch_bounds__(256) void build_z_kernel(const float* __restrict__ 
         zr[j] = f2bf(vq);
         zr[H + j] = f2bf(vc);
         zr[2 * H + j] = f2bf(fabsf(vq - vc));
+    }
+}
+
+// Fused inference head: one workgroup per 64 pairs.  The pair features
+// [Eq, Ec, |Eq - Ec|] are built 64 at a time into LDS as BF16, each
+// wavefront multiplies them with 64 rows of W3 on the matrix cores (K = 768),
+// and the epilogue applies b3, ReLU and w4, sums the four wavefronts' parts
+// in order and writes softplus(t + b4).  Rows outside the tables give NaN.
+__global__ __launch_bounds__(256) void rho_fused_kernel(const float* __restrict__ Eq_tab, int64_t nq,
+                                                        const float* __restrict__ Ec_tab, int64_t nc,
+                                                        const int32_t* __restrict__ qi,
+                                                        const int32_t* __restrict__ ci, int64_t B, SgQuant q,
+                                                        const float* __restrict__ theta, float* __restrict__ pred) {
+    constexpr int LD = 64 + 8;
+    __shared__ __align__(16) uint16_t zt[64 * LD];
+    __shared__ int64_t rq[64], rc[64];
+    __shared__ float red[4][64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r16 = lane & 15, kq = 8 * (lane >> 4);
+    const int64_t b0 = (int64_t)blockIdx.x * 64;
+    if (tid < 64) {
+        const int64_t b = b0 + tid;
+        int64_t sq = -2, sc = -2;  // -2: padding row, -1: index outside the table
+        if (b < B) {
+            sq = qi ? (int64_t)qi[b] : 0;
+            sc = ci ? (int64_t)ci[b] : b;
+            if (sq < 0 || sq >= nq) sq = -1;
+            if (sc < 0 || sc >= nc) sc = -1;
+        }
+        rq[tid] = sq;
+        rc[tid] = sc;
+    }
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[i][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    for (int kc = 0; kc < 3 * H / 64; ++kc) {
+        __syncthreads();
+        const int part = kc / (H / 64), col0 = (kc % (H / 64)) * 64;
+        for (int e = tid; e < 64 * 64; e += 256) {
+            const int row = e >> 6, f = e & 63;
+            const int64_t sq = rq[row], sc = rc[row];
+            float v = 0.f;
+            if (sq == -1 || sc == -1) {
+                v = NAN;
+            } else if (sq >= 0) {
+                const float xq = Eq_tab[sq * H + col0 + f], xc = Ec_tab[sc * H + col0 + f];
+                v = part == 0 ? xq : (part == 1 ? xc : fabsf(xq - xc));
+            }
+            zt[row * LD + f] = f2bf(v);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            bf16x8 bfr[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) bfr[b] = frag16(q.W3, 3 * H, wave * 64 + 16 * b + r16, H, kc * 64 + ks * 32 + kq);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                union {
+                    uint4 u;
+                    bf16x8 v;
+                } af;
+                af.u = *reinterpret_cast<const uint4*>(&zt[(16 * i + r16) * LD + ks * 32 + kq]);
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    acc[i][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af.v, bfr[b], acc[i][b], 0, 0, 0);
+            }
+        }
+    }
+    const float* b3 = theta + kSgB3;
+    // per-row partial over this wavefront's 64 columns
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            float sum = 0.f;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int col = wave * 64 + 16 * b + r16;
+                sum = fmaf(relu_nan(acc[i][b][r] + b3[col]), q.w4[col], sum);
+            }
+#pragma unroll
+            for (int o = 1; o < 16; o <<= 1) sum += __shfl_xor(sum, o);
+            if (r16 == 0) red[wave][16 * i + 4 * (lane >> 4) + r] = sum;
+        }
+    __syncthreads();
+    if (tid < 64 && b0 + tid < B) {
+        const float t = ((red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid])) + theta[kSgB4];
+        pred[b0 + tid] = softplusf(t);
     }
 }
 
@@ -489,30 +591,47 @@ __device__ inline uint64_t ord_key(double f) {
 
 constexpr int kTopkThreads = 1024;
 
-// The k smallest of n values, ascending by (value, index), in one workgroup:
-// radix select of the k-th key, stable collection, bitonic sort.
+constexpr int kTopkCap = 2 * kSgTopkMax;  // sort buffer
+
+// The k smallest of n values, ascending by (value, index), in one workgroup.
+// 1. Radix select of the k-th key, 8-bit digits, coalesced passes; a
+//    wavefront whose active lanes share one digit adds them with one atomic
+//    (the leading digits of similar values would otherwise serialise).
+// 2. Collection: all keys below it, and the keys equal to it, into an LDS
+//    buffer (unordered); if the equal keys overflow the buffer they are
+//    collected again in index order instead, as many as needed.
+// 3. Bitonic sort of the buffer by (key, index); the first k are the answer.
 template <typename V, typename K>
 __global__ __launch_bounds__(kTopkThreads) void topk_kernel(const V* __restrict__ vals, int64_t n, int k,
                                                             int32_t* __restrict__ out) {
     constexpr int T = kTopkThreads;
     constexpr int NB = (int)sizeof(K) * 8;
     __shared__ unsigned int hist[256];
-    __shared__ K skey[kSgTopkMax];
-    __shared__ int32_t sidx[kSgTopkMax];
+    __shared__ K skey[kTopkCap];
+    __shared__ int32_t sidx[kTopkCap];
     __shared__ int64_t scan[T];
     __shared__ K s_prefix;
     __shared__ int64_t s_need;
+    __shared__ int cnt_less, cnt_eq;
     const int tid = threadIdx.x;
-    const int64_t per = (n + T - 1) / T;
-    const int64_t lo = min<int64_t>(n, tid * per), hi = min<int64_t>(n, lo + per);
+    const int lane = tid & 63;
     K prefix = 0, mask = 0;
     int64_t need = k;
     for (int shift = NB - 8; shift >= 0; shift -= 8) {
         for (int b = tid; b < 256; b += T) hist[b] = 0u;
         __syncthreads();
-        for (int64_t i = lo; i < hi; ++i) {
+        for (int64_t i = tid; i < n; i += T) {
             const K key = ord_key(vals[i]);
-            if ((key & mask) == prefix) atomicAdd(&hist[(int)((key >> shift) & 0xff)], 1u);
+            const int bin = (key & mask) == prefix ? (int)((key >> shift) & 0xff) : -1;
+            const uint64_t active = __ballot(1);
+            const int b0 = __builtin_amdgcn_readfirstlane(bin);
+            const uint64_t same = __ballot(bin == b0);
+            if (same == active) {
+                if (b0 >= 0 && lane == __ffsll((unsigned long long)active) - 1)
+                    atomicAdd(&hist[b0], (unsigned int)__popcll(active));
+            } else if (bin >= 0) {
+                atomicAdd(&hist[bin], 1u);
+            }
         }
         __syncthreads();
         if (tid == 0) {
@@ -524,6 +643,8 @@ __global__ __launch_bounds__(kTopkThreads) void topk_kernel(const V* __restrict_
             }
             s_prefix = prefix | ((K)b << shift);
             s_need = need - c;
+            cnt_less = 0;
+            cnt_eq = 0;
         }
         __syncthreads();
         prefix = s_prefix;
@@ -532,61 +653,58 @@ __global__ __launch_bounds__(kTopkThreads) void topk_kernel(const V* __restrict_
         __syncthreads();
     }
     // prefix = key of the k-th smallest; need = how many of that key to take.
-    int64_t cl = 0, ce = 0;
-    for (int64_t i = lo; i < hi; ++i) {
-        const K key = ord_key(vals[i]);
-        cl += key < prefix;
-        ce += key == prefix;
-    }
-    scan[tid] = cl;
-    __syncthreads();
-    if (tid == 0) {
-        int64_t run = 0;
-        for (int t = 0; t < T; ++t) {
-            const int64_t v = scan[t];
-            scan[t] = run;
-            run += v;
-        }
-    }
-    __syncthreads();
-    int64_t wl = scan[tid];
-    __syncthreads();
-    scan[tid] = ce;
-    __syncthreads();
-    if (tid == 0) {
-        int64_t run = 0;
-        for (int t = 0; t < T; ++t) {
-            const int64_t v = scan[t];
-            scan[t] = run;
-            run += v;
-        }
-    }
-    __syncthreads();
     const int64_t nless = k - need;
-    int64_t we = scan[tid];
-    for (int64_t i = lo; i < hi; ++i) {
+    for (int64_t i = tid; i < n; i += T) {
         const K key = ord_key(vals[i]);
         if (key < prefix) {
-            skey[wl] = key;
-            sidx[wl] = (int32_t)i;
-            ++wl;
+            const int p = atomicAdd(&cnt_less, 1);
+            skey[p] = key;
+            sidx[p] = (int32_t)i;
         } else if (key == prefix) {
-            if (we < need) {
-                skey[nless + we] = key;
-                sidx[nless + we] = (int32_t)i;
+            const int64_t q = nless + atomicAdd(&cnt_eq, 1);
+            if (q < kTopkCap) {
+                skey[q] = key;
+                sidx[q] = (int32_t)i;
             }
-            ++we;
         }
     }
-    for (int e = k + tid; e < kSgTopkMax; e += T) {
+    __syncthreads();
+    int64_t filled = nless + cnt_eq;
+    if (filled > kTopkCap) {
+        // Too many equal keys: take the first `need` of them in index order.
+        const int64_t per = (n + T - 1) / T;
+        const int64_t lo = min<int64_t>(n, tid * per), hi = min<int64_t>(n, lo + per);
+        int64_t ce = 0;
+        for (int64_t i = lo; i < hi; ++i) ce += ord_key(vals[i]) == prefix;
+        scan[tid] = ce;
+        __syncthreads();
+        if (tid == 0) {
+            int64_t run = 0;
+            for (int t = 0; t < T; ++t) {
+                const int64_t v = scan[t];
+                scan[t] = run;
+                run += v;
+            }
+        }
+        __syncthreads();
+        int64_t we = scan[tid];
+        for (int64_t i = lo; i < hi && we < need; ++i) {
+            if (ord_key(vals[i]) == prefix) {
+                skey[nless + we] = prefix;
+                sidx[nless + we] = (int32_t)i;
+                ++we;
+            }
+        }
+        filled = k;
+    }
+    for (int64_t e = filled + tid; e < kTopkCap; e += T) {
         skey[e] = ~(K)0;
         sidx[e] = 0x7fffffff;
     }
     __syncthreads();
-    // bitonic sort of kSgTopkMax entries by (key, index)
-    for (int size = 2; size <= kSgTopkMax; size <<= 1) {
+    for (int size = 2; size <= kTopkCap; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int e = tid; e < kSgTopkMax; e += T) {
+            for (int e = tid; e < kTopkCap; e += T) {
                 const int o = e ^ stride;
                 if (o > e) {
                     const bool up = (e & size) == 0;
@@ -671,6 +789,11 @@ int launch_predict(const float* theta, const SgQuant& q, const float* Eq, int64_
     hipStream_t st = (hipStream_t)stream;
     if (B == 0) return 0;
     const int64_t Bpad = (B + 63) / 64 * 64;
+    if (!train_layout && t_out == nullptr) {
+        hipLaunchKernelGGL(rho_fused_kernel, dim3((unsigned)(Bpad / 64)), dim3(256), 0, st, Eq, nq, Ec, nc, qi, ci, B,
+                           q, theta, pred);
+        return (int)hipGetLastError();
+    }
     hipLaunchKernelGGL(build_z_kernel, dim3(grid_for(Bpad, 1)), dim3(256), 0, st, Eq, Ec, qi, ci, nq, nc, train_layout,
                        B, Bpad, w.Z);
     int err = (int)hipGetLastError();
@@ -704,8 +827,8 @@ int launch_loss_grad(const float* theta, const SgQuant& q, const float* X, const
     hipLaunchKernelGGL(head_bwd_kernel, dim3((unsigned)((B + 3) / 4)), dim3(256), 0, st, w.PRE3, theta, q.w4, w.t,
                        w.pred, labels, B, w.HB, w.dGq);
     if ((err = (int)hipGetLastError())) return err;
-    hipLaunchKernelGGL(colsum_kernel, dim3((kSgHbCols + 255) / 256), dim3(256), 0, st, w.HB, B, (int64_t)kSgHbCols,
-                       kSgHbCols, w.hsum, 0);
+    hipLaunchKernelGGL(colsum_kernel, dim3((kSgHbCols + 63) / 64), dim3(kColsumThreads), 0, st, w.HB, B,
+                       (int64_t)kSgHbCols, kSgHbCols, w.hsum, 0);
     hipLaunchKernelGGL(head_grad_scatter_kernel, dim3(1), dim3(256), 0, st, w.hsum, w.bad, grad, loss);
     // dW3 = dG^T Z: both transposed to K = pair index
     if ((err = transpose(w.dGq, H, (int)B, (int)Bpad, H, w.dGqT, Bpad, st))) return err;
@@ -719,7 +842,8 @@ int launch_loss_grad(const float* theta, const SgQuant& q, const float* X, const
     hipLaunchKernelGGL(pool_bwd_kernel, dim3((unsigned)S), dim3(256), 0, st, w.PRE2, theta + kSgB2, a, set_off, P,
                        w.dE, w.dP2q, w.db2p);
     if ((err = (int)hipGetLastError())) return err;
-    hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(256), 0, st, w.db2p, S, (int64_t)H, H, grad + kSgB2, 0);
+    hipLaunchKernelGGL(colsum_kernel, dim3(H / 64), dim3(kColsumThreads), 0, st, w.db2p, S, (int64_t)H, H,
+                       grad + kSgB2, 0);
     if ((err = transpose(w.dP2q, H, (int)P, (int)Ppad, H, w.dP2qT, Ppad, st))) return err;
     if ((err = transpose(w.H1q, H, (int)P, (int)Ppad, H, w.H1qT, Ppad, st))) return err;
     const int splits = (int)std::max<int64_t>(1, std::min<int64_t>(64, Ppad / 2048));
@@ -734,7 +858,8 @@ int launch_loss_grad(const float* theta, const SgQuant& q, const float* X, const
     hipLaunchKernelGGL(layer1_bwd_kernel, dim3((unsigned)nblk), dim3(256), 0, st, w.dH1, X, q.W1, theta + kSgB1, P,
                        chunk, w.l1p);
     if ((err = (int)hipGetLastError())) return err;
-    hipLaunchKernelGGL(colsum_kernel, dim3(4), dim3(256), 0, st, w.l1p, nblk, (int64_t)4 * H, 4 * H, w.l1s, 0);
+    hipLaunchKernelGGL(colsum_kernel, dim3(4 * H / 64), dim3(kColsumThreads), 0, st, w.l1p, nblk, (int64_t)4 * H,
+                       4 * H, w.l1s, 0);
     hipLaunchKernelGGL(layer1_grad_scatter_kernel, dim3(1), dim3(256), 0, st, w.l1s, grad);
     return (int)hipGetLastError();
 }
