@@ -75,6 +75,7 @@ def main():
     ap.add_argument("--graph", action="store_true", help="replay a captured graph of one step")
     ap.add_argument("--schedule", default="longest_first", choices=["longest_first", "as_given"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="batched_hist_3d: skip the launch autotuner")
     ap.add_argument("--no-single-pair", action="store_true")
     ap.add_argument("--single-pair-sample", type=int, default=512)
     ap.add_argument("--workload", default="batched_hist_3d",
@@ -141,6 +142,10 @@ def main():
                    plan_flow=torch.empty(total, dtype=torch.float64, device=dev),
                    plan_total=total)
     max_m, max_n = int(m_sizes.max()), int(n_sizes.max())
+    tuning = None
+    if not args.no_autotune and args.threads == 0:
+        tuning = binding.autotune(d, "l2", max_m, max_n, num_pairs=1024)
+        log(f"autotuned: {tuning}")
 
     def step():
         binding.emd_approx_batched(X, a, xo, Y, b, yo, max_m=max_m, max_n=max_n, metric="l2",
@@ -242,7 +247,9 @@ def main():
         "config": {"workload": "batched_hist_3d: 4096 pairs, m,n ~ U{128..1024}, 3-D U[0,1]^3 FP32, "
                                "Dirichlet(1) masses, L2, one launch, cost+plan+stats",
                    "num_pairs": P, "plan": want_plan, "graph": bool(args.graph),
-                   "threads": args.threads or 256, "schedule": args.schedule, "seed": ps.meta["seed"],
+                   "threads": args.threads or (tuning["threads"] if tuning else 256),
+                   "search_split": tuning["split"] if tuning else 2, "autotuned": tuning is not None,
+                   "schedule": args.schedule, "seed": ps.meta["seed"],
                    "rounds_mean": float(st["rounds"].mean())},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -32,7 +32,8 @@ STATS_DTYPE = np.dtype([("status", "<i4"), ("rounds", "<i4"), ("nnz", "<i8"), ("
 EXPORTS = ["nnsemd_create", "nnsemd_destroy", "nnsemd_status_string", "nnsemd_last_error",
            "emd_approx", "emd_approx_map", "emd_approx_batched",
            "nnsemd_sg_num_params", "nnsemd_sg_embed", "nnsemd_sg_predict", "nnsemd_sg_loss_grad",
-           "nnsemd_sg_train_step", "nnsemd_topk_smallest_f32", "nnsemd_topk_smallest_f64", "nnsemd_sg_retrieve"]
+           "nnsemd_sg_train_step", "nnsemd_topk_smallest_f32", "nnsemd_topk_smallest_f64", "nnsemd_sg_retrieve",
+           "nnsemd_autotune", "nnsemd_tuning_save", "nnsemd_tuning_load"]
 SG_HIDDEN = 256
 
 
@@ -47,6 +48,11 @@ class Options(ctypes.Structure):
                 ("max_rounds", ctypes.c_int64), ("seed", ctypes.c_uint64),
                 ("threads", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("path", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("threads", ctypes.c_int32), ("split", ctypes.c_int32),
+                ("ms_best", ctypes.c_float), ("ms_default", ctypes.c_float)]
 
 
 _lock = threading.Lock()
@@ -91,6 +97,11 @@ def load_library():
         lib.nnsemd_topk_smallest_f32.argtypes = [P, P, I64, I32, P, P]
         lib.nnsemd_topk_smallest_f64.argtypes = [P, P, I64, I32, P, P]
         lib.nnsemd_sg_retrieve.argtypes = [P, P, P, I64, P, P, I64, P, P, P, I64, I32, I32, P, P, P, P, P]
+        lib.nnsemd_autotune.argtypes = [P, I32, I32, I64, I64, I64, ctypes.POINTER(Tuning), P]
+        lib.nnsemd_tuning_save.argtypes = [P, ctypes.c_char_p]
+        lib.nnsemd_tuning_load.argtypes = [P, ctypes.c_char_p]
+        for fn in ("nnsemd_autotune", "nnsemd_tuning_save", "nnsemd_tuning_load"):
+            getattr(lib, fn).restype = I32
         for fn in ("nnsemd_sg_embed", "nnsemd_sg_predict", "nnsemd_sg_loss_grad", "nnsemd_sg_train_step",
                    "nnsemd_topk_smallest_f32", "nnsemd_topk_smallest_f64", "nnsemd_sg_retrieve"):
             getattr(lib, fn).restype = I32
@@ -399,3 +410,29 @@ def sg_retrieve(theta, index_E, Xq, aq, Ycat, bcat, y_off, max_n: int, keep: int
                                 _ptr(kept), _ptr(kst), _stream(torch, dev))
     _check(lib, h, st)
     return {"idx": idx, "cost": cost, "kept": kept, "kept_stats": kst}
+
+
+# ---------------------------------------------------------------- autotuning
+def autotune(d: int, metric: str, max_m: int, max_n: int, num_pairs: int = 1024, device: int = 0) -> dict:
+    """Time the batched point path's launch configurations on synthetic pairs
+    of this shape and record the fastest in the device's handle."""
+    import torch
+    lib = load_library()
+    h = handle(device)
+    t = Tuning()
+    st = lib.nnsemd_autotune(h, d, METRICS[metric], max_m, max_n, num_pairs, ctypes.byref(t),
+                             _stream(torch, device))
+    _check(lib, h, st)
+    return {"threads": t.threads, "split": t.split, "ms_best": t.ms_best, "ms_default": t.ms_default}
+
+
+def tuning_save(path: str, device: int = 0):
+    lib = load_library()
+    h = handle(device)
+    _check(lib, h, lib.nnsemd_tuning_save(h, path.encode()))
+
+
+def tuning_load(path: str, device: int = 0):
+    lib = load_library()
+    h = handle(device)
+    _check(lib, h, lib.nnsemd_tuning_load(h, path.encode()))

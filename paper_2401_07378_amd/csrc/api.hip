@@ -8,8 +8,11 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "internal.hpp"
+
+constexpr int nnsemd_tune_classes = 6;  // max side <= 128, 256, 512, 1024, 2048, 4096
 
 struct nnsemd_handle {
     int device = 0;
@@ -24,6 +27,12 @@ struct nnsemd_handle {
     nnsemd::LPState* lp_host = nullptr;          // pinned copy of the round state
     char* doc_tiles = nullptr;                   // key-tile scratch of the high-dimensional path
     size_t doc_bytes = 0;
+    // Autotuned launch configuration of the batched point path, by
+    // dimension (1..7), metric and size class of max(max_m, max_n).
+    struct Tune {
+        int32_t valid = 0, threads = 256, split = 2;
+        float ms = 0.f;
+    } tune[8][3][nnsemd_tune_classes];
     char* sg_quant = nullptr;                    // BF16 weight copies of the surrogate
     char* sg_ws = nullptr;                       // surrogate workspace
     size_t sg_bytes = 0;
@@ -84,11 +93,27 @@ nnsemd_status_t schedule(nnsemd_handle_t h, const int64_t* x_off, const int64_t*
     return NNSEMD_OK;
 }
 
+int tune_class(int64_t maxp) {
+    int c = 0;
+    for (int64_t lim = 128; c < nnsemd_tune_classes - 1 && maxp > lim; lim <<= 1) ++c;
+    return c;
+}
+
 // Common entry for one or many pairs of low-dimensional FP32 points.
+// forced_threads / forced_split > 0 bypass the options and the tuning table.
 nnsemd_status_t run_pairs(nnsemd_handle_t h, PairSolverArgs& A, int d, int64_t max_m, int64_t max_n,
-                          const nnsemd_options_t& o, void* stream) {
+                          const nnsemd_options_t& o, void* stream, int forced_threads = 0, int forced_split = 0) {
     if (d < 1 || d > 7) return fail(h, NNSEMD_ERR_UNSUPPORTED, "point path supports 1 <= d <= 7");
-    const int threads = o.threads > 0 ? o.threads : 256;
+    int threads = o.threads > 0 ? o.threads : 256;
+    int split = 2;
+    const auto& tn = h->tune[d][A.metric][tune_class(std::max<int64_t>(max_m, max_n))];
+    if (o.threads == 0 && tn.valid) {
+        threads = tn.threads;
+        split = tn.split;
+    }
+    if (forced_threads > 0) threads = forced_threads;
+    if (forced_split > 0) split = forced_split;
+    A.split = split;
     if (threads != 256 && threads != 512)
         return fail(h, NNSEMD_ERR_UNSUPPORTED, "workgroup size must be 256 or 512");
     const int64_t maxp = std::max<int64_t>({max_m, max_n, 1});
@@ -617,6 +642,176 @@ nnsemd_status_t emd_approx_batched(nnsemd_handle_t h, int64_t num_pairs, const v
     A.plan_off = plan ? plan_off : nullptr;
     A.stats = stats;
     return run_pairs(h, A, d, max_m, max_n, o, stream);
+}
+
+nnsemd_status_t nnsemd_autotune(nnsemd_handle_t h, int32_t d, nnsemd_metric_t metric, int64_t max_m, int64_t max_n,
+                                int64_t num_pairs, nnsemd_tuning_t* result, void* stream) {
+    if (h == nullptr) return NNSEMD_ERR_INVALID_ARG;
+    h->last_error.clear();
+    if (d < 1 || d > 7) return fail(h, NNSEMD_ERR_UNSUPPORTED, "autotuning covers the point path, 1 <= d <= 7");
+    if (metric != NNSEMD_L2 && metric != NNSEMD_SQEUCLIDEAN && metric != NNSEMD_L1)
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "bad metric");
+    if (max_m < 1 || max_n < 1 || max_m > 4096 || max_n > 4096 || num_pairs < 1 || num_pairs > 65536)
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "need 1 <= max_m, max_n <= 4096 and 1 <= num_pairs <= 65536");
+    DeviceGuard g(h->device);
+    hipStream_t st = (hipStream_t)stream;
+    // Synthetic pairs shaped like the caller's: sides uniform in
+    // [max/8, max], coordinates uniform in [0,1)^d, normalised exponential masses.
+    std::vector<int64_t> xo(num_pairs + 1, 0), yo(num_pairs + 1, 0);
+    uint64_t rs = 0x9E3779B97F4A7C15ull ^ (uint64_t)(d * 131 + metric * 7 + max_m * 3 + max_n);
+    auto next = [&rs]() {
+        rs += 0x9E3779B97F4A7C15ull;
+        uint64_t z = rs;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    auto unif = [&next]() { return (double)(next() >> 11) * 0x1.0p-53; };
+    for (int64_t p = 0; p < num_pairs; ++p) {
+        const int64_t lm = std::max<int64_t>(1, max_m / 8), ln = std::max<int64_t>(1, max_n / 8);
+        xo[p + 1] = xo[p] + lm + (int64_t)(unif() * (double)(max_m - lm + 1));
+        yo[p + 1] = yo[p] + ln + (int64_t)(unif() * (double)(max_n - ln + 1));
+    }
+    auto points = [&](const std::vector<int64_t>& off, std::vector<float>& P, std::vector<float>& w) {
+        P.resize((size_t)off.back() * d);
+        w.resize((size_t)off.back());
+        for (auto& v : P) v = (float)unif();
+        for (size_t s = 0; s + 1 < off.size(); ++s) {
+            double sum = 0.0;
+            for (int64_t i = off[s]; i < off[s + 1]; ++i) sum += (w[i] = (float)-std::log(1.0 - unif()));
+            for (int64_t i = off[s]; i < off[s + 1]; ++i) w[i] = (float)(w[i] / sum);
+        }
+    };
+    std::vector<float> X, a, Y, b;
+    points(xo, X, a);
+    points(yo, Y, b);
+    Carver c;
+    const size_t oX = c.take(4 * X.size()), oa = c.take(4 * a.size()), oY = c.take(4 * Y.size()),
+                 ob = c.take(4 * b.size()), oxo = c.take(8 * xo.size()), oyo = c.take(8 * yo.size()),
+                 oc = c.take(8 * (size_t)num_pairs);
+    char* base = nullptr;
+    if (hipMalloc((void**)&base, align_up(c.off, 256)) != hipSuccess)
+        return fail(h, NNSEMD_ERR_OUT_OF_MEMORY, "autotuning inputs");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    nnsemd_status_t status = NNSEMD_OK;
+    float best_ms = -1.f, default_ms = -1.f;
+    int best_t = 256, best_s = 2;
+    bool ok = hipMemcpyAsync(base + oX, X.data(), 4 * X.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
+              hipMemcpyAsync(base + oa, a.data(), 4 * a.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
+              hipMemcpyAsync(base + oY, Y.data(), 4 * Y.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
+              hipMemcpyAsync(base + ob, b.data(), 4 * b.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
+              hipMemcpyAsync(base + oxo, xo.data(), 8 * xo.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
+              hipMemcpyAsync(base + oyo, yo.data(), 8 * yo.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
+              hipStreamSynchronize(st) == hipSuccess && hipEventCreate(&e0) == hipSuccess &&
+              hipEventCreate(&e1) == hipSuccess;
+    if (!ok) status = fail(h, NNSEMD_ERR_DEVICE, "autotuning set-up");
+    const int threads_c[2] = {256, 512}, split_c[3] = {1, 2, 4};
+    for (int ti = 0; ti < 2 && status == NNSEMD_OK; ++ti) {
+        for (int si = 0; si < 3 && status == NNSEMD_OK; ++si) {
+            PairSolverArgs A{};
+            A.num_pairs = num_pairs;
+            A.X = reinterpret_cast<const float*>(base + oX);
+            A.a = reinterpret_cast<const float*>(base + oa);
+            A.x_off = reinterpret_cast<const int64_t*>(base + oxo);
+            A.num_x_sets = num_pairs;
+            A.Y = reinterpret_cast<const float*>(base + oY);
+            A.b = reinterpret_cast<const float*>(base + ob);
+            A.y_off = reinterpret_cast<const int64_t*>(base + oyo);
+            A.num_y_sets = num_pairs;
+            A.metric = metric;
+            A.costs = reinterpret_cast<double*>(base + oc);
+            const nnsemd_options_t o = default_options();
+            nnsemd_status_t s = run_pairs(h, A, d, max_m, max_n, o, stream, threads_c[ti], split_c[si]);
+            if (s == NNSEMD_ERR_UNSUPPORTED) {
+                h->last_error.clear();
+                continue;  // this configuration does not fit
+            }
+            if (s != NNSEMD_OK) {
+                status = s;
+                break;
+            }
+            float ms = 0.f;
+            bool good = hipEventRecord(e0, st) == hipSuccess;
+            for (int r = 0; r < 3 && good; ++r)
+                good = run_pairs(h, A, d, max_m, max_n, o, stream, threads_c[ti], split_c[si]) == NNSEMD_OK;
+            good = good && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                   hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+            if (!good) {
+                status = fail(h, NNSEMD_ERR_DEVICE, "autotuning launch");
+                break;
+            }
+            ms /= 3.f;
+            if (threads_c[ti] == 256 && split_c[si] == 2) default_ms = ms;
+            if (best_ms < 0.f || ms < best_ms) {
+                best_ms = ms;
+                best_t = threads_c[ti];
+                best_s = split_c[si];
+            }
+        }
+    }
+    (void)hipStreamSynchronize(st);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(base);
+    if (status != NNSEMD_OK) return status;
+    if (best_ms < 0.f) return fail(h, NNSEMD_ERR_UNSUPPORTED, "no launch configuration fits these sizes");
+    auto& tn = h->tune[d][metric][tune_class(std::max(max_m, max_n))];
+    tn.valid = 1;
+    tn.threads = best_t;
+    tn.split = best_s;
+    tn.ms = best_ms;
+    if (result) {
+        result->threads = best_t;
+        result->split = best_s;
+        result->ms_best = best_ms;
+        result->ms_default = default_ms;
+    }
+    return NNSEMD_OK;
+}
+
+nnsemd_status_t nnsemd_tuning_save(nnsemd_handle_t h, const char* path) {
+    if (h == nullptr || path == nullptr) return NNSEMD_ERR_INVALID_ARG;
+    FILE* f = std::fopen(path, "w");
+    if (f == nullptr) return fail(h, NNSEMD_ERR_INVALID_ARG, "cannot open the tuning file for writing");
+    std::fprintf(f, "nnsemd-tuning 1\n");
+    for (int d = 1; d <= 7; ++d)
+        for (int m = 0; m < 3; ++m)
+            for (int c = 0; c < nnsemd_tune_classes; ++c) {
+                const auto& t = h->tune[d][m][c];
+                if (t.valid) std::fprintf(f, "%d %d %d %d %d %.6f\n", d, m, c, t.threads, t.split, (double)t.ms);
+            }
+    const bool ok = std::fclose(f) == 0;
+    return ok ? NNSEMD_OK : fail(h, NNSEMD_ERR_INVALID_ARG, "writing the tuning file failed");
+}
+
+nnsemd_status_t nnsemd_tuning_load(nnsemd_handle_t h, const char* path) {
+    if (h == nullptr || path == nullptr) return NNSEMD_ERR_INVALID_ARG;
+    FILE* f = std::fopen(path, "r");
+    if (f == nullptr) return fail(h, NNSEMD_ERR_INVALID_ARG, "cannot open the tuning file");
+    int version = 0;
+    nnsemd_status_t s = NNSEMD_OK;
+    if (std::fscanf(f, "nnsemd-tuning %d", &version) != 1 || version != 1) {
+        s = fail(h, NNSEMD_ERR_INVALID_ARG, "not a tuning file (version 1)");
+    } else {
+        int d, m, c, t, sp;
+        double ms;
+        int n;
+        while ((n = std::fscanf(f, "%d %d %d %d %d %lf", &d, &m, &c, &t, &sp, &ms)) == 6) {
+            if (d < 1 || d > 7 || m < 0 || m > 2 || c < 0 || c >= nnsemd_tune_classes || (t != 256 && t != 512) ||
+                (sp != 1 && sp != 2 && sp != 4)) {
+                s = fail(h, NNSEMD_ERR_INVALID_ARG, "bad entry in the tuning file");
+                break;
+            }
+            auto& tn = h->tune[d][m][c];
+            tn.valid = 1;
+            tn.threads = t;
+            tn.split = sp;
+            tn.ms = (float)ms;
+        }
+        if (s == NNSEMD_OK && n != EOF) s = fail(h, NNSEMD_ERR_INVALID_ARG, "malformed tuning file");
+    }
+    std::fclose(f);
+    return s;
 }
 
 int64_t nnsemd_sg_num_params(void) { return kSgParams; }

@@ -46,6 +46,8 @@ struct PairSolverArgs {
     nnsemd_stats_t* stats;
     const int32_t* order;  // nullable: workgroup b solves pair order[b]
     unsigned long long* phase_cycles;  // profiling builds only: 9 per-phase cycle totals
+    int32_t split;         // search: lanes per consumer grow while nact * lanes * split <= threads
+    int32_t pad;
 };
 
 // Byte layout of the dynamic LDS of one workgroup (one pair at a time).

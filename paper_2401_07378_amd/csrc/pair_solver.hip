@@ -351,7 +351,7 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds& L, Sha
         // there are too few consumers to fill the workgroup; otherwise each
         // lane takes KC consumers so one record load feeds KC key chains.
         int S = 1;
-        while (S < kWave && nact * S * 2 <= T) S <<= 1;
+        while (S < kWave && nact * S * A.split <= T) S <<= 1;
         while (S > 1 && S > mact) S >>= 1;
         const int kc = S > 1 ? 1 : (nact > 2 * T ? 4 : (nact > T ? 2 : 1));
         {

@@ -243,3 +243,27 @@ def test_batched_workgroup_sizes(threads):
         ref = oracle_pair(X, a, Y, b, with_plan=False)
         assert_pair_matches({"cost": float(g["costs"][p]), "stats": g["stats"][p]}, ref, plan=False,
                             label=f"T{threads}-pair{p}")
+
+
+def test_autotune_records_a_configuration_and_keeps_results(tmp_path):
+    """The tuned launch configuration changes speed only: every pair's cost,
+    stats and plan stay bit-identical; the table survives save and load."""
+    from paper_2401_07378_amd import binding
+    ps = W.batched_hist_3d(48, lo=64, hi=400, seed=1501)
+    before = gpu_batched(ps, plan=True)
+    t = binding.autotune(3, "l2", 400, 400, num_pairs=256)
+    assert t["threads"] in (256, 512) and t["split"] in (1, 2, 4)
+    assert 0 < t["ms_best"] <= t["ms_default"] + 1e-6
+    after = gpu_batched(ps, plan=True)
+    for k in ("costs", "src", "dst", "flow"):
+        np.testing.assert_array_equal(after[k], before[k])
+    np.testing.assert_array_equal(after["stats"], before["stats"])
+    path = str(tmp_path / "tune.txt")
+    binding.tuning_save(path)
+    text = open(path).read().splitlines()
+    assert text[0] == "nnsemd-tuning 1" and any(line.startswith("3 0 2 ") for line in text[1:])
+    binding.tuning_load(path)
+    bad = tmp_path / "bad.txt"
+    bad.write_text("nnsemd-tuning 1\n3 0 2 384 2 1.0\n")
+    with pytest.raises(binding.NNSEMDError):
+        binding.tuning_load(str(bad))
