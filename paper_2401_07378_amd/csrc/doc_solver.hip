@@ -8,18 +8,25 @@
 // MFMA blocks); with FP32 inputs they run on the vector ALUs.  The tile goes
 // to a per-workgroup global scratch slot that the rounds read.
 //
-// Exactness.  An FP32 key differs from the exact one by at most
-// E = 2 (d + 1) u (||x|| + ||y||)^2 (u = 2^-24) for any accumulation order of
-// the d products, even if every addition rounded with error 2u.
-//  * Search: a consumer whose two best FP32 keys are closer than
-//    8 (d + 2) u (R + ||y||)^2 (R = max ||x||; twice the worst disagreement of
-//    two keys) is re-scored in FP64 on the suppliers whose FP32 key lies
-//    within that bound of the best, in the definition's operation order.
-//    Every pick is therefore the FP64 argmin, ties to the smallest index.
+// Exactness.  Products of BF16 (and the FP32 products fused into FMAs) are
+// exact; every addition is taken to round with error at most 2u (u = 2^-24),
+// whatever the order.  Bound on |key - exact| written t = tscale (R + ||y||)^2
+// with R = max ||x|| (R ||y|| <= (R + ||y||)^2 / 4):
+//   unsplit form (FP32 norms, FP32 accumulation over all d products):
+//     tscale = 4 (d + 2) u;
+//   split form (BF16, d <= 320: every MFMA sums 32 products from a zero
+//     accumulator, at most 31 roundings, and the 10 chunk sums and the norms
+//     are added in FP64): 2 * 62u R ||y|| + FP64 terms + the final rounding to
+//     FP32 <= 33u (R + ||y||)^2, with ||y||^2 rounded once more for the full
+//     key: tscale = 36u.
+//  * Search: a consumer whose two best FP32 keys are closer than 2t (twice
+//    the worst disagreement of two keys) is re-scored in FP64 on the
+//    suppliers whose FP32 key lies within 2t of the best, in the
+//    definition's operation order.  Every pick is therefore the FP64 argmin,
+//    ties to the smallest index.
 //  * Serve order (greedy protocol): claimants of one supplier are ordered by
-//    their full FP32 keys (tile + ||y||^2), whose error is at most
-//    t_j = 4 (d + 2) u (R + ||y_j||)^2; two claimants closer than t_a + t_b get
-//    exact FP64 keys and are compared on those.
+//    their full FP32 keys (tile + ||y||^2), each within t_j; two claimants
+//    closer than t_a + t_b get exact FP64 keys and are compared on those.
 //  * Cost: R = sum f * D over the plan, with every D recomputed in FP64 from
 //    the inputs after the rounds (all lanes busy, one pass).
 // The plan is thus the one of the FP64 definition, and R agrees with the
@@ -232,6 +239,150 @@ __device__ void key_tile_mfma(const uint16_t* __restrict__ X, const uint16_t* __
     }
 }
 
+// K steps of 32 whose consumer fragments stay in registers in
+// key_tile_mfma_stripes (d <= 320); larger d takes key_tile_mfma.
+constexpr int kStripeKSteps = 10;
+
+// Key tile with matrix cores for the split form, consumer-stationary: the
+// four wavefronts each own a stripe of 16 consumers (their BF16 fragments
+// for all of K loaded once into registers: the only read of the candidate
+// rows), while the workgroup stages the supplier rows 32 at a time in LDS
+// (zero-padded to whole K steps) and every wavefront multiplies its stripe
+// with them.  ||y||^2 and the finiteness of every coordinate come from the
+// consumers' fragments.  It also takes the first round's search from the
+// keys in registers: for every consumer the best and second-best key over
+// the suppliers of positive mass and the smallest local index holding the
+// best, with the same update and merge rules as the search over the stored
+// tile.  Lane layout as in key_tile_mfma.  xs: LDS, 32 x kStripeLdx BF16.
+constexpr int kStripeLdx = kStripeKSteps * 32 + 8;
+
+template <int T>
+__device__ void key_tile_mfma_stripes(const uint16_t* __restrict__ X, const uint16_t* __restrict__ Y, int m, int n,
+                                      int d, const double* __restrict__ xx, float* __restrict__ tile,
+                                      float* __restrict__ yy, bool& bad, const float* __restrict__ amass,
+                                      float* __restrict__ r1b1, float* __restrict__ r1b2, int32_t* __restrict__ r1bs,
+                                      uint16_t* __restrict__ xs) {
+    constexpr int KS = kStripeKSteps;
+    constexpr int NW = T / 64;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid / 64;
+    const int tm = (m + 31) / 32, tn = (n + 15) / 16;
+    const int ksteps = (d + 31) / 32;
+    const int kp = ksteps * 32;
+    const int r16 = lane & 15, kq = 8 * (lane >> 4);
+    const bool rows8 = (d & 3) == 0 && (reinterpret_cast<uintptr_t>(X) & 7u) == 0;
+    for (int sg = 0; sg < (tn + NW - 1) / NW; ++sg) {
+        const int cs = sg * NW + wave;
+        const bool mine = cs < tn;
+        const int j0 = cs * 16;
+        bf16x8 yb[KS];
+        float tb1 = INFINITY, tb2 = INFINITY;
+        int tbs = 0x7fffffff;
+        if (mine) {
+            double ss = 0.0;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                if (ks < ksteps) {
+                    yb[ks] = frag8(Y, j0 + r16, n, ks * 32 + kq, d);
+                    union {
+                        bf16x8 v;
+                        uint32_t w[4];
+                    } u;
+                    u.v = yb[ks];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        bad |= !finite_pair(u.w[e]);
+                        const double f0 = bf_lo(u.w[e]), f1 = bf_hi(u.w[e]);
+                        ss = fma(f0, f0, ss);
+                        ss = fma(f1, f1, ss);
+                    }
+                }
+            }
+            ss += __shfl_xor(ss, 16);
+            ss += __shfl_xor(ss, 32);
+            if (lane < 16 && j0 + r16 < n) yy[j0 + r16] = (float)ss;
+        }
+        for (int ib = 0; ib < tm; ++ib) {
+            const int i0 = ib * 32;
+            __syncthreads();  // the previous block's fragments have been read
+            if (rows8) {
+                for (int e = tid; e < 32 * (kp / 4); e += T) {
+                    const int r = e / (kp / 4), k = 4 * (e % (kp / 4));
+                    uint2 v = make_uint2(0u, 0u);
+                    if (i0 + r < m && k < d) v = *reinterpret_cast<const uint2*>(X + (size_t)(i0 + r) * d + k);
+                    *reinterpret_cast<uint2*>(&xs[r * kStripeLdx + k]) = v;
+                }
+            } else {
+                for (int e = tid; e < 32 * kp; e += T) {
+                    const int r = e / kp, k = e % kp;
+                    xs[r * kStripeLdx + k] = (i0 + r < m && k < d) ? X[(size_t)(i0 + r) * d + k] : (uint16_t)0;
+                }
+            }
+            __syncthreads();
+            if (!mine) continue;
+            // each K step from a zero accumulator (at most 31 roundings),
+            // the chunk sums added in FP64
+            double dot0[4] = {0.0, 0.0, 0.0, 0.0}, dot1[4] = {0.0, 0.0, 0.0, 0.0};
+            const f32x4 zero = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                if (ks < ksteps) {
+                    union {
+                        uint4 u;
+                        bf16x8 v;
+                    } f0, f1;
+                    f0.u = *reinterpret_cast<const uint4*>(&xs[r16 * kStripeLdx + ks * 32 + kq]);
+                    f1.u = *reinterpret_cast<const uint4*>(&xs[(16 + r16) * kStripeLdx + ks * 32 + kq]);
+                    const f32x4 c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f0.v, yb[ks], zero, 0, 0, 0);
+                    const f32x4 c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f1.v, yb[ks], zero, 0, 0, 0);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        dot0[r] += (double)c0[r];
+                        dot1[r] += (double)c1[r];
+                    }
+                }
+            }
+            const int j = j0 + r16;
+            // rows of this lane in ascending order: acc0's four, then acc1's
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = i0 + 16 * h + 4 * (lane >> 4) + r;
+                    if (i < m) {
+                        const float v = (float)(xx[i] - 2.0 * (h == 0 ? dot0[r] : dot1[r]));
+                        if (j < n) tile[(size_t)i * n + j] = v;
+                        if (amass[i] > 0.f) {
+                            const bool lt = v < tb1;
+                            tbs = lt ? i : tbs;
+                            tb2 = __builtin_amdgcn_fmed3f(tb1, v, tb2);
+                            tb1 = fminf(tb1, v);
+                        }
+                    }
+                }
+        }
+        if (mine) {
+#pragma unroll
+            for (int o = 16; o < 64; o <<= 1) {
+                const float c1 = __shfl_xor(tb1, o);
+                const float c2 = __shfl_xor(tb2, o);
+                const int cs2 = __shfl_xor(tbs, o);
+                const float n2 = fminf(fmaxf(tb1, c1), fminf(tb2, c2));
+                const bool take = (c1 < tb1) || (c1 == tb1 && cs2 < tbs);
+                tb1 = take ? c1 : tb1;
+                tbs = take ? cs2 : tbs;
+                tb2 = n2;
+            }
+            if (lane < 16 && j0 + r16 < n) {
+                r1b1[j0 + r16] = tb1;
+                r1b2[j0 + r16] = tb2;
+                r1bs[j0 + r16] = tbs;
+            }
+        }
+    }
+}
+
 // Key tile on the vector ALUs (FP32 inputs): each lane owns a 4 x 4 block
 // of (i, j) and walks the d products with 16-byte loads when rows allow it.
 template <int T>
@@ -356,18 +507,13 @@ __device__ inline void rank_greedy_doc(const Lds& L, Shared& sh, int nact, const
     if (threadIdx.x == 0) sh.namb = 0;
 }
 
-template <typename TIn, bool MFMA, int T, int CSMAX>
-__device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ slot, const Lds& L,
-                               float* __restrict__ xx, float* __restrict__ yy, float* __restrict__ yn,
-                               float* __restrict__ kap, int32_t* __restrict__ amb, Shared& sh) {
-    constexpr int NW = T / 64;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid / 64;
-    const int d = A.d;
-    NNSEMD_PH_DECL
-
-    int64_t x0 = 0, y0 = 0, m = A.single_m, n = A.single_n;
+// Row ranges of pair p (status INVALID_ARG and empty sides if the tables or
+// sizes are out of range).
+__device__ inline int resolve_pair(const DocArgs& A, int64_t p, int64_t& x0, int64_t& m, int64_t& y0, int64_t& n) {
+    x0 = 0;
+    y0 = 0;
+    m = A.single_m;
+    n = A.single_n;
     int status = NNSEMD_OK;
     if (A.x_off != nullptr) {
         const int64_t px = A.pair_x ? (int64_t)A.pair_x[p] : p;
@@ -386,6 +532,24 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
         status = NNSEMD_ERR_INVALID_ARG;
         m = n = 0;
     }
+    return status;
+}
+
+// SPLIT: the key tile, the norms, the coordinates' finiteness and the first
+// round's search were done by doc_tile_kernel into this workgroup's slot.
+template <typename TIn, bool MFMA, int T, int CSMAX, bool SPLIT>
+__device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ slot, const Lds& L,
+                               float* __restrict__ xx, float* __restrict__ yy, float* __restrict__ yn,
+                               float* __restrict__ kap, int32_t* __restrict__ amb, Shared& sh) {
+    constexpr int NW = T / 64;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid / 64;
+    const int d = A.d;
+    NNSEMD_PH_DECL
+
+    int64_t x0, y0, m, n;
+    int status = resolve_pair(A, p, x0, m, y0, n);
     int64_t plan_base = 0, plan_cap = 0;
     const bool want_plan = A.plan_src != nullptr;
     if (want_plan) {
@@ -434,14 +598,40 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
         red[1] += (double)bv;
     }
     const float infl = 1.f + (float)(d + 2) * kU32;  // covers the FP32 norms' own rounding
+    // In the split form the tile kernel took the norms, the finiteness and
+    // the first round's search; otherwise the norms are taken here.
+    const bool stripes = SPLIT;
+    const int nrows = SPLIT ? 0 : mi + ni;
+    if constexpr (SPLIT) {
+        const char* aux = slot + doc_aux_offset(A.max_m, A.max_n);
+        const float* axx = reinterpret_cast<const float*>(aux);
+        const float* ayy = axx + A.max_m;
+        const float* ab1 = ayy + A.max_n;
+        const float* ab2 = ab1 + A.max_n;
+        const int32_t* abs_ = reinterpret_cast<const int32_t*>(ab2 + A.max_n);
+        const int32_t* aflag = abs_ + A.max_n;
+        for (int i = tid; i < mi; i += T) {
+            xx[i] = axx[i];
+            red[3] = fmax(red[3], (double)axx[i]);
+        }
+        for (int j = tid; j < ni; j += T) {
+            const float s2 = ayy[j];
+            yy[j] = s2;
+            yn[j] = sqrtf(s2) * infl;
+            kap[j] = ab1[j];
+            L.ckey[j] = (double)ab2[j];
+            L.cnn[j] = abs_[j];
+        }
+        if (tid == 0 && mi + ni > 0 && *aflag != 0) red[2] = 1.0;
+    }
     {
         constexpr int G = 16;
         const int gl = tid & (G - 1);
-        for (int r0 = 0; r0 < mi + ni; r0 += T / G) {
+        for (int r0 = 0; r0 < nrows; r0 += T / G) {
             const int row = r0 + tid / G;
             bool bad = false;
             float s2 = 0.f;
-            if (row < mi + ni) {
+            if (row < nrows) {
                 const TIn* pr = row < mi ? X + (size_t)row * d : Y + (size_t)(row - mi) * d;
                 s2 = norm2_part<G, TIn>(pr, d, gl, bad);
             }
@@ -451,7 +641,7 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
                 s2 += __shfl_xor(s2, o);
                 bi |= __shfl_xor(bi, o);
             }
-            if (gl == 0 && row < mi + ni) {
+            if (gl == 0 && row < nrows) {
                 if (bi) red[2] = 1.0;
                 if (row < mi) {
                     xx[row] = s2;
@@ -471,17 +661,18 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
     }
     const float rhat = sqrtf((float)red[3]) * infl;
     // Key error bound t = tscale (R + ||y||)^2; the search gap threshold is 2t.
-    const float tscale = 4.f * (float)(d + 2) * kU32;
+    const float tscale = SPLIT ? 36.f * kU32 : 4.f * (float)(d + 2) * kU32;
 
     NNSEMD_PH(0)
     // ---- key tile
-    if (status == NNSEMD_OK) {
-        if constexpr (MFMA)
+    if (!SPLIT && status == NNSEMD_OK) {
+        if constexpr (MFMA) {
             key_tile_mfma<T>(reinterpret_cast<const uint16_t*>(X), reinterpret_cast<const uint16_t*>(Y), mi, ni, d, xx,
                              tile);
-        else
+        } else {
             key_tile_valu<T>(reinterpret_cast<const float*>(X), reinterpret_cast<const float*>(Y), mi, ni, d, xx,
                              tile);
+        }
     }
     __syncthreads();
     NNSEMD_PH(1)
@@ -512,6 +703,7 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
         for (int u = 0; u < CSMAX; ++u) {
             if (!(mv[u] > 0.0)) continue;
             L.sidx[ps] = slo + u;
+            L.soff[slo + u] = ps;  // slot of a local index, for the first round
             L.smass[ps] = mv[u];
             L.scnt[ps] = 0;
             ++ps;
@@ -536,6 +728,28 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
             break;
         }
         work += (int64_t)mact * nact;
+        if (rounds == 0 && stripes) {
+            // First round: the tile pass already found every consumer's best
+            // and second-best key (all suppliers of positive mass are active).
+            for (int q = tid; q < nact; q += T) {
+                const int j = L.cact[q];
+                const float b1 = kap[j], b2 = (float)L.ckey[j];
+                const int bl = L.cnn[j];
+                const float e = rhat + yn[j];
+                const float thr = 2.f * tscale * e * e + 1e-30f;
+                if (!(b2 - b1 > thr)) {
+                    const int f = atomicAdd(&sh.nflag, 1);
+                    L.list[f] = j;
+                    flag_b1[f] = b1;
+                } else {
+                    const int bs = L.soff[bl];
+                    L.cnn[j] = bs;
+                    kap[j] = b1 + yy[j];
+                    L.ckey[j] = -1.0;  // exact key not known
+                    atomicAdd(&L.scnt[bs], 1);
+                }
+            }
+        } else {
         // NNS over the key tile: S lanes per consumer when consumers are few.
         int S = 1;
         while (S < 64 && nact * S * 2 <= T) S <<= 1;
@@ -596,6 +810,7 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
                 }
             }
         }
+        }
         __syncthreads();
         NNSEMD_PH(2)
         const int nf = sh.nflag;
@@ -652,21 +867,54 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
         ++rounds;
     }
 
-    // ---- R = sum f * D over the plan, D from exact FP64 keys
     double fin[3] = {0.0, 0.0, 0.0};
     const int fop[3] = {0, 0, 0};
-    if (status == NNSEMD_OK) {
-        for (int64_t e = tid; e < nnz; e += T) {
-            const int64_t at = plan_base + e;
-            const int i = psrc[at], j = pdst[at];
-            fin[0] += pflow[at] * dist_of_key(dkey64<TIn>(X + (size_t)i * d, Y + (size_t)j * d, d), A.metric);
-        }
-    }
-    NNSEMD_PH(7)
     if (status == NNSEMD_OK || status == NNSEMD_ERR_NOT_CONVERGED) {
         for (int s = tid; s < mact; s += T) fin[1] += L.smass[s];
         for (int q = tid; q < nact; q += T) fin[2] += L.cmass[L.cact[q]];
     }
+    // ---- R = sum f * D over the plan, D from exact FP64 keys.  Entries are
+    // sorted by consumer (counting sort in LDS) and dealt to lanes in that
+    // order, so neighbouring lanes share a consumer row (one fetch) and heavy
+    // consumers are spread over many lanes; each entry's f * D goes to its
+    // own slot and the slots are summed in a fixed order, so R does not
+    // depend on the sort's order.
+    if (status == NNSEMD_OK) {
+        __syncthreads();  // residuals read; the LDS below is reused
+        int32_t* cnt = reinterpret_cast<int32_t*>(L.ckey);  // [N]
+        int32_t* off = cnt + A.max_n;                       // [N]
+        int32_t* ent = L.sidx;                              // [m + n] (sidx .. sorted are contiguous)
+        double* contrib = L.smass;                          // [m + n] (smass, cmass are contiguous)
+        const int ne = (int)nnz;
+        for (int j = tid; j < ni; j += T) cnt[j] = 0;
+        __syncthreads();
+        for (int e = tid; e < ne; e += T) atomicAdd(&cnt[pdst[plan_base + e]], 1);
+        __syncthreads();
+        {
+            const int cs = (ni + T - 1) / T;
+            const int lo = min(tid * cs, ni), hi = min(lo + cs, ni);
+            int sum = 0;
+            for (int j = lo; j < hi; ++j) sum += cnt[j];
+            unsigned long long tot;
+            int run = (int)block_scan_u64<T>((unsigned long long)sum, &tot, sh);
+            for (int j = lo; j < hi; ++j) {
+                off[j] = run;
+                run += cnt[j];
+            }
+        }
+        __syncthreads();
+        for (int e = tid; e < ne; e += T) ent[atomicAdd(&off[pdst[plan_base + e]], 1)] = e;
+        __syncthreads();
+        for (int q = tid; q < ne; q += T) {
+            const int e = ent[q];
+            const int i = psrc[plan_base + e], j = pdst[plan_base + e];
+            contrib[e] = pflow[plan_base + e] *
+                         dist_of_key(dkey64<TIn>(X + (size_t)i * d, Y + (size_t)j * d, d), A.metric);
+        }
+        __syncthreads();
+        for (int e = tid; e < ne; e += T) fin[0] += contrib[e];
+    }
+    NNSEMD_PH(7)
     block_reduce<T, 3>(fin, fop, sh);
     if (tid == 0) {
         A.costs[p] = status == NNSEMD_OK ? fin[0] : NAN;
@@ -686,8 +934,81 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
     NNSEMD_PH_FLUSH(A.phase_cycles)
 }
 
+// Tile kernel of the split form (BF16, K steps <= kStripeKSteps, sides <=
+// 1024): one workgroup per pair, the same pair <-> slot mapping as
+// doc_pair_kernel.  Supplier norms (16 lanes per row), the stripes tile with
+// the consumers' norms and the first round's search, and the finiteness of
+// every coordinate, into the slot.
+template <int T>
+__device__ void doc_tile_pair(const DocArgs& A, int64_t p, char* __restrict__ slot, double* __restrict__ xx,
+                              float* __restrict__ am, uint16_t* __restrict__ xs, Shared& sh) {
+    const int tid = threadIdx.x;
+    const int d = A.d;
+    int64_t x0, y0, m, n;
+    const int status = resolve_pair(A, p, x0, m, y0, n);
+    const int mi = status == NNSEMD_OK ? (int)m : 0, ni = status == NNSEMD_OK ? (int)n : 0;
+    const uint16_t* X = reinterpret_cast<const uint16_t*>(A.X) + x0 * d;
+    const uint16_t* Y = reinterpret_cast<const uint16_t*>(A.Y) + y0 * d;
+    char* aux = slot + doc_aux_offset(A.max_m, A.max_n);
+    float* axx = reinterpret_cast<float*>(aux);
+    float* ayy = axx + A.max_m;
+    float* ab1 = ayy + A.max_n;
+    float* ab2 = ab1 + A.max_n;
+    int32_t* abs_ = reinterpret_cast<int32_t*>(ab2 + A.max_n);
+    int32_t* aflag = abs_ + A.max_n;
+    bool bad = false;
+    for (int i = tid; i < mi; i += T) am[i] = A.a[x0 + i];
+    {
+        constexpr int G = 16;
+        const int gl = tid & (G - 1);
+        for (int r0 = 0; r0 < mi; r0 += T / G) {
+            const int row = r0 + tid / G;
+            bool rb = false;
+            double s2 = 0.0;
+            if (row < mi) {
+                const uint16_t* pr = X + (size_t)row * d;
+                for (int k = gl; k < d; k += G) {
+                    rb |= !finite_in(pr[k]);
+                    const double f = to_f32(pr[k]);
+                    s2 = fma(f, f, s2);
+                }
+            }
+            int bi = rb ? 1 : 0;
+#pragma unroll
+            for (int o = G / 2; o > 0; o >>= 1) {
+                s2 += __shfl_xor(s2, o);
+                bi |= __shfl_xor(bi, o);
+            }
+            if (gl == 0 && row < mi) {
+                bad |= bi != 0;
+                xx[row] = s2;
+                axx[row] = (float)s2;
+            }
+        }
+    }
+    __syncthreads();
+    key_tile_mfma_stripes<T>(X, Y, mi, ni, d, xx, reinterpret_cast<float*>(slot), ayy, bad, am, ab1, ab2, abs_, xs);
+    double bd[1] = {bad ? 1.0 : 0.0};
+    const int bop[1] = {2};
+    block_reduce<T, 1>(bd, bop, sh);
+    if (tid == 0) *aflag = bd[0] != 0.0 ? 1 : 0;
+}
+
 #ifndef NNSEMD_CPU_EMULATION
-template <typename TIn, bool MFMA, int T, int CSMAX>
+template <int T>
+__global__ __launch_bounds__(T) void doc_tile_kernel(DocArgs A) {
+    extern __shared__ __align__(16) char lds_dyn[];
+    __shared__ Shared sh;
+    __shared__ __align__(16) uint16_t xs[32 * kStripeLdx];
+    double* xx = reinterpret_cast<double*>(lds_dyn);
+    float* am = reinterpret_cast<float*>(xx + A.max_m);
+    const int64_t b = A.pair_base + (int64_t)blockIdx.x;
+    const int64_t p = A.order != nullptr ? (int64_t)A.order[b] : b;
+    char* slot = A.scratch + (size_t)blockIdx.x * (size_t)A.slot_bytes;
+    doc_tile_pair<T>(A, p, slot, xx, am, xs, sh);
+}
+
+template <typename TIn, bool MFMA, int T, int CSMAX, bool SPLIT>
 __global__ __launch_bounds__(T) void doc_pair_kernel(DocArgs A) {
     extern __shared__ __align__(16) char lds_dyn[];
     __shared__ Shared sh;
@@ -701,17 +1022,23 @@ __global__ __launch_bounds__(T) void doc_pair_kernel(DocArgs A) {
     const int64_t b = A.pair_base + (int64_t)blockIdx.x;
     const int64_t p = A.order != nullptr ? (int64_t)A.order[b] : b;
     char* slot = A.scratch + (size_t)blockIdx.x * (size_t)A.slot_bytes;
-    solve_doc_pair<TIn, MFMA, T, CSMAX>(A, p, slot, L, xx, yy, yn, kap, amb, sh);
+    solve_doc_pair<TIn, MFMA, T, CSMAX, SPLIT>(A, p, slot, L, xx, yy, yn, kap, amb, sh);
 }
 
-template <typename TIn, bool MFMA, int CSMAX>
+template <typename TIn, bool MFMA, int CSMAX, bool SPLIT>
 int doc_launch_typed(const DocArgs& A, size_t lds, int grid, hipStream_t st, bool run, int* blocks) {
-    auto k = doc_pair_kernel<TIn, MFMA, 256, CSMAX>;
+    auto k = doc_pair_kernel<TIn, MFMA, 256, CSMAX, SPLIT>;
     if (lds > 48 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return (int)e;
     }
     if (!run) return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k, 256, lds);
+    if constexpr (SPLIT) {
+        const size_t tl = (sizeof(double) + sizeof(float)) * (size_t)A.max_m;
+        hipLaunchKernelGGL(doc_tile_kernel<256>, dim3(grid), dim3(256), tl, st, A);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return (int)e;
+    }
     hipLaunchKernelGGL(k, dim3(grid), dim3(256), lds, st, A);
     return (int)hipGetLastError();
 }
@@ -730,12 +1057,14 @@ int launch_doc_solver(const DocArgs& A, bool bf16_mfma, int chunk_max, size_t ld
                       int* blocks) {
     const bool run = blocks == nullptr;
     hipStream_t st = (hipStream_t)stream;
+    const bool split = (A.d + 31) / 32 <= kStripeKSteps;
     if (bf16_mfma) {
-        if (chunk_max <= 4) return doc_launch_typed<uint16_t, true, 4>(A, lds, grid, st, run, blocks);
-        if (chunk_max <= 16) return doc_launch_typed<uint16_t, true, 16>(A, lds, grid, st, run, blocks);
+        if (chunk_max <= 4 && split) return doc_launch_typed<uint16_t, true, 4, true>(A, lds, grid, st, run, blocks);
+        if (chunk_max <= 4) return doc_launch_typed<uint16_t, true, 4, false>(A, lds, grid, st, run, blocks);
+        if (chunk_max <= 16) return doc_launch_typed<uint16_t, true, 16, false>(A, lds, grid, st, run, blocks);
     } else {
-        if (chunk_max <= 4) return doc_launch_typed<float, false, 4>(A, lds, grid, st, run, blocks);
-        if (chunk_max <= 16) return doc_launch_typed<float, false, 16>(A, lds, grid, st, run, blocks);
+        if (chunk_max <= 4) return doc_launch_typed<float, false, 4, false>(A, lds, grid, st, run, blocks);
+        if (chunk_max <= 16) return doc_launch_typed<float, false, 16, false>(A, lds, grid, st, run, blocks);
     }
     return (int)hipErrorInvalidValue;
 }

@@ -180,8 +180,14 @@ size_t doc_lds_bytes(int max_m, int max_n);
 __host__ __device__ inline size_t doc_tile_bytes(int max_m, int max_n) {
     return align_up(sizeof(float) * (size_t)max_m * (size_t)max_n, 256);
 }
-__host__ __device__ inline size_t doc_slot_bytes(int max_m, int max_n) {
+// After the plan area, the results of the separate tile kernel: xx[M],
+// yy[N], first-round best b1[N], second best b2[N] (FP32), best local index
+// bs[N] (int32), and a flag (non-finite coordinate seen).
+__host__ __device__ inline size_t doc_aux_offset(int max_m, int max_n) {
     return doc_tile_bytes(max_m, max_n) + align_up(16 * ((size_t)max_m + (size_t)max_n), 256);
+}
+__host__ __device__ inline size_t doc_slot_bytes(int max_m, int max_n) {
+    return doc_aux_offset(max_m, max_n) + align_up(4 * ((size_t)max_m + 4 * (size_t)max_n) + 16, 256);
 }
 // blocks == nullptr: launch; else query resident workgroups per CU.
 int launch_doc_solver(const DocArgs& A, bool bf16_mfma, int chunk_max, size_t lds, int grid, void* stream,
