@@ -261,7 +261,11 @@ __device__ void key_tile_mfma_stripes(const uint16_t* __restrict__ X, const uint
                                       int d, const double* __restrict__ xx, float* __restrict__ tile,
                                       float* __restrict__ yy, bool& bad, const float* __restrict__ amass,
                                       float* __restrict__ r1b1, float* __restrict__ r1b2, int32_t* __restrict__ r1bs,
-                                      uint16_t* __restrict__ xs) {
+                                      uint16_t* __restrict__ xs
+#ifdef NNSEMD_PHASE_TILE
+                                      , uint64_t (&ph)[9], uint64_t& ph_t
+#endif
+) {
     constexpr int KS = kStripeKSteps;
     constexpr int NW = T / 64;
     const int tid = threadIdx.x;
@@ -272,6 +276,24 @@ __device__ void key_tile_mfma_stripes(const uint16_t* __restrict__ X, const uint
     const int kp = ksteps * 32;
     const int r16 = lane & 15, kq = 8 * (lane >> 4);
     const bool rows8 = (d & 3) == 0 && (reinterpret_cast<uintptr_t>(X) & 7u) == 0;
+    // Double buffering (8-byte rows): the next supplier block is loaded into
+    // registers while the current one is multiplied.
+    constexpr int PRE = (32 * (KS * 32 / 4) + T - 1) / T;
+    const int nq = 32 * (kp / 4);
+    uint2 pre[PRE];
+    auto fetch = [&](int ib) {
+        const int i0 = ib * 32;
+#pragma unroll
+        for (int u = 0; u < PRE; ++u) {
+            const int e = tid + u * T;
+            pre[u] = make_uint2(0u, 0u);
+            if (e < nq) {
+                const int r = e / (kp / 4), k = 4 * (e % (kp / 4));
+                if (i0 + r < m && k < d) pre[u] = *reinterpret_cast<const uint2*>(X + (size_t)(i0 + r) * d + k);
+            }
+        }
+    };
+    if (rows8 && tm > 0) fetch(0);
     for (int sg = 0; sg < (tn + NW - 1) / NW; ++sg) {
         const int cs = sg * NW + wave;
         const bool mine = cs < tn;
@@ -280,11 +302,13 @@ __device__ void key_tile_mfma_stripes(const uint16_t* __restrict__ X, const uint
         float tb1 = INFINITY, tb2 = INFINITY;
         int tbs = 0x7fffffff;
         if (mine) {
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+                if (ks < ksteps) yb[ks] = frag8(Y, j0 + r16, n, ks * 32 + kq, d);
             double ss = 0.0;
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
                 if (ks < ksteps) {
-                    yb[ks] = frag8(Y, j0 + r16, n, ks * 32 + kq, d);
                     union {
                         bf16x8 v;
                         uint32_t w[4];
@@ -303,15 +327,20 @@ __device__ void key_tile_mfma_stripes(const uint16_t* __restrict__ X, const uint
             ss += __shfl_xor(ss, 32);
             if (lane < 16 && j0 + r16 < n) yy[j0 + r16] = (float)ss;
         }
+#ifdef NNSEMD_PHASE_TILE
+        NNSEMD_PH(1)
+#endif
         for (int ib = 0; ib < tm; ++ib) {
             const int i0 = ib * 32;
             __syncthreads();  // the previous block's fragments have been read
             if (rows8) {
-                for (int e = tid; e < 32 * (kp / 4); e += T) {
-                    const int r = e / (kp / 4), k = 4 * (e % (kp / 4));
-                    uint2 v = make_uint2(0u, 0u);
-                    if (i0 + r < m && k < d) v = *reinterpret_cast<const uint2*>(X + (size_t)(i0 + r) * d + k);
-                    *reinterpret_cast<uint2*>(&xs[r * kStripeLdx + k]) = v;
+#pragma unroll
+                for (int u = 0; u < PRE; ++u) {
+                    const int e = tid + u * T;
+                    if (e < nq) {
+                        const int r = e / (kp / 4), k = 4 * (e % (kp / 4));
+                        *reinterpret_cast<uint2*>(&xs[r * kStripeLdx + k]) = pre[u];
+                    }
                 }
             } else {
                 for (int e = tid; e < 32 * kp; e += T) {
@@ -320,6 +349,10 @@ __device__ void key_tile_mfma_stripes(const uint16_t* __restrict__ X, const uint
                 }
             }
             __syncthreads();
+            if (rows8) fetch(ib + 1 < tm ? ib + 1 : 0);  // next block (the first again for the next stripes)
+#ifdef NNSEMD_PHASE_TILE
+            NNSEMD_PH(2)
+#endif
             if (!mine) continue;
             // each K step from a zero accumulator (at most 31 roundings),
             // the chunk sums added in FP64
@@ -343,6 +376,9 @@ __device__ void key_tile_mfma_stripes(const uint16_t* __restrict__ X, const uint
                     }
                 }
             }
+#ifdef NNSEMD_PHASE_TILE
+            NNSEMD_PH(3)
+#endif
             const int j = j0 + r16;
             // rows of this lane in ascending order: acc0's four, then acc1's
 #pragma unroll
@@ -361,6 +397,9 @@ __device__ void key_tile_mfma_stripes(const uint16_t* __restrict__ X, const uint
                         }
                     }
                 }
+#ifdef NNSEMD_PHASE_TILE
+            NNSEMD_PH(4)
+#endif
         }
         if (mine) {
 #pragma unroll
@@ -931,7 +970,9 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
         }
     }
     NNSEMD_PH(8)
+#ifndef NNSEMD_PHASE_TILE
     NNSEMD_PH_FLUSH(A.phase_cycles)
+#endif
 }
 
 // Tile kernel of the split form (BF16, K steps <= kStripeKSteps, sides <=
@@ -944,6 +985,9 @@ __device__ void doc_tile_pair(const DocArgs& A, int64_t p, char* __restrict__ sl
                               float* __restrict__ am, uint16_t* __restrict__ xs, Shared& sh) {
     const int tid = threadIdx.x;
     const int d = A.d;
+#ifdef NNSEMD_PHASE_TILE
+    NNSEMD_PH_DECL
+#endif
     int64_t x0, y0, m, n;
     const int status = resolve_pair(A, p, x0, m, y0, n);
     const int mi = status == NNSEMD_OK ? (int)m : 0, ni = status == NNSEMD_OK ? (int)n : 0;
@@ -967,7 +1011,21 @@ __device__ void doc_tile_pair(const DocArgs& A, int64_t p, char* __restrict__ sl
             double s2 = 0.0;
             if (row < mi) {
                 const uint16_t* pr = X + (size_t)row * d;
-                for (int k = gl; k < d; k += G) {
+                int k0 = 0;
+                if ((d & 3) == 0 && (reinterpret_cast<uintptr_t>(pr) & 7u) == 0) {
+#pragma unroll 4
+                    for (int c = gl; c < d / 4; c += G) {
+                        const uint2 v = *reinterpret_cast<const uint2*>(pr + 4 * c);
+                        rb |= !finite_pair(v.x) || !finite_pair(v.y);
+                        const double f0 = bf_lo(v.x), f1 = bf_hi(v.x), f2 = bf_lo(v.y), f3 = bf_hi(v.y);
+                        s2 = fma(f0, f0, s2);
+                        s2 = fma(f1, f1, s2);
+                        s2 = fma(f2, f2, s2);
+                        s2 = fma(f3, f3, s2);
+                    }
+                    k0 = d;
+                }
+                for (int k = k0 + gl; k < d; k += G) {
                     rb |= !finite_in(pr[k]);
                     const double f = to_f32(pr[k]);
                     s2 = fma(f, f, s2);
@@ -987,11 +1045,21 @@ __device__ void doc_tile_pair(const DocArgs& A, int64_t p, char* __restrict__ sl
         }
     }
     __syncthreads();
+#ifdef NNSEMD_PHASE_TILE
+    NNSEMD_PH(0)
+    key_tile_mfma_stripes<T>(X, Y, mi, ni, d, xx, reinterpret_cast<float*>(slot), ayy, bad, am, ab1, ab2, abs_, xs,
+                             ph, ph_t);
+#else
     key_tile_mfma_stripes<T>(X, Y, mi, ni, d, xx, reinterpret_cast<float*>(slot), ayy, bad, am, ab1, ab2, abs_, xs);
+#endif
     double bd[1] = {bad ? 1.0 : 0.0};
     const int bop[1] = {2};
     block_reduce<T, 1>(bd, bop, sh);
     if (tid == 0) *aflag = bd[0] != 0.0 ? 1 : 0;
+#ifdef NNSEMD_PHASE_TILE
+    NNSEMD_PH(8)
+    NNSEMD_PH_FLUSH(A.phase_cycles)
+#endif
 }
 
 #ifndef NNSEMD_CPU_EMULATION
