@@ -14,8 +14,9 @@
 //   rescore  FP64 argmin of near-tie consumers, one wavefront each
 //   offsets  exclusive scan of the bucket counts (one workgroup)
 //   scatter  claimants into buckets
-//   rank     each claimant's position in its bucket ((D, j) or random key)
-//   walk     one lane per claimed supplier serves in order, FP64
+//   serve    one wavefront per claimed supplier selects its claimants in
+//            (D, j) (or random-key) order while it holds mass and serves
+//            them in FP64: only the served prefix of the order is formed
 //   compact  plan append + surviving suppliers / consumers: per-block counts,
 //            stable writes at the blocks' offsets, one-thread commit
 // Cost and map are accumulated per supplier (local index) in serve order, so
@@ -491,75 +492,115 @@ __global__ __launch_bounds__(kLpThreads) void lp_scatter(LPArgs A) {
     A.w.list[pos] = j;
 }
 
-// ------------------------------------------------------------------ rank
-__global__ __launch_bounds__(kLpThreads) void lp_rank(LPArgs A) {
-    const LPState* st = A.w.st;
-    if (!lp_live(st)) return;
-    const int q = blockIdx.x * kLpThreads + threadIdx.x;
-    if (q >= st->nact) return;
-    const int j = A.w.cact[st->parity][q];
-    const int sl = A.w.cnn[j];
-    const int c = A.w.scnt[sl];
-    const int end = A.w.soff[sl];
-    const int start = end - c;
-    int rank = 0;
-    if (c > 1) {
-        if (A.protocol == NNSEMD_GREEDY) {
-            const double k = A.w.ckey[j];
-            for (int e = start; e < end; ++e) {
-                const int j2 = A.w.list[e];
-                const double k2 = A.w.ckey[j2];
-                rank += (k2 < k) || (k2 == k && j2 < j);
-            }
-        } else {
-            const uint64_t k = lp_rp_key(A.seed, st->rounds, j);
-            for (int e = start; e < end; ++e) {
-                const int j2 = A.w.list[e];
-                const uint64_t k2 = lp_rp_key(A.seed, st->rounds, j2);
-                rank += (k2 < k) || (k2 == k && j2 < j);
-            }
-        }
-    }
-    A.w.sorted[start + rank] = j;
-}
-
-// ------------------------------------------------------------------ walk
+// ----------------------------------------------------------------- serve
+// Claimant order and serve fused, one wavefront per claimed supplier.  The
+// greedy protocol serves claimants in (key, j) order (the random one in
+// (random key, j) order) while the supplier holds mass, so only that prefix
+// of the order is needed: each step selects, by a wavefront-wide argmin,
+// the smallest claimant above the previous one, and the supplier serves it
+// with the definition's FP64 operations in the definition's order (one lane
+// does the arithmetic).  Served claimants go to the bucket's head in serve
+// order, unserved ones after them; flows replace keys after the walk (the
+// selection compares keys until then); flowtmp is free scratch indexed by
+// consumer.  Work O(served x bucket / 64) instead of O(bucket^2).
 template <int D>
-__global__ __launch_bounds__(kLpThreads) void lp_walk(LPArgs A) {
+__global__ __launch_bounds__(kLpThreads) void lp_serve(LPArgs A) {
 #pragma clang fp contract(off)
     const LPState* st = A.w.st;
     if (!lp_live(st)) return;
-    const int s = blockIdx.x * kLpThreads + threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int s = blockIdx.x * (kLpThreads / kWave) + threadIdx.x / kWave;
     const int par = st->parity;
-    if (s >= st->mact) return;
+    if (s >= st->mact) return;  // whole wavefronts
     const int c = A.w.scnt[s];
     if (c == 0) return;
     const int end = A.w.soff[s];
+    const int start = end - c;
     const int isup = A.w.sidx[par][s];
-    int pos = end - c;
+    const bool greedy = A.protocol == NNSEMD_GREEDY;
+    const uint64_t seed = A.seed;
+    const int64_t rnd = st->rounds;
+    double* flowtmp = reinterpret_cast<double*>(A.w.part);
+    auto okey = [&](int j) -> uint64_t {
+        // keys are >= +0, so their bit patterns order like the values
+        return greedy ? (uint64_t)__double_as_longlong(A.w.ckey[j]) : lp_rp_key(seed, rnd, j);
+    };
     double sm = A.w.smass[par][s];
     double acc = A.w.costacc[isup];
-    while (pos < end && sm > 0.0) {
-        const int j = A.w.sorted[pos];
-        const double cm = A.w.cmass[j];
+    uint64_t lk = 0;   // last served (key, j); nothing served yet
+    int lj = -1;
+    int served = 0;
+    while (served < c && sm > 0.0) {
+        uint64_t bk = ~0ull;
+        int bj = 0x7fffffff;
+        for (int e = start + lane; e < end; e += kWave) {
+            const int j = A.w.list[e];
+            const uint64_t k = okey(j);
+            const bool above = lj < 0 || k > lk || (k == lk && j > lj);
+            if (above && (k < bk || (k == bk && j < bj))) {
+                bk = k;
+                bj = j;
+            }
+        }
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) {
+            const uint64_t ck = __shfl_xor(bk, o);
+            const int cj = __shfl_xor(bj, o);
+            if (ck < bk || (ck == bk && cj < bj)) {
+                bk = ck;
+                bj = cj;
+            }
+        }
+        const double cm = A.w.cmass[bj];
         const double f = sm < cm ? sm : cm;
         sm = sm - f;
-        A.w.cmass[j] = cm - f;
-        const double key = A.w.ckey[j];
-        acc = acc + f * (A.metric == NNSEMD_L2 ? sqrt(key) : key);
-        if (A.w.wsum != nullptr) {
-            A.w.wsum[isup] = A.w.wsum[isup] + f;
+        if (lane == 0) {
+            A.w.cmass[bj] = cm - f;
+            const double key = A.w.ckey[bj];
+            acc = acc + f * (A.metric == NNSEMD_L2 ? sqrt(key) : key);
+            if (A.w.wsum != nullptr) {
+                A.w.wsum[isup] = A.w.wsum[isup] + f;
 #pragma unroll
-            for (int t = 0; t < D; ++t)
-                A.w.bsum[(int64_t)isup * D + t] = A.w.bsum[(int64_t)isup * D + t] + f * (double)A.Y[(int64_t)j * D + t];
+                for (int t = 0; t < D; ++t)
+                    A.w.bsum[(int64_t)isup * D + t] =
+                        A.w.bsum[(int64_t)isup * D + t] + f * (double)A.Y[(int64_t)bj * D + t];
+            }
+            flowtmp[bj] = f;
+            A.w.cnn[bj] = isup;
+            A.w.sorted[start + served] = bj;
         }
-        A.w.ckey[j] = f;
-        A.w.cnn[j] = isup;
-        ++pos;
+        lk = bk;
+        lj = bj;
+        ++served;
     }
-    for (int e = pos; e < end; ++e) A.w.ckey[A.w.sorted[e]] = 0.0;
-    A.w.smass[par][s] = sm;
-    A.w.costacc[isup] = acc;
+    // Unserved claimants (above the last served one, by their keys, which
+    // nobody has changed yet) go after the served ones with flow 0; then lane
+    // 0 replaces the served claimants' keys by their flows.
+    int pos = start + served;
+    for (int e0 = start; e0 < end; e0 += kWave) {
+        const int e = e0 + lane;
+        bool un = false;
+        int j = -1;
+        if (e < end) {
+            j = A.w.list[e];
+            const uint64_t k = okey(j);
+            un = lj < 0 || k > lk || (k == lk && j > lj);
+        }
+        const uint64_t m = __ballot(un);
+        if (un) {
+            A.w.sorted[pos + __popcll(m & ((1ull << lane) - 1ull))] = j;
+            A.w.ckey[j] = 0.0;
+        }
+        pos += __popcll(m);
+    }
+    if (lane == 0) {
+        for (int q = start; q < start + served; ++q) {
+            const int j = A.w.sorted[q];
+            A.w.ckey[j] = flowtmp[j];
+        }
+        A.w.smass[par][s] = sm;
+        A.w.costacc[isup] = acc;
+    }
 }
 
 // --------------------------------------------------------------- compact
@@ -766,10 +807,10 @@ int lp_launch_round(const LPArgs& A, int d, int mact_ub, int nact_ub, void* stre
     if ((int64_t)split * A.w.ncap > A.w.part_cap) split = (int)(A.w.part_cap / A.w.ncap);
     if (split < 1) split = 1;
     const int qblocks = (nact_ub + kLpThreads - 1) / kLpThreads;
-    const int sblocks = (mact_ub + kLpThreads - 1) / kLpThreads;
+    const int wblocks = (mact_ub + kLpThreads / kWave - 1) / (kLpThreads / kWave);  // one wavefront per supplier
     const int cmax = mact_ub > nact_ub ? mact_ub : nact_ub;
     const int cmblocks = (cmax + kLpCompactBlock - 1) / kLpCompactBlock;
-    if (qblocks == 0 || sblocks == 0) return 0;
+    if (qblocks == 0 || wblocks == 0) return 0;
     if (cmblocks > A.w.blkcnt_cap) return (int)hipErrorInvalidValue;
     NNSEMD_LP_DISPATCH(d, {
         if (kc == 4) {
@@ -788,8 +829,7 @@ int lp_launch_round(const LPArgs& A, int d, int mact_ub, int nact_ub, void* stre
         }
         hipLaunchKernelGGL(lp_offsets, dim3(1), dim3(kLpScanThreads), 0, st, A);
         hipLaunchKernelGGL(lp_scatter, dim3(qblocks), dim3(kLpThreads), 0, st, A);
-        hipLaunchKernelGGL(lp_rank, dim3(qblocks), dim3(kLpThreads), 0, st, A);
-        hipLaunchKernelGGL(lp_walk<DD>, dim3(sblocks), dim3(kLpThreads), 0, st, A);
+        hipLaunchKernelGGL(lp_serve<DD>, dim3(wblocks), dim3(kLpThreads), 0, st, A);
         hipLaunchKernelGGL(lp_ccount, dim3(cmblocks), dim3(kLpThreads), 0, st, A);
         hipLaunchKernelGGL(lp_cwrite<DD>, dim3(cmblocks), dim3(kLpThreads), 0, st, A);
         hipLaunchKernelGGL(lp_commit, dim3(1), dim3(1), 0, st, A, cmblocks);
