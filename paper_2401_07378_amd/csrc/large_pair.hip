@@ -11,7 +11,8 @@
 //   decide   merge the chunk partials; near ties (FP32 rounding bound) go to
 //            the FP64 re-score list, others store pick + exact FP64 key and
 //            count themselves into the pick's bucket
-//   rescore  FP64 argmin of near-tie consumers, one wavefront each
+//   rescore  FP64 argmin of near-tie consumers, one workgroup each: FP32
+//            keys filter the suppliers, FP64 keys decide among the rest
 //   offsets  exclusive scan of the bucket counts (one workgroup)
 //   scatter  claimants into buckets
 //   serve    one wavefront per claimed supplier selects its claimants in
@@ -100,6 +101,37 @@ __device__ inline double lp_block_sum(double v, double* scratch) {
     for (int k = 1; k < T / kWave; ++k) r += scratch[k];
     __syncthreads();
     return r;
+}
+
+// Adds one to cnt[t] for every active lane of the wavefront and returns the
+// lane's rank among the adds to its target.  Lanes with equal targets are
+// combined behind one atomic (up to kLpAggPasses targets per wavefront, the
+// rest add alone), so thousands of consumers picking one supplier do not
+// serialise on its counter.  Call with the whole wavefront.
+constexpr int kLpAggPasses = 4;
+
+__device__ inline int lp_count_rank(int* cnt, int t, bool active) {
+    const int lane = threadIdx.x & (kWave - 1);
+    bool todo = active;
+    int rank = 0;
+#pragma unroll 1
+    for (int pass = 0; pass < kLpAggPasses; ++pass) {
+        const unsigned long long m = __ballot(todo);
+        if (m == 0ull) return rank;
+        const int leader = __builtin_ctzll(m);
+        const int lt = __shfl(t, leader);
+        const bool mine = todo && t == lt;
+        const unsigned long long same = __ballot(mine);
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&cnt[lt], __popcll(same));
+        base = __shfl(base, leader);
+        if (mine) {
+            rank = base + __popcll(same & ((1ull << lane) - 1ull));
+            todo = false;
+        }
+    }
+    if (todo) rank = atomicAdd(&cnt[t], 1);
+    return rank;
 }
 
 // ---------------------------------------------------------------- ingest
@@ -381,25 +413,52 @@ __global__ __launch_bounds__(kLpThreads) void lp_search(LPArgs A, int split) {
 }
 
 // ---------------------------------------------------------------- decide
+// Best / second-best merge of two FP32 partials; equal keys keep the smaller
+// slot, so the result does not depend on the merge order.
+__device__ inline void lp_merge2(float& b1, float& b2, int& bs, float x1, float x2, int xs) {
+    const float n2 = fminf(fmaxf(b1, x1), fminf(b2, x2));
+    const bool take = (x1 < b1) || (x1 == b1 && xs < bs);
+    b1 = take ? x1 : b1;
+    bs = take ? xs : bs;
+    b2 = n2;
+}
+
+// kLpDecideSub lanes per consumer merge the supplier chunks' partials (four
+// loads in flight each), then combine by shuffles; the first lane decides.
+constexpr int kLpDecideSub = 8;
+constexpr int kLpDecideBatch = 4;
+
 template <int D, bool L1>
 __global__ __launch_bounds__(kLpThreads) void lp_decide(LPArgs A, int split) {
     LPState* st = A.w.st;
     if (!lp_live(st)) return;
     const int nact = st->nact, par = st->parity;
-    const int q = blockIdx.x * kLpThreads + threadIdx.x;
-    if (q >= nact) return;
+    const int sub = threadIdx.x & (kLpDecideSub - 1);
+    const int q = blockIdx.x * (kLpThreads / kLpDecideSub) + threadIdx.x / kLpDecideSub;
+    const bool valid = q < nact;  // the whole wavefront stays for the shuffles and counting
     float b1 = INFINITY, b2 = INFINITY;
     int bs = 0x7fffffff;
-    for (int c = 0; c < split; ++c) {
-        const float4 v = A.w.part[(size_t)c * A.w.ncap + q];
-        const int cs = __float_as_int(v.z);
-        const float n2 = fminf(fmaxf(b1, v.x), fminf(b2, v.y));
-        const bool take = (v.x < b1) || (v.x == b1 && cs < bs);
-        b1 = take ? v.x : b1;
-        bs = take ? cs : bs;
-        b2 = n2;
+    if (valid) {
+        for (int c0 = sub; c0 < split; c0 += kLpDecideBatch * kLpDecideSub) {
+            float4 v[kLpDecideBatch];
+#pragma unroll
+            for (int u = 0; u < kLpDecideBatch; ++u) {
+                const int c = c0 + u * kLpDecideSub;
+                v[u] = c < split ? A.w.part[(size_t)c * A.w.ncap + q]
+                                 : make_float4(INFINITY, INFINITY, __int_as_float(0x7fffffff), 0.f);
+            }
+#pragma unroll
+            for (int u = 0; u < kLpDecideBatch; ++u) lp_merge2(b1, b2, bs, v[u].x, v[u].y, __float_as_int(v[u].z));
+        }
     }
-    const int j = A.w.cact[par][q];
+#pragma unroll
+    for (int o = 1; o < kLpDecideSub; o <<= 1) {
+        const float x1 = __shfl_xor(b1, o), x2 = __shfl_xor(b2, o);
+        const int xs = __shfl_xor(bs, o);
+        lp_merge2(b1, b2, bs, x1, x2, xs);
+    }
+    const bool live = valid && sub == 0;
+    const int j = live ? A.w.cact[par][q] : 0;
     float thr;
     if (L1) {
         thr = 4.f * (float)(D + 1) * kU32 * b2 + 1e-30f;
@@ -413,36 +472,92 @@ __global__ __launch_bounds__(kLpThreads) void lp_decide(LPArgs A, int split) {
         const float e = st->rhat + sqrtf(yn2);
         thr = 32.f * kU32 * e * e + 1e-30f;
     }
-    if (!(b2 - b1 > thr)) {
-        const int f = atomicAdd(&st->nflag, 1);
+    const bool near = live && !(b2 - b1 > thr);
+    const bool pick = live && !near;
+    // The FP64 argmin's FP32 key is within half the threshold of b1 (two
+    // per-key bounds), so b1 + thr bounds the candidates of the re-score.
+    const int f = lp_count_rank(&st->nflag, 0, near);
+    if (near) {
         A.w.flagged[f] = j;
-    } else {
+        A.w.ckey[j] = (double)(b1 + thr);
+    }
+    // rank within the pick's bucket (sorted is free until the serve)
+    const int r = lp_count_rank(A.w.scnt, pick ? bs : 0, pick);
+    if (pick) {
         const int i = A.w.sidx[par][bs];
         A.w.cnn[j] = bs;
         A.w.ckey[j] = lp_key64<D, L1>(A.X + (int64_t)i * D, A.Y + (int64_t)j * D);
-        atomicAdd(&A.w.scnt[bs], 1);
+        A.w.sorted[j] = r;
     }
 }
 
 // --------------------------------------------------------------- rescore
+// One workgroup per near-tie consumer: every active supplier's FP32 key is
+// formed again from the slot records (contiguous, as in the search); only
+// those at or below the cutoff that decide stored (a NaN key or cutoff lets
+// every supplier through) are re-scored in FP64 from the original points.
+// The argmin over (FP64 key, slot) is order-free, hence deterministic.
+constexpr int kLpRescoreThreads = 1024;
+constexpr int kLpRescoreUnroll = 4;
+
 template <int D, bool L1>
-__global__ __launch_bounds__(kLpThreads) void lp_rescore(LPArgs A) {
+__global__ __launch_bounds__(kLpRescoreThreads) void lp_rescore(LPArgs A) {
+    constexpr int RS = record_stride(D);
+    constexpr int NW = kLpRescoreThreads / kWave;
+    __shared__ double sk[NW];
+    __shared__ int ss[NW];
     LPState* st = A.w.st;
     if (!lp_live(st)) return;
     const int nf = st->nflag, mact = st->mact, par = st->parity;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int gw = blockIdx.x * (kLpThreads / kWave) + threadIdx.x / kWave;
-    const int nw = gridDim.x * (kLpThreads / kWave);
-    for (int f = gw; f < nf; f += nw) {
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+    const float* __restrict__ srec = A.w.srec[par];
+    const int* __restrict__ sidx = A.w.sidx[par];
+    for (int f = blockIdx.x; f < nf; f += gridDim.x) {
         const int j = A.w.flagged[f];
         const float* yp = A.Y + (int64_t)j * D;
+        const float cut = (float)A.w.ckey[j];
+        float y[D];
+#pragma unroll
+        for (int t = 0; t < D; ++t) y[t] = L1 ? yp[t] : yp[t] - st->centre[t];
         double best = INFINITY;
         int bsl = 0x7fffffff;
-        for (int s = lane; s < mact; s += kWave) {
-            const double k = lp_key64<D, L1>(A.X + (int64_t)A.w.sidx[par][s] * D, yp);
-            if (k < best) {
-                best = k;
-                bsl = s;
+        for (int s0 = tid; s0 < mact; s0 += kLpRescoreThreads * kLpRescoreUnroll) {
+            float key[kLpRescoreUnroll];
+#pragma unroll
+            for (int u = 0; u < kLpRescoreUnroll; ++u) {
+                const int s = s0 + u * kLpRescoreThreads;
+                float rec[RS];
+                const float4* p = reinterpret_cast<const float4*>(srec + (size_t)(s < mact ? s : 0) * RS);
+#pragma unroll
+                for (int q = 0; q < RS / 4; ++q) {
+                    const float4 v = p[q];
+                    rec[4 * q] = v.x;
+                    rec[4 * q + 1] = v.y;
+                    rec[4 * q + 2] = v.z;
+                    rec[4 * q + 3] = v.w;
+                }
+                float kv;
+                if (L1) {
+                    kv = 0.f;
+#pragma unroll
+                    for (int t = 0; t < D; ++t) kv += fabsf(rec[t] - y[t]);
+                } else {
+                    kv = rec[D];
+#pragma unroll
+                    for (int t = D - 1; t >= 0; --t) kv = fmaf(rec[t], y[t], kv);
+                }
+                key[u] = kv;
+            }
+#pragma unroll
+            for (int u = 0; u < kLpRescoreUnroll; ++u) {
+                const int s = s0 + u * kLpRescoreThreads;
+                if (s < mact && !(key[u] > cut)) {
+                    const double k = lp_key64<D, L1>(A.X + (int64_t)sidx[s] * D, yp);
+                    if (k < best) {  // slots rise along the thread's walk: ties keep the first
+                        best = k;
+                        bsl = s;
+                    }
+                }
             }
         }
 #pragma unroll
@@ -455,41 +570,73 @@ __global__ __launch_bounds__(kLpThreads) void lp_rescore(LPArgs A) {
             }
         }
         if (lane == 0) {
+            sk[w] = best;
+            ss[w] = bsl;
+        }
+        __syncthreads();
+        if (tid == 0) {
+#pragma unroll
+            for (int k = 1; k < NW; ++k)
+                if (sk[k] < best || (sk[k] == best && ss[k] < bsl)) {
+                    best = sk[k];
+                    bsl = ss[k];
+                }
             A.w.cnn[j] = bsl;
             A.w.ckey[j] = best;
-            atomicAdd(&A.w.scnt[bsl], 1);
+            A.w.sorted[j] = atomicAdd(&A.w.scnt[bsl], 1);
         }
+        __syncthreads();
     }
 }
 
 // --------------------------------------------------------------- offsets
+// Exclusive scan of the bucket counts into bucket starts.  Each thread owns
+// a run of counts starting at a multiple of four (16-byte loads and stores).
 __global__ __launch_bounds__(kLpScanThreads) void lp_offsets(LPArgs A) {
     __shared__ unsigned long long scratch[kLpScanThreads / kWave];
     LPState* st = A.w.st;
     if (!lp_live(st)) return;
     const int mact = st->mact;
     const int tid = threadIdx.x;
-    const int cs = (mact + kLpScanThreads - 1) / kLpScanThreads;
+    const int cs = (((mact + kLpScanThreads - 1) / kLpScanThreads) + 3) & ~3;
     const int lo = min(tid * cs, mact), hi = min(lo + cs, mact);
+    const int hq = lo + ((hi - lo) & ~3);
+    const int* __restrict__ cnt = A.w.scnt;
     int sum = 0;
-    for (int s = lo; s < hi; ++s) sum += A.w.scnt[s];
+#pragma unroll 4
+    for (int s = lo; s < hq; s += 4) {
+        const int4 v = *reinterpret_cast<const int4*>(cnt + s);
+        sum += (v.x + v.y) + (v.z + v.w);
+    }
+    for (int s = hq; s < hi; ++s) sum += cnt[s];
     unsigned long long tot;
     int run = (int)lp_block_scan<kLpScanThreads>((unsigned long long)sum, &tot, scratch);
-    for (int s = lo; s < hi; ++s) {
+#pragma unroll 4
+    for (int s = lo; s < hq; s += 4) {
+        const int4 v = *reinterpret_cast<const int4*>(cnt + s);
+        int4 o;
+        o.x = run;
+        o.y = o.x + v.x;
+        o.z = o.y + v.y;
+        o.w = o.z + v.z;
+        run = o.w + v.w;
+        *reinterpret_cast<int4*>(A.w.soff + s) = o;
+    }
+    for (int s = hq; s < hi; ++s) {
         A.w.soff[s] = run;
-        run += A.w.scnt[s];
+        run += cnt[s];
     }
 }
 
 // --------------------------------------------------------------- scatter
+// Claimants into their buckets at the ranks the counting handed out.
 __global__ __launch_bounds__(kLpThreads) void lp_scatter(LPArgs A) {
     const LPState* st = A.w.st;
     if (!lp_live(st)) return;
     const int q = blockIdx.x * kLpThreads + threadIdx.x;
     if (q >= st->nact) return;
     const int j = A.w.cact[st->parity][q];
-    const int pos = atomicAdd(&A.w.soff[A.w.cnn[j]], 1);
-    A.w.list[pos] = j;
+    A.w.list[A.w.soff[A.w.cnn[j]] + A.w.sorted[j]] = j;
 }
 
 // ----------------------------------------------------------------- serve
@@ -503,6 +650,8 @@ __global__ __launch_bounds__(kLpThreads) void lp_scatter(LPArgs A) {
 // order, unserved ones after them; flows replace keys after the walk (the
 // selection compares keys until then); flowtmp is free scratch indexed by
 // consumer.  Work O(served x bucket / 64) instead of O(bucket^2).
+constexpr int kLpServeBatch = 4;  // bucket entries in flight per lane
+
 template <int D>
 __global__ __launch_bounds__(kLpThreads) void lp_serve(LPArgs A) {
 #pragma clang fp contract(off)
@@ -514,8 +663,8 @@ __global__ __launch_bounds__(kLpThreads) void lp_serve(LPArgs A) {
     if (s >= st->mact) return;  // whole wavefronts
     const int c = A.w.scnt[s];
     if (c == 0) return;
-    const int end = A.w.soff[s];
-    const int start = end - c;
+    const int start = A.w.soff[s];
+    const int end = start + c;
     const int isup = A.w.sidx[par][s];
     const bool greedy = A.protocol == NNSEMD_GREEDY;
     const uint64_t seed = A.seed;
@@ -533,13 +682,25 @@ __global__ __launch_bounds__(kLpThreads) void lp_serve(LPArgs A) {
     while (served < c && sm > 0.0) {
         uint64_t bk = ~0ull;
         int bj = 0x7fffffff;
-        for (int e = start + lane; e < end; e += kWave) {
-            const int j = A.w.list[e];
-            const uint64_t k = okey(j);
-            const bool above = lj < 0 || k > lk || (k == lk && j > lj);
-            if (above && (k < bk || (k == bk && j < bj))) {
-                bk = k;
-                bj = j;
+        for (int e0 = start + lane; e0 < end; e0 += kLpServeBatch * kWave) {
+            int jj[kLpServeBatch];
+            uint64_t kk[kLpServeBatch];
+#pragma unroll
+            for (int u = 0; u < kLpServeBatch; ++u) {
+                const int e = e0 + u * kWave;
+                jj[u] = e < end ? A.w.list[e] : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < kLpServeBatch; ++u) kk[u] = jj[u] >= 0 ? okey(jj[u]) : 0ull;
+#pragma unroll
+            for (int u = 0; u < kLpServeBatch; ++u) {
+                const int j = jj[u];
+                const uint64_t k = kk[u];
+                const bool above = lj < 0 || k > lk || (k == lk && j > lj);
+                if (j >= 0 && above && (k < bk || (k == bk && j < bj))) {
+                    bk = k;
+                    bj = j;
+                }
             }
         }
 #pragma unroll
@@ -577,21 +738,28 @@ __global__ __launch_bounds__(kLpThreads) void lp_serve(LPArgs A) {
     // nobody has changed yet) go after the served ones with flow 0; then lane
     // 0 replaces the served claimants' keys by their flows.
     int pos = start + served;
-    for (int e0 = start; e0 < end; e0 += kWave) {
-        const int e = e0 + lane;
-        bool un = false;
-        int j = -1;
-        if (e < end) {
-            j = A.w.list[e];
-            const uint64_t k = okey(j);
-            un = lj < 0 || k > lk || (k == lk && j > lj);
+    for (int e0 = start + lane; e0 < end + lane; e0 += kLpServeBatch * kWave) {
+        int jj[kLpServeBatch];
+        uint64_t kk[kLpServeBatch];
+#pragma unroll
+        for (int u = 0; u < kLpServeBatch; ++u) {
+            const int e = e0 + u * kWave;
+            jj[u] = e < end ? A.w.list[e] : -1;
         }
-        const uint64_t m = __ballot(un);
-        if (un) {
-            A.w.sorted[pos + __popcll(m & ((1ull << lane) - 1ull))] = j;
-            A.w.ckey[j] = 0.0;
+#pragma unroll
+        for (int u = 0; u < kLpServeBatch; ++u) kk[u] = jj[u] >= 0 ? okey(jj[u]) : 0ull;
+#pragma unroll
+        for (int u = 0; u < kLpServeBatch; ++u) {
+            const int j = jj[u];
+            const uint64_t k = kk[u];
+            const bool un = j >= 0 && (lj < 0 || k > lk || (k == lk && j > lj));
+            const uint64_t m = __ballot(un);
+            if (un) {
+                A.w.sorted[pos + __popcll(m & ((1ull << lane) - 1ull))] = j;
+                A.w.ckey[j] = 0.0;
+            }
+            pos += __popcll(m);
         }
-        pos += __popcll(m);
     }
     if (lane == 0) {
         for (int q = start; q < start + served; ++q) {
@@ -698,11 +866,21 @@ __global__ __launch_bounds__(kLpThreads) void lp_cwrite(LPArgs A) {
     }
 }
 
-__global__ void lp_commit(LPArgs A, int nblocks) {
+__global__ __launch_bounds__(kLpThreads) void lp_commit(LPArgs A, int nblocks) {
+    __shared__ unsigned long long red[kLpThreads / kWave];
     LPState* st = A.w.st;
     if (!lp_live(st)) return;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     unsigned long long tot = 0;
-    for (int b = 0; b < nblocks; ++b) tot += A.w.blkcnt[b];
+    for (int b = threadIdx.x; b < nblocks; b += kLpThreads) tot += A.w.blkcnt[b];
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) tot += __shfl_xor(tot, o);
+    if (lane == 0) red[w] = tot;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    tot = 0;
+#pragma unroll
+    for (int k = 0; k < kLpThreads / kWave; ++k) tot += red[k];
     const unsigned long long mask = (1ull << 21) - 1;
     const int m2 = (int)((tot >> 21) & mask), n2 = (int)(tot >> 42);
     st->nnz += (int64_t)(tot & mask);
@@ -807,6 +985,7 @@ int lp_launch_round(const LPArgs& A, int d, int mact_ub, int nact_ub, void* stre
     if ((int64_t)split * A.w.ncap > A.w.part_cap) split = (int)(A.w.part_cap / A.w.ncap);
     if (split < 1) split = 1;
     const int qblocks = (nact_ub + kLpThreads - 1) / kLpThreads;
+    const int dblocks = (nact_ub + kLpThreads / kLpDecideSub - 1) / (kLpThreads / kLpDecideSub);
     const int wblocks = (mact_ub + kLpThreads / kWave - 1) / (kLpThreads / kWave);  // one wavefront per supplier
     const int cmax = mact_ub > nact_ub ? mact_ub : nact_ub;
     const int cmblocks = (cmax + kLpCompactBlock - 1) / kLpCompactBlock;
@@ -821,18 +1000,18 @@ int lp_launch_round(const LPArgs& A, int d, int mact_ub, int nact_ub, void* stre
             else hipLaunchKernelGGL((lp_search<DD, false, 1>), dim3(cblocks, split), dim3(kLpThreads), 0, st, A, split);
         }
         if (l1) {
-            hipLaunchKernelGGL((lp_decide<DD, true>), dim3(qblocks), dim3(kLpThreads), 0, st, A, split);
-            hipLaunchKernelGGL((lp_rescore<DD, true>), dim3(256), dim3(kLpThreads), 0, st, A);
+            hipLaunchKernelGGL((lp_decide<DD, true>), dim3(dblocks), dim3(kLpThreads), 0, st, A, split);
+            hipLaunchKernelGGL((lp_rescore<DD, true>), dim3(512), dim3(kLpRescoreThreads), 0, st, A);
         } else {
-            hipLaunchKernelGGL((lp_decide<DD, false>), dim3(qblocks), dim3(kLpThreads), 0, st, A, split);
-            hipLaunchKernelGGL((lp_rescore<DD, false>), dim3(256), dim3(kLpThreads), 0, st, A);
+            hipLaunchKernelGGL((lp_decide<DD, false>), dim3(dblocks), dim3(kLpThreads), 0, st, A, split);
+            hipLaunchKernelGGL((lp_rescore<DD, false>), dim3(512), dim3(kLpRescoreThreads), 0, st, A);
         }
         hipLaunchKernelGGL(lp_offsets, dim3(1), dim3(kLpScanThreads), 0, st, A);
         hipLaunchKernelGGL(lp_scatter, dim3(qblocks), dim3(kLpThreads), 0, st, A);
         hipLaunchKernelGGL(lp_serve<DD>, dim3(wblocks), dim3(kLpThreads), 0, st, A);
         hipLaunchKernelGGL(lp_ccount, dim3(cmblocks), dim3(kLpThreads), 0, st, A);
         hipLaunchKernelGGL(lp_cwrite<DD>, dim3(cmblocks), dim3(kLpThreads), 0, st, A);
-        hipLaunchKernelGGL(lp_commit, dim3(1), dim3(1), 0, st, A, cmblocks);
+        hipLaunchKernelGGL(lp_commit, dim3(1), dim3(kLpThreads), 0, st, A, cmblocks);
     })
     return (int)hipGetLastError();
 }
