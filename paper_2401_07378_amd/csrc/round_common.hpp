@@ -50,9 +50,12 @@ struct Lds {
     int32_t* sorted;  // [N] claimant buckets in serve order
 };
 
+constexpr int kMaxWaves = 8;    // workgroups of up to 512 threads
+constexpr int kMaxReduce = 17;  // values per block reduction (3 + 2d, d <= 7)
+
 struct Shared {
-    double red[16][24];
-    unsigned long long scan[16];
+    double red[kMaxWaves][kMaxReduce];
+    unsigned long long scan[kMaxWaves];
     int32_t nflag;  // near-tie consumers of the search
     int32_t namb;   // claimants whose serve order needs exact keys (high-dimensional path)
 };
@@ -92,6 +95,7 @@ __device__ inline uint64_t rp_key(uint64_t seed, int64_t round, int32_t j) {
 template <int T>
 __device__ inline unsigned long long block_scan_u64(unsigned long long v, unsigned long long* total,
                                                     Shared& sh) {
+    static_assert(T / kWave <= kMaxWaves, "workgroup too large for the scan scratch");
     const int lane = threadIdx.x & (kWave - 1);
     const int w = threadIdx.x / kWave;
     unsigned long long x = v;
@@ -118,6 +122,7 @@ __device__ inline unsigned long long block_scan_u64(unsigned long long v, unsign
 // deterministic (fixed butterfly + fixed wave order).  Results in out[].
 template <int T, int K>
 __device__ inline void block_reduce(double (&v)[K], const int (&op)[K], Shared& sh) {
+    static_assert(T / kWave <= kMaxWaves && K <= kMaxReduce, "reduction scratch too small");
     const int lane = threadIdx.x & (kWave - 1);
     const int w = threadIdx.x / kWave;
 #pragma unroll
