@@ -189,10 +189,13 @@ def main():
     achieved = ops / (ms / 1e3)
     alg_bytes = int(ps.X.nbytes + ps.a.nbytes + ps.Y.nbytes + ps.b.nbytes + ps.x_off.nbytes
                     + ps.y_off.nbytes + P * (8 + 48) + (int(st["nnz"].sum()) * 16 if want_plan else 0))
+    threads_used = args.threads or (tuning["threads"] if tuning else 256)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_LANE_OPS / 1e12,
                 "unit": "Tops/s", "frac": achieved / PEAK_VALU_LANE_OPS,
                 "traffic": measured_traffic(alg_bytes),
-                "kernel": "pair_solver_kernel<3,256,4,L2>", "work_evals": work,
+                "kernel": "pair_solver_kernel<3,%d,%d,L2> + order_kernel (one step)" % (
+                    threads_used, -(-max(max_m, max_n) // threads_used)),
+                "work_evals": work,
                 "ops_per_eval": 2 * d + 2, "algorithmic_bytes": alg_bytes,
                 "hbm_gbs_algorithmic": alg_bytes / (ms / 1e3) / 1e9}
 
