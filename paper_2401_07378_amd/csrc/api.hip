@@ -27,6 +27,8 @@ struct nnsemd_handle {
     nnsemd::LPState* lp_host = nullptr;          // pinned copy of the round state
     char* doc_tiles = nullptr;                   // key-tile scratch of the high-dimensional path
     size_t doc_bytes = 0;
+    double* doc_xnorm = nullptr;                 // supplier-set norms of the split document form
+    size_t doc_xnorm_bytes = 0;
     // Autotuned launch configuration of the batched point path, by
     // dimension (1..7), metric and size class of max(max_m, max_n).
     struct Tune {
@@ -289,6 +291,22 @@ nnsemd_status_t run_docs(nnsemd_handle_t h, DocArgs& A, int64_t max_m, int64_t m
         if (s != NNSEMD_OK) return s;
         A.order = h->order;
     }
+    A.xnorm = nullptr;
+    if (doc_split_form(A.d, mfma, chunk) && A.num_pairs > 0) {
+        const int64_t sets = A.x_off != nullptr ? A.num_x_sets : 1;
+        const size_t xb = sizeof(double) * (size_t)std::max<int64_t>(sets, 1) * (size_t)mcap;
+        if (h->doc_xnorm_bytes < xb) {
+            if (h->doc_xnorm) (void)hipFree(h->doc_xnorm);
+            h->doc_xnorm = nullptr;
+            h->doc_xnorm_bytes = 0;
+            if (hipMalloc((void**)&h->doc_xnorm, xb) != hipSuccess)
+                return fail(h, NNSEMD_ERR_OUT_OF_MEMORY, "supplier norm scratch");
+            h->doc_xnorm_bytes = xb;
+        }
+        A.xnorm = h->doc_xnorm;
+        err = launch_doc_xnorm(A, stream);
+        if (err != 0) return device_fail(h, err, "supplier norm launch");
+    }
     for (int64_t base = 0; base < A.num_pairs; base += per_launch) {
         A.pair_base = base;
         const int grid = (int)std::min<int64_t>(per_launch, A.num_pairs - base);
@@ -418,6 +436,7 @@ nnsemd_status_t nnsemd_destroy(nnsemd_handle_t h) {
         if (h->order) (void)hipFree(h->order);
         if (h->lp_base) (void)hipFree(h->lp_base);
         if (h->lp_host) (void)hipHostFree(h->lp_host);
+        if (h->doc_xnorm) (void)hipFree(h->doc_xnorm);
         if (h->doc_tiles) (void)hipFree(h->doc_tiles);
         if (h->sg_quant) (void)hipFree(h->sg_quant);
         if (h->sg_ws) (void)hipFree(h->sg_ws);

@@ -1060,6 +1060,41 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
 #endif
 }
 
+// FP64 squared norm of one BF16 row shared by G lanes (lane gl of them), and
+// whether any coordinate is not finite; every lane returns both.
+template <int G>
+__device__ inline double row_norm_bf16(const uint16_t* __restrict__ pr, int d, int gl, bool& bad) {
+    bool rb = false;
+    double s2 = 0.0;
+    int k0 = 0;
+    if ((d & 3) == 0 && (reinterpret_cast<uintptr_t>(pr) & 7u) == 0) {
+#pragma unroll 4
+        for (int c = gl; c < d / 4; c += G) {
+            const uint2 v = *reinterpret_cast<const uint2*>(pr + 4 * c);
+            rb |= !finite_pair(v.x) || !finite_pair(v.y);
+            const double f0 = bf_lo(v.x), f1 = bf_hi(v.x), f2 = bf_lo(v.y), f3 = bf_hi(v.y);
+            s2 = fma(f0, f0, s2);
+            s2 = fma(f1, f1, s2);
+            s2 = fma(f2, f2, s2);
+            s2 = fma(f3, f3, s2);
+        }
+        k0 = d;
+    }
+    for (int k = k0 + gl; k < d; k += G) {
+        rb |= !finite_in(pr[k]);
+        const double f = to_f32(pr[k]);
+        s2 = fma(f, f, s2);
+    }
+    int bi = rb ? 1 : 0;
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) {
+        s2 += __shfl_xor(s2, o);
+        bi |= __shfl_xor(bi, o);
+    }
+    bad = bi != 0;
+    return s2;
+}
+
 // Tile kernel of the split form (BF16, K steps <= kStripeKSteps, sides <=
 // 1024): one workgroup per pair, the same pair <-> slot mapping as
 // doc_pair_kernel.  Supplier norms (16 lanes per row), the stripes tile with
@@ -1087,47 +1122,13 @@ __device__ void doc_tile_pair(const DocArgs& A, int64_t p, char* __restrict__ sl
     int32_t* aflag = abs_ + A.max_n;
     bool bad = false;
     for (int i = tid; i < mi; i += T) am[i] = A.a[x0 + i];
-    {
-        constexpr int G = 16;
-        const int gl = tid & (G - 1);
-        for (int r0 = 0; r0 < mi; r0 += T / G) {
-            const int row = r0 + tid / G;
-            bool rb = false;
-            double s2 = 0.0;
-            if (row < mi) {
-                const uint16_t* pr = X + (size_t)row * d;
-                int k0 = 0;
-                if ((d & 3) == 0 && (reinterpret_cast<uintptr_t>(pr) & 7u) == 0) {
-#pragma unroll 4
-                    for (int c = gl; c < d / 4; c += G) {
-                        const uint2 v = *reinterpret_cast<const uint2*>(pr + 4 * c);
-                        rb |= !finite_pair(v.x) || !finite_pair(v.y);
-                        const double f0 = bf_lo(v.x), f1 = bf_hi(v.x), f2 = bf_lo(v.y), f3 = bf_hi(v.y);
-                        s2 = fma(f0, f0, s2);
-                        s2 = fma(f1, f1, s2);
-                        s2 = fma(f2, f2, s2);
-                        s2 = fma(f3, f3, s2);
-                    }
-                    k0 = d;
-                }
-                for (int k = k0 + gl; k < d; k += G) {
-                    rb |= !finite_in(pr[k]);
-                    const double f = to_f32(pr[k]);
-                    s2 = fma(f, f, s2);
-                }
-            }
-            int bi = rb ? 1 : 0;
-#pragma unroll
-            for (int o = G / 2; o > 0; o >>= 1) {
-                s2 += __shfl_xor(s2, o);
-                bi |= __shfl_xor(bi, o);
-            }
-            if (gl == 0 && row < mi) {
-                bad |= bi != 0;
-                xx[row] = s2;
-                axx[row] = (float)s2;
-            }
-        }
+    // supplier norms from the set pass (NaN marks a non-finite row)
+    const int64_t px = A.x_off != nullptr ? (A.pair_x ? (int64_t)A.pair_x[p] : p) : 0;
+    for (int i = tid; i < mi; i += T) {
+        const double s2 = A.xnorm[px * A.max_m + i];
+        bad |= s2 != s2;
+        xx[i] = s2;
+        axx[i] = (float)s2;
     }
     __syncthreads();
 #ifdef NNSEMD_PHASE_TILE
@@ -1148,6 +1149,28 @@ __device__ void doc_tile_pair(const DocArgs& A, int64_t p, char* __restrict__ sl
 }
 
 #ifndef NNSEMD_CPU_EMULATION
+// Norm pass of the split form: every row (up to max_m) of every supplier
+// set, 16 lanes per row; blockIdx.x = set * chunks + chunk.  The suppliers
+// are shared by many pairs (one query against candidates), so their norms
+// are taken once here instead of once per pair.
+template <int T>
+__global__ __launch_bounds__(T) void doc_xnorm_kernel(DocArgs A, int chunks) {
+    constexpr int G = 16;
+    const int64_t set = blockIdx.x / chunks;
+    const int row = (int)(blockIdx.x % chunks) * (T / G) + (int)threadIdx.x / G;
+    const int gl = threadIdx.x & (G - 1);
+    int64_t x0 = 0, m = A.single_m;
+    if (A.x_off != nullptr) {
+        x0 = A.x_off[set];
+        m = A.x_off[set + 1] - x0;
+    }
+    if (m > A.max_m) m = A.max_m;  // such pairs are rejected; their rows are not needed
+    if (row >= m) return;          // whole 16-lane groups
+    bool bad;
+    const double s2 = row_norm_bf16<G>(reinterpret_cast<const uint16_t*>(A.X) + (x0 + row) * A.d, A.d, gl, bad);
+    if (gl == 0) A.xnorm[set * A.max_m + row] = bad ? (double)NAN : s2;
+}
+
 template <int T>
 __global__ __launch_bounds__(T) void doc_tile_kernel(DocArgs A) {
     extern __shared__ __align__(16) char lds_dyn[];
@@ -1205,12 +1228,27 @@ size_t doc_lds_bytes(int max_m, int max_n) {
     return pair_lds_layout(max_m, max_n, 0).total + sizeof(float) * ((size_t)max_m + 4 * (size_t)max_n);
 }
 
+bool doc_split_form(int d, bool bf16_mfma, int chunk_max) {
+    return bf16_mfma && chunk_max <= 4 && (d + 31) / 32 <= kStripeKSteps;
+}
+
 #ifndef NNSEMD_CPU_EMULATION
+int launch_doc_xnorm(const DocArgs& A, void* stream) {
+    constexpr int T = 256;
+    const int chunks = (A.max_m + T / 16 - 1) / (T / 16);
+    const int64_t sets = A.x_off != nullptr ? A.num_x_sets : 1;
+    const int64_t grid = sets * chunks;
+    if (grid <= 0) return 0;
+    if (grid > 0x7fffffffll) return (int)hipErrorInvalidValue;
+    hipLaunchKernelGGL(doc_xnorm_kernel<T>, dim3((unsigned)grid), dim3(T), 0, (hipStream_t)stream, A, chunks);
+    return (int)hipGetLastError();
+}
+
 int launch_doc_solver(const DocArgs& A, bool bf16_mfma, int chunk_max, size_t lds, int grid, void* stream,
                       int* blocks) {
     const bool run = blocks == nullptr;
     hipStream_t st = (hipStream_t)stream;
-    const bool split = (A.d + 31) / 32 <= kStripeKSteps;
+    const bool split = doc_split_form(A.d, bf16_mfma, chunk_max);
     if (bf16_mfma) {
         if (chunk_max <= 4 && split) return doc_launch_typed<uint16_t, true, 4, true>(A, lds, grid, st, run, blocks);
         if (chunk_max <= 4) return doc_launch_typed<uint16_t, true, 4, false>(A, lds, grid, st, run, blocks);

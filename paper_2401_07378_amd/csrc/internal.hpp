@@ -172,9 +172,15 @@ struct DocArgs {
     char* scratch;         // grid * slot_bytes: per-workgroup key tile, then the plan when none is requested
     int64_t slot_bytes;    // doc_slot_bytes(max_m, max_n)
     unsigned long long* phase_cycles;  // profiling builds only: 9 per-phase cycle totals
+    double* xnorm;         // split form: FP64 squared norms of the supplier sets' rows,
+                           // [set * max_m + i], NaN for a row with a non-finite coordinate
 };
 
 size_t doc_lds_bytes(int max_m, int max_n);
+// Whether a launch takes the split form (tile kernel + rounds kernel), and
+// the supplier-set norm pass it needs first (A.xnorm: num_x_sets * max_m).
+bool doc_split_form(int d, bool bf16_mfma, int chunk_max);
+int launch_doc_xnorm(const DocArgs& A, void* stream);
 // Scratch slot of one workgroup: the m x n FP32 key tile (256-byte aligned)
 // followed by m + n plan entries (int32 src, int32 dst, double flow).
 __host__ __device__ inline size_t doc_tile_bytes(int max_m, int max_n) {

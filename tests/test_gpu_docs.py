@@ -141,6 +141,46 @@ def test_document_batch_matches_oracle(mode):
         assert_pair_matches(gp, ref, label=f"pair{p}")
 
 
+def test_document_batch_several_supplier_sets():
+    """Three supplier sets of different sizes shared by nine pairs (the
+    supplier norms are taken once per set): plans against the oracle; a
+    non-finite coordinate in one set fails exactly the pairs that use it."""
+    d = 300
+    xs = [W.random_doc_pair(960 + s, m, 8, d)[:2] for s, m in enumerate((37, 211, 120))]
+    ys = [W.random_doc_pair(970 + c, 8, n, d)[2:] for c, n in enumerate((90, 15, 260, 33, 180, 64, 301, 22, 140))]
+    def cat(sets):
+        bits = np.concatenate([s[0] for s in sets]).astype(np.uint16)
+        mass = np.concatenate([s[1] for s in sets]).astype(np.float32)
+        off = np.concatenate([[0], np.cumsum([len(s[1]) for s in sets])]).astype(np.int64)
+        return bits, mass, off
+    xb, xa, xo = cat(xs)
+    yb, ya, yo = cat(ys)
+    px = np.array([p % 3 for p in range(9)], np.int32)
+    py = np.arange(9, dtype=np.int32)
+    def pairset(xbits):
+        return W.PairSet("several_sets", d, W.bf16_bits_to_f32(xbits).reshape(-1, d), xa, xo,
+                         W.bf16_bits_to_f32(yb).reshape(-1, d), ya, yo, pair_x=px, pair_y=py,
+                         metric="l2", dtype="bf16", X_bits=xbits, Y_bits=yb)
+    ps = pairset(xb)
+    g = gpu_batched(ps, plan=True, mode="bf16_mfma_refine")
+    for p in range(ps.num_pairs):
+        X, a, Y, b = ps.pair(p)
+        ref = oracle_pair(X, a, Y, b)
+        lo = g["plan_off"][p]
+        k = int(g["stats"][p]["nnz"])
+        gp = {"cost": float(g["costs"][p]), "stats": g["stats"][p], "src": g["src"][lo:lo + k],
+              "dst": g["dst"][lo:lo + k], "flow": g["flow"][lo:lo + k]}
+        assert_pair_matches(gp, ref, label=f"pair{p}")
+    bad = xb.copy()
+    bad[xo[1] + 5, 17] = 0x7F80  # +inf in supplier set 1
+    gb = gpu_batched(pairset(bad), mode="bf16_mfma_refine")
+    for p in range(9):
+        want = -1 if px[p] == 1 else 0
+        assert int(gb["stats"][p]["status"]) == want, p
+        if want == 0:
+            assert gb["costs"][p] == g["costs"][p], p
+
+
 def test_document_batch_as_given_schedule_same_bits():
     ps = _small_docs(32, seed=891)
     g1 = gpu_batched(ps, mode="bf16_mfma_refine")
