@@ -338,7 +338,10 @@ __global__ __launch_bounds__(256) void build_z_kernel(const float* __restrict__ 
 }
 
 // Fused inference head: one workgroup per 64 pairs.  The pair features
-// [Eq, Ec, |Eq - Ec|] are built 64 at a time into LDS as BF16, each
+// [Eq, Ec, |Eq - Ec|] are built into LDS as BF16 one 64-wide column block at
+// a time, all three parts together, so every embedding row is read once
+// (each thread one row's 16 features, 16-byte loads issued one block ahead,
+// so they overlap the products), each
 // wavefront multiplies them with 64 rows of W3 on the matrix cores (K = 768),
 // and the epilogue applies b3, ReLU and w4, sums the four wavefronts' parts
 // in order and writes softplus(t + b4).  Rows outside the tables give NaN.
@@ -348,60 +351,93 @@ __global__ __launch_bounds__(256) void rho_fused_kernel(const float* __restrict_
                                                         const int32_t* __restrict__ ci, int64_t B, SgQuant q,
                                                         const float* __restrict__ theta, float* __restrict__ pred) {
     constexpr int LD = 64 + 8;
-    __shared__ __align__(16) uint16_t zt[64 * LD];
-    __shared__ int64_t rq[64], rc[64];
+    constexpr int NCB = H / 64;  // 64-wide column blocks of an embedding
+    __shared__ __align__(16) uint16_t zt[3][64 * LD];
     __shared__ float red[4][64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r16 = lane & 15, kq = 8 * (lane >> 4);
     const int64_t b0 = (int64_t)blockIdx.x * 64;
-    if (tid < 64) {
-        const int64_t b = b0 + tid;
-        int64_t sq = -2, sc = -2;  // -2: padding row, -1: index outside the table
+    // Staging: thread -> (row, 16 consecutive features) of a 64 x 64 block.
+    const int srow = tid >> 2, sseg = (tid & 3) * 16;
+    int64_t sq = -2, sc = -2;  // -2: padding row, -1: index outside the table
+    {
+        const int64_t b = b0 + srow;
         if (b < B) {
             sq = qi ? (int64_t)qi[b] : 0;
             sc = ci ? (int64_t)ci[b] : b;
             if (sq < 0 || sq >= nq) sq = -1;
             if (sc < 0 || sc >= nc) sc = -1;
         }
-        rq[tid] = sq;
-        rc[tid] = sc;
     }
+    const bool rvalid = sq >= 0 && sc >= 0, rbad = sq == -1 || sc == -1;
+    float4 fq[4], fc[4];
+    auto load_feats = [&](int cb) {
+        const int col = cb * 64 + sseg;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            fq[v] = make_float4(0.f, 0.f, 0.f, 0.f);
+            fc[v] = fq[v];
+        }
+        if (rvalid) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                fq[v] = *reinterpret_cast<const float4*>(Eq_tab + sq * H + col + 4 * v);
+                fc[v] = *reinterpret_cast<const float4*>(Ec_tab + sc * H + col + 4 * v);
+            }
+        }
+    };
+    // W3 fragments of one 64-deep K block (part p, column block cb: K offset
+    // p * H + cb * 64), both 32-deep steps (L2-resident: every block reads W3).
+    bf16x8 w3[2][4];
+    auto load_w3 = [&](int kb) {
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) w3[ks][b] = frag16(q.W3, 3 * H, wave * 64 + 16 * b + r16, H, kb * 64 + ks * 32 + kq);
+    };
     f32x4 acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[i][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    for (int kc = 0; kc < 3 * H / 64; ++kc) {
-        __syncthreads();
-        const int part = kc / (H / 64), col0 = (kc % (H / 64)) * 64;
-        for (int e = tid; e < 64 * 64; e += 256) {
-            const int row = e >> 6, f = e & 63;
-            const int64_t sq = rq[row], sc = rc[row];
-            float v = 0.f;
-            if (sq == -1 || sc == -1) {
-                v = NAN;
-            } else if (sq >= 0) {
-                const float xq = Eq_tab[sq * H + col0 + f], xc = Ec_tab[sc * H + col0 + f];
-                v = part == 0 ? xq : (part == 1 ? xc : fabsf(xq - xc));
+    load_feats(0);
+    for (int cb = 0; cb < NCB; ++cb) {
+        __syncthreads();  // the previous column block's fragments have been read
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            uint32_t wv[8];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float a[4] = {fq[v].x, fq[v].y, fq[v].z, fq[v].w};
+                const float c[4] = {fc[v].x, fc[v].y, fc[v].z, fc[v].w};
+                float z[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) z[e] = rbad ? NAN : (p == 0 ? a[e] : (p == 1 ? c[e] : fabsf(a[e] - c[e])));
+                wv[2 * v] = (uint32_t)f2bf(z[0]) | ((uint32_t)f2bf(z[1]) << 16);
+                wv[2 * v + 1] = (uint32_t)f2bf(z[2]) | ((uint32_t)f2bf(z[3]) << 16);
             }
-            zt[row * LD + f] = f2bf(v);
+            uint4* dst = reinterpret_cast<uint4*>(&zt[p][srow * LD + sseg]);
+            dst[0] = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+            dst[1] = make_uint4(wv[4], wv[5], wv[6], wv[7]);
         }
         __syncthreads();
+        if (cb + 1 < NCB) load_feats(cb + 1);  // in flight during the products
+        for (int p = 0; p < 3; ++p) {
+            load_w3(p * NCB + cb);
+            const auto& wc = w3;
 #pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-            bf16x8 bfr[4];
+            for (int ks = 0; ks < 2; ++ks) {
 #pragma unroll
-            for (int b = 0; b < 4; ++b) bfr[b] = frag16(q.W3, 3 * H, wave * 64 + 16 * b + r16, H, kc * 64 + ks * 32 + kq);
+                for (int i = 0; i < 4; ++i) {
+                    union {
+                        uint4 u;
+                        bf16x8 v;
+                    } af;
+                    af.u = *reinterpret_cast<const uint4*>(&zt[p][(16 * i + r16) * LD + ks * 32 + kq]);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                union {
-                    uint4 u;
-                    bf16x8 v;
-                } af;
-                af.u = *reinterpret_cast<const uint4*>(&zt[(16 * i + r16) * LD + ks * 32 + kq]);
-#pragma unroll
-                for (int b = 0; b < 4; ++b)
-                    acc[i][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af.v, bfr[b], acc[i][b], 0, 0, 0);
+                    for (int b = 0; b < 4; ++b)
+                        acc[i][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af.v, wc[ks][b], acc[i][b], 0, 0, 0);
+                }
             }
         }
     }
@@ -789,7 +825,9 @@ int launch_predict(const float* theta, const SgQuant& q, const float* Eq, int64_
     hipStream_t st = (hipStream_t)stream;
     if (B == 0) return 0;
     const int64_t Bpad = (B + 63) / 64 * 64;
-    if (!train_layout && t_out == nullptr) {
+    // The fused kernel reads embedding rows with 16-byte loads.
+    const bool aligned = ((reinterpret_cast<uintptr_t>(Eq) | reinterpret_cast<uintptr_t>(Ec)) & 15u) == 0;
+    if (!train_layout && t_out == nullptr && aligned) {
         hipLaunchKernelGGL(rho_fused_kernel, dim3((unsigned)(Bpad / 64)), dim3(256), 0, st, Eq, nq, Ec, nc, qi, ci, B,
                            q, theta, pred);
         return (int)hipGetLastError();

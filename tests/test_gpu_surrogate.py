@@ -68,6 +68,28 @@ def test_predict_matches_twin_and_flags_bad_indices():
     qi[9] = -1
     got = binding.sg_predict(to_dev(th), to_dev(Eq), to_dev(Ec), to_dev(qi), to_dev(ci)).cpu().numpy()
     assert np.isnan(got[5]) and np.isnan(got[9]) and np.isfinite(np.delete(got, [5, 9])).all()
+
+
+def test_predict_unaligned_tables_take_the_general_path():
+    """Embedding tables that start off a 16-byte boundary (a view one float
+    in) go through the unfused head; same values as the aligned call."""
+    import torch
+    from paper_2401_07378_amd import binding
+    r = np.random.default_rng(31)
+    th = _theta(32)
+    Eq = W.to_f32(np.abs(r.normal(0, 0.5, (2, 256))))
+    Ec = W.to_f32(np.abs(r.normal(0, 0.5, (200, 256))))
+    qi = r.integers(0, 2, 150).astype(np.int32)
+    ci = r.integers(0, 200, 150).astype(np.int32)
+    flat = torch.zeros(1 + Ec.size, dtype=torch.float32, device="cuda")
+    flat[1:] = to_dev(Ec).reshape(-1)
+    Ec_off = flat[1:].view(200, 256)
+    assert Ec_off.data_ptr() % 16 != 0
+    a = binding.sg_predict(to_dev(th), to_dev(Eq), to_dev(Ec), to_dev(qi), to_dev(ci)).cpu().numpy()
+    b = binding.sg_predict(to_dev(th), to_dev(Eq), Ec_off, to_dev(qi), to_dev(ci)).cpu().numpy()
+    want = SO.head(th, Eq[qi], Ec[ci], rounding=True)
+    np.testing.assert_allclose(a, want, rtol=1e-3)
+    np.testing.assert_allclose(b, want, rtol=1e-3)
     torch.cuda.synchronize()
 
 
