@@ -27,6 +27,7 @@ struct nnsemd_handle {
     nnsemd::LPState* lp_host = nullptr;          // pinned copy of the round state
     char* doc_tiles = nullptr;                   // key-tile scratch of the high-dimensional path
     size_t doc_bytes = 0;
+    char* topk_ws = nullptr;                     // top-k threshold, count and candidate buffer
     double* doc_xnorm = nullptr;                 // supplier-set norms of the split document form
     size_t doc_xnorm_bytes = 0;
     // Autotuned launch configuration of the batched point path, by
@@ -436,6 +437,7 @@ nnsemd_status_t nnsemd_destroy(nnsemd_handle_t h) {
         if (h->order) (void)hipFree(h->order);
         if (h->lp_base) (void)hipFree(h->lp_base);
         if (h->lp_host) (void)hipHostFree(h->lp_host);
+        if (h->topk_ws) (void)hipFree(h->topk_ws);
         if (h->doc_xnorm) (void)hipFree(h->doc_xnorm);
         if (h->doc_tiles) (void)hipFree(h->doc_tiles);
         if (h->sg_quant) (void)hipFree(h->sg_quant);
@@ -981,6 +983,16 @@ nnsemd_status_t nnsemd_sg_train_step(nnsemd_handle_t h, float* theta, float* ada
     return NNSEMD_OK;
 }
 
+// Top-k scratch of the handle (allocated once).
+nnsemd_status_t topk_workspace(nnsemd_handle_t h) {
+    if (h->topk_ws) return NNSEMD_OK;
+    if (hipMalloc((void**)&h->topk_ws, sg::topk_ws_bytes()) != hipSuccess) {
+        h->topk_ws = nullptr;
+        return fail(h, NNSEMD_ERR_OUT_OF_MEMORY, "top-k scratch");
+    }
+    return NNSEMD_OK;
+}
+
 nnsemd_status_t nnsemd_topk_smallest_f32(nnsemd_handle_t h, const float* values, int64_t n, int32_t k, int32_t* idx,
                                          void* stream) {
     if (h == nullptr) return NNSEMD_ERR_INVALID_ARG;
@@ -988,7 +1000,9 @@ nnsemd_status_t nnsemd_topk_smallest_f32(nnsemd_handle_t h, const float* values,
     if (values == nullptr || idx == nullptr || k < 1 || k > kSgTopkMax || n < k || n > 0x7fffffffLL)
         return fail(h, NNSEMD_ERR_INVALID_ARG, "top-k needs 1 <= k <= min(n, 1024), n < 2^31");
     DeviceGuard g(h->device);
-    const int err = sg::launch_topk_f32(values, n, k, idx, stream);
+    nnsemd_status_t s = topk_workspace(h);
+    if (s != NNSEMD_OK) return s;
+    const int err = sg::launch_topk_f32(values, n, k, idx, h->topk_ws, stream);
     if (err != 0) return device_fail(h, err, "top-k");
     return NNSEMD_OK;
 }
@@ -1000,7 +1014,9 @@ nnsemd_status_t nnsemd_topk_smallest_f64(nnsemd_handle_t h, const double* values
     if (values == nullptr || idx == nullptr || k < 1 || k > kSgTopkMax || n < k || n > 0x7fffffffLL)
         return fail(h, NNSEMD_ERR_INVALID_ARG, "top-k needs 1 <= k <= min(n, 1024), n < 2^31");
     DeviceGuard g(h->device);
-    const int err = sg::launch_topk_f64(values, n, k, idx, stream);
+    nnsemd_status_t s = topk_workspace(h);
+    if (s != NNSEMD_OK) return s;
+    const int err = sg::launch_topk_f64(values, n, k, idx, h->topk_ws, stream);
     if (err != 0) return device_fail(h, err, "top-k");
     return NNSEMD_OK;
 }
@@ -1021,6 +1037,7 @@ nnsemd_status_t nnsemd_sg_retrieve(nnsemd_handle_t h, const float* theta, const 
     sg::SgQuant q;
     nnsemd_status_t s = sg_quantize(h, theta, q, stream);
     if (s != NNSEMD_OK) return s;
+    if ((s = topk_workspace(h)) != NNSEMD_OK) return s;
     Carver c;
     const size_t oEq = c.take(4 * kSgHidden), oqoff = c.take(2 * 8), opred = c.take(4 * (size_t)num_candidates);
     const size_t osel = c.take(4 * (size_t)keep), ozero = c.take(4 * (size_t)keep), oxoff = c.take(16);
@@ -1044,7 +1061,7 @@ nnsemd_status_t nnsemd_sg_retrieve(nnsemd_handle_t h, const float* theta, const 
     if (err == 0)
         err = sg::launch_predict(theta, q, Eq, 1, index_E, num_candidates, nullptr, nullptr, 0, num_candidates, pw,
                                  nullptr, pred, stream);
-    if (err == 0) err = sg::launch_topk_f32(pred, num_candidates, keep, sel, stream);
+    if (err == 0) err = sg::launch_topk_f32(pred, num_candidates, keep, sel, h->topk_ws, stream);
     if (err == 0) err = sg::launch_fill_i32(zeros, keep, 0, stream);
     if (err == 0) err = sg::launch_two_offsets(xoff, mq, stream);
     if (err != 0) return device_fail(h, err, "surrogate retrieval");
@@ -1065,7 +1082,7 @@ nnsemd_status_t nnsemd_sg_retrieve(nnsemd_handle_t h, const float* theta, const 
     A.stats = st;
     const nnsemd_options_t o = default_options();
     if ((s = run_pairs(h, A, 3, mq, max_n, o, stream)) != NNSEMD_OK) return s;
-    err = sg::launch_topk_f64(costs, keep, top, pos, stream);
+    err = sg::launch_topk_f64(costs, keep, top, pos, h->topk_ws, stream);
     if (err == 0) err = sg::launch_gather_ranked(pos, sel, costs, top, out_idx, out_cost, stream);
     if (err != 0) return device_fail(h, err, "re-rank selection");
     return NNSEMD_OK;

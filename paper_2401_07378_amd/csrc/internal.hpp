@@ -248,8 +248,10 @@ int launch_loss_grad(const float* theta, const SgQuant& q, const float* X, const
                      void* stream);
 int launch_adam(float* theta, float* m, float* v, const float* grad, float lr, double beta1, double beta2, float eps,
                 float bc1, float bc2, void* stream);
-int launch_topk_f32(const float* vals, int64_t n, int k, int32_t* out, void* stream);
-int launch_topk_f64(const double* vals, int64_t n, int k, int32_t* out, void* stream);
+// ws: topk_ws_bytes() of device scratch (nullable: single-workgroup scan only).
+size_t topk_ws_bytes();
+int launch_topk_f32(const float* vals, int64_t n, int k, int32_t* out, void* ws, void* stream);
+int launch_topk_f64(const double* vals, int64_t n, int k, int32_t* out, void* ws, void* stream);
 int launch_gather_ranked(const int32_t* pos, const int32_t* sel, const double* vals, int k, int32_t* out_idx,
                          double* out_val, void* stream);
 int launch_fill_i32(int32_t* p, int64_t n, int32_t v, void* stream);

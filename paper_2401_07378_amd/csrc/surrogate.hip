@@ -628,6 +628,8 @@ __device__ inline uint64_t ord_key(double f) {
 constexpr int kTopkThreads = 1024;
 
 constexpr int kTopkCap = 2 * kSgTopkMax;  // sort buffer
+constexpr int kTopkSample = 4096;         // sampled keys of the threshold pass
+constexpr int kTopkBuf = 16384;           // candidate buffer behind the threshold
 
 // The k smallest of n values, ascending by (value, index), in one workgroup.
 // 1. Radix select of the k-th key, 8-bit digits, coalesced passes; a
@@ -637,9 +639,18 @@ constexpr int kTopkCap = 2 * kSgTopkMax;  // sort buffer
 //    buffer (unordered); if the equal keys overflow the buffer they are
 //    collected again in index order instead, as many as needed.
 // 3. Bitonic sort of the buffer by (key, index); the first k are the answer.
-template <typename V, typename K>
+// When all n values fit the buffer, steps 1 and 2 are skipped.
+// BUF: the values were first narrowed to the candidates at or below a
+// sampled threshold (bkey / bidx, *count of them, original indices); those
+// are used when they hold at least k and fit, and the direct pass over all
+// values runs otherwise, or when the equal keys would need the index-order
+// collection (the buffer is in arrival order).  Either way the answer is the
+// exact (key, index) order of all n values.
+template <typename V, typename K, bool BUF>
 __global__ __launch_bounds__(kTopkThreads) void topk_kernel(const V* __restrict__ vals, int64_t n, int k,
-                                                            int32_t* __restrict__ out) {
+                                                            int32_t* __restrict__ out, const K* __restrict__ bkey,
+                                                            const int32_t* __restrict__ bidx,
+                                                            const unsigned int* __restrict__ count) {
     constexpr int T = kTopkThreads;
     constexpr int NB = (int)sizeof(K) * 8;
     __shared__ unsigned int hist[256];
@@ -651,13 +662,34 @@ __global__ __launch_bounds__(kTopkThreads) void topk_kernel(const V* __restrict_
     __shared__ int cnt_less, cnt_eq;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
+    bool use_buf = false;
+    int64_t nn = n;
+    if constexpr (BUF) {
+        const unsigned int c = *count;
+        use_buf = c >= (unsigned int)k && c <= (unsigned int)kTopkBuf;
+        if (use_buf) nn = c;
+    }
+    auto key_at = [&](int64_t i) -> K { return use_buf ? bkey[i] : ord_key(vals[i]); };
+    auto idx_at = [&](int64_t i) -> int32_t { return use_buf ? bidx[i] : (int32_t)i; };
+    int64_t filled = 0;
+    for (int attempt = 0; attempt < 2; ++attempt) {  // the second only when the buffer cannot serve
     K prefix = 0, mask = 0;
     int64_t need = k;
+    filled = 0;
+    bool redo = false;
+    if (nn <= kTopkCap) {
+        // Everything fits the sort buffer: no selection needed.
+        for (int64_t i = tid; i < nn; i += T) {
+            skey[i] = key_at(i);
+            sidx[i] = idx_at(i);
+        }
+        filled = nn;
+    } else {
     for (int shift = NB - 8; shift >= 0; shift -= 8) {
         for (int b = tid; b < 256; b += T) hist[b] = 0u;
         __syncthreads();
-        for (int64_t i = tid; i < n; i += T) {
-            const K key = ord_key(vals[i]);
+        for (int64_t i = tid; i < nn; i += T) {
+            const K key = key_at(i);
             const int bin = (key & mask) == prefix ? (int)((key >> shift) & 0xff) : -1;
             const uint64_t active = __ballot(1);
             const int b0 = __builtin_amdgcn_readfirstlane(bin);
@@ -690,28 +722,30 @@ __global__ __launch_bounds__(kTopkThreads) void topk_kernel(const V* __restrict_
     }
     // prefix = key of the k-th smallest; need = how many of that key to take.
     const int64_t nless = k - need;
-    for (int64_t i = tid; i < n; i += T) {
-        const K key = ord_key(vals[i]);
+    for (int64_t i = tid; i < nn; i += T) {
+        const K key = key_at(i);
         if (key < prefix) {
             const int p = atomicAdd(&cnt_less, 1);
             skey[p] = key;
-            sidx[p] = (int32_t)i;
+            sidx[p] = idx_at(i);
         } else if (key == prefix) {
             const int64_t q = nless + atomicAdd(&cnt_eq, 1);
             if (q < kTopkCap) {
                 skey[q] = key;
-                sidx[q] = (int32_t)i;
+                sidx[q] = idx_at(i);
             }
         }
     }
     __syncthreads();
-    int64_t filled = nless + cnt_eq;
-    if (filled > kTopkCap) {
+    filled = nless + cnt_eq;
+    if (filled > kTopkCap && use_buf) {
+        redo = true;  // index order is not the buffer's order: take all values
+    } else if (filled > kTopkCap) {
         // Too many equal keys: take the first `need` of them in index order.
-        const int64_t per = (n + T - 1) / T;
-        const int64_t lo = min<int64_t>(n, tid * per), hi = min<int64_t>(n, lo + per);
+        const int64_t per = (nn + T - 1) / T;
+        const int64_t lo = min<int64_t>(nn, tid * per), hi = min<int64_t>(nn, lo + per);
         int64_t ce = 0;
-        for (int64_t i = lo; i < hi; ++i) ce += ord_key(vals[i]) == prefix;
+        for (int64_t i = lo; i < hi; ++i) ce += key_at(i) == prefix;
         scan[tid] = ce;
         __syncthreads();
         if (tid == 0) {
@@ -725,13 +759,19 @@ __global__ __launch_bounds__(kTopkThreads) void topk_kernel(const V* __restrict_
         __syncthreads();
         int64_t we = scan[tid];
         for (int64_t i = lo; i < hi && we < need; ++i) {
-            if (ord_key(vals[i]) == prefix) {
+            if (key_at(i) == prefix) {
                 skey[nless + we] = prefix;
-                sidx[nless + we] = (int32_t)i;
+                sidx[nless + we] = idx_at(i);
                 ++we;
             }
         }
         filled = k;
+    }
+    }  // nn > kTopkCap
+    if (!redo) break;
+    use_buf = false;  // workgroup-uniform
+    nn = n;
+    __syncthreads();
     }
     for (int64_t e = filled + tid; e < kTopkCap; e += T) {
         skey[e] = ~(K)0;
@@ -759,6 +799,78 @@ __global__ __launch_bounds__(kTopkThreads) void topk_kernel(const V* __restrict_
         }
     }
     for (int e = tid; e < k; e += T) out[e] = sidx[e];
+}
+
+// Threshold for the candidate pass: kTopkSample evenly spaced keys, sorted;
+// the key 1.5 k / n of the way up plus 16 ranks (about four standard
+// deviations of the sample quantile above rank k at 10^5 values), so that at
+// least k values lie at or below it unless the sample misleads -- then the
+// selection falls back to all values.  Also clears the candidate count.
+template <typename V, typename K>
+__global__ __launch_bounds__(kTopkThreads) void topk_sample_kernel(const V* __restrict__ vals, int64_t n, int k,
+                                                                   K* __restrict__ thr, unsigned int* __restrict__ count) {
+    constexpr int T = kTopkThreads, S = kTopkSample;
+    __shared__ K sk[S];
+    const int tid = threadIdx.x;
+    for (int j = tid; j < S; j += T) sk[j] = ord_key(vals[(int64_t)j * n / S]);
+    __syncthreads();
+    for (int size = 2; size <= S; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int e = tid; e < S; e += T) {
+                const int o = e ^ stride;
+                if (o > e) {
+                    const bool up = (e & size) == 0;
+                    if ((sk[e] > sk[o]) == up) {
+                        const K t = sk[e];
+                        sk[e] = sk[o];
+                        sk[o] = t;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (tid == 0) {
+        const double frac = 1.5 * (double)k / (double)n;
+        int r = (int)(frac * S) + 16;
+        if (r > S - 1) r = S - 1;
+        *thr = sk[r];
+        *count = 0u;
+    }
+}
+
+// Every value whose key is at or below the threshold, appended (key,
+// index) in arrival order; the count keeps rising past the buffer so the
+// selection can tell an overflow.
+template <typename V, typename K>
+__global__ __launch_bounds__(256) void topk_collect_kernel(const V* __restrict__ vals, int64_t n,
+                                                           const K* __restrict__ thr, unsigned int* __restrict__ count,
+                                                           K* __restrict__ bkey, int32_t* __restrict__ bidx) {
+    const K t = *thr;
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < n; i0 += stride) {  // uniform per wavefront
+        const int64_t i = i0 + threadIdx.x;
+        K key = 0;
+        bool take = false;
+        if (i < n) {
+            key = ord_key(vals[i]);
+            take = key <= t;
+        }
+        const unsigned long long m = __ballot(take);
+        if (m == 0ull) continue;
+        const int leader = __builtin_ctzll(m);
+        unsigned int base = 0u;
+        if (lane == leader) base = atomicAdd(count, (unsigned int)__popcll(m));
+        base = __shfl(base, leader);
+        if (take) {
+            const unsigned int pos = base + (unsigned int)__popcll(m & ((1ull << lane) - 1ull));
+            if (pos < (unsigned int)kTopkBuf) {
+                bkey[pos] = key;
+                bidx[pos] = (int32_t)i;
+            }
+        }
+    }
 }
 
 // out_idx[r] = sel[pos[r]], out_val[r] = vals[pos[r]].
@@ -910,16 +1022,37 @@ int launch_adam(float* theta, float* m, float* v, const float* grad, float lr, d
     return (int)hipGetLastError();
 }
 
-int launch_topk_f32(const float* vals, int64_t n, int k, int32_t* out, void* stream) {
-    hipLaunchKernelGGL((topk_kernel<float, uint32_t>), dim3(1), dim3(kTopkThreads), 0, (hipStream_t)stream, vals, n, k,
-                       out);
+size_t topk_ws_bytes() { return 256 + (size_t)kTopkBuf * (sizeof(uint64_t) + sizeof(int32_t)); }
+
+template <typename V, typename K>
+int launch_topk(const V* vals, int64_t n, int k, int32_t* out, void* ws, void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    // Large inputs: sampled threshold and a grid-wide candidate pass first.
+    if (ws != nullptr && n > 2 * (int64_t)kTopkBuf) {
+        char* b = static_cast<char*>(ws);
+        K* thr = reinterpret_cast<K*>(b);
+        unsigned int* count = reinterpret_cast<unsigned int*>(b + 64);
+        K* bkey = reinterpret_cast<K*>(b + 256);
+        int32_t* bidx = reinterpret_cast<int32_t*>(b + 256 + (size_t)kTopkBuf * sizeof(K));
+        hipLaunchKernelGGL((topk_sample_kernel<V, K>), dim3(1), dim3(kTopkThreads), 0, st, vals, n, k, thr, count);
+        const int64_t blocks = std::min<int64_t>((n + 255) / 256, 2048);
+        hipLaunchKernelGGL((topk_collect_kernel<V, K>), dim3((unsigned)blocks), dim3(256), 0, st, vals, n, thr, count,
+                           bkey, bidx);
+        hipLaunchKernelGGL((topk_kernel<V, K, true>), dim3(1), dim3(kTopkThreads), 0, st, vals, n, k, out, bkey, bidx,
+                           count);
+        return (int)hipGetLastError();
+    }
+    hipLaunchKernelGGL((topk_kernel<V, K, false>), dim3(1), dim3(kTopkThreads), 0, st, vals, n, k, out, nullptr,
+                       nullptr, nullptr);
     return (int)hipGetLastError();
 }
 
-int launch_topk_f64(const double* vals, int64_t n, int k, int32_t* out, void* stream) {
-    hipLaunchKernelGGL((topk_kernel<double, uint64_t>), dim3(1), dim3(kTopkThreads), 0, (hipStream_t)stream, vals, n, k,
-                       out);
-    return (int)hipGetLastError();
+int launch_topk_f32(const float* vals, int64_t n, int k, int32_t* out, void* ws, void* stream) {
+    return launch_topk<float, uint32_t>(vals, n, k, out, ws, stream);
+}
+
+int launch_topk_f64(const double* vals, int64_t n, int k, int32_t* out, void* ws, void* stream) {
+    return launch_topk<double, uint64_t>(vals, n, k, out, ws, stream);
 }
 
 int launch_gather_ranked(const int32_t* pos, const int32_t* sel, const double* vals, int k, int32_t* out_idx,

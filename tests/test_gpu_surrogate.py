@@ -157,6 +157,34 @@ def test_topk_matches_brute_force(n, k, dtype):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("case", ["continuous", "sampled_positions_small", "all_equal", "narrow"])
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_topk_large_inputs_threshold_pass(case, dtype):
+    """Above 32768 values a sampled threshold narrows the input first; the
+    answer must still be the exact (value, index) order: continuous values,
+    the smallest values placed exactly at the sampled positions, every value
+    equal (the candidates overflow and the direct pass runs), and a narrow
+    band with heavy ties at the threshold."""
+    import torch
+    from paper_2401_07378_amd import binding
+    r = np.random.default_rng(77)
+    n, k = 200003, 1000
+    v = r.random(n)
+    if case == "sampled_positions_small":
+        pos = (np.arange(4096, dtype=np.int64) * n) // 4096
+        v[pos] = -1.0 - r.random(4096)
+    elif case == "all_equal":
+        v[:] = 0.25
+    elif case == "narrow":
+        v = np.round(r.random(n) * 300) / 300
+    v[r.choice(n, 5, replace=False)] = np.nan
+    v[r.choice(n, 3, replace=False)] = -0.0
+    v = v.astype(np.float32) if dtype == "f32" else v
+    got = binding.topk_smallest(to_dev(v), k).cpu().numpy()
+    np.testing.assert_array_equal(got, SO.topk_smallest(v, k))
+    torch.cuda.synchronize()
+
+
 def _train(num_pairs, epochs, seed=11):
     import torch
     X, a, off = W.surrogate_training_pairs(num_pairs, seed=3100 + seed)
