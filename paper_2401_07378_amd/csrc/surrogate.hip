@@ -631,6 +631,73 @@ constexpr int kTopkCap = 2 * kSgTopkMax;  // sort buffer
 constexpr int kTopkSample = 4096;         // sampled keys of the threshold pass
 constexpr int kTopkBuf = 16384;           // candidate buffer behind the threshold
 
+// Ascending bitonic sort of T * E (key, index) pairs held in registers:
+// element e = s * T + threadIdx.x sits in slot s.  Partners at strides of T
+// and above are in the same thread (register swap), below 64 in the same
+// wavefront (shuffles); only strides 64 .. T/2 go through LDS (xk, xi: T * E
+// entries each), with barriers.  Order: key, then index (WITH_IDX), so the
+// result is unique; without indices equal keys are interchangeable.
+template <typename K, int T, int E, bool WITH_IDX>
+__device__ inline void bitonic_regs(K (&k)[E], int32_t (&ix)[E], K* xk, int32_t* xi) {
+    const int tid = threadIdx.x;
+    constexpr int N = T * E;
+    auto greater = [](K a, int32_t ia, K b, int32_t ib) { return a > b || (WITH_IDX && a == b && ia > ib); };
+    for (int size = 2; size <= N; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            if (stride >= T) {
+                const int ds = stride / T;
+#pragma unroll
+                for (int s = 0; s < E; ++s) {
+                    if (s & ds) continue;
+                    const int ps = s | ds;
+                    const bool up = ((s * T + tid) & size) == 0;
+                    if (greater(k[s], ix[s], k[ps], ix[ps]) == up) {
+                        const K tk = k[s];
+                        k[s] = k[ps];
+                        k[ps] = tk;
+                        const int32_t ti = ix[s];
+                        ix[s] = ix[ps];
+                        ix[ps] = ti;
+                    }
+                }
+                continue;
+            }
+            K pk[E];
+            int32_t pi[E];
+            if (stride >= 64) {
+                __syncthreads();  // earlier readers of xk / xi are done
+#pragma unroll
+                for (int s = 0; s < E; ++s) {
+                    xk[s * T + tid] = k[s];
+                    if (WITH_IDX) xi[s * T + tid] = ix[s];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int s = 0; s < E; ++s) {
+                    pk[s] = xk[(s * T + tid) ^ stride];
+                    pi[s] = WITH_IDX ? xi[(s * T + tid) ^ stride] : 0;
+                }
+            } else {
+#pragma unroll
+                for (int s = 0; s < E; ++s) {
+                    pk[s] = __shfl_xor(k[s], stride);
+                    pi[s] = WITH_IDX ? __shfl_xor(ix[s], stride) : 0;
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < E; ++s) {
+                const int e = s * T + tid;
+                const bool keep_min = ((e & stride) == 0) == ((e & size) == 0);
+                const bool take = keep_min ? greater(k[s], ix[s], pk[s], pi[s]) : greater(pk[s], pi[s], k[s], ix[s]);
+                if (take) {
+                    k[s] = pk[s];
+                    ix[s] = pi[s];
+                }
+            }
+        }
+    }
+}
+
 // The k smallest of n values, ascending by (value, index), in one workgroup.
 // 1. Radix select of the k-th key, 8-bit digits, coalesced passes; a
 //    wavefront whose active lanes share one digit adds them with one atomic
@@ -778,27 +845,18 @@ __global__ __launch_bounds__(kTopkThreads) void topk_kernel(const V* __restrict_
         sidx[e] = 0x7fffffff;
     }
     __syncthreads();
-    for (int size = 2; size <= kTopkCap; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int e = tid; e < kTopkCap; e += T) {
-                const int o = e ^ stride;
-                if (o > e) {
-                    const bool up = (e & size) == 0;
-                    const bool gt = skey[e] > skey[o] || (skey[e] == skey[o] && sidx[e] > sidx[o]);
-                    if (gt == up) {
-                        const K tk = skey[e];
-                        skey[e] = skey[o];
-                        skey[o] = tk;
-                        const int32_t ti = sidx[e];
-                        sidx[e] = sidx[o];
-                        sidx[o] = ti;
-                    }
-                }
-            }
-            __syncthreads();
-        }
+    constexpr int E = kTopkCap / T;
+    K rk[E];
+    int32_t ri[E];
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        rk[s] = skey[s * T + tid];
+        ri[s] = sidx[s * T + tid];
     }
-    for (int e = tid; e < k; e += T) out[e] = sidx[e];
+    bitonic_regs<K, T, E, true>(rk, ri, skey, sidx);
+#pragma unroll
+    for (int s = 0; s < E; ++s)
+        if (s * T + tid < k) out[s * T + tid] = ri[s];
 }
 
 // Threshold for the candidate pass: kTopkSample evenly spaced keys, sorted;
@@ -812,24 +870,19 @@ __global__ __launch_bounds__(kTopkThreads) void topk_sample_kernel(const V* __re
     constexpr int T = kTopkThreads, S = kTopkSample;
     __shared__ K sk[S];
     const int tid = threadIdx.x;
-    for (int j = tid; j < S; j += T) sk[j] = ord_key(vals[(int64_t)j * n / S]);
-    __syncthreads();
-    for (int size = 2; size <= S; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int e = tid; e < S; e += T) {
-                const int o = e ^ stride;
-                if (o > e) {
-                    const bool up = (e & size) == 0;
-                    if ((sk[e] > sk[o]) == up) {
-                        const K t = sk[e];
-                        sk[e] = sk[o];
-                        sk[o] = t;
-                    }
-                }
-            }
-            __syncthreads();
-        }
+    constexpr int E = S / T;
+    K rk[E];
+    int32_t ri[E];
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        rk[s] = ord_key(vals[(int64_t)(s * T + tid) * n / S]);
+        ri[s] = 0;
     }
+    bitonic_regs<K, T, E, false>(rk, ri, sk, nullptr);
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < E; ++s) sk[s * T + tid] = rk[s];
+    __syncthreads();
     if (tid == 0) {
         const double frac = 1.5 * (double)k / (double)n;
         int r = (int)(frac * S) + 16;
