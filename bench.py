@@ -84,7 +84,7 @@ def main():
     ap.add_argument("--graph", action="store_true", help="replay a captured graph of one step")
     ap.add_argument("--schedule", default="longest_first", choices=["longest_first", "as_given"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true", help="batched_hist_3d: skip the launch autotuner")
+    ap.add_argument("--no-autotune", action="store_true", help="batched_hist_3d, retrieval_3d: skip the launch autotuner")
     ap.add_argument("--no-single-pair", action="store_true")
     ap.add_argument("--single-pair-sample", type=int, default=512)
     ap.add_argument("--workload", default="batched_hist_3d",
@@ -522,6 +522,10 @@ def bench_retrieval(args, dev):
               "stats": torch.empty(N * 48, dtype=torch.uint8, device=dev)}
     pr_out = {}
     truth, got = [], []
+    tuning = None
+    if not args.no_autotune and args.threads == 0:
+        tuning = binding.autotune(3, "l2", 256, 256, num_pairs=1024)  # the re-rank's and the scan's pair size
+        log(f"autotuned: {tuning}")
     for q in range(min(2, Q)):  # warm-up
         SG.retrieve(tr.theta, E, queries[q], aq, Y, b, yo, 256, out=pr_out)
         binding.emd_approx_batched(queries[q], aq, xo, Y, b, yo, pair_x=zeros, pair_y=cand, max_m=256, max_n=256,
@@ -582,7 +586,9 @@ def bench_retrieval(args, dev):
                                    "uniform masses, L2; surrogate keeps 1000, NNS-EMD re-ranks, top 10",
                        "train_pairs": args.train_pairs, "epochs": args.epochs, "loss_first": hist[0],
                        "loss_last": hist[-1], "train_s": t_train, "labels_s": t_labels, "index_ms": ms_index,
-                       "queries": Q, "recall_at_10": recall},
+                       "queries": Q, "recall_at_10": recall,
+                       "pair_launch": ({"threads": tuning["threads"], "search_split": tuning["split"], "autotuned": True}
+                                       if tuning else {"autotuned": False})},
             "exhaustive_nnsemd": {"value": N / (ms_exh / 1e3), "unit": "pairs/s", "ms_per_query": ms_exh,
                                   "speedup_pruned": ms_exh / ms_pruned},
             "roofline": roofline, "cpu_baseline": cpu}

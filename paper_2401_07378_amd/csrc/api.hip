@@ -137,6 +137,17 @@ nnsemd_status_t run_pairs(nnsemd_handle_t h, PairSolverArgs& A, int d, int64_t m
     int err = pair_solver_blocks_per_cu(d, A.metric, threads, chunk, lay.total, &blocks);
     if (err != 0) return device_fail(h, err, "occupancy query");
     if (blocks < 1) return fail(h, NNSEMD_ERR_UNSUPPORTED, "pair workgroup does not fit on a compute unit");
+    // Coordinates in LDS (no HBM reads inside the rounds) whenever that costs
+    // no resident workgroup.
+    const PairLdsLayout lay_c = pair_lds_layout(mcap, ncap, record_stride(d), d);
+    bool coords = false;
+    if (lay_c.total + 8192 <= h->max_lds) {
+        int bc = 0;
+        if ((err = pair_solver_blocks_per_cu(d, A.metric, threads, chunk, lay_c.total, &bc, true)) != 0)
+            return device_fail(h, err, "occupancy query");
+        coords = bc >= blocks;
+    }
+    const size_t lds_bytes = coords ? lay_c.total : lay.total;
     const int64_t grid = A.num_pairs;
     if (A.x_off != nullptr && A.num_pairs > 1 && o.schedule == NNSEMD_SCHEDULE_LONGEST_FIRST) {
         nnsemd_status_t s = schedule(h, A.x_off, A.y_off, A.pair_x, A.pair_y, A.num_pairs, A.num_x_sets,
@@ -144,7 +155,7 @@ nnsemd_status_t run_pairs(nnsemd_handle_t h, PairSolverArgs& A, int d, int64_t m
         if (s != NNSEMD_OK) return s;
         A.order = h->order;
     }
-    err = launch_pair_solver(A, d, threads, chunk, lay.total, (int)grid, stream);
+    err = launch_pair_solver(A, d, threads, chunk, coords, lds_bytes, (int)grid, stream);
     if (err != 0) return device_fail(h, err, "solver launch");
     return NNSEMD_OK;
 }

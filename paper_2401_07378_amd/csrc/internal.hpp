@@ -52,12 +52,14 @@ struct PairSolverArgs {
 
 // Byte layout of the dynamic LDS of one workgroup (one pair at a time).
 struct PairLdsLayout {
-    size_t smass, cmass, ckey, srec, sidx, scnt, soff, cact, cnn, list, sorted, total;
+    size_t smass, cmass, ckey, srec, sidx, scnt, soff, cact, cnn, list, sorted, xl, yl, total;
 };
 
 __host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-__host__ __device__ inline PairLdsLayout pair_lds_layout(int M, int N, int rs) {
+// cd > 0: also the pair's coordinates, cd floats per point (suppliers then
+// consumers, by local index), so the rounds never read them from HBM.
+__host__ __device__ inline PairLdsLayout pair_lds_layout(int M, int N, int rs, int cd = 0) {
     PairLdsLayout L;
     size_t o = 0;
     L.smass = o; o += sizeof(double) * (size_t)M;
@@ -72,6 +74,9 @@ __host__ __device__ inline PairLdsLayout pair_lds_layout(int M, int N, int rs) {
     L.cnn = o;   o += sizeof(int32_t) * (size_t)N;
     L.list = o;  o += sizeof(int32_t) * (size_t)N;
     L.sorted = o; o += sizeof(int32_t) * (size_t)N;
+    o = align_up(o, 16);
+    L.xl = o;    o += sizeof(float) * (size_t)cd * (size_t)M;
+    L.yl = o;    o += sizeof(float) * (size_t)cd * (size_t)N;
     L.total = align_up(o, 16);
     return L;
 }
@@ -260,11 +265,12 @@ int launch_two_offsets(int64_t* off, int64_t m, void* stream);
 
 // Launch entry points (defined in pair_solver.hip).
 // Returns hipSuccess-compatible int (0 on success).
-int launch_pair_solver(const PairSolverArgs& args, int d, int threads, int chunk_max,
+int launch_pair_solver(const PairSolverArgs& args, int d, int threads, int chunk_max, bool coords,
                        size_t lds_bytes, int grid, void* stream);
 int launch_order(const int64_t* x_off, const int64_t* y_off, const int32_t* pair_x, const int32_t* pair_y,
                  int64_t num_pairs, int64_t num_x_sets, int64_t num_y_sets, int32_t* order, void* stream);
-int pair_solver_blocks_per_cu(int d, int metric, int threads, int chunk_max, size_t lds_bytes,
-                              int* blocks);
+// coords: the variant that keeps the pair's coordinates in LDS.
+int pair_solver_blocks_per_cu(int d, int metric, int threads, int chunk_max, size_t lds_bytes, int* blocks,
+                              bool coords = false);
 
 }  // namespace nnsemd

@@ -179,7 +179,9 @@ __device__ inline void nns_pass(const Lds& L, Shared& sh, const float* __restric
     }
 }
 
-template <int D, int T, int CSMAX, bool L1>
+// CL: the pair's coordinates are copied into LDS at ingest (L.xl, L.yl) and
+// every later read takes them from there; otherwise from HBM.
+template <int D, int T, int CSMAX, bool L1, bool CL>
 __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds& L, Shared& sh) {
     constexpr int RS = record_stride(D);
     constexpr int NW = T / kWave;
@@ -222,9 +224,12 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds& L, Sha
             m = n = 0;
         }
     }
-    const float* __restrict__ X = A.X + x0 * D;
-    const float* __restrict__ Y = A.Y + y0 * D;
+    const float* __restrict__ Xg = A.X + x0 * D;
+    const float* __restrict__ Yg = A.Y + y0 * D;
     const int mi = (int)m, ni = (int)n;
+    // coordinates for the rounds (LDS copies in the CL variant, filled below)
+    const float* __restrict__ X = CL ? L.xl : Xg;
+    const float* __restrict__ Y = CL ? L.yl : Yg;
 
     // ------------------------------------- ingest: masses, checks, bounding box
     double red[3 + 2 * D];
@@ -244,7 +249,8 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds& L, Sha
         red[0] += (double)av;
 #pragma unroll
         for (int t = 0; t < D; ++t) {
-            float xv = X[(size_t)i * D + t];
+            float xv = Xg[(size_t)i * D + t];
+            if constexpr (CL) L.xl[(size_t)i * D + t] = xv;
             if (!isfinite(xv)) red[2] = 1.0;
             red[3 + t] = fmin(red[3 + t], (double)xv);
             red[3 + D + t] = fmax(red[3 + D + t], (double)xv);
@@ -256,8 +262,11 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds& L, Sha
         L.cmass[j] = (double)bv;
         red[1] += (double)bv;
 #pragma unroll
-        for (int t = 0; t < D; ++t)
-            if (!isfinite(Y[(size_t)j * D + t])) red[2] = 1.0;
+        for (int t = 0; t < D; ++t) {
+            const float yv = Yg[(size_t)j * D + t];
+            if constexpr (CL) L.yl[(size_t)j * D + t] = yv;
+            if (!isfinite(yv)) red[2] = 1.0;
+        }
     }
     block_reduce<T, 3 + 2 * D>(red, rop, sh);
     if (status == NNSEMD_OK && red[2] != 0.0) status = NNSEMD_ERR_INVALID_ARG;
@@ -452,13 +461,13 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds& L, Sha
 // used here: its back-edge merges with the thread-0-only result write, and
 // the structurized code lets lanes 1-63 of wave 0 pass the following
 // barrier without the fetch, re-solving the same pair forever.)
-template <int D, int T, int CSMAX, bool L1>
+template <int D, int T, int CSMAX, bool L1, bool CL>
 __global__ __launch_bounds__(T) void pair_solver_kernel(PairSolverArgs A) {
     extern __shared__ __align__(16) char lds_dyn[];
     __shared__ Shared sh;
-    const Lds L = carve(lds_dyn, A.max_m, A.max_n, record_stride(D));
+    const Lds L = carve(lds_dyn, A.max_m, A.max_n, record_stride(D), CL ? D : 0);
     const int64_t p = A.order != nullptr ? (int64_t)A.order[blockIdx.x] : (int64_t)blockIdx.x;
-    solve_pair<D, T, CSMAX, L1>(A, p, L, sh);
+    solve_pair<D, T, CSMAX, L1, CL>(A, p, L, sh);
 }
 
 // Longest-first schedule: order[] lists the pairs by decreasing m * n (in
@@ -506,39 +515,41 @@ __global__ __launch_bounds__(1024) void order_kernel(const int64_t* __restrict__
     }
 }
 
-template <int D, int T, int CSMAX, bool L1>
+template <int D, int T, int CSMAX, bool L1, bool CL>
 int launch_typed(const PairSolverArgs& A, size_t lds, int grid, hipStream_t st) {
     if (lds > 48 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void*)pair_solver_kernel<D, T, CSMAX, L1>,
+        hipError_t e = hipFuncSetAttribute((const void*)pair_solver_kernel<D, T, CSMAX, L1, CL>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return (int)e;
     }
-    hipLaunchKernelGGL((pair_solver_kernel<D, T, CSMAX, L1>), dim3(grid), dim3(T), lds, st, A);
+    hipLaunchKernelGGL((pair_solver_kernel<D, T, CSMAX, L1, CL>), dim3(grid), dim3(T), lds, st, A);
     return (int)hipGetLastError();
 }
 
-template <int D, int T, int CSMAX, bool L1>
+template <int D, int T, int CSMAX, bool L1, bool CL>
 int occupancy_typed(size_t lds, int* blocks) {
     if (lds > 48 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void*)pair_solver_kernel<D, T, CSMAX, L1>,
+        hipError_t e = hipFuncSetAttribute((const void*)pair_solver_kernel<D, T, CSMAX, L1, CL>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return (int)e;
     }
-    return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, pair_solver_kernel<D, T, CSMAX, L1>, T, lds);
+    return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, pair_solver_kernel<D, T, CSMAX, L1, CL>, T,
+                                                             lds);
 }
 
-// Dispatch over (D, metric class, chunk class) for one workgroup size.
-template <int T, int CSMAX>
+// Dispatch over (D, metric class) for one workgroup size, chunk class and
+// coordinate placement.
+template <int T, int CSMAX, bool CL>
 int dispatch(bool run, const PairSolverArgs& A, int d, size_t lds, int grid, hipStream_t st,
              int* blocks) {
     const bool l1 = A.metric == NNSEMD_L1;
 #define NNSEMD_CASE(DD)                                                                      \
     case DD:                                                                                 \
         if (run)                                                                             \
-            return l1 ? launch_typed<DD, T, CSMAX, true>(A, lds, grid, st)                   \
-                      : launch_typed<DD, T, CSMAX, false>(A, lds, grid, st);                 \
-        return l1 ? occupancy_typed<DD, T, CSMAX, true>(lds, blocks)                         \
-                  : occupancy_typed<DD, T, CSMAX, false>(lds, blocks);
+            return l1 ? launch_typed<DD, T, CSMAX, true, CL>(A, lds, grid, st)               \
+                      : launch_typed<DD, T, CSMAX, false, CL>(A, lds, grid, st);             \
+        return l1 ? occupancy_typed<DD, T, CSMAX, true, CL>(lds, blocks)                     \
+                  : occupancy_typed<DD, T, CSMAX, false, CL>(lds, blocks);
     switch (d) {
         NNSEMD_CASE(1)
         NNSEMD_CASE(2)
@@ -553,25 +564,32 @@ int dispatch(bool run, const PairSolverArgs& A, int d, size_t lds, int grid, hip
 #undef NNSEMD_CASE
 }
 
-int dispatch_all(bool run, const PairSolverArgs& A, int d, int threads, int chunk_max, size_t lds,
-                 int grid, hipStream_t st, int* blocks) {
+template <bool CL>
+int dispatch_cl(bool run, const PairSolverArgs& A, int d, int threads, int chunk_max, size_t lds, int grid,
+                hipStream_t st, int* blocks) {
     if (threads == 256) {
-        if (chunk_max <= 4) return dispatch<256, 4>(run, A, d, lds, grid, st, blocks);
-        if (chunk_max <= 16) return dispatch<256, 16>(run, A, d, lds, grid, st, blocks);
+        if (chunk_max <= 4) return dispatch<256, 4, CL>(run, A, d, lds, grid, st, blocks);
+        if (chunk_max <= 16) return dispatch<256, 16, CL>(run, A, d, lds, grid, st, blocks);
     } else if (threads == 512) {
-        if (chunk_max <= 2) return dispatch<512, 2>(run, A, d, lds, grid, st, blocks);
-        if (chunk_max <= 8) return dispatch<512, 8>(run, A, d, lds, grid, st, blocks);
+        if (chunk_max <= 2) return dispatch<512, 2, CL>(run, A, d, lds, grid, st, blocks);
+        if (chunk_max <= 8) return dispatch<512, 8, CL>(run, A, d, lds, grid, st, blocks);
     }
     return (int)hipErrorInvalidValue;
+}
+
+int dispatch_all(bool run, const PairSolverArgs& A, int d, int threads, int chunk_max, size_t lds,
+                 int grid, hipStream_t st, int* blocks, bool coords) {
+    return coords ? dispatch_cl<true>(run, A, d, threads, chunk_max, lds, grid, st, blocks)
+                  : dispatch_cl<false>(run, A, d, threads, chunk_max, lds, grid, st, blocks);
 }
 
 #endif  // NNSEMD_CPU_EMULATION
 }  // namespace
 
 #ifndef NNSEMD_CPU_EMULATION
-int launch_pair_solver(const PairSolverArgs& args, int d, int threads, int chunk_max, size_t lds_bytes,
+int launch_pair_solver(const PairSolverArgs& args, int d, int threads, int chunk_max, bool coords, size_t lds_bytes,
                        int grid, void* stream) {
-    return dispatch_all(true, args, d, threads, chunk_max, lds_bytes, grid, (hipStream_t)stream, nullptr);
+    return dispatch_all(true, args, d, threads, chunk_max, lds_bytes, grid, (hipStream_t)stream, nullptr, coords);
 }
 
 int launch_order(const int64_t* x_off, const int64_t* y_off, const int32_t* pair_x, const int32_t* pair_y,
@@ -581,10 +599,11 @@ int launch_order(const int64_t* x_off, const int64_t* y_off, const int32_t* pair
     return (int)hipGetLastError();
 }
 
-int pair_solver_blocks_per_cu(int d, int metric, int threads, int chunk_max, size_t lds_bytes, int* blocks) {
+int pair_solver_blocks_per_cu(int d, int metric, int threads, int chunk_max, size_t lds_bytes, int* blocks,
+                              bool coords) {
     PairSolverArgs A{};
     A.metric = metric;
-    return dispatch_all(false, A, d, threads, chunk_max, lds_bytes, 0, nullptr, blocks);
+    return dispatch_all(false, A, d, threads, chunk_max, lds_bytes, 0, nullptr, blocks, coords);
 }
 
 #endif  // NNSEMD_CPU_EMULATION

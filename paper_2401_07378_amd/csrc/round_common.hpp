@@ -48,6 +48,8 @@ struct Lds {
     int32_t* cnn;   // [N] pick (active slot) by consumer; after the serve: supplier local index
     int32_t* list;    // [N] near-tie consumers during the search; claimant buckets after
     int32_t* sorted;  // [N] claimant buckets in serve order
+    float* xl;        // [M * cd] supplier coordinates by local index (coordinate variant only)
+    float* yl;        // [N * cd] consumer coordinates by local index (coordinate variant only)
 };
 
 constexpr int kMaxWaves = 8;    // workgroups of up to 512 threads
@@ -60,8 +62,8 @@ struct Shared {
     int32_t namb;   // claimants whose serve order needs exact keys (high-dimensional path)
 };
 
-__device__ inline Lds carve(char* base, int M, int N, int rs) {
-    PairLdsLayout L = pair_lds_layout(M, N, rs);
+__device__ inline Lds carve(char* base, int M, int N, int rs, int cd = 0) {
+    PairLdsLayout L = pair_lds_layout(M, N, rs, cd);
     Lds s;
     s.smass = reinterpret_cast<double*>(base + L.smass);
     s.cmass = reinterpret_cast<double*>(base + L.cmass);
@@ -74,6 +76,8 @@ __device__ inline Lds carve(char* base, int M, int N, int rs) {
     s.cnn = reinterpret_cast<int32_t*>(base + L.cnn);
     s.list = reinterpret_cast<int32_t*>(base + L.list);
     s.sorted = reinterpret_cast<int32_t*>(base + L.sorted);
+    s.xl = reinterpret_cast<float*>(base + L.xl);
+    s.yl = reinterpret_cast<float*>(base + L.yl);
     return s;
 }
 
