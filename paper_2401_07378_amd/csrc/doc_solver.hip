@@ -569,6 +569,7 @@ __device__ inline void rank_greedy_doc(const Lds& L, Shared& sh, int nact, const
                 const float ea = rhat + yn[j];
                 const float ta = tscale * ea * ea;
                 const double ka = L.ckey[j];
+#pragma unroll 4
                 for (int e = start; e < end; ++e) {
                     const int j2 = L.list[e];
                     if (j2 == j) continue;

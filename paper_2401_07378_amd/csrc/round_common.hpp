@@ -214,6 +214,7 @@ __device__ inline void round_rank(const Lds& L, int nact, int protocol, uint64_t
         if (c > 1) {
             if (protocol == NNSEMD_GREEDY) {
                 const double k = L.ckey[j];
+#pragma unroll 4
                 for (int e = start; e < end; ++e) {
                     const int j2 = L.list[e];
                     const double k2 = L.ckey[j2];
@@ -221,6 +222,7 @@ __device__ inline void round_rank(const Lds& L, int nact, int protocol, uint64_t
                 }
             } else {
                 const uint64_t k = rp_key(seed, rounds, j);
+#pragma unroll 4
                 for (int e = start; e < end; ++e) {
                     const int j2 = L.list[e];
                     const uint64_t k2 = rp_key(seed, rounds, j2);
