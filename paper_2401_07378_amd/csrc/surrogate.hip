@@ -260,13 +260,20 @@ __global__ __launch_bounds__(256) void embed_fused_kernel(const float* __restric
     int64_t lo, hi;
     set_range(off, s, P, lo, hi);
     float colsum[4] = {0.f, 0.f, 0.f, 0.f};  // column 64 wave + 16 b + r16, after the lane reduction
+    static_assert(H == 256, "layer 1: one hidden unit per thread");
+    // this thread's hidden unit of layer 1 (same operation order as layer1_pre)
+    const int j1 = tid;
+    const float w10 = q.W1[3 * j1], w11 = q.W1[3 * j1 + 1], w12 = q.W1[3 * j1 + 2], b1j = b1[j1];
     for (int64_t p0 = lo; p0 < hi; p0 += 64) {
         const int np = (int)min<int64_t>(64, hi - p0);
-        for (int e = tid; e < 64 * H; e += 256) {
-            const int pr = e / H, j = e % H;
+#pragma unroll 8
+        for (int pr = 0; pr < 64; ++pr) {
             float h = 0.f;
-            if (pr < np) h = fmaxf(layer1_pre(X + 3 * (p0 + pr), q.W1, b1, j), 0.f);
-            h1[pr * LD + j] = f2bf(h);
+            if (pr < np) {
+                const float* x = X + 3 * (p0 + pr);
+                h = fmaxf(fmaf(x[2], w12, fmaf(x[1], w11, fmaf(x[0], w10, b1j))), 0.f);
+            }
+            h1[pr * LD + j1] = f2bf(h);
         }
         if (tid < 64) am[tid] = tid < np ? a[p0 + tid] : 0.f;
         __syncthreads();
