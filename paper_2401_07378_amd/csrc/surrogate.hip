@@ -246,12 +246,16 @@ __global__ __launch_bounds__(256) void pool_kernel(const float* __restrict__ PRE
 // Fused inference: one workgroup per set, 64 points at a time: layer 1 into
 // LDS (BF16), layer 2 on the matrix cores (each wavefront 64 points x 64
 // outputs), bias + ReLU + mass weighting, column sums kept in registers.
-__global__ __launch_bounds__(256) void embed_fused_kernel(const float* __restrict__ X, const float* __restrict__ a,
+// Global loads are issued ahead of their use (the next chunk's points and
+// masses, the next K step's W2 fragments); three waves per SIMD are asked
+// for, which the compiler meets without spilling.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void embed_fused_kernel(const float* __restrict__ X, const float* __restrict__ a,
                                                           const int64_t* __restrict__ off, int64_t P, SgQuant q,
                                                           const float* __restrict__ theta, float* __restrict__ E) {
     constexpr int LD = H + 8;  // padded row (elements) against bank conflicts
     __shared__ __align__(16) uint16_t h1[64 * LD];
     __shared__ float am[64];
+    __shared__ float xs[64 * 3];
     const int s = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r16 = lane & 15, kq = 8 * (lane >> 4);
@@ -264,28 +268,47 @@ __global__ __launch_bounds__(256) void embed_fused_kernel(const float* __restric
     // this thread's hidden unit of layer 1 (same operation order as layer1_pre)
     const int j1 = tid;
     const float w10 = q.W1[3 * j1], w11 = q.W1[3 * j1 + 1], w12 = q.W1[3 * j1 + 2], b1j = b1[j1];
+    // The next 64 points' coordinates (threads 0..191) and masses (192..255)
+    // are loaded one chunk ahead, so their latency overlaps the products.
+    float pre = 0.f;
+    auto fetch = [&](int64_t pn) {
+        const int64_t npn = min<int64_t>(64, hi - pn);
+        if (tid < 192)
+            pre = tid < 3 * npn ? X[3 * pn + tid] : 0.f;
+        else
+            pre = tid - 192 < npn ? a[pn + tid - 192] : 0.f;
+    };
+    fetch(lo);
     for (int64_t p0 = lo; p0 < hi; p0 += 64) {
         const int np = (int)min<int64_t>(64, hi - p0);
+        if (tid < 192)
+            xs[tid] = pre;
+        else
+            am[tid - 192] = pre;
+        // first K step of this wavefront's W2 fragments, in flight during layer 1
+        bf16x8 bfr[4], bnx[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) bfr[b] = frag16(q.W2, H, wave * 64 + 16 * b + r16, H, kq);
+        __syncthreads();
+        if (p0 + 64 < hi) fetch(p0 + 64);
 #pragma unroll 8
         for (int pr = 0; pr < 64; ++pr) {
             float h = 0.f;
-            if (pr < np) {
-                const float* x = X + 3 * (p0 + pr);
-                h = fmaxf(fmaf(x[2], w12, fmaf(x[1], w11, fmaf(x[0], w10, b1j))), 0.f);
-            }
+            if (pr < np) h = fmaxf(fmaf(xs[3 * pr + 2], w12, fmaf(xs[3 * pr + 1], w11, fmaf(xs[3 * pr], w10, b1j))), 0.f);
             h1[pr * LD + j1] = f2bf(h);
         }
-        if (tid < 64) am[tid] = tid < np ? a[p0 + tid] : 0.f;
         __syncthreads();
         f32x4 acc[4][4];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int b = 0; b < 4; ++b) acc[i][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
-        for (int k0 = 0; k0 < H; k0 += 32) {
-            bf16x8 bfr[4];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) bfr[b] = frag16(q.W2, H, wave * 64 + 16 * b + r16, H, k0 + kq);
+        for (int k0 = 0; k0 < H; k0 += 32) {
+            if (k0 + 32 < H) {
+#pragma unroll
+                for (int b = 0; b < 4; ++b) bnx[b] = frag16(q.W2, H, wave * 64 + 16 * b + r16, H, k0 + 32 + kq);
+            }
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 union {
@@ -296,6 +319,10 @@ __global__ __launch_bounds__(256) void embed_fused_kernel(const float* __restric
 #pragma unroll
                 for (int b = 0; b < 4; ++b)
                     acc[i][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af.v, bfr[b], acc[i][b], 0, 0, 0);
+            }
+            if (k0 + 32 < H) {
+#pragma unroll
+                for (int b = 0; b < 4; ++b) bfr[b] = bnx[b];
             }
         }
 #pragma unroll
