@@ -376,7 +376,8 @@ __global__ __launch_bounds__(256) void build_z_kernel(const float* __restrict__ 
 // a time, all three parts together, so every embedding row is read once
 // (each thread one row's 16 features, 16-byte loads issued one block ahead,
 // so they overlap the products), each
-// wavefront multiplies them with 64 rows of W3 on the matrix cores (K = 768),
+// wavefront multiplies them with 64 rows of W3 on the matrix cores (K = 768,
+// each 64-deep block's W3 fragments loaded during the previous block),
 // and the epilogue applies b3, ReLU and w4, sums the four wavefronts' parts
 // in order and writes softplus(t + b4).  Rows outside the tables give NaN.
 __global__ __launch_bounds__(256) void rho_fused_kernel(const float* __restrict__ Eq_tab, int64_t nq,
@@ -422,12 +423,12 @@ __global__ __launch_bounds__(256) void rho_fused_kernel(const float* __restrict_
     };
     // W3 fragments of one 64-deep K block (part p, column block cb: K offset
     // p * H + cb * 64), both 32-deep steps (L2-resident: every block reads W3).
-    bf16x8 w3[2][4];
-    auto load_w3 = [&](int kb) {
+    bf16x8 w3[2][4], w3n[2][4];
+    auto load_w3 = [&](bf16x8 (&w)[2][4], int kb) {
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
-            for (int b = 0; b < 4; ++b) w3[ks][b] = frag16(q.W3, 3 * H, wave * 64 + 16 * b + r16, H, kb * 64 + ks * 32 + kq);
+            for (int b = 0; b < 4; ++b) w[ks][b] = frag16(q.W3, 3 * H, wave * 64 + 16 * b + r16, H, kb * 64 + ks * 32 + kq);
     };
     f32x4 acc[4][4];
 #pragma unroll
@@ -435,6 +436,7 @@ __global__ __launch_bounds__(256) void rho_fused_kernel(const float* __restrict_
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[i][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
     load_feats(0);
+    load_w3(w3, 0);  // K block (part 0, column block 0)
     for (int cb = 0; cb < NCB; ++cb) {
         __syncthreads();  // the previous column block's fragments have been read
 #pragma unroll
@@ -456,8 +458,11 @@ __global__ __launch_bounds__(256) void rho_fused_kernel(const float* __restrict_
         }
         __syncthreads();
         if (cb + 1 < NCB) load_feats(cb + 1);  // in flight during the products
+#pragma unroll
         for (int p = 0; p < 3; ++p) {
-            load_w3(p * NCB + cb);
+            // the next K block's W3 fragments, in flight during these products
+            const bool more = p < 2 || cb + 1 < NCB;
+            if (more) load_w3(w3n, p < 2 ? (p + 1) * NCB + cb : cb + 1);
             const auto& wc = w3;
 #pragma unroll
             for (int ks = 0; ks < 2; ++ks) {
@@ -472,6 +477,12 @@ __global__ __launch_bounds__(256) void rho_fused_kernel(const float* __restrict_
                     for (int b = 0; b < 4; ++b)
                         acc[i][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af.v, wc[ks][b], acc[i][b], 0, 0, 0);
                 }
+            }
+            if (more) {
+#pragma unroll
+                for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) w3[ks][b] = w3n[ks][b];
             }
         }
     }
