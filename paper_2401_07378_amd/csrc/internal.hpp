@@ -86,7 +86,7 @@ __host__ __device__ inline PairLdsLayout pair_lds_layout(int M, int N, int rs, i
 struct LPState {
     int32_t status, mact, nact, nflag;
     int64_t nnz, work, near;
-    int32_t rounds, done, parity, pad0;
+    int32_t rounds, done, parity, ticket;  // ticket: blocks of the round's last kernel that have finished
     float centre[8];
     float rhat, pad1;
     double sum_a, sum_b;

@@ -300,6 +300,7 @@ __global__ __launch_bounds__(kLpScanThreads) void lp_setup(LPArgs A, int nblocks
         st->work = 0;
         st->near = 0;
         st->rounds = 0;
+        st->ticket = 0;
         st->parity = 1;
         st->done = (st->mact == 0 || st->nact == 0) ? 1 : 0;
         st->rhat = __uint_as_float(rbits) * (1.f + 1e-6f);
@@ -591,7 +592,11 @@ __global__ __launch_bounds__(kLpRescoreThreads) void lp_rescore(LPArgs A) {
 
 // --------------------------------------------------------------- offsets
 // Exclusive scan of the bucket counts into bucket starts.  Each thread owns
-// a run of counts starting at a multiple of four (16-byte loads and stores).
+// a run of counts starting at a multiple of four (16-byte loads and stores);
+// runs of up to 4 kLpOffRegs counts (up to 65536 suppliers) are loaded all at
+// once and kept in registers.
+constexpr int kLpOffRegs = 16;
+
 __global__ __launch_bounds__(kLpScanThreads) void lp_offsets(LPArgs A) {
     __shared__ unsigned long long scratch[kLpScanThreads / kWave];
     LPState* st = A.w.st;
@@ -602,6 +607,44 @@ __global__ __launch_bounds__(kLpScanThreads) void lp_offsets(LPArgs A) {
     const int lo = min(tid * cs, mact), hi = min(lo + cs, mact);
     const int hq = lo + ((hi - lo) & ~3);
     const int* __restrict__ cnt = A.w.scnt;
+    if (cs <= 4 * kLpOffRegs) {
+        int4 v[kLpOffRegs];
+        int sum = 0;
+#pragma unroll
+        for (int u = 0; u < kLpOffRegs; ++u) {
+            const int s = lo + 4 * u;
+            v[u] = s < hq ? *reinterpret_cast<const int4*>(cnt + s) : make_int4(0, 0, 0, 0);
+        }
+        int tail[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) tail[k] = hq + k < hi ? cnt[hq + k] : 0;
+#pragma unroll
+        for (int u = 0; u < kLpOffRegs; ++u) sum += (v[u].x + v[u].y) + (v[u].z + v[u].w);
+        sum += tail[0] + tail[1] + tail[2];
+        unsigned long long tot;
+        int run = (int)lp_block_scan<kLpScanThreads>((unsigned long long)sum, &tot, scratch);
+#pragma unroll
+        for (int u = 0; u < kLpOffRegs; ++u) {
+            const int s = lo + 4 * u;
+            if (s < hq) {
+                int4 o;
+                o.x = run;
+                o.y = o.x + v[u].x;
+                o.z = o.y + v[u].y;
+                o.w = o.z + v[u].z;
+                run = o.w + v[u].w;
+                *reinterpret_cast<int4*>(A.w.soff + s) = o;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (hq + k < hi) {
+                A.w.soff[hq + k] = run;
+                run += tail[k];
+            }
+        }
+        return;
+    }
     int sum = 0;
 #pragma unroll 4
     for (int s = lo; s < hq; s += 4) {
@@ -807,11 +850,62 @@ __global__ __launch_bounds__(kLpThreads) void lp_ccount(LPArgs A) {
     if (threadIdx.x == 0) A.w.blkcnt[blockIdx.x] = tot;
 }
 
+// Ends the round: packed totals of the three compaction streams (the one
+// block's own total, or the per-block counts of lp_ccount), new active
+// sizes, plan length, statistics, termination.  Run by one whole block;
+// reads only data that no block of the running kernel writes.
+__device__ void lp_commit_round(const LPArgs& A, int nblocks, bool single, unsigned long long own,
+                                unsigned long long* red) {
+    LPState* st = A.w.st;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    unsigned long long tot = 0;
+    if (!single) {
+        for (int b = threadIdx.x; b < nblocks; b += kLpThreads) tot += A.w.blkcnt[b];
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) tot += __shfl_xor(tot, o);
+        if (lane == 0) red[w] = tot;
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    if (single) {
+        tot = own;
+    } else {
+        tot = 0;
+#pragma unroll
+        for (int k = 0; k < kLpThreads / kWave; ++k) tot += red[k];
+    }
+    const unsigned long long mask = (1ull << 21) - 1;
+    const int m2 = (int)((tot >> 21) & mask), n2 = (int)(tot >> 42);
+    st->nnz += (int64_t)(tot & mask);
+    st->work += (int64_t)st->mact * st->nact;
+    st->near += st->nflag;
+    st->nflag = 0;
+    st->rounds += 1;
+    st->mact = m2;
+    st->nact = n2;
+    st->parity = 1 - st->parity;
+    st->ticket = 0;
+    if (m2 == 0 || n2 == 0) {
+        st->done = 1;
+    } else if (A.max_rounds > 0 && st->rounds >= A.max_rounds) {
+        st->status = NNSEMD_ERR_NOT_CONVERGED;
+        st->done = 1;
+    }
+}
+
+// Compaction writes of the round and, in the block that takes the last
+// ticket, the round's commit.  With several blocks the packed per-block
+// counts come from lp_ccount; a single block (at most kLpCompactBlock
+// elements per stream) counts its own and no counting kernel runs.  Every
+// block has used the round state it read before it takes its ticket, so the
+// last block may update it; the compaction outputs are read only by later
+// kernels.
 template <int D>
 __global__ __launch_bounds__(kLpThreads) void lp_cwrite(LPArgs A) {
     constexpr int RS = record_stride(D);
     __shared__ unsigned long long scratch[kLpThreads / kWave];
     __shared__ unsigned long long base_sh;
+    __shared__ int last_sh;
     const LPState* st = A.w.st;
     if (!lp_live(st)) return;
     const int mact = st->mact, nact = st->nact, par = st->parity;
@@ -864,39 +958,10 @@ __global__ __launch_bounds__(kLpThreads) void lp_cwrite(LPArgs A) {
         }
         if (fc[u]) A.w.cact[np][wc++] = A.w.cact[par][e];
     }
-}
-
-__global__ __launch_bounds__(kLpThreads) void lp_commit(LPArgs A, int nblocks) {
-    __shared__ unsigned long long red[kLpThreads / kWave];
-    LPState* st = A.w.st;
-    if (!lp_live(st)) return;
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    unsigned long long tot = 0;
-    for (int b = threadIdx.x; b < nblocks; b += kLpThreads) tot += A.w.blkcnt[b];
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) tot += __shfl_xor(tot, o);
-    if (lane == 0) red[w] = tot;
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    tot = 0;
-#pragma unroll
-    for (int k = 0; k < kLpThreads / kWave; ++k) tot += red[k];
-    const unsigned long long mask = (1ull << 21) - 1;
-    const int m2 = (int)((tot >> 21) & mask), n2 = (int)(tot >> 42);
-    st->nnz += (int64_t)(tot & mask);
-    st->work += (int64_t)st->mact * st->nact;
-    st->near += st->nflag;
-    st->nflag = 0;
-    st->rounds += 1;
-    st->mact = m2;
-    st->nact = n2;
-    st->parity = 1 - st->parity;
-    if (m2 == 0 || n2 == 0) {
-        st->done = 1;
-    } else if (A.max_rounds > 0 && st->rounds >= A.max_rounds) {
-        st->status = NNSEMD_ERR_NOT_CONVERGED;
-        st->done = 1;
-    }
+    if (tid == 0) last_sh = atomicAdd(&A.w.st->ticket, 1) == (int)gridDim.x - 1;
+    __syncthreads();
+    if (last_sh) lp_commit_round(A, (int)gridDim.x, gridDim.x == 1, tot, scratch);
 }
 
 // ---------------------------------------------------------------- finish
@@ -1009,9 +1074,8 @@ int lp_launch_round(const LPArgs& A, int d, int mact_ub, int nact_ub, void* stre
         hipLaunchKernelGGL(lp_offsets, dim3(1), dim3(kLpScanThreads), 0, st, A);
         hipLaunchKernelGGL(lp_scatter, dim3(qblocks), dim3(kLpThreads), 0, st, A);
         hipLaunchKernelGGL(lp_serve<DD>, dim3(wblocks), dim3(kLpThreads), 0, st, A);
-        hipLaunchKernelGGL(lp_ccount, dim3(cmblocks), dim3(kLpThreads), 0, st, A);
+        if (cmblocks > 1) hipLaunchKernelGGL(lp_ccount, dim3(cmblocks), dim3(kLpThreads), 0, st, A);
         hipLaunchKernelGGL(lp_cwrite<DD>, dim3(cmblocks), dim3(kLpThreads), 0, st, A);
-        hipLaunchKernelGGL(lp_commit, dim3(1), dim3(kLpThreads), 0, st, A, cmblocks);
     })
     return (int)hipGetLastError();
 }

@@ -24,6 +24,11 @@ CASES = [
     (5, 129, 1100, 5, "dirichlet", "l2", "greedy"),
     (6, 1, 50, 3, "dirichlet", "l2", "greedy"),
     (7, 50, 1, 3, "dirichlet", "l2", "greedy"),
+    # several compaction blocks per round (the last to finish commits the
+    # round), then a single one (it counts its own elements)
+    (8, 5000, 4500, 3, "dirichlet", "l2", "greedy"),
+    (9, 3000, 3000, 3, "uniform", "sqeuclidean", "greedy"),
+    (10, 12000, 9000, 3, "dirichlet", "l2", "greedy"),
 ]
 
 
