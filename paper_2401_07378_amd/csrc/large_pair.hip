@@ -959,7 +959,7 @@ __global__ __launch_bounds__(kLpThreads) void lp_cwrite(LPArgs A) {
         if (fc[u]) A.w.cact[np][wc++] = A.w.cact[par][e];
     }
     __syncthreads();
-    if (tid == 0) last_sh = atomicAdd(&A.w.st->ticket, 1) == (int)gridDim.x - 1;
+    if (tid == 0) last_sh = gridDim.x == 1 || atomicAdd(&A.w.st->ticket, 1) == (int)gridDim.x - 1;
     __syncthreads();
     if (last_sh) lp_commit_round(A, (int)gridDim.x, gridDim.x == 1, tot, scratch);
 }
