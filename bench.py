@@ -237,13 +237,17 @@ def main():
     parity = None
     if not args.no_cpu_baseline:
         import oracle
-        log("oracle on the same pairs (CPU, OpenMP over pairs)")
+        log("oracle on the same pairs (CPU, OpenMP over pairs), repeated for about 10 s")
         t0 = time.perf_counter()
         ref, threads = oracle.solve_batched(ps.X, ps.a, ps.x_off, ps.Y, ps.b, ps.y_off)
+        passes = 1
+        while time.perf_counter() - t0 < 10.0:
+            oracle.solve_batched(ps.X, ps.a, ps.x_off, ps.Y, ps.b, ps.y_off)
+            passes += 1
         dt = time.perf_counter() - t0
-        cpu = {"value": P / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
-               "sample": f"all {P} pairs of the workload, cost only, FP64, {threads} OpenMP threads",
-               "seconds": dt}
+        cpu = {"value": passes * P / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+               "sample": f"all {P} pairs of the workload, {passes} passes, cost only, FP64, "
+                         f"{threads} OpenMP threads", "seconds": dt}
         rc = np.array([r["cost"] for r in ref])
         rel = np.abs(costs - rc) / np.abs(rc)
         same = (np.array([r["rounds"] for r in ref]) == st["rounds"]) & \
@@ -504,14 +508,15 @@ def bench_documents(args, dev):
     cpu = parity = None
     if not args.no_cpu_baseline:
         import oracle
-        S = min(P, 1024)
+        S = P  # about 7 s of FP64 work on 16 host threads
         log(f"oracle on the first {S} pairs (CPU, OpenMP over pairs)")
         t0 = time.perf_counter()
         ref, threads = oracle.solve_batched(ps.X, ps.a, ps.x_off, ps.Y, ps.b, ps.y_off,
                                             pair_x=ps.pair_x[:S], pair_y=ps.pair_y[:S])
         dt = time.perf_counter() - t0
         cpu = {"value": S / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
-               "sample": f"first {S} of the {P} pairs, cost only, FP64, {threads} OpenMP threads", "seconds": dt}
+               "sample": (f"all {P} pairs" if S == P else f"first {S} of the {P} pairs")
+                         + f", cost only, FP64, {threads} OpenMP threads", "seconds": dt}
         rc = np.array([r["cost"] for r in ref])
         rel = np.abs(costs[:S] - rc) / np.abs(rc)
         same = (np.array([r["rounds"] for r in ref]) == st["rounds"][:S]) & \
@@ -635,7 +640,7 @@ def bench_retrieval(args, dev):
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        S = 64000  # about 10 s of FP64 work on 16 host threads
+        S = N  # the whole exhaustive scan of query 0: about 8 s of FP64 work on 16 host threads
         log(f"oracle on {S} of the exhaustive pairs of query 0 (CPU, OpenMP)")
         Xq0 = W.retrieval_query(0)
         t0 = time.perf_counter()
