@@ -41,7 +41,8 @@ def _close_blockwise(got, want, rel):
 
 def test_embed_matches_twin():
     from paper_2401_07378_amd import binding
-    sizes = [1, 2, 63, 64, 65, 128, 200, 256, 300, 7]
+    # ragged chunks of 64 points, an empty set (zero row) and a 16-chunk set
+    sizes = [1, 2, 63, 64, 65, 0, 128, 129, 200, 256, 300, 1000, 7]
     X, a, off = _sets(1, sizes)
     th = _theta(2)
     E = binding.sg_embed(to_dev(th), to_dev(X), to_dev(a), to_dev(off)).cpu().numpy()
