@@ -124,7 +124,7 @@ nnsemd_status_t run_pairs(nnsemd_handle_t h, PairSolverArgs& A, int d, int64_t m
     const int chunk_cap = threads == 256 ? 16 : 8;
     if (chunk > chunk_cap) return fail(h, NNSEMD_ERR_UNSUPPORTED, "set too large for the on-chip pair path");
     const int mcap = (int)std::max<int64_t>(max_m, 1), ncap = (int)std::max<int64_t>(max_n, 1);
-    const PairLdsLayout lay = pair_lds_layout(mcap, ncap, record_stride(d));
+    const PairLdsLayout lay = pair_lds_layout(mcap, ncap, record_stride(d), 0, true);
     if (lay.total + 8192 > h->max_lds)
         return fail(h, NNSEMD_ERR_UNSUPPORTED, "set too large for the on-chip pair path (LDS)");
     A.max_m = mcap;
@@ -139,7 +139,7 @@ nnsemd_status_t run_pairs(nnsemd_handle_t h, PairSolverArgs& A, int d, int64_t m
     if (blocks < 1) return fail(h, NNSEMD_ERR_UNSUPPORTED, "pair workgroup does not fit on a compute unit");
     // Coordinates in LDS (no HBM reads inside the rounds) whenever that costs
     // no resident workgroup.
-    const PairLdsLayout lay_c = pair_lds_layout(mcap, ncap, record_stride(d), d);
+    const PairLdsLayout lay_c = pair_lds_layout(mcap, ncap, record_stride(d), d, true);
     bool coords = false;
     if (lay_c.total + 8192 <= h->max_lds) {
         int bc = 0;
@@ -521,7 +521,7 @@ nnsemd_status_t emd_approx(nnsemd_handle_t h, const void* X, const float* a, int
         const int64_t maxp = std::max<int64_t>({m, n, 1});
         const int chunk_cap = threads == 256 ? 16 : 8;
         const PairLdsLayout lay = pair_lds_layout((int)std::max<int64_t>(m, 1), (int)std::max<int64_t>(n, 1),
-                                                  record_stride(std::max(1, std::min(d, 7))));
+                                                  record_stride(std::max(1, std::min(d, 7))), 0, true);
         multi = (maxp + threads - 1) / threads > chunk_cap || lay.total + 8192 > h->max_lds;
     }
     if (multi) {

@@ -756,7 +756,7 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
             }
         }
     }
-    block_reduce<T, 4>(red, rop, sh);
+    block_reduce<T, 4>(red, rop, &sh.red[0][0]);
     if (status == NNSEMD_OK && red[2] != 0.0) status = NNSEMD_ERR_INVALID_ARG;
     if (status == NNSEMD_OK) {
         const double big = fmax(red[0], red[1]);
@@ -1040,7 +1040,7 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
         for (int e = tid; e < ne; e += T) fin[0] += contrib[e];
     }
     NNSEMD_PH(7)
-    block_reduce<T, 3>(fin, fop, sh);
+    block_reduce<T, 3>(fin, fop, &sh.red[0][0]);
     if (tid == 0) {
         A.costs[p] = status == NNSEMD_OK ? fin[0] : NAN;
         if (A.stats != nullptr) {
@@ -1141,7 +1141,7 @@ __device__ void doc_tile_pair(const DocArgs& A, int64_t p, char* __restrict__ sl
 #endif
     double bd[1] = {bad ? 1.0 : 0.0};
     const int bop[1] = {2};
-    block_reduce<T, 1>(bd, bop, sh);
+    block_reduce<T, 1>(bd, bop, &sh.red[0][0]);
     if (tid == 0) *aflag = bd[0] != 0.0 ? 1 : 0;
 #ifdef NNSEMD_PHASE_TILE
     NNSEMD_PH(8)

@@ -59,21 +59,34 @@ __host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a -
 
 // cd > 0: also the pair's coordinates, cd floats per point (suppliers then
 // consumers, by local index), so the rounds never read them from HBM.
-__host__ __device__ inline PairLdsLayout pair_lds_layout(int M, int N, int rs, int cd = 0) {
+// compact (point path): 16-bit index arrays (even lengths, 4-byte aligned,
+// so a packed 32-bit counter atomic stays inside its array), the serve order
+// written over the claimant buckets, and the FP64 key array at least
+// kPairRedBytes long: it is the block reductions' scratch outside the rounds.
+constexpr size_t kPairRedBytes = 8 * 17 * 8;
+__host__ __device__ inline PairLdsLayout pair_lds_layout(int M, int N, int rs, int cd = 0, bool compact = false) {
     PairLdsLayout L;
+    const size_t isz = compact ? 2 : 4;
+    const size_t Me = compact ? (size_t)((M + 1) & ~1) : (size_t)M;
+    const size_t Ne = compact ? (size_t)((N + 1) & ~1) : (size_t)N;
     size_t o = 0;
     L.smass = o; o += sizeof(double) * (size_t)M;
     L.cmass = o; o += sizeof(double) * (size_t)N;
-    L.ckey = o;  o += sizeof(double) * (size_t)N;
+    L.ckey = o;  o += compact && sizeof(double) * (size_t)N < kPairRedBytes ? kPairRedBytes : sizeof(double) * (size_t)N;
     o = align_up(o, 16);
     L.srec = o;  o += sizeof(float) * (size_t)rs * (size_t)M;
-    L.sidx = o;  o += sizeof(int32_t) * (size_t)M;
-    L.scnt = o;  o += sizeof(int32_t) * (size_t)M;
-    L.soff = o;  o += sizeof(int32_t) * (size_t)M;
-    L.cact = o;  o += sizeof(int32_t) * (size_t)N;
-    L.cnn = o;   o += sizeof(int32_t) * (size_t)N;
-    L.list = o;  o += sizeof(int32_t) * (size_t)N;
-    L.sorted = o; o += sizeof(int32_t) * (size_t)N;
+    o = align_up(o, 4);
+    L.sidx = o;  o += isz * Me;
+    L.scnt = o;  o += isz * Me;
+    L.soff = o;  o += isz * Me;
+    L.cact = o;  o += isz * Ne;
+    L.cnn = o;   o += isz * Ne;
+    L.list = o;  o += isz * Ne;
+    if (compact) {
+        L.sorted = L.list;
+    } else {
+        L.sorted = o; o += isz * Ne;
+    }
     o = align_up(o, 16);
     L.xl = o;    o += sizeof(float) * (size_t)cd * (size_t)M;
     L.yl = o;    o += sizeof(float) * (size_t)cd * (size_t)N;

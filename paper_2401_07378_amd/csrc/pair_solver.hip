@@ -76,7 +76,7 @@ __device__ inline float key32(const float* __restrict__ rec, const float (&y)[D]
 // rounding bound the consumer is queued for the FP64 re-score, otherwise its
 // pick and the exact FP64 key of the pick are stored.
 template <int D, int RS, bool L1, int KC>
-__device__ inline void nns_pass(const Lds& L, Shared& sh, const float* __restrict__ X,
+__device__ inline void nns_pass(const Lds16& L, SharedCore& sh, const float* __restrict__ X,
                                 const float* __restrict__ Y, const float (&centre)[D], float rhat,
                                 int mact, int nact, int S, int qa, int G, int r) {
     int jj[KC];
@@ -174,7 +174,7 @@ __device__ inline void nns_pass(const Lds& L, Shared& sh, const float* __restric
         } else {
             L.cnn[jj[k]] = pick[k];
             L.ckey[jj[k]] = key64<D, L1>(X + (size_t)L.sidx[pick[k]] * D, Y + (size_t)jj[k] * D);
-            atomicAdd(&L.scnt[pick[k]], 1);
+            cnt_add(L.scnt, pick[k]);
         }
     }
 }
@@ -182,7 +182,7 @@ __device__ inline void nns_pass(const Lds& L, Shared& sh, const float* __restric
 // CL: the pair's coordinates are copied into LDS at ingest (L.xl, L.yl) and
 // every later read takes them from there; otherwise from HBM.
 template <int D, int T, int CSMAX, bool L1, bool CL>
-__device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds& L, Shared& sh) {
+__device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds16& L, SharedCore& sh) {
     constexpr int RS = record_stride(D);
     constexpr int NW = T / kWave;
     const int tid = threadIdx.x;
@@ -268,7 +268,7 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds& L, Sha
             if (!isfinite(yv)) red[2] = 1.0;
         }
     }
-    block_reduce<T, 3 + 2 * D>(red, rop, sh);
+    block_reduce<T, 3 + 2 * D>(red, rop, L.ckey);  // the key array is free outside the rounds
     if (status == NNSEMD_OK && red[2] != 0.0) status = NNSEMD_ERR_INVALID_ARG;
     if (status == NNSEMD_OK) {
         double big = fmax(red[0], red[1]);
@@ -335,7 +335,7 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds& L, Sha
             if (L.cmass[j] > 0.0) L.cact[pc++] = j;
         double rr[1] = {(double)rmax};
         const int ro[1] = {2};
-        block_reduce<T, 1>(rr, ro, sh);  // also orders the writes above
+        block_reduce<T, 1>(rr, ro, L.ckey);  // also orders the writes above
         rhat = (float)rr[0] * (1.f + 1e-6f);
         if (tid == 0) sh.nflag = 0;
         __syncthreads();
@@ -405,7 +405,7 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds& L, Sha
                 if (lane == 0) {
                     L.cnn[j] = bsl;
                     L.ckey[j] = best;
-                    atomicAdd(&L.scnt[bsl], 1);
+                    cnt_add(L.scnt, bsl);
                 }
             }
             near += nf;
@@ -417,7 +417,7 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds& L, Sha
         round_buckets<T>(L, sh, mact, nact);
         NNSEMD_PH(3)
         // ---- 3. flow & cost: claimant order, then the serve walk
-        round_rank<T>(L, nact, A.protocol, A.seed, rounds);
+        round_rank<T, CSMAX>(L, nact, A.protocol, A.seed, rounds);
         NNSEMD_PH(5)
         round_walk<T>(L, mact, A.metric, cost);
         NNSEMD_PH(6)
@@ -435,7 +435,7 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds& L, Sha
         for (int s = tid; s < mact; s += T) fin[1] += L.smass[s];
         for (int q = tid; q < nact; q += T) fin[2] += L.cmass[L.cact[q]];
     }
-    block_reduce<T, 3>(fin, fop, sh);
+    block_reduce<T, 3>(fin, fop, L.ckey);
     NNSEMD_PH(8)
     NNSEMD_PH_FLUSH(A.phase_cycles)
     if (tid == 0) {
@@ -464,8 +464,8 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds& L, Sha
 template <int D, int T, int CSMAX, bool L1, bool CL>
 __global__ __launch_bounds__(T) void pair_solver_kernel(PairSolverArgs A) {
     extern __shared__ __align__(16) char lds_dyn[];
-    __shared__ Shared sh;
-    const Lds L = carve(lds_dyn, A.max_m, A.max_n, record_stride(D), CL ? D : 0);
+    __shared__ SharedCore sh;
+    const Lds16 L = carve16(lds_dyn, A.max_m, A.max_n, record_stride(D), CL ? D : 0);
     const int64_t p = A.order != nullptr ? (int64_t)A.order[blockIdx.x] : (int64_t)blockIdx.x;
     solve_pair<D, T, CSMAX, L1, CL>(A, p, L, sh);
 }

@@ -36,49 +36,78 @@ namespace rc {
 
 constexpr int kWave = 64;
 
-struct Lds {
+// LDS arrays of one pair; I is the index type (int32_t, or uint16_t in the
+// compact layout of the point path, where sorted and list share storage).
+template <typename I>
+struct LdsT {
     double* smass;  // [M] supplier mass (by local index while loading, then by active slot)
     double* cmass;  // [N] consumer mass by local index
     double* ckey;   // [N] FP64 key of (pick, j); after the serve: flow (0 = unserved)
     float* srec;    // [M * RS] active supplier records, compacted
-    int32_t* sidx;  // [M] local index of active supplier slot
-    int32_t* scnt;  // [M] claimant count by active slot
-    int32_t* soff;  // [M] bucket start, then bucket end, by active slot
-    int32_t* cact;  // [N] active consumers, compacted, ascending
-    int32_t* cnn;   // [N] pick (active slot) by consumer; after the serve: supplier local index
-    int32_t* list;    // [N] near-tie consumers during the search; claimant buckets after
-    int32_t* sorted;  // [N] claimant buckets in serve order
-    float* xl;        // [M * cd] supplier coordinates by local index (coordinate variant only)
-    float* yl;        // [N * cd] consumer coordinates by local index (coordinate variant only)
+    I* sidx;        // [M] local index of active supplier slot
+    I* scnt;        // [M] claimant count by active slot
+    I* soff;        // [M] bucket start, then bucket end, by active slot
+    I* cact;        // [N] active consumers, compacted, ascending
+    I* cnn;         // [N] pick (active slot) by consumer; after the serve: supplier local index
+    I* list;        // [N] near-tie consumers during the search; claimant buckets after
+    I* sorted;      // [N] claimant buckets in serve order (the list's storage when compact)
+    float* xl;      // [M * cd] supplier coordinates by local index (coordinate variant only)
+    float* yl;      // [N * cd] consumer coordinates by local index (coordinate variant only)
 };
+using Lds = LdsT<int32_t>;
+using Lds16 = LdsT<uint16_t>;
 
 constexpr int kMaxWaves = 8;    // workgroups of up to 512 threads
 constexpr int kMaxReduce = 17;  // values per block reduction (3 + 2d, d <= 7)
+static_assert(sizeof(double) * kMaxWaves * kMaxReduce == kPairRedBytes, "reduction scratch size");
 
-struct Shared {
-    double red[kMaxWaves][kMaxReduce];
+// Static LDS of a workgroup: scan scratch and counters.  The block
+// reductions' scratch (kMaxWaves x kMaxReduce doubles) is passed separately:
+// Shared carries one, the compact point path lends its FP64 key array.
+struct SharedCore {
     unsigned long long scan[kMaxWaves];
     int32_t nflag;  // near-tie consumers of the search
     int32_t namb;   // claimants whose serve order needs exact keys (high-dimensional path)
 };
+struct Shared : SharedCore {
+    double red[kMaxWaves][kMaxReduce];
+};
 
-__device__ inline Lds carve(char* base, int M, int N, int rs, int cd = 0) {
-    PairLdsLayout L = pair_lds_layout(M, N, rs, cd);
-    Lds s;
+template <typename I>
+__device__ inline LdsT<I> carve_t(char* base, const PairLdsLayout& L) {
+    LdsT<I> s;
     s.smass = reinterpret_cast<double*>(base + L.smass);
     s.cmass = reinterpret_cast<double*>(base + L.cmass);
     s.ckey = reinterpret_cast<double*>(base + L.ckey);
     s.srec = reinterpret_cast<float*>(base + L.srec);
-    s.sidx = reinterpret_cast<int32_t*>(base + L.sidx);
-    s.scnt = reinterpret_cast<int32_t*>(base + L.scnt);
-    s.soff = reinterpret_cast<int32_t*>(base + L.soff);
-    s.cact = reinterpret_cast<int32_t*>(base + L.cact);
-    s.cnn = reinterpret_cast<int32_t*>(base + L.cnn);
-    s.list = reinterpret_cast<int32_t*>(base + L.list);
-    s.sorted = reinterpret_cast<int32_t*>(base + L.sorted);
+    s.sidx = reinterpret_cast<I*>(base + L.sidx);
+    s.scnt = reinterpret_cast<I*>(base + L.scnt);
+    s.soff = reinterpret_cast<I*>(base + L.soff);
+    s.cact = reinterpret_cast<I*>(base + L.cact);
+    s.cnn = reinterpret_cast<I*>(base + L.cnn);
+    s.list = reinterpret_cast<I*>(base + L.list);
+    s.sorted = reinterpret_cast<I*>(base + L.sorted);
     s.xl = reinterpret_cast<float*>(base + L.xl);
     s.yl = reinterpret_cast<float*>(base + L.yl);
     return s;
+}
+
+__device__ inline Lds carve(char* base, int M, int N, int rs, int cd = 0) {
+    return carve_t<int32_t>(base, pair_lds_layout(M, N, rs, cd));
+}
+
+__device__ inline Lds16 carve16(char* base, int M, int N, int rs, int cd = 0) {
+    return carve_t<uint16_t>(base, pair_lds_layout(M, N, rs, cd, true));
+}
+
+// Claimant counter increment; returns the count before it.  16-bit counters
+// take a 32-bit atomic on their word (counts stay below 2^16, so nothing
+// carries into the neighbouring counter).
+__device__ inline int cnt_add(int32_t* a, int s) { return atomicAdd(&a[s], 1); }
+__device__ inline int cnt_add(uint16_t* a, int s) {
+    unsigned* w = reinterpret_cast<unsigned*>(a) + (s >> 1);
+    const int sh = (s & 1) * 16;
+    return (int)((atomicAdd(w, 1u << sh) >> sh) & 0xffffu);
 }
 
 __device__ inline double dist_of_key(double key, int metric) {
@@ -98,7 +127,7 @@ __device__ inline uint64_t rp_key(uint64_t seed, int64_t round, int32_t j) {
 // Exclusive block scan of one 64-bit value per thread; *total = block sum.
 template <int T>
 __device__ inline unsigned long long block_scan_u64(unsigned long long v, unsigned long long* total,
-                                                    Shared& sh) {
+                                                    SharedCore& sh) {
     static_assert(T / kWave <= kMaxWaves, "workgroup too large for the scan scratch");
     const int lane = threadIdx.x & (kWave - 1);
     const int w = threadIdx.x / kWave;
@@ -125,7 +154,8 @@ __device__ inline unsigned long long block_scan_u64(unsigned long long v, unsign
 // Block-wide reduction of K values per thread (op 0 = sum, 1 = min, 2 = max),
 // deterministic (fixed butterfly + fixed wave order).  Results in out[].
 template <int T, int K>
-__device__ inline void block_reduce(double (&v)[K], const int (&op)[K], Shared& sh) {
+__device__ inline void block_reduce(double (&v)[K], const int (&op)[K], double* scratch) {
+    double(*red)[kMaxReduce] = reinterpret_cast<double(*)[kMaxReduce]>(scratch);
     static_assert(T / kWave <= kMaxWaves && K <= kMaxReduce, "reduction scratch too small");
     const int lane = threadIdx.x & (kWave - 1);
     const int w = threadIdx.x / kWave;
@@ -136,15 +166,15 @@ __device__ inline void block_reduce(double (&v)[K], const int (&op)[K], Shared& 
             double y = __shfl_xor(v[k], o);
             v[k] = op[k] == 0 ? v[k] + y : (op[k] == 1 ? fmin(v[k], y) : fmax(v[k], y));
         }
-        if (lane == 0) sh.red[w][k] = v[k];
+        if (lane == 0) red[w][k] = v[k];
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        double r = sh.red[0][k];
+        double r = red[0][k];
 #pragma unroll
         for (int q = 1; q < T / kWave; ++q) {
-            double y = sh.red[q][k];
+            double y = red[q][k];
             r = op[k] == 0 ? r + y : (op[k] == 1 ? fmin(r, y) : fmax(r, y));
         }
         v[k] = r;
@@ -176,8 +206,8 @@ __device__ inline void store_rec(float* __restrict__ base, int s, const float (&
 
 
 // ---- claimant sets a_i: scan the counts, scatter the claimants
-template <int T>
-__device__ inline void round_buckets(const Lds& L, Shared& sh, int mact, int nact) {
+template <int T, typename LT>
+__device__ inline void round_buckets(const LT& L, SharedCore& sh, int mact, int nact) {
     const int tid = threadIdx.x;
     {
         const int cs = (mact + T - 1) / T;
@@ -194,43 +224,69 @@ __device__ inline void round_buckets(const Lds& L, Shared& sh, int mact, int nac
     __syncthreads();
     for (int q = tid; q < nact; q += T) {
         const int j = L.cact[q];
-        const int pos = atomicAdd(&L.soff[L.cnn[j]], 1);
+        const int pos = cnt_add(L.soff, L.cnn[j]);
         L.list[pos] = j;
     }
     __syncthreads();
 }
 
 // ---- claimant order: each claimant counts the bucket members that precede
-// it and writes itself to that rank; no dependent chains.
-template <int T>
-__device__ inline void round_rank(const Lds& L, int nact, int protocol, uint64_t seed, int rounds) {
-    for (int q = threadIdx.x; q < nact; q += T) {
-        const int j = L.cact[q];
-        const int sl = L.cnn[j];
-        const int c = L.scnt[sl];
-        const int end = L.soff[sl];
-        const int start = end - c;
-        int rank = 0;
-        if (c > 1) {
-            if (protocol == NNSEMD_GREEDY) {
-                const double k = L.ckey[j];
+// it and writes itself to that rank; no dependent chains.  When the serve
+// order shares the buckets' storage (compact layout), every rank is taken
+// first (at most CS claimants per thread, kept in registers) and written
+// after a barrier.
+template <typename LT>
+__device__ inline int claimant_place(const LT& L, int j, int protocol, uint64_t seed, int rounds) {
+    const int sl = L.cnn[j];
+    const int c = L.scnt[sl];
+    const int end = L.soff[sl];
+    const int start = end - c;
+    int rank = 0;
+    if (c > 1) {
+        if (protocol == NNSEMD_GREEDY) {
+            const double k = L.ckey[j];
 #pragma unroll 4
-                for (int e = start; e < end; ++e) {
-                    const int j2 = L.list[e];
-                    const double k2 = L.ckey[j2];
-                    rank += (k2 < k) || (k2 == k && j2 < j);
-                }
-            } else {
-                const uint64_t k = rp_key(seed, rounds, j);
+            for (int e = start; e < end; ++e) {
+                const int j2 = L.list[e];
+                const double k2 = L.ckey[j2];
+                rank += (k2 < k) || (k2 == k && j2 < j);
+            }
+        } else {
+            const uint64_t k = rp_key(seed, rounds, j);
 #pragma unroll 4
-                for (int e = start; e < end; ++e) {
-                    const int j2 = L.list[e];
-                    const uint64_t k2 = rp_key(seed, rounds, j2);
-                    rank += (k2 < k) || (k2 == k && j2 < j);
-                }
+            for (int e = start; e < end; ++e) {
+                const int j2 = L.list[e];
+                const uint64_t k2 = rp_key(seed, rounds, j2);
+                rank += (k2 < k) || (k2 == k && j2 < j);
             }
         }
-        L.sorted[start + rank] = j;
+    }
+    return start + rank;
+}
+
+template <int T, int CS = 1, typename LT>
+__device__ inline void round_rank(const LT& L, int nact, int protocol, uint64_t seed, int rounds) {
+    if (L.sorted == L.list) {
+        int pos[CS], jv[CS];
+#pragma unroll
+        for (int u = 0; u < CS; ++u) {
+            const int q = threadIdx.x + u * T;
+            pos[u] = -1;
+            jv[u] = 0;
+            if (q < nact) {
+                jv[u] = L.cact[q];
+                pos[u] = claimant_place(L, jv[u], protocol, seed, rounds);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < CS; ++u)
+            if (pos[u] >= 0) L.sorted[pos[u]] = jv[u];
+    } else {
+        for (int q = threadIdx.x; q < nact; q += T) {
+            const int j = L.cact[q];
+            L.sorted[claimant_place(L, j, protocol, seed, rounds)] = j;
+        }
     }
     __syncthreads();
 }
@@ -240,8 +296,8 @@ __device__ inline void round_rank(const Lds& L, int nact, int protocol, uint64_t
 // index of its supplier (for the plan) and its flow in place of its key; an
 // unserved one gets flow 0.  With COST, `cost` accumulates this thread's part
 // of R from the exact keys; without, R is left to the caller.
-template <int T, bool COST = true>
-__device__ inline void round_walk(const Lds& L, int mact, int metric, double& cost) {
+template <int T, bool COST = true, typename LT>
+__device__ inline void round_walk(const LT& L, int mact, int metric, double& cost) {
     for (int s = threadIdx.x; s < mact; s += T) {
         const int c = L.scnt[s];
         if (c == 0) continue;
@@ -268,8 +324,8 @@ __device__ inline void round_walk(const Lds& L, int mact, int metric, double& co
 
 // ---- weights update: plan append + compaction of the active sets (and of
 // the RS-float search records when RS > 0), one scan for all three streams.
-template <int T, int CSMAX, int RS>
-__device__ inline void round_compact(const Lds& L, Shared& sh, int& mact, int& nact, int64_t& nnz,
+template <int T, int CSMAX, int RS, typename LT>
+__device__ inline void round_compact(const LT& L, SharedCore& sh, int& mact, int& nact, int64_t& nnz,
                                      int32_t* plan_src, int32_t* plan_dst, double* plan_flow, int64_t plan_base) {
     constexpr int RSA = RS > 0 ? RS : 4;
     const int tid = threadIdx.x;
