@@ -124,30 +124,37 @@ nnsemd_status_t run_pairs(nnsemd_handle_t h, PairSolverArgs& A, int d, int64_t m
     const int chunk_cap = threads == 256 ? 16 : 8;
     if (chunk > chunk_cap) return fail(h, NNSEMD_ERR_UNSUPPORTED, "set too large for the on-chip pair path");
     const int mcap = (int)std::max<int64_t>(max_m, 1), ncap = (int)std::max<int64_t>(max_n, 1);
-    const PairLdsLayout lay = pair_lds_layout(mcap, ncap, record_stride(d), 0, true);
-    if (lay.total + 8192 > h->max_lds)
-        return fail(h, NNSEMD_ERR_UNSUPPORTED, "set too large for the on-chip pair path (LDS)");
     A.max_m = mcap;
     A.max_n = ncap;
     A.protocol = o.protocol;
     A.seed = o.seed;
     A.max_rounds = o.max_rounds;
     A.phase_cycles = h->phase_cycles;
-    int blocks = 0;
-    int err = pair_solver_blocks_per_cu(d, A.metric, threads, chunk, lay.total, &blocks);
-    if (err != 0) return device_fail(h, err, "occupancy query");
-    if (blocks < 1) return fail(h, NNSEMD_ERR_UNSUPPORTED, "pair workgroup does not fit on a compute unit");
-    // Coordinates in LDS (no HBM reads inside the rounds) whenever that costs
-    // no resident workgroup.
-    const PairLdsLayout lay_c = pair_lds_layout(mcap, ncap, record_stride(d), d, true);
-    bool coords = false;
-    if (lay_c.total + 8192 <= h->max_lds) {
-        int bc = 0;
-        if ((err = pair_solver_blocks_per_cu(d, A.metric, threads, chunk, lay_c.total, &bc, true)) != 0)
-            return device_fail(h, err, "occupancy query");
-        coords = bc >= blocks;
+    // LDS layout: the serve order gets its own array unless sharing the
+    // bucket array's storage adds a resident workgroup; the coordinates are
+    // copied into LDS (no HBM reads inside the rounds) whenever that costs no
+    // resident workgroup.
+    int blocks = 0, err = 0;
+    bool share = false, coords = false;
+    size_t lds_bytes = 0;
+    for (int c = 0; c < 2; ++c) {
+        for (int sh = 0; sh < 2; ++sh) {
+            const PairLdsLayout lay = pair_lds_layout(mcap, ncap, record_stride(d), c ? d : 0, true, sh != 0);
+            if (lay.total + 8192 > h->max_lds) continue;
+            int b = 0;
+            if ((err = pair_solver_blocks_per_cu(d, A.metric, threads, chunk, lay.total, &b, c != 0)) != 0)
+                return device_fail(h, err, "occupancy query");
+            // more resident workgroups first; then the separate order, then the coordinates
+            if (b > blocks || (b == blocks && b > 0 && ((share && !sh) || (!share == !sh && c)))) {
+                blocks = b;
+                share = sh != 0;
+                coords = c != 0;
+                lds_bytes = lay.total;
+            }
+        }
     }
-    const size_t lds_bytes = coords ? lay_c.total : lay.total;
+    if (blocks < 1) return fail(h, NNSEMD_ERR_UNSUPPORTED, "pair workgroup does not fit on a compute unit");
+    A.share_order = share ? 1 : 0;
     const int64_t grid = A.num_pairs;
     if (A.x_off != nullptr && A.num_pairs > 1 && o.schedule == NNSEMD_SCHEDULE_LONGEST_FIRST) {
         nnsemd_status_t s = schedule(h, A.x_off, A.y_off, A.pair_x, A.pair_y, A.num_pairs, A.num_x_sets,

@@ -47,7 +47,7 @@ struct PairSolverArgs {
     const int32_t* order;  // nullable: workgroup b solves pair order[b]
     unsigned long long* phase_cycles;  // profiling builds only: 9 per-phase cycle totals
     int32_t split;         // search: lanes per consumer grow while nact * lanes * split <= threads
-    int32_t pad;
+    int32_t share_order;   // LDS layout: the serve order written over the claimant buckets
 };
 
 // Byte layout of the dynamic LDS of one workgroup (one pair at a time).
@@ -60,11 +60,14 @@ __host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a -
 // cd > 0: also the pair's coordinates, cd floats per point (suppliers then
 // consumers, by local index), so the rounds never read them from HBM.
 // compact (point path): 16-bit index arrays (even lengths, 4-byte aligned,
-// so a packed 32-bit counter atomic stays inside its array), the serve order
-// written over the claimant buckets, and the FP64 key array at least
-// kPairRedBytes long: it is the block reductions' scratch outside the rounds.
+// so a packed 32-bit counter atomic stays inside its array) and the FP64 key
+// array at least kPairRedBytes long: it is the block reductions' scratch
+// outside the rounds.  share (compact only): the serve order is written over
+// the claimant buckets (one more barrier per round, 2 bytes less per
+// consumer).
 constexpr size_t kPairRedBytes = 8 * 17 * 8;
-__host__ __device__ inline PairLdsLayout pair_lds_layout(int M, int N, int rs, int cd = 0, bool compact = false) {
+__host__ __device__ inline PairLdsLayout pair_lds_layout(int M, int N, int rs, int cd = 0, bool compact = false,
+                                                         bool share = true) {
     PairLdsLayout L;
     const size_t isz = compact ? 2 : 4;
     const size_t Me = compact ? (size_t)((M + 1) & ~1) : (size_t)M;
@@ -82,7 +85,7 @@ __host__ __device__ inline PairLdsLayout pair_lds_layout(int M, int N, int rs, i
     L.cact = o;  o += isz * Ne;
     L.cnn = o;   o += isz * Ne;
     L.list = o;  o += isz * Ne;
-    if (compact) {
+    if (compact && share) {
         L.sorted = L.list;
     } else {
         L.sorted = o; o += isz * Ne;

@@ -461,11 +461,14 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds16& L, S
 // used here: its back-edge merges with the thread-0-only result write, and
 // the structurized code lets lanes 1-63 of wave 0 pass the following
 // barrier without the fetch, re-solving the same pair forever.)
+// Up to four claimants per thread the kernel is held to 128 VGPRs (four
+// waves per SIMD, no spills): small pairs keep four workgroups per CU.
 template <int D, int T, int CSMAX, bool L1, bool CL>
-__global__ __launch_bounds__(T) void pair_solver_kernel(PairSolverArgs A) {
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(CSMAX <= 4 ? 4 : 1)))
+void pair_solver_kernel(PairSolverArgs A) {
     extern __shared__ __align__(16) char lds_dyn[];
     __shared__ SharedCore sh;
-    const Lds16 L = carve16(lds_dyn, A.max_m, A.max_n, record_stride(D), CL ? D : 0);
+    const Lds16 L = carve16(lds_dyn, A.max_m, A.max_n, record_stride(D), CL ? D : 0, A.share_order != 0);
     const int64_t p = A.order != nullptr ? (int64_t)A.order[blockIdx.x] : (int64_t)blockIdx.x;
     solve_pair<D, T, CSMAX, L1, CL>(A, p, L, sh);
 }

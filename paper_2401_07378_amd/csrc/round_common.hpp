@@ -96,8 +96,8 @@ __device__ inline Lds carve(char* base, int M, int N, int rs, int cd = 0) {
     return carve_t<int32_t>(base, pair_lds_layout(M, N, rs, cd));
 }
 
-__device__ inline Lds16 carve16(char* base, int M, int N, int rs, int cd = 0) {
-    return carve_t<uint16_t>(base, pair_lds_layout(M, N, rs, cd, true));
+__device__ inline Lds16 carve16(char* base, int M, int N, int rs, int cd, bool share) {
+    return carve_t<uint16_t>(base, pair_lds_layout(M, N, rs, cd, true, share));
 }
 
 // Claimant counter increment; returns the count before it.  16-bit counters
