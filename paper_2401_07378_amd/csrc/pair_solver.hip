@@ -358,11 +358,12 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds16& L, S
         // each decided consumer also counts itself into its pick's bucket.
         // S lanes share one consumer (each scans every S-th supplier) when
         // there are too few consumers to fill the workgroup; otherwise each
-        // lane takes KC consumers so one record load feeds KC key chains.
+        // lane takes KC (1 to 4, the fewest that cover the active consumers)
+        // so one record load feeds KC key chains.
         int S = 1;
         while (S < kWave && nact * S * A.split <= T) S <<= 1;
         while (S > 1 && S > mact) S >>= 1;
-        const int kc = S > 1 ? 1 : (nact > 2 * T ? 4 : (nact > T ? 2 : 1));
+        const int kc = S > 1 ? 1 : (nact > 3 * T ? 4 : (nact > 2 * T ? 3 : (nact > T ? 2 : 1)));
         {
             const int r = tid & (S - 1);
             const int g = tid / S;
@@ -370,6 +371,8 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds16& L, S
             for (int q0 = 0; q0 < nact; q0 += G * kc) {
                 if (kc == 4)
                     nns_pass<D, RS, L1, 4>(L, sh, X, Y, centre, rhat, mact, nact, S, q0 + g, G, r);
+                else if (kc == 3)
+                    nns_pass<D, RS, L1, 3>(L, sh, X, Y, centre, rhat, mact, nact, S, q0 + g, G, r);
                 else if (kc == 2)
                     nns_pass<D, RS, L1, 2>(L, sh, X, Y, centre, rhat, mact, nact, S, q0 + g, G, r);
                 else
