@@ -117,6 +117,17 @@ def test_random_protocol(seed):
     assert_pair_matches(gpu_pair(X, a, Y, b, **kw), oracle_pair(X, a, Y, b, **kw), label="rp")
 
 
+@pytest.mark.parametrize("protocol", ["greedy", "random"])
+def test_shared_serve_order_layout(protocol):
+    """1000 x 1024 points: the serve order is written over the claimant
+    buckets (the layout that fits three such pairs per CU); lattice
+    coordinates and integer masses make exact key ties in the buckets."""
+    X, a, Y, b = W.random_pair(96, 1000, 1024, 3, masses="integer", lattice=10)
+    kw = dict(protocol=protocol, seed=77)
+    g = gpu_pair(X, a, Y, b, **kw)
+    assert_pair_matches(g, oracle_pair(X, a, Y, b, **kw), label=protocol)
+
+
 def test_translated_copy_one_round():
     g = np.arange(20, dtype=np.float64)
     X = np.stack(np.meshgrid(g, g), -1).reshape(-1, 2).astype(np.float32)
