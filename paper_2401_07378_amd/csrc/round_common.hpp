@@ -331,8 +331,24 @@ __device__ inline void round_compact(const LT& L, SharedCore& sh, int& mact, int
     const int tid = threadIdx.x;
     const int pc = (nact + T - 1) / T;
     const int plo = min(tid * pc, nact), phi = min(plo + pc, nact);
+    // this thread's claimants in serve order and their flows (pc <= CSMAX),
+    // read once for the count and the plan append (kept in registers for up
+    // to four per thread)
+    constexpr int PK = CSMAX <= 4 ? CSMAX : 1;
+    int pj[PK];
+    double pf[PK];
     int kp = 0;
-    for (int k = plo; k < phi; ++k) kp += L.ckey[L.sorted[k]] > 0.0;
+    if constexpr (CSMAX <= 4) {
+#pragma unroll
+        for (int u = 0; u < CSMAX; ++u) {
+            const int k = plo + u;
+            pj[u] = k < phi ? (int)L.sorted[k] : 0;
+            pf[u] = k < phi ? L.ckey[pj[u]] : 0.0;
+            kp += pf[u] > 0.0;
+        }
+    } else {
+        for (int k = plo; k < phi; ++k) kp += L.ckey[L.sorted[k]] > 0.0;
+    }
     const int cs = (mact + T - 1) / T;
     const int slo = min(tid * cs, mact);
     float rec[CSMAX][RSA];
@@ -368,15 +384,29 @@ __device__ inline void round_compact(const LT& L, SharedCore& sh, int& mact, int
     const unsigned long long mask = (1ull << 21) - 1;
     int wp = (int)(pre & mask), ws = (int)((pre >> 21) & mask), wc = (int)(pre >> 42);
     if (plan_src != nullptr) {
-        for (int k = plo; k < phi; ++k) {
-            const int j = L.sorted[k];
-            const double f = L.ckey[j];
-            if (f > 0.0) {
-                const int64_t e = plan_base + nnz + wp;
-                plan_src[e] = L.cnn[j];
-                plan_dst[e] = j;
-                plan_flow[e] = f;
-                ++wp;
+        if constexpr (CSMAX <= 4) {
+#pragma unroll
+            for (int u = 0; u < CSMAX; ++u) {
+                if (pf[u] > 0.0) {
+                    const int j = pj[u];
+                    const int64_t e = plan_base + nnz + wp;
+                    plan_src[e] = L.cnn[j];
+                    plan_dst[e] = j;
+                    plan_flow[e] = pf[u];
+                    ++wp;
+                }
+            }
+        } else {
+            for (int k = plo; k < phi; ++k) {
+                const int j = L.sorted[k];
+                const double f = L.ckey[j];
+                if (f > 0.0) {
+                    const int64_t e = plan_base + nnz + wp;
+                    plan_src[e] = L.cnn[j];
+                    plan_dst[e] = j;
+                    plan_flow[e] = f;
+                    ++wp;
+                }
             }
         }
     }
