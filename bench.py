@@ -199,7 +199,7 @@ def main():
     ops = work * (2 * d + 2)
     achieved = ops / (ms / 1e3)
     alg_bytes = int(ps.X.nbytes + ps.a.nbytes + ps.Y.nbytes + ps.b.nbytes + ps.x_off.nbytes
-                    + ps.y_off.nbytes + P * (8 + 48) + (int(st["nnz"].sum()) * 16 if want_plan else 0))
+                    + ps.y_off.nbytes + P * (8 + binding.STATS_BYTES) + (int(st["nnz"].sum()) * 16 if want_plan else 0))
     threads_used = args.threads or (tuning["threads"] if tuning else 256)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_LANE_OPS / 1e12,
                 "unit": "Tops/s", "frac": achieved / PEAK_VALU_LANE_OPS,
@@ -219,7 +219,7 @@ def main():
             xs, xe, ys, ye = ps.x_off[p], ps.x_off[p + 1], ps.y_off[p], ps.y_off[p + 1]
             views.append((X[xs:xe], a[xs:xe], Y[ys:ye], b[ys:ye]))
         outs = [{"cost": torch.empty(1, dtype=torch.float64, device=dev),
-                 "stats": torch.empty(48, dtype=torch.uint8, device=dev)} for _ in range(S)]
+                 "stats": torch.empty(binding.STATS_BYTES, dtype=torch.uint8, device=dev)} for _ in range(S)]
         for p in range(min(S, 8)):
             binding.emd_approx(*views[p], "l2", plan=False, out=outs[p])
         torch.cuda.synchronize()
@@ -253,9 +253,13 @@ def main():
         same = (np.array([r["rounds"] for r in ref]) == st["rounds"]) & \
                (np.array([r["work"] for r in ref]) == st["work"]) & \
                (np.array([r["nnz"] for r in ref]) == st["nnz"])
+        near_same = (np.array([r["near_ties_nn"] for r in ref]) == st["near_ties_nn"]) & \
+                    (np.array([r["near_ties_order"] for r in ref]) == st["near_ties_order"])
         parity = {"max_rel_err": float(rel.max()), "mean_rel_err": float(rel.mean()),
                   "pairs_checked": P, "stats_identical": int(same.sum()),
-                  "near_tie_rescored_consumers": int(st["near_ties"].sum()), "tolerance": 1e-5}
+                  "rescored_consumers": int(st["rescored"].sum()),
+                  "near_ties_nn": int(st["near_ties_nn"].sum()), "near_ties_order": int(st["near_ties_order"].sum()),
+                  "near_ties_identical": int(near_same.sum()), "tolerance": 1e-5}
         log(f"oracle {cpu['value']:.1f} pairs/s on {threads} threads; max rel err {rel.max():.3g}")
 
     line = {
@@ -393,7 +397,8 @@ def bench_colour_transfer(args, dev):
             "dtype": "f32", "data": "synthetic",
             "config": {"workload": "colour_transfer_3d: one 65536 x 65536 pair, 2-component Gaussian mixtures "
                                    "clipped to [0,1]^3, uniform masses, squared Euclidean, cost + barycentric map",
-                       "rounds": int(st["rounds"]), "near_tie_rescored": int(st["near_ties"])},
+                       "rounds": int(st["rounds"]), "rescored": int(st["rescored"]),
+                       "near_ties_nn": int(st["near_ties_nn"]), "near_ties_order": int(st["near_ties_order"])},
             "roofline": roofline, "cpu_baseline": cpu}
     print(json.dumps(line), flush=True)
 
@@ -475,7 +480,7 @@ def bench_documents(args, dev):
             ys, ye = ps.y_off[ps.pair_y[p]], ps.y_off[ps.pair_y[p] + 1]
             views.append((Xf[xs:xe], a[xs:xe], Yf[ys:ye], b[ys:ye]))
         outs = [{"cost": torch.empty(1, dtype=torch.float64, device=dev),
-                 "stats": torch.empty(48, dtype=torch.uint8, device=dev)} for _ in range(S)]
+                 "stats": torch.empty(binding.STATS_BYTES, dtype=torch.uint8, device=dev)} for _ in range(S)]
         for p in range(min(S, 8)):
             binding.emd_approx(*views[p], "l2", plan=False, out=outs[p])
         torch.cuda.synchronize()
@@ -493,7 +498,7 @@ def bench_documents(args, dev):
     flops = float(2.0 * (m_sizes * n_sizes).sum() * d)
     work = int(st["work"].sum())
     alg_bytes = int(ps.X_bits.nbytes + ps.a.nbytes + ps.Y_bits.nbytes + ps.b.nbytes + ps.x_off.nbytes
-                    + ps.y_off.nbytes + 8 * P + P * (8 + 48)
+                    + ps.y_off.nbytes + 8 * P + P * (8 + binding.STATS_BYTES)
                     + (int(st["nnz"].sum()) * 16 if want_plan else 0))
     # One query of m points against the candidates: about m flops per byte
     # of candidate rows, below the BF16 ridge (2.5e15 / 8e12 = 312), so the
@@ -522,8 +527,12 @@ def bench_documents(args, dev):
         same = (np.array([r["rounds"] for r in ref]) == st["rounds"][:S]) & \
                (np.array([r["work"] for r in ref]) == st["work"][:S]) & \
                (np.array([r["nnz"] for r in ref]) == st["nnz"][:S])
+        near_same = (np.array([r["near_ties_nn"] for r in ref]) == st["near_ties_nn"][:S]) & \
+                    (np.array([r["near_ties_order"] for r in ref]) == st["near_ties_order"][:S])
         parity = {"max_rel_err": float(rel.max()), "pairs_checked": S, "stats_identical": int(same.sum()),
-                  "near_tie_rescored_consumers": int(st["near_ties"].sum()), "tolerance": 1e-3,
+                  "rescored_consumers": int(st["rescored"].sum()),
+                  "near_ties_nn": int(st["near_ties_nn"].sum()), "near_ties_order": int(st["near_ties_order"].sum()),
+                  "near_ties_identical": int(near_same.sum()), "tolerance": 1e-3,
                   "fp32_vector_path_identical_costs": same_bits}
         log(f"oracle {cpu['value']:.1f} pairs/s; max rel err {rel.max():.3g}")
 
@@ -591,7 +600,7 @@ def bench_retrieval(args, dev):
     Q = args.queries
     queries = [t(W.retrieval_query(q)) for q in range(Q)]
     ex_out = {"costs": torch.empty(N, dtype=torch.float64, device=dev),
-              "stats": torch.empty(N * 48, dtype=torch.uint8, device=dev)}
+              "stats": torch.empty(N * binding.STATS_BYTES, dtype=torch.uint8, device=dev)}
     pr_out = {}
     truth, got = [], []
     tuning = None

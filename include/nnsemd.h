@@ -102,15 +102,28 @@ typedef struct {
     int32_t reserved;   /* must be 0 */
 } nnsemd_options_t;
 
-/* Per-pair results, written by the device (48 bytes). */
+/* Per-pair results, written by the device (64 bytes).
+ * A near tie is a gap of at most 1e-6 relative between two distances D
+ * (second - first <= 1e-6 * first, or <= 1e-12 when first is 0), evaluated
+ * in FP64 on the exact keys.  Both counters are those of a plain FP64 run
+ * of Algorithm 1 on the same inputs, whatever the search precision. */
 typedef struct {
-    int32_t status;      /* nnsemd_status_t of this pair */
-    int32_t rounds;      /* NNS iterations t */
-    int64_t nnz;         /* plan entries (serves), <= m + n - 1 */
-    int64_t work;        /* sum over rounds of |active S| * |active C| */
-    int64_t near_ties;   /* consumers re-scored in FP64 (FP32 keys too close) */
-    double residual_src; /* supplier mass left when the rounds stopped */
-    double residual_dst; /* consumer mass left when the rounds stopped */
+    int32_t status;          /* nnsemd_status_t of this pair */
+    int32_t rounds;          /* NNS iterations t */
+    int64_t nnz;             /* plan entries (serves), <= m + n - 1 */
+    int64_t work;            /* sum over rounds of |active S| * |active C| */
+    int64_t rescored;        /* consumer searches settled by an FP64 re-score
+                                (the FP32 keys were closer than their proven
+                                error bound or a near-tie window) */
+    double residual_src;     /* supplier mass left when the rounds stopped */
+    double residual_dst;     /* consumer mass left when the rounds stopped */
+    int64_t near_ties_nn;    /* NNS step: active consumers (with >= 2 active
+                                suppliers) whose nearest and second-nearest
+                                suppliers are a near tie, summed over rounds */
+    int64_t near_ties_order; /* greedy protocol: neighbouring claimants of a
+                                supplier, in serve order, that are a near tie,
+                                summed over suppliers and rounds (0 under the
+                                random protocol) */
 } nnsemd_stats_t;
 
 /* Create a handle on HIP device `device` (its workspace grows on demand).
@@ -163,10 +176,13 @@ nnsemd_status_t emd_approx(nnsemd_handle_t h,
  * emd_approx_map -- emd_approx plus the per-supplier barycentric transport
  * map of the plan (colour transfer, Sec. IV-D): map[i*d + k] =
  * sum_j F*_ij y_jk / sum_j F*_ij, accumulated in FP64 in plan order; rows of
- * suppliers that sent nothing are NaN.  map: device, m x d doubles.  Uses
- * the multi-workgroup path (the calling thread waits for the device); FP32
- * points with 1 <= d <= 7 only (else UNSUPPORTED).
- * Plan arrays may be NULL as in emd_approx.
+ * suppliers that sent nothing are NaN.  map: device, m x d doubles.  FP32
+ * points with 1 <= d <= 7 only (else UNSUPPORTED).  The path is chosen as in
+ * emd_approx: a pair that fits one workgroup is solved on chip and its map
+ * taken by the kernels of emd_barycentric_map (asynchronous); a larger pair
+ * (or opts->path = MULTI) runs on the multi-workgroup path, which forms the
+ * map while it serves.  Plan arrays and stats may be NULL as in emd_approx
+ * (library workspace then holds the plan).
  */
 nnsemd_status_t emd_approx_map(nnsemd_handle_t h,
                                const void* X, const float* a, int64_t m,
@@ -178,6 +194,40 @@ nnsemd_status_t emd_approx_map(nnsemd_handle_t h,
                                int64_t plan_capacity,
                                nnsemd_stats_t* stats,
                                void* stream);
+
+/* Which side of a plan a barycentric map is taken for. */
+typedef enum { NNSEMD_MAP_SUPPLIERS = 0, NNSEMD_MAP_CONSUMERS = 1 } nnsemd_map_side_t;
+
+/*
+ * emd_barycentric_map -- barycentric transport map of a given plan (colour
+ * transfer, Sec. IV-D: each colour moves to the F*-weighted mean of the
+ * colours it is transported to).
+ *   side SUPPLIERS: rows = m suppliers, P = Y (the consumers, p_rows = n):
+ *     map[i*d + k] = sum_j F_ij y_jk / sum_j F_ij;
+ *   side CONSUMERS: rows = n consumers, P = X (the suppliers, p_rows = m):
+ *     map[j*d + k] = sum_i F_ij x_ik / sum_i F_ij (recolouring the side
+ *     that consumes).
+ * Each row is summed in FP64 in plan order, so the map of a plan is the same
+ * bit for bit whichever path produced the plan; rows without flow are NaN.
+ *   plan_src, plan_dst, plan_flow: device, plan_capacity entries (a plan
+ *     written by emd_approx, emd_approx_map or emd_approx_batched, or any
+ *     list of (supplier, consumer, flow) entries).
+ *   plan_nnz: device, nullable: the number of entries in use, e.g.
+ *     &stats->nnz of the call that wrote the plan, so no host round trip is
+ *     needed; NULL uses all plan_capacity entries.
+ *   P: device, p_rows x d FP32; map: device, rows x d doubles.
+ * Entries with a supplier or consumer index outside the sizes are skipped.
+ * Asynchronous on stream; the handle's workspace grows on the first call
+ * for a size.  1 <= d <= 8; rows, p_rows, plan_capacity < 2^31.
+ * Errors: INVALID_ARG (NULL arrays, sizes, side), UNSUPPORTED (d),
+ * OUT_OF_MEMORY, DEVICE.
+ */
+nnsemd_status_t emd_barycentric_map(nnsemd_handle_t h,
+                                    const int32_t* plan_src, const int32_t* plan_dst, const double* plan_flow,
+                                    int64_t plan_capacity, const int64_t* plan_nnz,
+                                    const float* P, int64_t p_rows, int32_t d,
+                                    int64_t rows, nnsemd_map_side_t side, double* map,
+                                    void* stream);
 
 /*
  * emd_approx_batched -- NNS-EMD of many independent ragged pairs in one

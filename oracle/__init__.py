@@ -87,6 +87,13 @@ def _load():
             lib.nnsemd_oracle_solve_batched.argtypes = [
                 ctypes.c_int64, P, P, P, P, P, P, P, P, ctypes.c_int32, ctypes.c_int32,
                 ctypes.c_int32, ctypes.c_uint64, P]
+            lib.nnsemd_oracle_solve_cost.restype = ctypes.c_int
+            lib.nnsemd_oracle_solve_cost.argtypes = [
+                P, P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64,
+                ctypes.c_int64, P, P, P, ctypes.c_int64, ctypes.POINTER(OracleStats)]
+            lib.nnsemd_oracle_barycentric_dst.restype = None
+            lib.nnsemd_oracle_barycentric_dst.argtypes = [
+                P, P, P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_int32, P]
             lib.nnsemd_oracle_barycentric.restype = None
             lib.nnsemd_oracle_barycentric.argtypes = [
                 P, P, P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_int32, P]
@@ -147,6 +154,38 @@ def solve(X, a, Y, b, metric: str = "l2", protocol: str = "greedy", seed: int = 
     return out
 
 
+def solve_cost(D, a, b, protocol: str = "greedy", seed: int = 0, with_plan: bool = True,
+               max_rounds: int = 0) -> dict:
+    """Run NNS-EMD on a given ground-distance matrix D (m x n; Algorithm 1's
+    input): suppliers carry masses a (m), consumers b (n).  D_ij is the key
+    of the search and of the greedy order and the distance of the cost.
+    Same result dict as solve()."""
+    lib = _load()
+    D = np.ascontiguousarray(np.asarray(D, dtype=np.float64))
+    a = _f64(a, 1)
+    b = _f64(b, 1)
+    m, n = len(a), len(b)
+    if D.shape != (m, n):
+        raise ValueError("D must be m x n")
+    st = OracleStats()
+    if with_plan:
+        cap = max(m + n - 1, 1)
+        src = np.zeros(cap, np.int32)
+        dst = np.zeros(cap, np.int32)
+        flow = np.zeros(cap, np.float64)
+    else:
+        cap, src, dst, flow = 0, None, None, None
+    lib.nnsemd_oracle_solve_cost(_ptr(D), _ptr(a), m, _ptr(b), n, PROTOCOLS[protocol],
+                                 seed & (2**64 - 1), max_rounds, _ptr(src), _ptr(dst), _ptr(flow),
+                                 cap, ctypes.byref(st))
+    out = st.as_dict()
+    out["status_name"] = STATUS.get(out["status"], str(out["status"]))
+    if with_plan and out["status"] in (0, -6):
+        k = out["nnz"]
+        out["src"], out["dst"], out["flow"] = src[:k].copy(), dst[:k].copy(), flow[:k].copy()
+    return out
+
+
 def solve_batched(Xcat, acat, x_off, Ycat, bcat, y_off, pair_x=None, pair_y=None,
                   metric: str = "l2", protocol: str = "greedy", seed: int = 0,
                   num_pairs: int | None = None) -> tuple[list, int]:
@@ -182,6 +221,19 @@ def barycentric(src, dst, flow, Y, m: int) -> np.ndarray:
     out = np.zeros((m, Y.shape[1]), np.float64)
     lib.nnsemd_oracle_barycentric(_ptr(src), _ptr(dst), _ptr(flow), len(src), _ptr(Y), m,
                                   Y.shape[1], _ptr(out))
+    return out
+
+
+def barycentric_dst(src, dst, flow, X, n: int) -> np.ndarray:
+    """T_j = sum_i F_ij x_i / sum_i F_ij for every consumer j (NaN if none)."""
+    lib = _load()
+    src = np.ascontiguousarray(src, np.int32)
+    dst = np.ascontiguousarray(dst, np.int32)
+    flow = np.ascontiguousarray(flow, np.float64)
+    X = _f64(X, 2)
+    out = np.zeros((n, X.shape[1]), np.float64)
+    lib.nnsemd_oracle_barycentric_dst(_ptr(src), _ptr(dst), _ptr(flow), len(src), _ptr(X), n,
+                                      X.shape[1], _ptr(out))
     return out
 
 

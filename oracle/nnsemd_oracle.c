@@ -33,7 +33,8 @@
  *     agree to 1e-5 relative.
  * D is never stored: each entry is recomputed from the coordinates, in
  * dimension order, in FP64, without fused multiply-add (build with
- * -ffp-contract=off).
+ * -ffp-contract=off).  Algorithm 1 itself takes D as its input; that form
+ * (nnsemd_oracle_solve_cost) runs the same steps on a given m x n matrix.
  */
 #include <math.h>
 #include <stdint.h>
@@ -53,6 +54,7 @@
 #define ORC_METRIC_L2 0
 #define ORC_METRIC_SQEUCLIDEAN 1
 #define ORC_METRIC_L1 2
+#define ORC_METRIC_GIVEN 3 /* D is given: key = distance = D_ij */
 
 #define ORC_PROTOCOL_GREEDY 0
 #define ORC_PROTOCOL_RANDOM 1
@@ -84,9 +86,25 @@ static double key_of(const double* x, const double* y, int d, int metric) {
     return acc;
 }
 
-/* Ground distance D_ij used in the cost. */
+/* Ground distance D_ij used in the cost (a given matrix: the entry itself). */
 static double dist_of_key(double key, int metric) {
     return metric == ORC_METRIC_L2 ? sqrt(key) : key;
+}
+
+/* Where the keys come from: two point sets and a metric, or the m x n
+ * ground-distance matrix D itself (Algorithm 1 takes D as its input). */
+typedef struct {
+    const double* X; /* m x d suppliers (points mode) */
+    const double* Y; /* n x d consumers (points mode) */
+    int d;
+    int metric;      /* ORC_METRIC_*, ORC_METRIC_GIVEN for a matrix */
+    const double* D; /* m x n row-major, or NULL (points mode) */
+    int64_t n;
+} ground_t;
+
+static double ground_key(const ground_t* g, int64_t i, int64_t j) {
+    if (g->D != NULL) return g->D[i * g->n + j];
+    return key_of(g->X + i * g->d, g->Y + j * g->d, g->d, g->metric);
 }
 
 static int near_tie(double d1, double d2) {
@@ -128,19 +146,17 @@ static int cmp_random(const void* pa, const void* pb) {
 }
 
 /*
- * Solve one pair.  X: m x d row-major suppliers, a: m masses; Y: n x d
- * consumers, b: n masses.  Plan arrays may be NULL (plan_capacity ignored);
- * otherwise they must hold m + n - 1 entries.  max_rounds <= 0 means m + n.
+ * One pair on a ground (points or a given matrix); see nnsemd_oracle_solve.
  */
-int nnsemd_oracle_solve(const double* X, const double* a, int64_t m,
-                        const double* Y, const double* b, int64_t n,
-                        int32_t d, int32_t metric, int32_t protocol,
+static int solve_ground(const ground_t* G, const double* a, int64_t m,
+                        const double* b, int64_t n, int32_t protocol,
                         uint64_t seed, int64_t max_rounds,
                         int32_t* plan_src, int32_t* plan_dst,
                         double* plan_flow, int64_t plan_capacity,
                         oracle_stats* st) {
+    const int metric = G->metric;
     memset(st, 0, sizeof(*st));
-    if (m < 0 || n < 0 || d < 1 || (metric < 0 || metric > 2) ||
+    if (m < 0 || n < 0 || (G->D == NULL && G->d < 1) ||
         (protocol != ORC_PROTOCOL_GREEDY && protocol != ORC_PROTOCOL_RANDOM)) {
         st->status = ORC_ERR_INVALID_ARG;
         return st->status;
@@ -149,18 +165,28 @@ int nnsemd_oracle_solve(const double* X, const double* a, int64_t m,
         st->status = ORC_ERR_CAPACITY;
         return st->status;
     }
-    /* Input checks: finite coordinates, finite non-negative masses. */
+    /* Input checks: finite coordinates (or finite, non-negative entries of a
+     * given D), finite non-negative masses. */
     double sum_a = 0.0, sum_b = 0.0;
     for (int64_t i = 0; i < m; ++i) {
         if (!isfinite(a[i]) || a[i] < 0.0) { st->status = ORC_ERR_INVALID_ARG; return st->status; }
-        for (int k = 0; k < d; ++k)
-            if (!isfinite(X[i * d + k])) { st->status = ORC_ERR_INVALID_ARG; return st->status; }
+        if (G->D == NULL) {
+            for (int k = 0; k < G->d; ++k)
+                if (!isfinite(G->X[i * G->d + k])) { st->status = ORC_ERR_INVALID_ARG; return st->status; }
+        } else {
+            for (int64_t j = 0; j < n; ++j)
+                if (!isfinite(G->D[i * n + j]) || G->D[i * n + j] < 0.0) {
+                    st->status = ORC_ERR_INVALID_ARG;
+                    return st->status;
+                }
+        }
         sum_a += a[i];
     }
     for (int64_t j = 0; j < n; ++j) {
         if (!isfinite(b[j]) || b[j] < 0.0) { st->status = ORC_ERR_INVALID_ARG; return st->status; }
-        for (int k = 0; k < d; ++k)
-            if (!isfinite(Y[j * d + k])) { st->status = ORC_ERR_INVALID_ARG; return st->status; }
+        if (G->D == NULL)
+            for (int k = 0; k < G->d; ++k)
+                if (!isfinite(G->Y[j * G->d + k])) { st->status = ORC_ERR_INVALID_ARG; return st->status; }
         sum_b += b[j];
     }
     double big = sum_a > sum_b ? sum_a : sum_b;
@@ -199,12 +225,11 @@ int nnsemd_oracle_solve(const double* X, const double* a, int64_t m,
          * the first (smallest index) of equal minima wins. */
         for (int64_t q = 0; q < nc; ++q) {
             int64_t j = N[q];
-            const double* y = Y + j * d;
             double best = INFINITY, second = INFINITY;
             int64_t arg = -1;
             for (int64_t p = 0; p < mm; ++p) {
                 int64_t i = M[p];
-                double k = key_of(X + i * d, y, d, metric);
+                double k = ground_key(G, i, j);
                 if (k < best) { second = best; best = k; arg = i; }
                 else if (k < second) { second = k; }
             }
@@ -223,7 +248,7 @@ int nnsemd_oracle_solve(const double* X, const double* a, int64_t m,
             int64_t i = nn[j];
             claimant* e = &cl[bucket_fill[i]++];
             e->j = (int32_t)j;
-            e->key = key_of(X + i * d, Y + j * d, d, metric);
+            e->key = ground_key(G, i, j);
             e->rk = nnsemd_oracle_rp_key(seed, t, j);
         }
 
@@ -268,6 +293,49 @@ int nnsemd_oracle_solve(const double* X, const double* a, int64_t m,
     st->status = status;
     free(s); free(c); free(M); free(N); free(nn); free(bucket_start); free(bucket_fill); free(cl);
     return status;
+}
+
+/*
+ * Solve one pair.  X: m x d row-major suppliers, a: m masses; Y: n x d
+ * consumers, b: n masses.  Plan arrays may be NULL (plan_capacity ignored);
+ * otherwise they must hold m + n - 1 entries.  max_rounds <= 0 means m + n.
+ */
+int nnsemd_oracle_solve(const double* X, const double* a, int64_t m,
+                        const double* Y, const double* b, int64_t n,
+                        int32_t d, int32_t metric, int32_t protocol,
+                        uint64_t seed, int64_t max_rounds,
+                        int32_t* plan_src, int32_t* plan_dst,
+                        double* plan_flow, int64_t plan_capacity,
+                        oracle_stats* st) {
+    if (metric < 0 || metric > 2) {
+        memset(st, 0, sizeof(*st));
+        st->status = ORC_ERR_INVALID_ARG;
+        return st->status;
+    }
+    ground_t G = {X, Y, d, metric, NULL, n};
+    return solve_ground(&G, a, m, b, n, protocol, seed, max_rounds, plan_src, plan_dst,
+                        plan_flow, plan_capacity, st);
+}
+
+/*
+ * Solve one pair whose ground distances are given (Algorithm 1's input D):
+ * D is m x n row-major, D[i * n + j] = D_ij, finite and non-negative; the
+ * search, the greedy order and the cost all use D_ij itself.
+ */
+int nnsemd_oracle_solve_cost(const double* D, const double* a, int64_t m,
+                             const double* b, int64_t n, int32_t protocol,
+                             uint64_t seed, int64_t max_rounds,
+                             int32_t* plan_src, int32_t* plan_dst,
+                             double* plan_flow, int64_t plan_capacity,
+                             oracle_stats* st) {
+    ground_t G = {NULL, NULL, 1, ORC_METRIC_GIVEN, D, n};
+    if (D == NULL && m > 0 && n > 0) {
+        memset(st, 0, sizeof(*st));
+        st->status = ORC_ERR_INVALID_ARG;
+        return st->status;
+    }
+    return solve_ground(&G, a, m, b, n, protocol, seed, max_rounds, plan_src, plan_dst,
+                        plan_flow, plan_capacity, st);
 }
 
 /*
@@ -322,5 +390,27 @@ void nnsemd_oracle_barycentric(const int32_t* plan_src, const int32_t* plan_dst,
     for (int64_t i = 0; i < m; ++i)
         for (int k = 0; k < d; ++k)
             out[i * d + k] = w[i] > 0.0 ? out[i * d + k] / w[i] : NAN;
+    free(w);
+}
+
+/*
+ * The other direction (recolouring the source of a colour transfer, where
+ * the source palette consumes): for every consumer j,
+ * T_j = sum_i F_ij x_i / sum_i F_ij, NaN for consumers that received
+ * nothing.  `out` is n x d; sums run in plan order.
+ */
+void nnsemd_oracle_barycentric_dst(const int32_t* plan_src, const int32_t* plan_dst,
+                                   const double* plan_flow, int64_t nnz,
+                                   const double* X, int64_t n, int32_t d, double* out) {
+    double* w = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    for (int64_t j = 0; j < n * d; ++j) out[j] = 0.0;
+    for (int64_t e = 0; e < nnz; ++e) {
+        int64_t i = plan_src[e], j = plan_dst[e];
+        w[j] += plan_flow[e];
+        for (int k = 0; k < d; ++k) out[j * d + k] += plan_flow[e] * X[i * d + k];
+    }
+    for (int64_t j = 0; j < n; ++j)
+        for (int k = 0; k < d; ++k)
+            out[j * d + k] = w[j] > 0.0 ? out[j * d + k] / w[j] : NAN;
     free(w);
 }

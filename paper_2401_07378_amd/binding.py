@@ -25,12 +25,14 @@ PROTOCOLS = {"greedy": 0, "random": 1}
 MODES = {"fp32": 0, "bf16_mfma_refine": 1}
 DTYPES = {"f32": 0, "bf16": 1}
 
-# nnsemd_stats_t as a numpy record (48 bytes, written by the device).
+# nnsemd_stats_t as a numpy record (64 bytes, written by the device).
 STATS_DTYPE = np.dtype([("status", "<i4"), ("rounds", "<i4"), ("nnz", "<i8"), ("work", "<i8"),
-                        ("near_ties", "<i8"), ("residual_src", "<f8"), ("residual_dst", "<f8")])
+                        ("rescored", "<i8"), ("residual_src", "<f8"), ("residual_dst", "<f8"),
+                        ("near_ties_nn", "<i8"), ("near_ties_order", "<i8")])
+STATS_BYTES = STATS_DTYPE.itemsize
 
 EXPORTS = ["nnsemd_create", "nnsemd_destroy", "nnsemd_status_string", "nnsemd_last_error",
-           "emd_approx", "emd_approx_map", "emd_approx_batched",
+           "emd_approx", "emd_approx_map", "emd_approx_batched", "emd_barycentric_map",
            "nnsemd_sg_num_params", "nnsemd_sg_embed", "nnsemd_sg_predict", "nnsemd_sg_loss_grad",
            "nnsemd_sg_train_step", "nnsemd_topk_smallest_f32", "nnsemd_topk_smallest_f64", "nnsemd_sg_retrieve",
            "nnsemd_autotune", "nnsemd_tuning_save", "nnsemd_tuning_load"]
@@ -87,6 +89,8 @@ def load_library():
         lib.emd_approx_map.argtypes = [P, P, P, I64, P, P, I64, I32, I32, I32, ctypes.POINTER(Options),
                                        P, P, P, P, P, I64, P, P]
         lib.emd_approx_map.restype = I32
+        lib.emd_barycentric_map.argtypes = [P, P, P, P, I64, P, P, I64, I32, I64, I32, P, P]
+        lib.emd_barycentric_map.restype = I32
         F32 = ctypes.c_float
         lib.nnsemd_sg_num_params.argtypes = []
         lib.nnsemd_sg_num_params.restype = I64
@@ -167,7 +171,7 @@ def emd_approx(X, a, Y, b, metric: str = "l2", *, plan: bool = True, protocol: s
                path: str = "auto", out: dict | None = None) -> dict:
     """NNS-EMD of one pair on the GPU.  X (m x d) / a (m): suppliers; Y (n x d)
     / b (n): consumers; FP32 CUDA tensors.  Returns device tensors: cost (1,),
-    stats (48 uint8), and with plan=True plan_src/plan_dst/plan_flow of
+    stats (STATS_BYTES uint8), and with plan=True plan_src/plan_dst/plan_flow of
     capacity m + n - 1 (the first stats.nnz entries are the plan).  Runs
     asynchronously on the current stream."""
     import torch
@@ -205,9 +209,10 @@ def emd_approx(X, a, Y, b, metric: str = "l2", *, plan: bool = True, protocol: s
 
 
 def emd_approx_map(X, a, Y, b, metric: str = "l2", *, plan: bool = True, protocol: str = "greedy",
-                   seed: int = 0, max_rounds: int = 0) -> dict:
+                   seed: int = 0, max_rounds: int = 0, path: str = "auto") -> dict:
     """emd_approx plus the per-supplier barycentric map (m x d FP64 device
-    tensor 'map'); multi-workgroup path, returns when the device is done."""
+    tensor 'map').  On chip (asynchronous) when the pair fits one workgroup,
+    else on the multi-workgroup path."""
     import torch
     lib = load_library()
     dev = X.device.index if X.device.index is not None else torch.cuda.current_device()
@@ -225,12 +230,43 @@ def emd_approx_map(X, a, Y, b, metric: str = "l2", *, plan: bool = True, protoco
         src = torch.empty(cap, dtype=torch.int32, device=X.device)
         dst = torch.empty(cap, dtype=torch.int32, device=X.device)
         flow = torch.empty(cap, dtype=torch.float64, device=X.device)
-    opts = _options(protocol, "fp32", max_rounds, seed, 0)
+    opts = _options(protocol, "fp32", max_rounds, seed, 0, path=path)
     st = lib.emd_approx_map(h, _ptr(X), _ptr(a), m, _ptr(Y), _ptr(b), n, d, DTYPES["f32"], METRICS[metric],
                             ctypes.byref(opts), _ptr(cost), _ptr(mp), _ptr(src), _ptr(dst), _ptr(flow),
                             cap if plan else 0, _ptr(stats), _stream(torch, dev))
     _check(lib, h, st)
     return {"cost": cost, "map": mp[:m], "stats": stats, "plan_src": src, "plan_dst": dst, "plan_flow": flow}
+
+
+MAP_SIDES = {"suppliers": 0, "consumers": 1}
+
+
+def barycentric_map(plan_src, plan_dst, plan_flow, P, rows: int, side: str = "suppliers", nnz=None, out=None):
+    """Barycentric map of a device plan (FP64 rows x d).  side 'suppliers':
+    P = consumer points, rows = m; 'consumers': P = supplier points, rows = n.
+    nnz: optional device int64 tensor (or view, e.g. of a stats record) with
+    the number of plan entries in use; default all of them.  Asynchronous."""
+    import torch
+    lib = load_library()
+    dev = _dev_of(P)
+    h = handle(dev)
+    _require(P, torch.float32, "P")
+    for t, nm, dt in ((plan_src, "plan_src", torch.int32), (plan_dst, "plan_dst", torch.int32),
+                      (plan_flow, "plan_flow", torch.float64)):
+        _require(t, dt, nm)
+    d = P.shape[1] if P.dim() == 2 else 1
+    m = out if out is not None else torch.empty((max(rows, 1), d), dtype=torch.float64, device=P.device)
+    st = lib.emd_barycentric_map(h, _ptr(plan_src), _ptr(plan_dst), _ptr(plan_flow), plan_src.numel(), _ptr(nnz),
+                                 _ptr(P), P.shape[0], d, int(rows), MAP_SIDES[side], _ptr(m), _stream(torch, dev))
+    _check(lib, h, st)
+    return m[:rows]
+
+
+def stats_field(stats_tensor, index: int, field: str):
+    """Device view of one int64 field of a stats record (e.g. 'nnz'), to pass
+    as a device count without a host round trip."""
+    off = STATS_DTYPE.fields[field][1] + index * STATS_BYTES
+    return stats_tensor[off:off + 8].view(__import__("torch").int64)
 
 
 def plan_offsets(m_sizes, n_sizes) -> np.ndarray:
@@ -250,7 +286,7 @@ def emd_approx_batched(Xcat, acat, x_off, Ycat, bcat, y_off, *, max_m: int, max_
     pair tables are int64/int32 CUDA tensors; max_m/max_n are host bounds on
     the set sizes.  With plan_off (CUDA int64, num_pairs + 1) the plans are
     written too.  Returns device tensors costs (num_pairs,), stats
-    (num_pairs * 48 uint8) and the plan buffers.  Asynchronous."""
+    (num_pairs * STATS_BYTES uint8) and the plan buffers.  Asynchronous."""
     import torch
     lib = load_library()
     dev = Xcat.device.index if Xcat.device.index is not None else torch.cuda.current_device()

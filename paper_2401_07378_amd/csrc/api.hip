@@ -39,6 +39,10 @@ struct nnsemd_handle {
     char* sg_quant = nullptr;                    // BF16 weight copies of the surrogate
     char* sg_ws = nullptr;                       // surrogate workspace
     size_t sg_bytes = 0;
+    char* map_ws = nullptr;                      // barycentric map: row buckets
+    size_t map_bytes = 0;
+    char* map_plan = nullptr;                    // emd_approx_map: plan and stats when the caller keeps none
+    size_t map_plan_bytes = 0;
 };
 
 namespace {
@@ -335,6 +339,17 @@ nnsemd_status_t run_docs(nnsemd_handle_t h, DocArgs& A, int64_t max_m, int64_t m
     return NNSEMD_OK;
 }
 
+// Whether one pair of FP32 points fits the one-workgroup path.
+bool fits_on_chip(nnsemd_handle_t h, int64_t m, int64_t n, int32_t d, int32_t threads_opt) {
+    const int threads = threads_opt > 0 ? threads_opt : 256;
+    const int64_t maxp = std::max<int64_t>({m, n, 1});
+    const int chunk_cap = threads == 256 ? 16 : 8;
+    const PairLdsLayout lay = pair_lds_layout((int)std::min<int64_t>(std::max<int64_t>(m, 1), 1 << 20),
+                                              (int)std::min<int64_t>(std::max<int64_t>(n, 1), 1 << 20),
+                                              record_stride(std::max(1, std::min(d, 7))), 0, true);
+    return (maxp + threads - 1) / threads <= chunk_cap && lay.total + 8192 <= h->max_lds;
+}
+
 // FP32 points with d <= 7 take the point path; BF16 points (matrix-core
 // mode) and FP32 points with d > 7 take the high-dimensional path.
 bool use_doc_path(int32_t d, nnsemd_dtype_t dtype) { return dtype == NNSEMD_BF16 || d > 7; }
@@ -395,6 +410,34 @@ sg::SgPredictWork sg_predict_carve(char* base, int64_t B) {
 }
 
 constexpr int64_t kSgMaxRows = (int64_t)1 << 30;
+
+// Grow-on-demand device buffer of the handle (contents are not kept).
+nnsemd_status_t grow(nnsemd_handle_t h, char** buf, size_t* cap, size_t bytes, const char* what) {
+    if (*cap >= bytes) return NNSEMD_OK;
+    if (*buf) (void)hipFree(*buf);
+    *buf = nullptr;
+    *cap = 0;
+    if (hipMalloc((void**)buf, bytes) != hipSuccess) {
+        *buf = nullptr;
+        return fail(h, NNSEMD_ERR_OUT_OF_MEMORY, what);
+    }
+    *cap = bytes;
+    return NNSEMD_OK;
+}
+
+// Barycentric map of a device plan; rows and the plan capacity are host
+// values, the number of entries used may be a device count.
+nnsemd_status_t run_map(nnsemd_handle_t h, const int32_t* src, const int32_t* dst, const double* flow, int64_t cap,
+                        const int64_t* nnz, const float* P, int64_t p_rows, int d, int side, int64_t rows,
+                        double* map, void* stream) {
+    if (rows == 0) return NNSEMD_OK;
+    nnsemd_status_t s = grow(h, &h->map_ws, &h->map_bytes, map_ws_bytes(rows, cap), "map workspace");
+    if (s != NNSEMD_OK) return s;
+    const MapWork w = map_ws_carve(h->map_ws, rows, cap);
+    const int err = launch_barycentric_map(src, dst, flow, cap, nnz, P, p_rows, d, side, rows, map, w, stream);
+    if (err != 0) return device_fail(h, err, "barycentric map launch");
+    return NNSEMD_OK;
+}
 
 nnsemd_status_t check_common(nnsemd_handle_t h, int32_t d, nnsemd_dtype_t dtype, nnsemd_metric_t metric,
                              const nnsemd_options_t& o) {
@@ -460,6 +503,8 @@ nnsemd_status_t nnsemd_destroy(nnsemd_handle_t h) {
         if (h->doc_tiles) (void)hipFree(h->doc_tiles);
         if (h->sg_quant) (void)hipFree(h->sg_quant);
         if (h->sg_ws) (void)hipFree(h->sg_ws);
+        if (h->map_ws) (void)hipFree(h->map_ws);
+        if (h->map_plan) (void)hipFree(h->map_plan);
     }
     delete h;
     return NNSEMD_OK;
@@ -522,15 +567,7 @@ nnsemd_status_t emd_approx(nnsemd_handle_t h, const void* X, const float* a, int
         A.stats = stats;
         return run_docs(h, A, m, n, dtype, o, stream);
     }
-    bool multi = o.path == NNSEMD_PATH_MULTI;
-    if (o.path == NNSEMD_PATH_AUTO) {
-        const int threads = o.threads > 0 ? o.threads : 256;
-        const int64_t maxp = std::max<int64_t>({m, n, 1});
-        const int chunk_cap = threads == 256 ? 16 : 8;
-        const PairLdsLayout lay = pair_lds_layout((int)std::max<int64_t>(m, 1), (int)std::max<int64_t>(n, 1),
-                                                  record_stride(std::max(1, std::min(d, 7))), 0, true);
-        multi = (maxp + threads - 1) / threads > chunk_cap || lay.total + 8192 > h->max_lds;
-    }
+    const bool multi = o.path == NNSEMD_PATH_MULTI || (o.path == NNSEMD_PATH_AUTO && !fits_on_chip(h, m, n, d, o.threads));
     if (multi) {
         LPArgs L{};
         L.m = m;
@@ -590,24 +627,87 @@ nnsemd_status_t emd_approx_map(nnsemd_handle_t h, const void* X, const float* a,
     if (use_doc_path(d, dtype))
         return fail(h, NNSEMD_ERR_UNSUPPORTED, "the transport map is computed for FP32 points with d <= 7");
     DeviceGuard g(h->device);
-    LPArgs L{};
-    L.m = m;
-    L.n = n;
-    L.X = static_cast<const float*>(X);
-    L.a = a;
-    L.Y = static_cast<const float*>(Y);
-    L.b = b;
-    L.metric = metric;
-    L.protocol = o.protocol;
-    L.seed = o.seed;
-    L.max_rounds = o.max_rounds;
-    L.cost = cost;
-    L.plan_src = plan ? plan_src : nullptr;
-    L.plan_dst = plan ? plan_dst : nullptr;
-    L.plan_flow = plan ? plan_flow : nullptr;
-    L.stats = stats;
-    L.map = map;
-    return run_large(h, L, d, stream);
+    if (o.path == NNSEMD_PATH_MULTI || (o.path == NNSEMD_PATH_AUTO && !fits_on_chip(h, m, n, d, o.threads))) {
+        // the multi-workgroup path accumulates the map while it serves
+        LPArgs L{};
+        L.m = m;
+        L.n = n;
+        L.X = static_cast<const float*>(X);
+        L.a = a;
+        L.Y = static_cast<const float*>(Y);
+        L.b = b;
+        L.metric = metric;
+        L.protocol = o.protocol;
+        L.seed = o.seed;
+        L.max_rounds = o.max_rounds;
+        L.cost = cost;
+        L.plan_src = plan ? plan_src : nullptr;
+        L.plan_dst = plan ? plan_dst : nullptr;
+        L.plan_flow = plan ? plan_flow : nullptr;
+        L.stats = stats;
+        L.map = map;
+        return run_large(h, L, d, stream);
+    }
+    // On-chip solve into the caller's plan (or the handle's), then the map of
+    // that plan; the entry count is read on the device from the stats.
+    const int64_t cap = std::max<int64_t>(m + n - 1, 1);
+    int32_t* ps = plan_src;
+    int32_t* pd = plan_dst;
+    double* pf = plan_flow;
+    nnsemd_stats_t* st = stats;
+    int64_t pcap = plan ? plan_capacity : cap;
+    if (!plan || stats == nullptr) {
+        const size_t need = align_up(sizeof(nnsemd_stats_t), 256) + (plan ? 0 : align_up(16 * (size_t)cap, 256));
+        if ((s = grow(h, &h->map_plan, &h->map_plan_bytes, need, "map plan scratch")) != NNSEMD_OK) return s;
+        char* base = h->map_plan;
+        if (stats == nullptr) st = reinterpret_cast<nnsemd_stats_t*>(base);
+        if (!plan) {
+            char* pb = base + align_up(sizeof(nnsemd_stats_t), 256);
+            pf = reinterpret_cast<double*>(pb);
+            ps = reinterpret_cast<int32_t*>(pb + 8 * (size_t)cap);
+            pd = ps + cap;
+        }
+    }
+    nnsemd_options_t oc = o;
+    oc.path = NNSEMD_PATH_ON_CHIP;
+    PairSolverArgs A{};
+    A.num_pairs = 1;
+    A.X = static_cast<const float*>(X);
+    A.a = a;
+    A.Y = static_cast<const float*>(Y);
+    A.b = b;
+    A.single_m = m;
+    A.single_n = n;
+    A.metric = metric;
+    A.costs = cost;
+    A.plan_src = ps;
+    A.plan_dst = pd;
+    A.plan_flow = pf;
+    A.single_plan_cap = pcap;
+    A.stats = st;
+    if ((s = run_pairs(h, A, d, m, n, oc, stream)) != NNSEMD_OK) return s;
+    return run_map(h, ps, pd, pf, pcap, &st->nnz, static_cast<const float*>(Y), n, d, NNSEMD_MAP_SUPPLIERS, m, map,
+                   stream);
+}
+
+nnsemd_status_t emd_barycentric_map(nnsemd_handle_t h, const int32_t* plan_src, const int32_t* plan_dst,
+                                    const double* plan_flow, int64_t plan_capacity, const int64_t* plan_nnz,
+                                    const float* P, int64_t p_rows, int32_t d, int64_t rows, nnsemd_map_side_t side,
+                                    double* map, void* stream) {
+    if (h == nullptr) return NNSEMD_ERR_INVALID_ARG;
+    h->last_error.clear();
+    if (side != NNSEMD_MAP_SUPPLIERS && side != NNSEMD_MAP_CONSUMERS)
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "bad map side");
+    if (d < 1 || d > 8) return fail(h, NNSEMD_ERR_UNSUPPORTED, "the map supports 1 <= d <= 8");
+    if (plan_capacity < 0 || p_rows < 0 || rows < 0 || rows > 0x7fffffffLL || p_rows > 0x7fffffffLL ||
+        plan_capacity > 0x7fffffffLL)
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "sizes must be in [0, 2^31)");
+    if (rows > 0 && map == nullptr) return fail(h, NNSEMD_ERR_INVALID_ARG, "map must not be NULL");
+    if (plan_capacity > 0 && (plan_src == nullptr || plan_dst == nullptr || plan_flow == nullptr || P == nullptr))
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "NULL plan or point array");
+    DeviceGuard g(h->device);
+    return run_map(h, plan_src, plan_dst, plan_flow, plan_capacity, plan_nnz, P, p_rows, d, (int)side, rows, map,
+                   stream);
 }
 
 nnsemd_status_t emd_approx_batched(nnsemd_handle_t h, int64_t num_pairs, const void* Xcat, const float* acat,
@@ -901,7 +1001,7 @@ nnsemd_status_t nnsemd_sg_predict(nnsemd_handle_t h, const float* theta, const f
 namespace {
 // Carve the training workspace for B pairs and P points; returns bytes
 // needed (base == nullptr: size only).
-size_t sg_train_carve(char* base, int64_t B, int64_t P, bool own_grad, sg::SgTrainWork& w, float** grad) {
+static size_t sg_train_carve(char* base, int64_t B, int64_t P, bool own_grad, sg::SgTrainWork& w, float** grad) {
     constexpr int64_t Hd = kSgHidden;
     const int64_t Ppad = (P + 63) / 64 * 64, Bpad = (B + 63) / 64 * 64, S = 2 * B;
     const int64_t nblk = std::max<int64_t>(1, (P + 511) / 512);
@@ -949,7 +1049,7 @@ size_t sg_train_carve(char* base, int64_t B, int64_t P, bool own_grad, sg::SgTra
     return align_up(c.off, 256);
 }
 
-nnsemd_status_t sg_loss_grad_common(nnsemd_handle_t h, const float* theta, const float* X, const float* a,
+static nnsemd_status_t sg_loss_grad_common(nnsemd_handle_t h, const float* theta, const float* X, const float* a,
                                     const int64_t* set_off, int64_t num_pairs, int64_t num_points,
                                     const float* labels, float* loss, float** grad, sg::SgQuant& q, void* stream) {
     if (num_pairs < 1 || num_pairs > (1 << 20) || num_points < 1 || num_points > (int64_t)1 << 26)
@@ -1002,7 +1102,7 @@ nnsemd_status_t nnsemd_sg_train_step(nnsemd_handle_t h, float* theta, float* ada
 }
 
 // Top-k scratch of the handle (allocated once).
-nnsemd_status_t topk_workspace(nnsemd_handle_t h) {
+static nnsemd_status_t topk_workspace(nnsemd_handle_t h) {
     if (h->topk_ws) return NNSEMD_OK;
     if (hipMalloc((void**)&h->topk_ws, sg::topk_ws_bytes()) != hipSuccess) {
         h->topk_ws = nullptr;

@@ -31,9 +31,7 @@
 //    the inputs after the rounds (all lanes busy, one pass).
 // The plan is thus the one of the FP64 definition, and R agrees with the
 // sequential FP64 sum up to the summation order.
-#ifndef NNSEMD_CPU_EMULATION
 #include <hip/hip_runtime.h>
-#endif
 #include <math.h>
 #include <stdint.h>
 
@@ -45,13 +43,8 @@ namespace {
 
 using namespace rc;
 
-#ifndef NNSEMD_CPU_EMULATION
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
-#else
-typedef emu_bf16x8 bf16x8;
-typedef emu_f32x4 f32x4;
-#endif
 
 __device__ inline float to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 __device__ inline float to_f32(float v) { return v; }
@@ -549,11 +542,16 @@ __device__ void key_tile_valu(const float* __restrict__ X, const float* __restri
 // Greedy serve order of the claimants (see the file comment): rank of each
 // claimant in its bucket from the full FP32 keys; claimants with an
 // undecided comparison get exact keys and are ranked again.
+// Comparisons closer than the two keys' bounds plus the near-tie window are
+// settled on exact keys, so every pair of neighbours in the final order that
+// may be a near tie carries exact keys, and the near ties of neighbouring
+// claimants are counted on those (ties_order).
 template <int T, typename TIn>
 __device__ inline void rank_greedy_doc(const Lds& L, Shared& sh, int nact, const float* __restrict__ kap,
                                        const float* __restrict__ yn, float rhat, float tscale,
                                        int32_t* __restrict__ amb, const TIn* __restrict__ X,
-                                       const TIn* __restrict__ Y, int d, int64_t& near) {
+                                       const TIn* __restrict__ Y, int d, int metric, int64_t& near,
+                                       int64_t& ties_order) {
     for (int pass = 0; pass < 2; ++pass) {
         const int cnt = pass == 0 ? nact : sh.namb;
         for (int q = threadIdx.x; q < cnt; q += T) {
@@ -575,7 +573,8 @@ __device__ inline void rank_greedy_doc(const Lds& L, Shared& sh, int nact, const
                     if (j2 == j) continue;
                     const float b = kap[j2];
                     const float eb = rhat + yn[j2];
-                    const float tol = ta + tscale * eb * eb;
+                    const float tb = ta + tscale * eb * eb;
+                    const float tol = tb + near_window(fmaxf(a, b) + tb, false);
                     if (b < a - tol) {
                         ++rank;
                     } else if (!(b > a + tol)) {
@@ -607,6 +606,16 @@ __device__ inline void rank_greedy_doc(const Lds& L, Shared& sh, int nact, const
         __syncthreads();
     }
     __syncthreads();
+    // neighbours in serve order: a near tie needs both exact keys (above)
+    for (int e = threadIdx.x; e < nact; e += T) {
+        const int j = L.sorted[e];
+        const int sl = L.cnn[j];
+        if (e > L.soff[sl] - L.scnt[sl]) {
+            const double kp = L.ckey[L.sorted[e - 1]], kj = L.ckey[j];
+            if (kp >= 0.0 && kj >= 0.0 && near_tie_dist(dist_of_key(kp, metric), dist_of_key(kj, metric)))
+                ++ties_order;
+        }
+    }
     if (threadIdx.x == 0) sh.namb = 0;
 }
 
@@ -824,7 +833,8 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
     const int64_t max_rounds = A.max_rounds > 0 ? A.max_rounds : (int64_t)mi + ni;
     int rounds = 0;
     int64_t work = 0, nnz = 0, near = 0;
-    float* flag_b1 = reinterpret_cast<float*>(L.sorted);  // best FP32 key of each flagged consumer
+    int64_t ties_nn = 0, ties_order = 0;  // this thread's near-tie counts
+    float* flag_b1 = reinterpret_cast<float*>(L.sorted);  // re-score cutoff of each flagged consumer
     while (status == NNSEMD_OK && mact > 0 && nact > 0) {
         if (rounds >= max_rounds) {
             status = NNSEMD_ERR_NOT_CONVERGED;
@@ -840,10 +850,11 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
                 const int bl = L.cnn[j];
                 const float e = rhat + yn[j];
                 const float thr = 2.f * tscale * e * e + 1e-30f;
-                if (!(b2 - b1 > thr)) {
+                const float win = thr + near_window(b1 + yy[j] + thr, false);
+                if (!(b2 - b1 > win)) {
                     const int f = atomicAdd(&sh.nflag, 1);
                     L.list[f] = j;
-                    flag_b1[f] = b1;
+                    flag_b1[f] = b1 + win;
                 } else {
                     const int bs = L.soff[bl];
                     L.cnn[j] = bs;
@@ -901,10 +912,11 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
             if (valid && r == 0) {
                 const float e = rhat + yn[j];
                 const float thr = 2.f * tscale * e * e + 1e-30f;
-                if (!(b2 - b1 > thr)) {
+                const float win = thr + near_window(b1 + yy[j] + thr, false);
+                if (!(b2 - b1 > win)) {
                     const int f = atomicAdd(&sh.nflag, 1);
                     L.list[f] = j;
-                    flag_b1[f] = b1;
+                    flag_b1[f] = b1 + win;
                 } else {
                     L.cnn[j] = bs;
                     kap[j] = b1 + yy[j];
@@ -918,28 +930,33 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
         NNSEMD_PH(2)
         const int nf = sh.nflag;
         if (nf > 0) {
-            // Near ties: the FP64 argmin is among the suppliers whose FP32
-            // key is within the threshold of the best one; only those are
-            // re-scored.
+            // Flagged consumers: the FP64 argmin, and any supplier that is a
+            // near tie with it, lie among the suppliers whose FP32 key is at
+            // most the stored cutoff (best + bound + near-tie window); only
+            // those are re-scored.
             for (int f = wave; f < nf; f += NW) {
                 const int j = L.list[f];
-                const float e = rhat + yn[j];
-                const float lim = flag_b1[f] + (2.f * tscale * e * e + 1e-30f);
-                double best = INFINITY;
+                const float lim = flag_b1[f];
+                double best = INFINITY, sec = INFINITY;
                 int bsl = 0x7fffffff;
                 for (int s = lane; s < mact; s += 64) {
                     const int i = L.sidx[s];
                     if (tile[(size_t)i * ni + j] > lim) continue;
                     const double k = dkey64<TIn>(X + (size_t)i * d, Y + (size_t)j * d, d);
                     if (k < best) {
+                        sec = best;
                         best = k;
                         bsl = s;
+                    } else if (k < sec) {
+                        sec = k;
                     }
                 }
 #pragma unroll
                 for (int o = 32; o > 0; o >>= 1) {
                     const double cb = __shfl_xor(best, o);
+                    const double c2 = __shfl_xor(sec, o);
                     const int cs2 = __shfl_xor(bsl, o);
+                    sec = fmin(fmax(best, cb), fmin(sec, c2));
                     if (cb < best || (cb == best && cs2 < bsl)) {
                         best = cb;
                         bsl = cs2;
@@ -950,6 +967,8 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
                     L.ckey[j] = best;
                     kap[j] = tile[(size_t)L.sidx[bsl] * ni + j] + yy[j];
                     atomicAdd(&L.scnt[bsl], 1);
+                    if (mact > 1 && near_tie_dist(dist_of_key(best, A.metric), dist_of_key(sec, A.metric)))
+                        ++ties_nn;
                 }
             }
             near += nf;
@@ -958,7 +977,7 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
         NNSEMD_PH(3)
         round_buckets<T>(L, sh, mact, nact);
         if (A.protocol == NNSEMD_GREEDY)
-            rank_greedy_doc<T, TIn>(L, sh, nact, kap, yn, rhat, tscale, amb, X, Y, d, near);
+            rank_greedy_doc<T, TIn>(L, sh, nact, kap, yn, rhat, tscale, amb, X, Y, d, A.metric, near, ties_order);
         else
             round_rank<T>(L, nact, A.protocol, A.seed, rounds);
         NNSEMD_PH(4)
@@ -970,8 +989,8 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
         ++rounds;
     }
 
-    double fin[3] = {0.0, 0.0, 0.0};
-    const int fop[3] = {0, 0, 0};
+    double fin[5] = {0.0, 0.0, 0.0, (double)ties_nn, (double)ties_order};
+    const int fop[5] = {0, 0, 0, 0, 0};
     if (status == NNSEMD_OK || status == NNSEMD_ERR_NOT_CONVERGED) {
         for (int s = tid; s < mact; s += T) fin[1] += L.smass[s];
         for (int q = tid; q < nact; q += T) fin[2] += L.cmass[L.cact[q]];
@@ -1040,7 +1059,7 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
         for (int e = tid; e < ne; e += T) fin[0] += contrib[e];
     }
     NNSEMD_PH(7)
-    block_reduce<T, 3>(fin, fop, &sh.red[0][0]);
+    block_reduce<T, 5>(fin, fop, &sh.red[0][0]);
     if (tid == 0) {
         A.costs[p] = status == NNSEMD_OK ? fin[0] : NAN;
         if (A.stats != nullptr) {
@@ -1049,9 +1068,11 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
             st.rounds = rounds;
             st.nnz = nnz;
             st.work = work;
-            st.near_ties = near;
+            st.rescored = near;
             st.residual_src = fin[1];
             st.residual_dst = fin[2];
+            st.near_ties_nn = (int64_t)fin[3];
+            st.near_ties_order = (int64_t)fin[4];
             A.stats[p] = st;
         }
     }
@@ -1149,7 +1170,6 @@ __device__ void doc_tile_pair(const DocArgs& A, int64_t p, char* __restrict__ sl
 #endif
 }
 
-#ifndef NNSEMD_CPU_EMULATION
 // Norm pass of the split form: every row (up to max_m) of every supplier
 // set, 16 lanes per row; blockIdx.x = set * chunks + chunk.  The suppliers
 // are shared by many pairs (one query against candidates), so their norms
@@ -1220,7 +1240,6 @@ int doc_launch_typed(const DocArgs& A, size_t lds, int grid, hipStream_t st, boo
     return (int)hipGetLastError();
 }
 
-#endif  // NNSEMD_CPU_EMULATION
 
 }  // namespace
 
@@ -1233,7 +1252,6 @@ bool doc_split_form(int d, bool bf16_mfma, int chunk_max) {
     return bf16_mfma && chunk_max <= 4 && (d + 31) / 32 <= kStripeKSteps;
 }
 
-#ifndef NNSEMD_CPU_EMULATION
 int launch_doc_xnorm(const DocArgs& A, void* stream) {
     constexpr int T = 256;
     const int chunks = (A.max_m + T / 16 - 1) / (T / 16);
@@ -1260,6 +1278,5 @@ int launch_doc_solver(const DocArgs& A, bool bf16_mfma, int chunk_max, size_t ld
     }
     return (int)hipErrorInvalidValue;
 }
-#endif  // NNSEMD_CPU_EMULATION
 
 }  // namespace nnsemd

@@ -102,6 +102,7 @@ __host__ __device__ inline PairLdsLayout pair_lds_layout(int M, int N, int rs, i
 struct LPState {
     int32_t status, mact, nact, nflag;
     int64_t nnz, work, near;
+    int64_t ties_nn, ties_order;  // near-tie counters (see nnsemd_stats_t)
     int32_t rounds, done, parity, ticket;  // ticket: blocks of the round's last kernel that have finished
     float centre[8];
     float rhat, pad1;
@@ -278,6 +279,24 @@ int launch_gather_ranked(const int32_t* pos, const int32_t* sel, const double* v
 int launch_fill_i32(int32_t* p, int64_t n, int32_t v, void* stream);
 int launch_two_offsets(int64_t* off, int64_t m, void* stream);
 }  // namespace sg
+
+// ---------------------------------------------------------------------
+// Barycentric map of a plan (transport_map.hip): per-row buckets of plan
+// positions, so every row is summed in plan order.
+struct MapWork {
+    int32_t* cnt;     // [rows] entries per row
+    int32_t* start;   // [rows] bucket start
+    int32_t* cursor;  // [rows] scatter cursor
+    int32_t* big;     // [rows] rows handled by a wavefront
+    int32_t* ent;     // [cap] plan positions by row
+    int32_t* nbig;    // [1]
+};
+size_t map_ws_bytes(int64_t rows, int64_t cap);
+MapWork map_ws_carve(char* base, int64_t rows, int64_t cap);
+// side 0: rows are suppliers (P = consumer points), 1: rows are consumers.
+int launch_barycentric_map(const int32_t* src, const int32_t* dst, const double* flow, int64_t cap,
+                           const int64_t* nnz, const float* P, int64_t p_rows, int d, int side, int64_t rows,
+                           double* map, const MapWork& w, void* stream);
 
 // Launch entry points (defined in pair_solver.hip).
 // Returns hipSuccess-compatible int (0 on success).

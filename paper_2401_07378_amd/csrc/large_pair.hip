@@ -54,6 +54,37 @@ __device__ inline double lp_key64(const float* __restrict__ x, const float* __re
     return acc;
 }
 
+// Search gap bound of the FP32 keys, as in the one-workgroup path: one key
+// of a consumer is within B = (2D + 2) u e^2 (e = rhat + ||y^||) of
+// ||x - y||^2 - ||y^||^2 -- D roundings of the record's norm, D of the FMA
+// chain, 2u e^2 from centring both points -- so a wrong FP32 argmin needs a
+// second key within 2B of the best; the threshold 4B = 8 (D + 1) u e^2 leaves
+// a factor 2.  L1 keys: relative error D u each, threshold 4 (D + 1) u b1.
+template <int D>
+__device__ inline float lp_gap_bound(float rhat, float yn2) {
+    const float e = rhat + sqrtf(yn2);
+    return 8.f * (float)(D + 1) * kU32 * e * e + 1e-30f;
+}
+
+template <int D>
+__device__ inline float lp_gap_bound_l1(float b1) {
+    return 4.f * (float)(D + 1) * kU32 * b1 + 1e-30f;
+}
+
+// Near tie: two distances whose gap is at most 1e-6 relative (1e-12 at 0).
+__device__ inline bool lp_near_tie(double d1, double d2) {
+    const double gap = d2 - d1;
+    return d1 == 0.0 ? gap <= 1e-12 : gap <= 1e-6 * d1;
+}
+
+// Key-space width past the bound in which a near tie may hide (squared keys:
+// a 1e-6 distance gap is at most (2e-6 + 1e-12) of the squared distance).
+__device__ inline float lp_near_window(float kmax, bool l1) {
+    return (l1 ? 1.1e-6f : 2.2e-6f) * fmaxf(kmax, 0.f) + 1e-12f;
+}
+
+__device__ inline double lp_dist(double key, int metric) { return metric == NNSEMD_L2 ? sqrt(key) : key; }
+
 __device__ inline uint64_t lp_rp_key(uint64_t seed, int64_t round, int32_t j) {
     uint64_t ctr = ((uint64_t)round << 32) ^ (uint64_t)(uint32_t)j;
     uint64_t z = seed + (ctr + 1u) * 0x9E3779B97F4A7C15ull;
@@ -299,6 +330,8 @@ __global__ __launch_bounds__(kLpScanThreads) void lp_setup(LPArgs A, int nblocks
         st->nnz = 0;
         st->work = 0;
         st->near = 0;
+        st->ties_nn = 0;
+        st->ties_order = 0;
         st->rounds = 0;
         st->ticket = 0;
         st->parity = 1;
@@ -460,9 +493,11 @@ __global__ __launch_bounds__(kLpThreads) void lp_decide(LPArgs A, int split) {
     }
     const bool live = valid && sub == 0;
     const int j = live ? A.w.cact[par][q] : 0;
-    float thr;
+    // Gap threshold: the proven per-key bound B taken twice, with a factor 2
+    // of margin (derivation at lp_gap_bound), plus the near-tie window.
+    float win;
     if (L1) {
-        thr = 4.f * (float)(D + 1) * kU32 * b2 + 1e-30f;
+        win = lp_gap_bound_l1<D>(b1) + lp_near_window(b1, true);
     } else {
         float yn2 = 0.f;
 #pragma unroll
@@ -470,17 +505,18 @@ __global__ __launch_bounds__(kLpThreads) void lp_decide(LPArgs A, int split) {
             const float yv = A.Y[(int64_t)j * D + t] - st->centre[t];
             yn2 = fmaf(yv, yv, yn2);
         }
-        const float e = st->rhat + sqrtf(yn2);
-        thr = 32.f * kU32 * e * e + 1e-30f;
+        const float thr = lp_gap_bound<D>(st->rhat, yn2);
+        win = thr + lp_near_window(b1 + yn2 + thr, false);
     }
-    const bool near = live && !(b2 - b1 > thr);
+    const bool near = live && !(b2 - b1 > win);
     const bool pick = live && !near;
-    // The FP64 argmin's FP32 key is within half the threshold of b1 (two
-    // per-key bounds), so b1 + thr bounds the candidates of the re-score.
+    // The FP64 argmin's FP32 key lies within 2B of b1 (half the bound part of
+    // win), and a supplier that is a near tie with it within 2B + the window,
+    // so b1 + win bounds every candidate the re-score must see.
     const int f = lp_count_rank(&st->nflag, 0, near);
     if (near) {
         A.w.flagged[f] = j;
-        A.w.ckey[j] = (double)(b1 + thr);
+        A.w.ckey[j] = (double)(b1 + win);
     }
     // rank within the pick's bucket (sorted is free until the serve)
     const int r = lp_count_rank(A.w.scnt, pick ? bs : 0, pick);
@@ -506,6 +542,7 @@ __global__ __launch_bounds__(kLpRescoreThreads) void lp_rescore(LPArgs A) {
     constexpr int RS = record_stride(D);
     constexpr int NW = kLpRescoreThreads / kWave;
     __shared__ double sk[NW];
+    __shared__ double s2[NW];
     __shared__ int ss[NW];
     LPState* st = A.w.st;
     if (!lp_live(st)) return;
@@ -520,7 +557,7 @@ __global__ __launch_bounds__(kLpRescoreThreads) void lp_rescore(LPArgs A) {
         float y[D];
 #pragma unroll
         for (int t = 0; t < D; ++t) y[t] = L1 ? yp[t] : yp[t] - st->centre[t];
-        double best = INFINITY;
+        double best = INFINITY, sec = INFINITY;
         int bsl = 0x7fffffff;
         for (int s0 = tid; s0 < mact; s0 += kLpRescoreThreads * kLpRescoreUnroll) {
             float key[kLpRescoreUnroll];
@@ -555,8 +592,11 @@ __global__ __launch_bounds__(kLpRescoreThreads) void lp_rescore(LPArgs A) {
                 if (s < mact && !(key[u] > cut)) {
                     const double k = lp_key64<D, L1>(A.X + (int64_t)sidx[s] * D, yp);
                     if (k < best) {  // slots rise along the thread's walk: ties keep the first
+                        sec = best;
                         best = k;
                         bsl = s;
+                    } else if (k < sec) {
+                        sec = k;
                     }
                 }
             }
@@ -564,7 +604,9 @@ __global__ __launch_bounds__(kLpRescoreThreads) void lp_rescore(LPArgs A) {
 #pragma unroll
         for (int o = kWave / 2; o > 0; o >>= 1) {
             const double cb = __shfl_xor(best, o);
+            const double c2 = __shfl_xor(sec, o);
             const int cs = __shfl_xor(bsl, o);
+            sec = fmin(fmax(best, cb), fmin(sec, c2));
             if (cb < best || (cb == best && cs < bsl)) {
                 best = cb;
                 bsl = cs;
@@ -573,18 +615,25 @@ __global__ __launch_bounds__(kLpRescoreThreads) void lp_rescore(LPArgs A) {
         if (lane == 0) {
             sk[w] = best;
             ss[w] = bsl;
+            s2[w] = sec;
         }
         __syncthreads();
         if (tid == 0) {
 #pragma unroll
-            for (int k = 1; k < NW; ++k)
+            for (int k = 1; k < NW; ++k) {
+                sec = fmin(fmax(best, sk[k]), fmin(sec, s2[k]));
                 if (sk[k] < best || (sk[k] == best && ss[k] < bsl)) {
                     best = sk[k];
                     bsl = ss[k];
                 }
+            }
             A.w.cnn[j] = bsl;
             A.w.ckey[j] = best;
             A.w.sorted[j] = atomicAdd(&A.w.scnt[bsl], 1);
+            // The second-nearest supplier is among the survivors of the cut
+            // whenever it is a near tie with the nearest one.
+            if (mact > 1 && lp_near_tie(lp_dist(best, A.metric), lp_dist(sec, A.metric)))
+                atomicAdd((unsigned long long*)&st->ties_nn, 1ull);
         }
         __syncthreads();
     }
@@ -680,6 +729,43 @@ __global__ __launch_bounds__(kLpThreads) void lp_scatter(LPArgs A) {
     if (q >= st->nact) return;
     const int j = A.w.cact[st->parity][q];
     A.w.list[A.w.soff[A.w.cnn[j]] + A.w.sorted[j]] = j;
+}
+
+// ------------------------------------------------------------------ ties
+// Greedy protocol: near ties of neighbouring claimants in each supplier's
+// serve order, over the whole bucket (served or not).  One thread per
+// claimant finds its predecessor in (key, j) order -- the largest bucket
+// member below it -- by a scan of the bucket, and counts a near tie of the
+// two distances.  Keys are the exact FP64 keys the decide / re-score stored.
+__global__ __launch_bounds__(kLpThreads) void lp_ties(LPArgs A) {
+    const LPState* st = A.w.st;
+    if (!lp_live(st)) return;
+    const int q = blockIdx.x * kLpThreads + threadIdx.x;
+    const int nact = st->nact;
+    int hit = 0;
+    if (q < nact) {
+        const int j = A.w.cact[st->parity][q];
+        const int s = A.w.cnn[j];
+        const int c = A.w.scnt[s];
+        if (c > 1) {
+            const int start = A.w.soff[s];
+            const double k = A.w.ckey[j];
+            double pk = -INFINITY;
+            bool any = false;
+            for (int e = start; e < start + c; ++e) {
+                const int j2 = A.w.list[e];
+                const double k2 = A.w.ckey[j2];
+                if (k2 < k || (k2 == k && j2 < j)) {
+                    pk = fmax(pk, k2);
+                    any = true;
+                }
+            }
+            hit = any && lp_near_tie(lp_dist(pk, A.metric), lp_dist(k, A.metric));
+        }
+    }
+    const unsigned long long m = __ballot(hit != 0);
+    if ((threadIdx.x & (kWave - 1)) == 0 && m != 0ull)
+        atomicAdd((unsigned long long*)&A.w.st->ties_order, (unsigned long long)__popcll(m));
 }
 
 // ----------------------------------------------------------------- serve
@@ -1002,9 +1088,11 @@ __global__ __launch_bounds__(kLpScanThreads) void lp_finish(LPArgs A) {
             out.rounds = st->rounds;
             out.nnz = st->nnz;
             out.work = st->work;
-            out.near_ties = st->near;
+            out.rescored = st->near;
             out.residual_src = rs;
             out.residual_dst = rc;
+            out.near_ties_nn = st->ties_nn;
+            out.near_ties_order = st->ties_order;
             A.stats[0] = out;
         }
     }
@@ -1073,6 +1161,7 @@ int lp_launch_round(const LPArgs& A, int d, int mact_ub, int nact_ub, void* stre
         }
         hipLaunchKernelGGL(lp_offsets, dim3(1), dim3(kLpScanThreads), 0, st, A);
         hipLaunchKernelGGL(lp_scatter, dim3(qblocks), dim3(kLpThreads), 0, st, A);
+        if (A.protocol == NNSEMD_GREEDY) hipLaunchKernelGGL(lp_ties, dim3(qblocks), dim3(kLpThreads), 0, st, A);
         hipLaunchKernelGGL(lp_serve<DD>, dim3(wblocks), dim3(kLpThreads), 0, st, A);
         if (cmblocks > 1) hipLaunchKernelGGL(lp_ccount, dim3(cmblocks), dim3(kLpThreads), 0, st, A);
         hipLaunchKernelGGL(lp_cwrite<DD>, dim3(cmblocks), dim3(kLpThreads), 0, st, A);

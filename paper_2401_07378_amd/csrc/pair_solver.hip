@@ -22,9 +22,7 @@
 //      contiguous chunks, wavefront shuffles, one LDS hop).
 // One launch covers any number of ragged pairs, one workgroup each (the
 // batching of Sec. III-D without padding).
-#ifndef NNSEMD_CPU_EMULATION
 #include <hip/hip_runtime.h>
-#endif
 #include <math.h>
 #include <stdint.h>
 
@@ -53,6 +51,30 @@ __device__ inline double key64(const float* __restrict__ x, const float* __restr
             acc = acc + diff * diff;
     }
     return acc;
+}
+
+// Search gap bound (Euclidean metrics).  With x^ = fl(x - c), y^ = fl(y - c)
+// (c the FP32 centre of the supplier box), the record (-2 x^, fl(||x^||^2))
+// and the FMA chain key = ||x^||^2 + sum_t (-2 x^_t) y^_t, one key differs
+// from ||x - y||^2 - ||y^||^2 by at most B = (2D + 2) u e^2 to first order,
+// e = ||x^|| + ||y^|| <= rhat + ||y^|| (u = 2^-24): D roundings in the norm
+// (<= D u ||x^||^2), D in the chain (<= D u (||x^||^2 + 2 ||x^|| ||y^||)) and
+// 2u e^2 from the two centring subtractions.  If the FP32 argmin were not
+// the FP64 one, some other key would lie within 2B of the best, so the
+// threshold 2 x 2B = 8 (D + 1) u e^2 leaves a factor 2 for second-order
+// terms, the FP64 reference's own rounding and the rounding of e.
+template <int D>
+__device__ inline float search_gap_bound(float rhat, float yn2) {
+    const float e = rhat + sqrtf(yn2);
+    return 8.f * (float)(D + 1) * kU32 * e * e + 1e-30f;
+}
+
+// L1 keys sum D rounded |x_t - y_t| terms (no centring): relative error at
+// most D u of the key, so two keys of one consumer can disagree with their
+// FP64 order only within 2 D u b1; 4 (D + 1) u b1 leaves a factor 2.
+template <int D>
+__device__ inline float search_gap_bound_l1(float b1) {
+    return 4.f * (float)(D + 1) * kU32 * b1 + 1e-30f;
 }
 
 template <int D, int RS, bool L1>
@@ -155,14 +177,17 @@ __device__ inline void nns_pass(const Lds16& L, SharedCore& sh, const float* __r
     int pick[KC];
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
-        float thr;
+        // win: the proven search bound (see search_gap_bound) plus the window
+        // in which the two nearest suppliers may still be a near tie.
+        float win;
         if (L1) {
-            thr = 4.f * (float)(D + 1) * kU32 * b2[k] + 1e-30f;
+            const float thr = search_gap_bound_l1<D>(b1[k]);
+            win = thr + near_window(b1[k], true);
         } else {
-            const float e = rhat + sqrtf(yn2[k]);
-            thr = 32.f * kU32 * e * e + 1e-30f;
+            const float thr = search_gap_bound<D>(rhat, yn2[k]);
+            win = thr + near_window(b1[k] + yn2[k] + thr, false);
         }
-        flag[k] = !(b2[k] - b1[k] > thr);
+        flag[k] = !(b2[k] - b1[k] > win);
         pick[k] = flag[k] ? 0 : bs[k];
     }
 #pragma unroll
@@ -346,6 +371,7 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds16& L, S
     const int64_t max_rounds = A.max_rounds > 0 ? A.max_rounds : (int64_t)mi + ni;
     int rounds = 0;
     int64_t work = 0, nnz = 0, near = 0;
+    int64_t ties_nn = 0, ties_order = 0;  // this thread's near-tie counts
     double cost = 0.0;  // this thread's part of R
     while (status == NNSEMD_OK && mact > 0 && nact > 0) {
         if (rounds >= max_rounds) {
@@ -383,23 +409,30 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds16& L, S
         NNSEMD_PH(1)
         const int nf = sh.nflag;
         if (nf > 0) {
-            // FP64 re-score of near-tie consumers, one wavefront per consumer.
+            // FP64 re-score of the flagged consumers, one wavefront per
+            // consumer: the argmin (ties to the smallest slot) and the
+            // second-smallest key decide the pick and the near-tie count.
             for (int f = wave; f < nf; f += NW) {
                 const int j = L.list[f];
                 const float* yp = Y + (size_t)j * D;
-                double best = INFINITY;
+                double best = INFINITY, sec = INFINITY;
                 int bsl = 0x7fffffff;
                 for (int s = lane; s < mact; s += kWave) {
                     const double k = key64<D, L1>(X + (size_t)L.sidx[s] * D, yp);
                     if (k < best) {
+                        sec = best;
                         best = k;
                         bsl = s;
+                    } else if (k < sec) {
+                        sec = k;
                     }
                 }
 #pragma unroll
                 for (int o = kWave / 2; o > 0; o >>= 1) {
                     const double cb = __shfl_xor(best, o);
+                    const double c2 = __shfl_xor(sec, o);
                     const int cs2 = __shfl_xor(bsl, o);
+                    sec = fmin(fmax(best, cb), fmin(sec, c2));
                     if (cb < best || (cb == best && cs2 < bsl)) {
                         best = cb;
                         bsl = cs2;
@@ -409,6 +442,8 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds16& L, S
                     L.cnn[j] = bsl;
                     L.ckey[j] = best;
                     cnt_add(L.scnt, bsl);
+                    if (mact > 1 && near_tie_dist(dist_of_key(best, A.metric), dist_of_key(sec, A.metric)))
+                        ++ties_nn;
                 }
             }
             near += nf;
@@ -422,7 +457,7 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds16& L, S
         // ---- 3. flow & cost: claimant order, then the serve walk
         round_rank<T, CSMAX>(L, nact, A.protocol, A.seed, rounds);
         NNSEMD_PH(5)
-        round_walk<T>(L, mact, A.metric, cost);
+        round_walk<T>(L, mact, A.metric, cost, A.protocol == NNSEMD_GREEDY, &ties_order);
         NNSEMD_PH(6)
         // ---- 4. weights update: plan append + compaction
         round_compact<T, CSMAX, RS>(L, sh, mact, nact, nnz, want_plan ? A.plan_src : nullptr, A.plan_dst,
@@ -432,13 +467,13 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds16& L, S
     }
 
     // ---------------------------------------------------------- results
-    double fin[3] = {cost, 0.0, 0.0};
-    const int fop[3] = {0, 0, 0};
+    double fin[5] = {cost, 0.0, 0.0, (double)ties_nn, (double)ties_order};
+    const int fop[5] = {0, 0, 0, 0, 0};
     if (status == NNSEMD_OK || status == NNSEMD_ERR_NOT_CONVERGED) {
         for (int s = tid; s < mact; s += T) fin[1] += L.smass[s];
         for (int q = tid; q < nact; q += T) fin[2] += L.cmass[L.cact[q]];
     }
-    block_reduce<T, 3>(fin, fop, L.ckey);
+    block_reduce<T, 5>(fin, fop, L.ckey);
     NNSEMD_PH(8)
     NNSEMD_PH_FLUSH(A.phase_cycles)
     if (tid == 0) {
@@ -449,15 +484,16 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds16& L, S
             st.rounds = rounds;
             st.nnz = nnz;
             st.work = work;
-            st.near_ties = near;
+            st.rescored = near;
             st.residual_src = fin[1];
             st.residual_dst = fin[2];
+            st.near_ties_nn = (int64_t)fin[3];
+            st.near_ties_order = (int64_t)fin[4];
             A.stats[p] = st;
         }
     }
 }
 
-#ifndef NNSEMD_CPU_EMULATION
 // One workgroup per pair: the hardware dispatcher hands out workgroups as
 // earlier ones retire, which balances ragged pairs without a software queue.
 // (A persistent loop whose head is a thread-0-only queue fetch must not be
@@ -589,10 +625,8 @@ int dispatch_all(bool run, const PairSolverArgs& A, int d, int threads, int chun
                   : dispatch_cl<false>(run, A, d, threads, chunk_max, lds, grid, st, blocks);
 }
 
-#endif  // NNSEMD_CPU_EMULATION
 }  // namespace
 
-#ifndef NNSEMD_CPU_EMULATION
 int launch_pair_solver(const PairSolverArgs& args, int d, int threads, int chunk_max, bool coords, size_t lds_bytes,
                        int grid, void* stream) {
     return dispatch_all(true, args, d, threads, chunk_max, lds_bytes, grid, (hipStream_t)stream, nullptr, coords);
@@ -612,6 +646,5 @@ int pair_solver_blocks_per_cu(int d, int metric, int threads, int chunk_max, siz
     return dispatch_all(false, A, d, threads, chunk_max, lds_bytes, 0, nullptr, blocks, coords);
 }
 
-#endif  // NNSEMD_CPU_EMULATION
 
 }  // namespace nnsemd

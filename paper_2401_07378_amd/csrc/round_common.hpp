@@ -114,6 +114,23 @@ __device__ inline double dist_of_key(double key, int metric) {
     return metric == NNSEMD_L2 ? sqrt(key) : key;
 }
 
+// Near tie of two distances d1 <= d2 (FP64): a gap of at most 1e-6 relative,
+// or at most 1e-12 when d1 is 0.
+__device__ inline bool near_tie_dist(double d1, double d2) {
+    const double gap = d2 - d1;
+    return d1 == 0.0 ? gap <= 1e-12 : gap <= 1e-6 * d1;
+}
+
+// Width, in FP32 key units, of the window past the proven search bound in
+// which two keys may still be a near tie.  Squared keys: the distances'
+// relative gap 1e-6 is a key gap of at most (2e-6 + 1e-12) of the smaller
+// squared distance (2.2e-6 bounds it with room for the FP32 roundings); L1
+// keys are distances (1.1e-6).  kmax bounds the larger true key; the 1e-12
+// covers the absolute rule at zero distance.
+__device__ inline float near_window(float kmax, bool l1) {
+    return (l1 ? 1.1e-6f : 2.2e-6f) * fmaxf(kmax, 0.f) + 1e-12f;
+}
+
 // SplitMix64 output function of the counter (seed, round, consumer): the
 // random protocol's serve order key.
 __device__ inline uint64_t rp_key(uint64_t seed, int64_t round, int32_t j) {
@@ -294,29 +311,51 @@ __device__ inline void round_rank(const LT& L, int nact, int protocol, uint64_t 
 // ---- flow & cost: one lane per claimed supplier walks its ordered
 // claimants while it still holds mass.  A served claimant records the local
 // index of its supplier (for the plan) and its flow in place of its key; an
-// unserved one gets flow 0.  With COST, `cost` accumulates this thread's part
-// of R from the exact keys; without, R is left to the caller.
+// unserved one gets flow 0.  With COST (the keys are the exact FP64 keys),
+// `cost` accumulates this thread's part of R, and with `ties` (greedy order)
+// `ties_order` counts neighbouring claimants whose distances are a near tie;
+// without COST, R and the tie count are left to the caller.
 template <int T, bool COST = true, typename LT>
-__device__ inline void round_walk(const LT& L, int mact, int metric, double& cost) {
+__device__ inline void round_walk(const LT& L, int mact, int metric, double& cost, bool ties = false,
+                                  int64_t* ties_order = nullptr) {
     for (int s = threadIdx.x; s < mact; s += T) {
         const int c = L.scnt[s];
         if (c == 0) continue;
         const int end = L.soff[s];
+        const int start = end - c;
         const int isup = L.sidx[s];
-        int pos = end - c;
+        int pos = start;
         double sm = L.smass[s];
+        double prev = 0.0;  // distance of the previous claimant in the order
         while (pos < end && sm > 0.0) {
             const int j = L.sorted[pos];
             const double cm = L.cmass[j];
             const double f = sm < cm ? sm : cm;
             sm = sm - f;
             L.cmass[j] = cm - f;
-            if constexpr (COST) cost = cost + f * dist_of_key(L.ckey[j], metric);
+            if constexpr (COST) {
+                const double dj = dist_of_key(L.ckey[j], metric);
+                cost = cost + f * dj;
+                if (ties) {
+                    if (pos > start && near_tie_dist(prev, dj)) ++*ties_order;
+                    prev = dj;
+                }
+            }
             L.ckey[j] = f;
             L.cnn[j] = isup;
             ++pos;
         }
-        for (int e = pos; e < end; ++e) L.ckey[L.sorted[e]] = 0.0;
+        for (int e = pos; e < end; ++e) {
+            const int j = L.sorted[e];
+            if constexpr (COST) {
+                if (ties) {
+                    const double dj = dist_of_key(L.ckey[j], metric);
+                    if (e > start && near_tie_dist(prev, dj)) ++*ties_order;
+                    prev = dj;
+                }
+            }
+            L.ckey[j] = 0.0;
+        }
         L.smass[s] = sm;
     }
     __syncthreads();

@@ -113,9 +113,10 @@ def gpu_pair_map(X, a, Y, b, metric="l2", **kw):
     return out
 
 
-def assert_pair_matches(g, ref, rel=1e-12, plan=True, label=""):
-    """GPU result g vs oracle ref: status, rounds, work, nnz equal; plan
-    bit-identical; cost within rel (summation order differs)."""
+def assert_pair_matches(g, ref, rel=1e-12, plan=True, label="", ties=True):
+    """GPU result g vs oracle ref: status, rounds, work, nnz and the near-tie
+    counters equal; plan bit-identical; cost within rel (summation order
+    differs)."""
     st = g["stats"]
     assert int(st["status"]) == ref["status"], (label, int(st["status"]), ref["status"])
     if ref["status"] != 0:
@@ -127,6 +128,11 @@ def assert_pair_matches(g, ref, rel=1e-12, plan=True, label=""):
     assert abs(c - ref["cost"]) <= rel * max(abs(ref["cost"]), 1e-300), (label, c, ref["cost"])
     assert abs(float(st["residual_src"]) - ref["residual_src"]) <= 1e-12
     assert abs(float(st["residual_dst"]) - ref["residual_dst"]) <= 1e-12
+    if ties:
+        # near ties (gap <= 1e-6 relative): counted, and equal to the oracle's
+        assert int(st["near_ties_nn"]) == ref["near_ties_nn"], (label, int(st["near_ties_nn"]), ref["near_ties_nn"])
+        assert int(st["near_ties_order"]) == ref["near_ties_order"], \
+            (label, int(st["near_ties_order"]), ref["near_ties_order"])
     if plan:
         np.testing.assert_array_equal(g["src"], ref["src"], err_msg=label)
         np.testing.assert_array_equal(g["dst"], ref["dst"], err_msg=label)

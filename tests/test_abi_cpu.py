@@ -33,9 +33,11 @@ def test_status_strings_without_gpu():
 
 
 def test_stats_record_layout():
-    # int32 status, int32 rounds, int64 nnz, work, near_ties, double x2
-    assert binding.STATS_DTYPE.itemsize == 48
+    # int32 status, int32 rounds, int64 nnz, work, rescored, double x2,
+    # int64 near_ties_nn, near_ties_order
+    assert binding.STATS_DTYPE.itemsize == 64
     assert binding.STATS_DTYPE.fields["residual_dst"][1] == 40
+    assert binding.STATS_DTYPE.fields["near_ties_order"][1] == 56
     assert ctypes.sizeof(binding.Options) == 40
 
 

@@ -47,7 +47,7 @@ def test_batched_point_pairs_graph_replay():
     po = to_dev(binding.plan_offsets(m, n))
     total = int(binding.plan_offsets(m, n)[-1])
     bufs = {"costs": torch.empty(96, dtype=torch.float64, device="cuda"),
-            "stats": torch.empty(96 * 48, dtype=torch.uint8, device="cuda"),
+            "stats": torch.empty(96 * binding.STATS_BYTES, dtype=torch.uint8, device="cuda"),
             "plan_src": torch.empty(total, dtype=torch.int32, device="cuda"),
             "plan_dst": torch.empty(total, dtype=torch.int32, device="cuda"),
             "plan_flow": torch.empty(total, dtype=torch.float64, device="cuda"), "plan_total": total}
@@ -68,7 +68,7 @@ def test_batched_documents_graph_replay():
     X, Y = to_dev_bf16(ps.X_bits), to_dev_bf16(ps.Y_bits)
     a, xo, b, yo, px, py = (to_dev(v) for v in (ps.a, ps.x_off, ps.b, ps.y_off, ps.pair_x, ps.pair_y))
     bufs = {"costs": torch.empty(40, dtype=torch.float64, device="cuda"),
-            "stats": torch.empty(40 * 48, dtype=torch.uint8, device="cuda")}
+            "stats": torch.empty(40 * binding.STATS_BYTES, dtype=torch.uint8, device="cuda")}
 
     def call():
         r = binding.emd_approx_batched(X, a, xo, Y, b, yo, pair_x=px, pair_y=py, max_m=int(m.max()),

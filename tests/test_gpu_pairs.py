@@ -64,7 +64,7 @@ def test_lattice_ties(seed):
     FP64 re-score path decides them by the smallest index."""
     X, a, Y, b = W.random_pair(60 + seed, 200, 240, 2, masses="integer", lattice=6)
     g = gpu_pair(X, a, Y, b)
-    assert int(g["stats"]["near_ties"]) > 0
+    assert int(g["stats"]["rescored"]) > 0
     assert_pair_matches(g, oracle_pair(X, a, Y, b), label=f"lattice{seed}")
 
 
@@ -278,3 +278,58 @@ def test_autotune_records_a_configuration_and_keeps_results(tmp_path):
     bad.write_text("nnsemd-tuning 1\n3 0 2 384 2 1.0\n")
     with pytest.raises(binding.NNSEMDError):
         binding.tuning_load(str(bad))
+
+
+# ------------------------------------------------- FP32 bound at d = 5..7
+# The search bound grows with D (8 (D + 1) u e^2); these inputs put exact and
+# near ties and rounded centring in front of it at the top of the range.
+def _offset(X, off):
+    return (np.asarray(X, np.float64) + off).astype(np.float32)
+
+
+@pytest.mark.parametrize("d", [5, 6, 7])
+@pytest.mark.parametrize("metric", ["l2", "sqeuclidean", "l1"])
+def test_high_dims_lattice_ties(d, metric):
+    X, a, Y, b = W.random_pair(400 + d, 350, 300, d, masses="integer", lattice=3)
+    ref = oracle_pair(X, a, Y, b, metric)
+    assert ref["near_ties_nn"] > 0 and ref["near_ties_order"] > 0
+    assert_pair_matches(gpu_pair(X, a, Y, b, metric), ref, label=f"lattice-d{d}-{metric}")
+
+
+@pytest.mark.parametrize("d", [5, 6, 7])
+@pytest.mark.parametrize("metric", ["l2", "sqeuclidean", "l1"])
+def test_high_dims_large_common_offset(d, metric):
+    """1e3 + U[0,1]^d: FP32 keeps 14 fraction bits there, so coordinates
+    collide on a 2^-14 grid (exact and near ties) and every key is formed
+    from large, cancelling terms."""
+    X, a, Y, b = W.random_pair(410 + d, 320, 360, d)
+    X, Y = _offset(X, 1000.0), _offset(Y, 1000.0)
+    assert_pair_matches(gpu_pair(X, a, Y, b, metric), oracle_pair(X, a, Y, b, metric),
+                        label=f"offset-d{d}-{metric}")
+
+
+@pytest.mark.parametrize("d", [5, 7])
+def test_high_dims_centring_rounds(d):
+    """Points in [0,1]^d plus one supplier at 1000 (1,...,1): the box centre
+    is near 500 and x - centre rounds for every other point."""
+    X, a, Y, b = W.random_pair(420 + d, 300, 310, d)
+    X = X.copy()
+    X[17] = 1000.0
+    for metric in ("l2", "sqeuclidean"):
+        assert_pair_matches(gpu_pair(X, a, Y, b, metric), oracle_pair(X, a, Y, b, metric),
+                            label=f"centre-d{d}-{metric}")
+
+
+# ------------------------------------------------------------- near ties
+@pytest.mark.parametrize("metric,far", [("l2", 2 + 2.0 ** -21), ("l2", 2 + 2.0 ** -20), ("l2", 2 + 2.0 ** -19),
+                                        ("sqeuclidean", 2 + 2.0 ** -20), ("l1", 2 + 2.0 ** -21)])
+def test_near_tie_counts_hand_inputs(metric, far):
+    """Dyadic 1-D inputs whose distances sit just inside or outside the 1e-6
+    relative near-tie window (the oracle's hand-derived counts)."""
+    X, a, Y, b = [[0.0], [far]], [0.5, 0.5], [[1.0]], [1.0]
+    assert_pair_matches(gpu_pair(X, a, Y, b, metric), oracle_pair(X, a, Y, b, metric), label=f"{metric}-{far}")
+    X, a = [[0.0]], [1.0]
+    Y, b = [[1.0], [-(1 + 2.0 ** -21)], [1 + 2.0 ** -19]], [0.25, 0.25, 0.5]
+    g = gpu_pair(X, a, Y, b, metric)
+    assert int(g["stats"]["near_ties_order"]) == 1
+    assert_pair_matches(g, oracle_pair(X, a, Y, b, metric), label="order")

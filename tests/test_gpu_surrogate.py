@@ -39,6 +39,22 @@ def _close_blockwise(got, want, rel):
         assert err <= rel, (name, err)
 
 
+def _close_elementwise(got, want, rtol, atol_frac, label=""):
+    """Every gradient element: |g - w| <= rtol |w| + atol_frac max|w| of its
+    parameter block.  The twin rounds to BF16 at the kernels' points, so the
+    two differ by FP32 accumulation and by an occasional BF16 rounding that
+    an FP32 intermediate takes the other way (one BF16 step, 2^-8 relative,
+    in that intermediate); rtol and the block-scaled floor cover those,
+    while a wrong sign, a dropped chunk or a swapped index on any element
+    above the floor does not pass."""
+    for name, o, shp in SG.param_layout()[0]:
+        n = int(np.prod(shp))
+        g, w = got[o:o + n].astype(np.float64), want[o:o + n]
+        scale = max(float(np.abs(w).max()), 1e-30)
+        bad = np.abs(g - w) > rtol * np.abs(w) + atol_frac * scale
+        assert not bad.any(), (label, name, int(bad.sum()), n, float(np.abs(g - w).max() / scale))
+
+
 def test_embed_matches_twin():
     from paper_2401_07378_amd import binding
     # ragged chunks of 64 points, an empty set (zero row) and a 16-chunk set
@@ -105,7 +121,9 @@ def test_loss_grad_matches_twin(pairs, lo, hi):
     loss, grad = binding.sg_loss_grad(to_dev(th), to_dev(X), to_dev(a), to_dev(off), to_dev(y))
     want_loss, want_grad = SO.loss_and_grad(th, X, a, off, y, rounding=True)
     assert float(loss.item()) == pytest.approx(want_loss, rel=1e-3)
-    _close_blockwise(grad.cpu().numpy(), want_grad, 1e-2)
+    g = grad.cpu().numpy()
+    _close_blockwise(g, want_grad, 1e-2)
+    _close_elementwise(g, want_grad, 3e-2, 3e-3, label=f"{pairs}-{lo}-{hi}")
 
 
 def test_loss_is_nan_for_bad_offsets():
@@ -215,14 +233,15 @@ def test_training_reduces_loss_and_ranks_held_out_pairs():
 
 
 def test_retrieval_recall_and_gain():
-    """100 queries against 100000 candidates: the trained surrogate keeps
-    1000 (1 % of the NNS-EMD work) and NNS-EMD re-ranks them; the top-10
+    """The retrieval configuration as stated: the surrogate trained on 200000
+    NNS-EMD labels; 100 queries against 100000 candidates: the trained
+    surrogate keeps 1000 (1 % of the NNS-EMD work) and NNS-EMD re-ranks them; the top-10
     must match exhaustive NNS-EMD with recall >= 0.99, every returned cost
     must be the exhaustive NNS-EMD value, and the untrained network must do
     clearly worse (what training gains)."""
     import torch
     from paper_2401_07378_amd import binding
-    tr, _ = _train(50000, 16)
+    tr, _ = _train(200000, 16)
     ps = W.retrieval_3d(100000)
     Y, b, yo = to_dev(ps.Y), to_dev(ps.b), to_dev(ps.y_off)
     E_tr = SG.build_index(tr.theta, Y, b, yo)

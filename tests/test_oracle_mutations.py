@@ -33,6 +33,14 @@ MUTANTS = {
     "serve_when_empty": ("if (!(s[i] > 0.0)) break;", "if (s[i] < 0.0) break;"),
     # one flow is sent the wrong way: f = max instead of min
     "flow_max": ("double f = s[i] < c[j] ? s[i] : c[j];", "double f = s[i] > c[j] ? s[i] : c[j];"),
+    # near ties judged without the absolute rule at distance 0
+    "near_tie_no_zero_rule": ("if (d1 == 0.0) return gap <= 1e-12;", ""),
+    # near ties of the NNS step judged on squared keys instead of distances
+    "near_tie_on_keys": ("near_tie(dist_of_key(best, metric), dist_of_key(second, metric))",
+                         "near_tie(best, second)"),
+    # a given D read with its columns mirrored (consumer j sees column n-1-j)
+    "given_D_mirrored": ("if (g->D != NULL) return g->D[i * g->n + j];",
+                         "if (g->D != NULL) return g->D[i * g->n + (g->n - 1 - j)];"),
 }
 
 

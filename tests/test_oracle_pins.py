@@ -324,3 +324,197 @@ def test_barycentric_map():
     r = oracle.solve(ps.X, ps.a, ps.Y, ps.b)
     T = oracle.barycentric(r["src"], r["dst"], r["flow"], ps.Y, 64)
     np.testing.assert_array_equal(T[r["src"]], ps.Y[r["dst"]].astype(np.float64))
+
+
+# ------------------------------------------------------------ near-tie counters
+# A near tie is a gap of at most 1e-6 relative between two distances (second
+# - first <= 1e-6 * first), or at most 1e-12 when the first is 0.  Inputs are
+# dyadic, so every distance below is exact in FP32 and FP64 and the expected
+# counts follow by hand.
+def test_near_ties_exact_counts_on_tie_rules_example():
+    """E3: c0 is equidistant from s0 and s1 (one NNS near tie); c0 and c1
+    both claim s0 at distance 1 (one neighbour near tie in the greedy order);
+    round 2 has a single supplier, which counts nothing."""
+    ex = {e["name"]: e for e in _golden()["examples"]}["E3_tie_rules"]
+    r = oracle.solve(ex["X"], ex["a"], ex["Y"], ex["b"])
+    assert r["near_ties_nn"] == 1 and r["near_ties_order"] == 1
+
+
+@pytest.mark.parametrize("metric,far,want", [
+    # L2: distances 1 and 1 + 2^-21 (gap 4.8e-7 <= 1e-6) / 1 + 2^-19 (1.9e-6)
+    ("l2", 2 + 2.0 ** -21, 1), ("l2", 2 + 2.0 ** -19, 0),
+    # 1 + 2^-20: a distance gap of 9.5e-7 (near) is a squared-key gap of 1.9e-6
+    ("l2", 2 + 2.0 ** -20, 1), ("sqeuclidean", 2 + 2.0 ** -20, 0),
+    # squared: 1 and (1 + 2^-21)^2 (gap 9.5e-7) / (1 + 2^-19)^2 (gap 3.8e-6)
+    ("sqeuclidean", 2 + 2.0 ** -21, 1), ("sqeuclidean", 2 + 2.0 ** -19, 0),
+    ("l1", 2 + 2.0 ** -21, 1), ("l1", 2 + 2.0 ** -19, 0),
+])
+def test_near_tie_nn_relative_rule(metric, far, want):
+    """One consumer at 1 between suppliers at 0 and `far` (1-D): it picks
+    s0 in round 1 (counted when the second distance is within 1e-6); round 2
+    has one supplier left and counts nothing."""
+    r = oracle.solve([[0.0], [far]], [0.5, 0.5], [[1.0]], [1.0], metric=metric)
+    assert r["status"] == 0 and r["rounds"] == 2
+    assert r["near_ties_nn"] == want and r["near_ties_order"] == 0
+
+
+@pytest.mark.parametrize("metric,far,want", [
+    # the consumer sits on s0 (distance 0): absolute rule, gap <= 1e-12
+    ("l2", 2.0 ** -41, 1),           # 4.5e-13
+    ("l2", 2.0 ** -39, 0),           # 1.8e-12
+    ("sqeuclidean", 2.0 ** -39, 1),  # squared: 3.3e-24
+    ("l1", 2.0 ** -39, 0),
+])
+def test_near_tie_nn_absolute_rule_at_zero(metric, far, want):
+    r = oracle.solve([[0.0], [far]], [0.5, 0.5], [[0.0]], [1.0], metric=metric)
+    assert r["near_ties_nn"] == want
+
+
+def test_near_tie_order_neighbours_only():
+    """Three claimants of one supplier at distances 1, 1 + 2^-21, 1 + 2^-19:
+    the first two neighbours are a near tie, the second two are not
+    (gap 2^-19 - 2^-21 = 1.4e-6), and the first and last are not neighbours."""
+    r = oracle.solve([[0.0]], [1.0], [[1.0], [-(1 + 2.0 ** -21)], [1 + 2.0 ** -19]], [0.25, 0.25, 0.5])
+    assert r["rounds"] == 1 and r["near_ties_order"] == 1 and r["near_ties_nn"] == 0
+    rr = oracle.solve([[0.0]], [1.0], [[1.0], [-(1 + 2.0 ** -21)], [1 + 2.0 ** -19]], [0.25, 0.25, 0.5],
+                      protocol="random", seed=3)
+    assert rr["near_ties_order"] == 0  # counted for the greedy order only
+
+
+# ------------------------------------------------------------ batched driver
+@pytest.mark.parametrize("metric,protocol", [("l2", "greedy"), ("sqeuclidean", "random"), ("l1", "greedy")])
+def test_solve_batched_matches_per_pair_solve(metric, protocol):
+    """Pair tables that reuse sets (one supplier set against many consumer
+    sets, repeated pairs, swapped indices): every pair's stats and cost equal
+    the single-pair solve of the same two sets."""
+    ps = W.batched_hist_3d(12, lo=3, hi=40, seed=2024)
+    pair_x = np.array([0, 3, 3, 7, 11, 2, 5, 0, 9, 9], np.int32)
+    pair_y = np.array([1, 3, 4, 7, 0, 11, 5, 1, 2, 10], np.int32)
+    stats, threads = oracle.solve_batched(ps.X, ps.a, ps.x_off, ps.Y, ps.b, ps.y_off, pair_x=pair_x,
+                                          pair_y=pair_y, metric=metric, protocol=protocol, seed=77)
+    assert threads >= 1 and len(stats) == len(pair_x)
+    for p, (px, py) in enumerate(zip(pair_x, pair_y)):
+        xs, xe, ys, ye = ps.x_off[px], ps.x_off[px + 1], ps.y_off[py], ps.y_off[py + 1]
+        ref = oracle.solve(ps.X[xs:xe], ps.a[xs:xe], ps.Y[ys:ye], ps.b[ys:ye], metric=metric,
+                           protocol=protocol, seed=77, with_plan=False)
+        for k in ("status", "rounds", "nnz", "work", "near_ties_nn", "near_ties_order"):
+            assert stats[p][k] == ref[k], (p, k)
+        assert stats[p]["cost"] == ref["cost"]
+        assert stats[p]["residual_src"] == ref["residual_src"]
+
+
+# ------------------------------------------------------------ given D (Alg. 1 input)
+def _squared_keys(X, Y):
+    """Squared distances summed in dimension order (no fused multiply-add)."""
+    X = np.asarray(X, np.float64)
+    Y = np.asarray(Y, np.float64)
+    acc = np.zeros((len(X), len(Y)))
+    for k in range(X.shape[1]):
+        t = X[:, None, k] - Y[None, :, k]
+        acc = acc + t * t
+    return acc
+
+
+@pytest.mark.parametrize("ex", _golden()["examples"], ids=lambda e: e["name"])
+def test_given_D_hand_examples(ex):
+    """The hand-worked runs, fed as their ground-distance matrices."""
+    D = ground(ex["X"], ex["Y"], ex["metric"])
+    r = oracle.solve_cost(D, ex["a"], ex["b"])
+    e = ex["expected"]
+    assert r["status"] == 0 and r["rounds"] == e["rounds"] and r["work"] == e["work"]
+    assert r["cost"] == pytest.approx(e["cost"], rel=0, abs=1e-15)
+    assert _plan(r) == e["plan"]
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_given_D_equals_points_run_on_the_same_keys(seed):
+    """Squared Euclidean: key, order and distance are the same number in both
+    forms, so the whole run is identical."""
+    X, a, Y, b = W.random_pair(600 + seed, 90, 110, 3, masses=["dirichlet", "integer", "uniform"][seed])
+    r1 = oracle.solve(X, a, Y, b, metric="sqeuclidean")
+    r2 = oracle.solve_cost(_squared_keys(X, Y), a, b)
+    for k in ("status", "rounds", "nnz", "work", "near_ties_nn", "near_ties_order", "cost"):
+        assert r1[k] == r2[k], k
+    assert _plan(r1) == _plan(r2)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_given_D_lower_and_upper_bounds(seed):
+    """Any non-negative D (not a metric): R >= LP optimum (Theorem 1's lower
+    bound needs only feasibility) and the per-supplier upper bound of the
+    same theorem with the optimal plan."""
+    rng = np.random.default_rng(700 + seed)
+    m, n = int(rng.integers(2, 12)), int(rng.integers(2, 12))
+    D = rng.random((m, n)) * rng.integers(1, 4, size=(m, n))
+    a = rng.random(m) + 0.1
+    b = rng.random(n) + 0.1
+    a, b = a / a.sum(), b / b.sum()
+    r = oracle.solve_cost(D, a, b)
+    assert r["status"] == 0 and np.all(r["flow"] > 0) and r["nnz"] <= m + n - 1
+    np.testing.assert_allclose(np.bincount(r["src"], weights=r["flow"], minlength=m), a, atol=1e-12)
+    np.testing.assert_allclose(np.bincount(r["dst"], weights=r["flow"], minlength=n), b, atol=1e-12)
+    assert r["cost"] == pytest.approx(float((r["flow"] * D[r["src"], r["dst"]]).sum()), rel=1e-13)
+    A_eq = np.zeros((m + n, m * n))
+    for i in range(m):
+        A_eq[i, i * n:(i + 1) * n] = 1.0
+    for j in range(n):
+        A_eq[m + j, j::n] = 1.0
+    from scipy.optimize import linprog
+    lp = linprog(D.ravel(), A_eq=A_eq, b_eq=np.concatenate([a, b]), bounds=(0, None), method="highs")
+    assert r["cost"] >= lp.fun - 1e-12
+    F = lp.x.reshape(m, n)
+    bound = 0.0
+    for i in np.unique(r["src"]):
+        J = np.unique(r["dst"][r["src"] == i])
+        bound += D[i, J].max() * float((b[J] - F[i, J]).sum())
+    assert r["cost"] - lp.fun <= bound + 1e-12
+
+
+def test_given_D_special_cases():
+    rng = np.random.default_rng(9)
+    # m = 1: one round, R = sum_j b_j D_0j
+    D = rng.random((1, 7))
+    b = rng.random(7)
+    b = b / b.sum()
+    r = oracle.solve_cost(D, [1.0], b)
+    assert r["rounds"] == 1 and r["cost"] == pytest.approx(float((b * D[0]).sum()), rel=1e-14)
+    # n = 1: suppliers served nearest first, one per round
+    D = rng.random((6, 1))
+    a = np.full(6, 1 / 6)
+    r = oracle.solve_cost(D, a, [1.0])
+    assert r["rounds"] == 6 and list(r["src"]) == list(np.argsort(D[:, 0], kind="stable"))
+    # zero on a permutation, uniform masses: the permutation, cost 0, 1 round
+    perm = rng.permutation(8)
+    D = rng.random((8, 8)) + 0.5
+    D[np.arange(8), perm] = 0.0
+    r = oracle.solve_cost(D, np.full(8, 0.125), np.full(8, 0.125))
+    assert r["cost"] == 0.0 and r["rounds"] == 1 and np.array_equal(perm[r["src"]], r["dst"])
+    # invalid entries
+    D[0, 0] = -1.0
+    assert oracle.solve_cost(D, np.full(8, 0.125), np.full(8, 0.125))["status_name"] == "INVALID_ARG"
+    D[0, 0] = np.inf
+    assert oracle.solve_cost(D, np.full(8, 0.125), np.full(8, 0.125))["status_name"] == "INVALID_ARG"
+
+
+# ------------------------------------------------------------ per-consumer map
+def test_barycentric_dst_hand_values():
+    """E1's plan: c1 receives .25 from s0 = (0,0) and .125 from s1 = (1,0),
+    so T(c1) = (1/3, 0); c0 <- s0 only, c2 <- s1 only."""
+    ex = {e["name"]: e for e in _golden()["examples"]}["E1_partial_serve_carry_over"]
+    r = oracle.solve(ex["X"], ex["a"], ex["Y"], ex["b"])
+    T = oracle.barycentric_dst(r["src"], r["dst"], r["flow"], ex["X"], 3)
+    np.testing.assert_allclose(T, [[0, 0], [1 / 3, 0], [1, 0]], rtol=0, atol=1e-16)
+
+
+def test_barycentric_dst_permutation_and_empty_rows():
+    ps = W.single_pair_2d(64)
+    r = oracle.solve(ps.X, ps.a, ps.Y, ps.b)
+    T = oracle.barycentric_dst(r["src"], r["dst"], r["flow"], ps.X, 64)
+    np.testing.assert_array_equal(T[r["dst"]], ps.X[r["src"]].astype(np.float64))
+    X, a, Y, b = W.random_pair(15, 30, 40, 3)
+    b = b.copy()
+    b[[4, 17]] = 0
+    b = (b / b.astype(np.float64).sum()).astype(np.float32)
+    r = oracle.solve(X, a, Y, b)
+    T = oracle.barycentric_dst(r["src"], r["dst"], r["flow"], X, 40)
+    assert np.all(np.isnan(T[[4, 17]])) and not np.any(np.isnan(np.delete(T, [4, 17], axis=0)))
