@@ -66,7 +66,8 @@ typedef enum {
     NNSEMD_L1 = 2           /* D = ||x - y||_1 */
 } nnsemd_metric_t;
 
-typedef enum { NNSEMD_F32 = 0, NNSEMD_BF16 = 1 } nnsemd_dtype_t;
+/* Element type of points (F32, BF16) or of a given distance matrix (F32, F64). */
+typedef enum { NNSEMD_F32 = 0, NNSEMD_BF16 = 1, NNSEMD_F64 = 2 } nnsemd_dtype_t;
 
 /* Flow protocol of Sec. III-A: greedy serves claimants nearest-first (ties
  * by consumer index); random serves them in the order of the SplitMix64
@@ -195,6 +196,55 @@ nnsemd_status_t emd_approx_map(nnsemd_handle_t h,
                                nnsemd_stats_t* stats,
                                void* stream);
 
+/*
+ * emd_approx_cost -- NNS-EMD of one pair whose ground distances are given:
+ * Algorithm 1 (Sec. III-A) takes the m x n matrix D as its input, and the
+ * method works with any valid D (Sec. IV-F), so no coordinates are needed.
+ *   D: device, m x n row-major (D[i * n + j] = D_ij between supplier i and
+ *      consumer j), dtype F32 or F64, every entry finite and >= 0 (else the
+ *      pair's status is INVALID_ARG); caller-owned, read in place.
+ *   a: device, m FP32 supplier masses; b: device, n FP32 consumer masses.
+ *   Each consumer picks argmin_i D_ij over the active suppliers (entries
+ *   compared exactly, ties to the smallest i); the greedy order is by
+ *   (D_ij, j); R = sum f * D_ij in FP64.  Options, cost, plan and stats as
+ *   in emd_approx (opts->mode, metric-related and path fields are ignored).
+ *   One workgroup per pair on chip: 1 <= m, n <= 4096 (else UNSUPPORTED).
+ * Errors: INVALID_ARG, CAPACITY, UNSUPPORTED, OUT_OF_MEMORY, DEVICE.
+ */
+nnsemd_status_t emd_approx_cost(nnsemd_handle_t h,
+                                const void* D, nnsemd_dtype_t dtype,
+                                const float* a, int64_t m, const float* b, int64_t n,
+                                const nnsemd_options_t* opts,
+                                double* cost,
+                                int32_t* plan_src, int32_t* plan_dst, double* plan_flow,
+                                int64_t plan_capacity,
+                                nnsemd_stats_t* stats,
+                                void* stream);
+
+/*
+ * emd_approx_cost_batched -- many independent pairs of given distance
+ * matrices in one launch (one workgroup per pair, longest first unless
+ * opts->schedule says otherwise), each solved exactly as by emd_approx_cost.
+ *   Dcat: device, the matrices back to back; d_off: device, num_pairs + 1
+ *      int64 entry offsets (pair p's m_p x n_p matrix at
+ *      [d_off[p], d_off[p+1]), which must hold m_p * n_p entries).
+ *   acat / a_off, bcat / b_off: device masses and num_pairs + 1 int64
+ *      offsets (m_p = a_off[p+1] - a_off[p], n_p likewise).
+ *   max_m, max_n: host bounds on every m_p, n_p (<= 4096).
+ *   costs, plan arrays, plan_off, stats: as in emd_approx_batched.
+ */
+nnsemd_status_t emd_approx_cost_batched(nnsemd_handle_t h, int64_t num_pairs,
+                                        const void* Dcat, const int64_t* d_off, nnsemd_dtype_t dtype,
+                                        const float* acat, const int64_t* a_off,
+                                        const float* bcat, const int64_t* b_off,
+                                        int64_t max_m, int64_t max_n,
+                                        const nnsemd_options_t* opts,
+                                        double* costs,
+                                        int32_t* plan_src, int32_t* plan_dst, double* plan_flow,
+                                        const int64_t* plan_off,
+                                        nnsemd_stats_t* stats,
+                                        void* stream);
+
 /* Which side of a plan a barycentric map is taken for. */
 typedef enum { NNSEMD_MAP_SUPPLIERS = 0, NNSEMD_MAP_CONSUMERS = 1 } nnsemd_map_side_t;
 
@@ -264,6 +314,40 @@ nnsemd_status_t emd_approx_batched(nnsemd_handle_t h, int64_t num_pairs,
                                    const int64_t* plan_off,
                                    nnsemd_stats_t* stats,
                                    void* stream);
+
+/*
+ * nnsemd_colour_transfer -- colour transfer by NNS-EMD (Sec. IV-D).  The
+ * colours of each 8-bit RGB image are reduced to a palette by k-means (the
+ * reference to k_ref bins, the source to k_src bins: Lloyd iteration with
+ * `iters` update steps, started from the colours of pixels floor(k P / K),
+ * FP64 distances in channel order with ties to the smallest bin, integer
+ * cluster sums, so the palettes are reproducible bit for bit); each palette
+ * is a colour histogram (bin colour / 255 in [0,1]^3, mass = share of
+ * pixels, both FP32).  NNS-EMD (`metric`, opts as in emd_approx) moves the
+ * reference palette (suppliers) onto the source palette (consumers), and
+ * every source pixel takes the per-consumer barycentric colour of its bin,
+ * T_j = sum_i F_ij c_i / sum_i F_ij (as emd_barycentric_map with side
+ * CONSUMERS), written as round-half-even(255 T) clamped to 0..255 (a bin
+ * that received no flow keeps its pixels' colours).
+ *   ref_rgb: device, ref_pixels x 3 uint8; src_rgb: device, src_pixels x 3.
+ *   out_rgb: device, src_pixels x 3 uint8, the recoloured source.
+ *   ref_palette / src_palette (k x 3 FP32), ref_mass / src_mass (k FP32),
+ *   src_assign (src_pixels int32, the bin of each source pixel), cost (1
+ *   double) and stats (one record of the NNS-EMD solve): device, nullable.
+ * 1 <= k_ref, k_src <= 1024, 0 <= iters <= 1000, 1 <= pixels < 2^31.
+ * Asynchronous; the handle's workspace holds the palettes and the plan.
+ * Errors: INVALID_ARG, UNSUPPORTED, OUT_OF_MEMORY, DEVICE.
+ */
+nnsemd_status_t nnsemd_colour_transfer(nnsemd_handle_t h,
+                                       const uint8_t* ref_rgb, int64_t ref_pixels,
+                                       const uint8_t* src_rgb, int64_t src_pixels,
+                                       int32_t k_ref, int32_t k_src, int32_t iters,
+                                       nnsemd_metric_t metric, const nnsemd_options_t* opts,
+                                       uint8_t* out_rgb,
+                                       float* ref_palette, float* ref_mass,
+                                       float* src_palette, float* src_mass, int32_t* src_assign,
+                                       double* cost, nnsemd_stats_t* stats,
+                                       void* stream);
 
 /* ------------------------------------------------------------------------
  * Autotuning of the batched point path (FP32, 1 <= d <= 7).  The launch

@@ -97,6 +97,10 @@ def _load():
             lib.nnsemd_oracle_barycentric.restype = None
             lib.nnsemd_oracle_barycentric.argtypes = [
                 P, P, P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_int32, P]
+            lib.nnsemd_oracle_kmeans.restype = None
+            lib.nnsemd_oracle_kmeans.argtypes = [P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P, P, P]
+            lib.nnsemd_oracle_recolour.restype = None
+            lib.nnsemd_oracle_recolour.argtypes = [P, P, ctypes.c_int64, P, P]
             lib.nnsemd_oracle_rp_key.restype = ctypes.c_uint64
             lib.nnsemd_oracle_rp_key.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64]
             _lib = lib
@@ -235,6 +239,55 @@ def barycentric_dst(src, dst, flow, X, n: int) -> np.ndarray:
     lib.nnsemd_oracle_barycentric_dst(_ptr(src), _ptr(dst), _ptr(flow), len(src), _ptr(X), n,
                                       X.shape[1], _ptr(out))
     return out
+
+
+def kmeans(pixels, K: int, iters: int):
+    """k-means palette of an 8-bit RGB image (pixels: (P, 3) uint8): returns
+    (centroids (K, 3) FP64 on the 0..255 scale, counts (K,) int64,
+    assignment (P,) int32) -- the reproducible Lloyd iteration of the C file."""
+    lib = _load()
+    px = np.ascontiguousarray(np.asarray(pixels, np.uint8).reshape(-1, 3))
+    P = px.shape[0]
+    C = np.zeros((K, 3), np.float64)
+    cnt = np.zeros(K, np.int64)
+    asg = np.zeros(P, np.int32)
+    lib.nnsemd_oracle_kmeans(_ptr(px), P, K, iters, _ptr(C), _ptr(cnt), _ptr(asg))
+    return C, cnt, asg
+
+
+def palette_histogram(C, counts):
+    """A palette as a colour histogram: bin colours C / 255 rounded to FP32,
+    masses counts / sum(counts) rounded to FP32 (both from FP64)."""
+    counts = np.asarray(counts, np.int64)
+    pts = (np.asarray(C, np.float64) / 255.0).astype(np.float32)
+    mass = (counts.astype(np.float64) / float(counts.sum())).astype(np.float32)
+    return pts, mass
+
+
+def recolour(pixels, assign, colour_map):
+    """Pixels recoloured through a per-bin colour map in [0,1]^3 (NaN rows
+    keep the pixel's colour); uint8 (P, 3)."""
+    lib = _load()
+    px = np.ascontiguousarray(np.asarray(pixels, np.uint8).reshape(-1, 3))
+    asg = np.ascontiguousarray(assign, np.int32)
+    T = np.ascontiguousarray(colour_map, np.float64)
+    out = np.zeros_like(px)
+    lib.nnsemd_oracle_recolour(_ptr(px), _ptr(asg), px.shape[0], _ptr(T), _ptr(out))
+    return out
+
+
+def colour_transfer(ref_pixels, src_pixels, k_ref: int, k_src: int, iters: int, metric: str = "l2"):
+    """Colour transfer (Sec. IV-D) step by step on the host: both palettes,
+    NNS-EMD from the reference palette (suppliers) to the source palette
+    (consumers), the per-consumer barycentric map, the recoloured source."""
+    Cr, nr, _ = kmeans(ref_pixels, k_ref, iters)
+    Cs, ns, asg = kmeans(src_pixels, k_src, iters)
+    Xr, ar = palette_histogram(Cr, nr)
+    Ys, bs = palette_histogram(Cs, ns)
+    r = solve(Xr, ar, Ys, bs, metric=metric)
+    T = barycentric_dst(r["src"], r["dst"], r["flow"], Xr, k_src)
+    return {"ref_palette": Xr, "ref_mass": ar, "src_palette": Ys, "src_mass": bs, "assign": asg,
+            "solve": r, "map": T, "image": recolour(src_pixels, asg, T)}
 
 
 def rp_key(seed: int, round_: int, j: int) -> int:

@@ -414,3 +414,74 @@ void nnsemd_oracle_barycentric_dst(const int32_t* plan_src, const int32_t* plan_
             out[j * d + k] = w[j] > 0.0 ? out[j * d + k] / w[j] : NAN;
     free(w);
 }
+
+
+/*
+ * Colour transfer application (Sec. IV-D): k-means palette reduction of an
+ * 8-bit RGB image, and the recolouring of an image through a per-bin colour
+ * map.  The paper reduces the reference image's colours with k-means before
+ * transporting them; it gives no further detail, so this is plain Lloyd
+ * iteration with every step fixed so that any implementation reproduces it:
+ *   - start: centroid k = the colour of pixel floor(k * P / K);
+ *   - assignment: argmin_k sum_c (p_c - C_kc)^2 in FP64, channels in order,
+ *     no fused multiply-add, ties to the smallest k;
+ *   - update: integer sums of the assigned pixels' channels and counts, then
+ *     C_kc = S_kc / n_k (FP64, correctly rounded); an empty cluster keeps its
+ *     centroid;
+ *   - `iters` assignment + update steps, then one final assignment.
+ * Outputs: centroids (K x 3, FP64, 0..255 scale), counts (K), assignment (P).
+ */
+static int nearest_centroid(const uint8_t* px, const double* C, int32_t K) {
+    int best = 0;
+    double bd = INFINITY;
+    for (int k = 0; k < K; ++k) {
+        double acc = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            double t = (double)px[c] - C[k * 3 + c];
+            acc = acc + t * t;
+        }
+        if (acc < bd) { bd = acc; best = k; }
+    }
+    return best;
+}
+
+void nnsemd_oracle_kmeans(const uint8_t* pixels, int64_t P, int32_t K, int32_t iters,
+                          double* centroids, int64_t* counts, int32_t* assign) {
+    int64_t* S = (int64_t*)calloc((size_t)K * 3, sizeof(int64_t));
+    for (int k = 0; k < K; ++k) {
+        int64_t src = (int64_t)k * P / K;
+        for (int c = 0; c < 3; ++c) centroids[k * 3 + c] = (double)pixels[src * 3 + c];
+    }
+    for (int it = 0; it <= iters; ++it) {
+        for (int64_t p = 0; p < P; ++p) assign[p] = nearest_centroid(pixels + p * 3, centroids, K);
+        for (int k = 0; k < K; ++k) counts[k] = 0;
+        for (int64_t k = 0; k < (int64_t)K * 3; ++k) S[k] = 0;
+        for (int64_t p = 0; p < P; ++p) {
+            counts[assign[p]]++;
+            for (int c = 0; c < 3; ++c) S[assign[p] * 3 + c] += pixels[p * 3 + c];
+        }
+        if (it == iters) break;  /* the final assignment is not followed by an update */
+        for (int k = 0; k < K; ++k)
+            if (counts[k] > 0)
+                for (int c = 0; c < 3; ++c) centroids[k * 3 + c] = (double)S[k * 3 + c] / (double)counts[k];
+    }
+    free(S);
+}
+
+/*
+ * Recolour: pixel p takes the colour map[assign[p]] (a colour in [0,1]^3),
+ * written as round-half-even of 255 * value clamped to 0..255; a bin whose
+ * map row is NaN (it received no flow) keeps the pixel's own colour.
+ */
+void nnsemd_oracle_recolour(const uint8_t* pixels, const int32_t* assign, int64_t P,
+                            const double* map, uint8_t* out) {
+    for (int64_t p = 0; p < P; ++p) {
+        const double* T = map + (int64_t)assign[p] * 3;
+        for (int c = 0; c < 3; ++c) {
+            if (isnan(T[c])) { out[p * 3 + c] = pixels[p * 3 + c]; continue; }
+            double v = nearbyint(255.0 * T[c]);
+            v = v < 0.0 ? 0.0 : (v > 255.0 ? 255.0 : v);
+            out[p * 3 + c] = (uint8_t)v;
+        }
+    }
+}

@@ -23,7 +23,7 @@ STATUS = {
 METRICS = {"l2": 0, "sqeuclidean": 1, "l1": 2}
 PROTOCOLS = {"greedy": 0, "random": 1}
 MODES = {"fp32": 0, "bf16_mfma_refine": 1}
-DTYPES = {"f32": 0, "bf16": 1}
+DTYPES = {"f32": 0, "bf16": 1, "f64": 2}
 
 # nnsemd_stats_t as a numpy record (64 bytes, written by the device).
 STATS_DTYPE = np.dtype([("status", "<i4"), ("rounds", "<i4"), ("nnz", "<i8"), ("work", "<i8"),
@@ -33,6 +33,7 @@ STATS_BYTES = STATS_DTYPE.itemsize
 
 EXPORTS = ["nnsemd_create", "nnsemd_destroy", "nnsemd_status_string", "nnsemd_last_error",
            "emd_approx", "emd_approx_map", "emd_approx_batched", "emd_barycentric_map",
+           "emd_approx_cost", "emd_approx_cost_batched",
            "nnsemd_sg_num_params", "nnsemd_sg_embed", "nnsemd_sg_predict", "nnsemd_sg_loss_grad",
            "nnsemd_sg_train_step", "nnsemd_topk_smallest_f32", "nnsemd_topk_smallest_f64", "nnsemd_sg_retrieve",
            "nnsemd_autotune", "nnsemd_tuning_save", "nnsemd_tuning_load"]
@@ -91,6 +92,11 @@ def load_library():
         lib.emd_approx_map.restype = I32
         lib.emd_barycentric_map.argtypes = [P, P, P, P, I64, P, P, I64, I32, I64, I32, P, P]
         lib.emd_barycentric_map.restype = I32
+        lib.emd_approx_cost.argtypes = [P, P, I32, P, I64, P, I64, ctypes.POINTER(Options), P, P, P, P, I64, P, P]
+        lib.emd_approx_cost.restype = I32
+        lib.emd_approx_cost_batched.argtypes = [P, I64, P, P, I32, P, P, P, P, I64, I64, ctypes.POINTER(Options),
+                                                P, P, P, P, P, P, P]
+        lib.emd_approx_cost_batched.restype = I32
         F32 = ctypes.c_float
         lib.nnsemd_sg_num_params.argtypes = []
         lib.nnsemd_sg_num_params.restype = I64
@@ -236,6 +242,82 @@ def emd_approx_map(X, a, Y, b, metric: str = "l2", *, plan: bool = True, protoco
                             cap if plan else 0, _ptr(stats), _stream(torch, dev))
     _check(lib, h, st)
     return {"cost": cost, "map": mp[:m], "stats": stats, "plan_src": src, "plan_dst": dst, "plan_flow": flow}
+
+
+def _d_dtype(D):
+    import torch
+    if D.dtype == torch.float32:
+        return DTYPES["f32"]
+    if D.dtype == torch.float64:
+        return DTYPES["f64"]
+    raise ValueError("D must be float32 or float64")
+
+
+def emd_approx_cost(D, a, b, *, plan: bool = True, protocol: str = "greedy", seed: int = 0,
+                    max_rounds: int = 0, schedule: str = "longest_first", out: dict | None = None) -> dict:
+    """NNS-EMD of one pair from its ground-distance matrix D (m x n device
+    tensor, FP32 or FP64; Algorithm 1's input) and FP32 masses a (m), b (n).
+    Returns device tensors cost (1,), stats and the plan (capacity m+n-1)."""
+    import torch
+    lib = load_library()
+    dev = _dev_of(D)
+    h = handle(dev)
+    _require(D, D.dtype, "D")
+    _require(a, torch.float32, "a")
+    _require(b, torch.float32, "b")
+    m, n = a.numel(), b.numel()
+    if D.numel() != m * n:
+        raise ValueError("D must hold m x n entries")
+    o = out or {}
+    cost = o.get("cost") if o.get("cost") is not None else torch.empty(1, dtype=torch.float64, device=D.device)
+    stats = o.get("stats") if o.get("stats") is not None else \
+        torch.empty(STATS_BYTES, dtype=torch.uint8, device=D.device)
+    cap = max(m + n - 1, 1)
+    src = dst = flow = None
+    if plan:
+        src = torch.empty(cap, dtype=torch.int32, device=D.device)
+        dst = torch.empty(cap, dtype=torch.int32, device=D.device)
+        flow = torch.empty(cap, dtype=torch.float64, device=D.device)
+    opts = _options(protocol, "fp32", max_rounds, seed, 0, schedule)
+    st = lib.emd_approx_cost(h, _ptr(D), _d_dtype(D), _ptr(a), m, _ptr(b), n, ctypes.byref(opts), _ptr(cost),
+                             _ptr(src), _ptr(dst), _ptr(flow), cap if plan else 0, _ptr(stats), _stream(torch, dev))
+    _check(lib, h, st)
+    return {"cost": cost, "stats": stats, "plan_src": src, "plan_dst": dst, "plan_flow": flow}
+
+
+def emd_approx_cost_batched(Dcat, d_off, acat, a_off, bcat, b_off, *, max_m: int, max_n: int, plan_off=None,
+                            protocol: str = "greedy", seed: int = 0, max_rounds: int = 0,
+                            schedule: str = "longest_first", out: dict | None = None) -> dict:
+    """Many pairs of given distance matrices in one launch (offsets are int64
+    device tensors of num_pairs + 1 entries).  Asynchronous."""
+    import torch
+    lib = load_library()
+    dev = _dev_of(Dcat)
+    h = handle(dev)
+    for t, nm in ((d_off, "d_off"), (a_off, "a_off"), (b_off, "b_off")):
+        _require(t, torch.int64, nm)
+    _require(acat, torch.float32, "acat")
+    _require(bcat, torch.float32, "bcat")
+    P = a_off.numel() - 1
+    o = out or {}
+    costs = o.get("costs") if o.get("costs") is not None else \
+        torch.empty(max(P, 1), dtype=torch.float64, device=Dcat.device)
+    stats = o.get("stats") if o.get("stats") is not None else \
+        torch.empty(max(P, 1) * STATS_BYTES, dtype=torch.uint8, device=Dcat.device)
+    src = dst = flow = None
+    if plan_off is not None:
+        _require(plan_off, torch.int64, "plan_off")
+        total = int(plan_off[-1].item())
+        src = torch.empty(max(total, 1), dtype=torch.int32, device=Dcat.device)
+        dst = torch.empty(max(total, 1), dtype=torch.int32, device=Dcat.device)
+        flow = torch.empty(max(total, 1), dtype=torch.float64, device=Dcat.device)
+    opts = _options(protocol, "fp32", max_rounds, seed, 0, schedule)
+    st = lib.emd_approx_cost_batched(h, P, _ptr(Dcat), _ptr(d_off), _d_dtype(Dcat), _ptr(acat), _ptr(a_off),
+                                     _ptr(bcat), _ptr(b_off), int(max_m), int(max_n), ctypes.byref(opts),
+                                     _ptr(costs), _ptr(src), _ptr(dst), _ptr(flow), _ptr(plan_off), _ptr(stats),
+                                     _stream(torch, dev))
+    _check(lib, h, st)
+    return {"costs": costs, "stats": stats, "plan_src": src, "plan_dst": dst, "plan_flow": flow}
 
 
 MAP_SIDES = {"suppliers": 0, "consumers": 1}

@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libnnsemd.so")
 SOURCES = ["api.hip", "pair_solver.hip", "large_pair.hip", "doc_solver.hip", "surrogate.hip",
-           "transport_map.hip"]
+           "transport_map.hip", "cost_solver.hip", "colour_transfer.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -43,6 +43,8 @@ struct nnsemd_handle {
     size_t map_bytes = 0;
     char* map_plan = nullptr;                    // emd_approx_map: plan and stats when the caller keeps none
     size_t map_plan_bytes = 0;
+    char* ct_ws = nullptr;                       // colour transfer: palettes, assignments, plan, map
+    size_t ct_bytes = 0;
 };
 
 namespace {
@@ -171,6 +173,49 @@ nnsemd_status_t run_pairs(nnsemd_handle_t h, PairSolverArgs& A, int d, int64_t m
     return NNSEMD_OK;
 }
 
+// Given distance matrices: one workgroup per pair (on chip, sides <= 4096).
+constexpr int kCostMaxSide = 4096;
+
+nnsemd_status_t run_cost(nnsemd_handle_t h, CostArgs& A, int64_t max_m, int64_t max_n, bool f64,
+                         const nnsemd_options_t& o, void* stream) {
+    if (max_m > kCostMaxSide || max_n > kCostMaxSide)
+        return fail(h, NNSEMD_ERR_UNSUPPORTED, "given-D path supports up to 4096 points per side");
+    const int mcap = (int)std::max<int64_t>(max_m, 1), ncap = (int)std::max<int64_t>(max_n, 1);
+    const int chunk = (std::max(mcap, ncap) + 255) / 256;
+    const PairLdsLayout lay = pair_lds_layout(mcap, ncap, 0, 0, true, true);
+    if (lay.total + 8192 > h->max_lds) return fail(h, NNSEMD_ERR_UNSUPPORTED, "pair does not fit in LDS");
+    A.max_m = mcap;
+    A.max_n = ncap;
+    A.protocol = o.protocol;
+    A.seed = o.seed;
+    A.max_rounds = o.max_rounds;
+    int blocks = 0;
+    int err = launch_cost_solver(A, f64, chunk, lay.total, 0, stream, &blocks);
+    if (err != 0) return device_fail(h, err, "occupancy query");
+    if (blocks < 1) return fail(h, NNSEMD_ERR_UNSUPPORTED, "pair workgroup does not fit on a compute unit");
+    if (A.a_off != nullptr && A.num_pairs > 1 && o.schedule == NNSEMD_SCHEDULE_LONGEST_FIRST) {
+        nnsemd_status_t s = schedule(h, A.a_off, A.b_off, nullptr, nullptr, A.num_pairs, A.num_pairs, A.num_pairs,
+                                     stream);
+        if (s != NNSEMD_OK) return s;
+        A.order = h->order;
+    }
+    err = launch_cost_solver(A, f64, chunk, lay.total, (int)A.num_pairs, stream, nullptr);
+    if (err != 0) return device_fail(h, err, "given-D solver launch");
+    return NNSEMD_OK;
+}
+
+// Option checks of the given-D calls (no metric, points dtype or mode).
+nnsemd_status_t check_cost_options(nnsemd_handle_t h, nnsemd_dtype_t dtype, const nnsemd_options_t& o) {
+    if (dtype != NNSEMD_F32 && dtype != NNSEMD_F64) return fail(h, NNSEMD_ERR_INVALID_ARG, "D must be F32 or F64");
+    if (o.protocol != NNSEMD_GREEDY && o.protocol != NNSEMD_RANDOM)
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "bad protocol");
+    if (o.schedule != NNSEMD_SCHEDULE_LONGEST_FIRST && o.schedule != NNSEMD_SCHEDULE_AS_GIVEN)
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "bad schedule");
+    if (o.threads != 0 && o.threads != 256) return fail(h, NNSEMD_ERR_UNSUPPORTED, "given-D path runs 256 threads");
+    if (o.reserved != 0) return fail(h, NNSEMD_ERR_INVALID_ARG, "reserved option field must be 0");
+    return NNSEMD_OK;
+}
+
 // Multi-workgroup path for one pair (any size).  Carves one device
 // allocation into the round state and per-point arrays, enqueues rounds and
 // reads the round state back every kChunk rounds to shrink the grids.
@@ -270,10 +315,15 @@ constexpr size_t kDocTileBudget = (size_t)4 << 30;
 constexpr int kDocMaxSide = 4096;
 constexpr int kDocMaxDim = 65536;
 
+// High-dimensional L1: the exact FP64 distance matrix of each pair (dimension
+// order, the definition's operations), then the given-D solver on it, in
+// chunks whose matrices fit the scratch budget.
+nnsemd_status_t run_docs_l1(nnsemd_handle_t h, DocArgs& A, int64_t max_m, int64_t max_n, nnsemd_dtype_t dtype,
+                            const nnsemd_options_t& o, void* stream);
+
 nnsemd_status_t run_docs(nnsemd_handle_t h, DocArgs& A, int64_t max_m, int64_t max_n, nnsemd_dtype_t dtype,
                          const nnsemd_options_t& o, void* stream) {
-    if (A.metric == NNSEMD_L1)
-        return fail(h, NNSEMD_ERR_UNSUPPORTED, "high-dimensional path supports the L2 and squared Euclidean metrics");
+    if (A.metric == NNSEMD_L1) return run_docs_l1(h, A, max_m, max_n, dtype, o, stream);
     if (A.d > kDocMaxDim) return fail(h, NNSEMD_ERR_UNSUPPORTED, "d above 65536");
     if (o.threads != 0 && o.threads != 256)
         return fail(h, NNSEMD_ERR_UNSUPPORTED, "high-dimensional path runs 256-thread workgroups");
@@ -348,6 +398,68 @@ bool fits_on_chip(nnsemd_handle_t h, int64_t m, int64_t n, int32_t d, int32_t th
                                               (int)std::min<int64_t>(std::max<int64_t>(n, 1), 1 << 20),
                                               record_stride(std::max(1, std::min(d, 7))), 0, true);
     return (maxp + threads - 1) / threads <= chunk_cap && lay.total + 8192 <= h->max_lds;
+}
+
+nnsemd_status_t run_docs_l1(nnsemd_handle_t h, DocArgs& A, int64_t max_m, int64_t max_n, nnsemd_dtype_t dtype,
+                            const nnsemd_options_t& o, void* stream) {
+    if (A.d > kDocMaxDim) return fail(h, NNSEMD_ERR_UNSUPPORTED, "d above 65536");
+    if (max_m > kCostMaxSide || max_n > kCostMaxSide)
+        return fail(h, NNSEMD_ERR_UNSUPPORTED, "high-dimensional L1 supports up to 4096 points per side");
+    if (o.threads != 0 && o.threads != 256)
+        return fail(h, NNSEMD_ERR_UNSUPPORTED, "high-dimensional path runs 256-thread workgroups");
+    const int64_t mcap = std::max<int64_t>(max_m, 1), ncap = std::max<int64_t>(max_n, 1);
+    A.max_m = (int32_t)mcap;
+    A.max_n = (int32_t)ncap;
+    const int64_t stride = mcap * ncap;  // FP64 entries per pair
+    const int64_t per_launch =
+        std::max<int64_t>(1, std::min<int64_t>(A.num_pairs, (int64_t)(kDocTileBudget / (8 * (size_t)stride))));
+    const size_t need = 8 * (size_t)stride * (size_t)per_launch;
+    if (h->doc_bytes < need) {
+        if (h->doc_tiles) (void)hipFree(h->doc_tiles);
+        h->doc_tiles = nullptr;
+        h->doc_bytes = 0;
+        if (hipMalloc((void**)&h->doc_tiles, need) != hipSuccess)
+            return fail(h, NNSEMD_ERR_OUT_OF_MEMORY, "L1 distance scratch");
+        h->doc_bytes = need;
+    }
+    double* tiles = reinterpret_cast<double*>(h->doc_tiles);
+    CostArgs C{};
+    C.num_pairs = A.num_pairs;
+    C.D = tiles;
+    C.d_stride = stride;
+    C.a = A.a;
+    C.b = A.b;
+    C.single_m = A.single_m;
+    C.single_n = A.single_n;
+    if (A.x_off != nullptr) {
+        C.a_off = A.x_off;
+        C.b_off = A.y_off;
+        C.pair_x = A.pair_x;
+        C.pair_y = A.pair_y;
+        C.num_a_sets = A.num_x_sets;
+        C.num_b_sets = A.num_y_sets;
+    }
+    C.costs = A.costs;
+    C.plan_src = A.plan_src;
+    C.plan_dst = A.plan_dst;
+    C.plan_flow = A.plan_flow;
+    C.plan_off = A.plan_off;
+    C.single_plan_cap = A.single_plan_cap;
+    C.stats = A.stats;
+    nnsemd_options_t oc = o;
+    oc.schedule = NNSEMD_SCHEDULE_AS_GIVEN;  // chunks run in the given order
+    for (int64_t base = 0; base < A.num_pairs; base += per_launch) {
+        const int grid = (int)std::min<int64_t>(per_launch, A.num_pairs - base);
+        A.pair_base = base;
+        const int err = launch_l1_tiles(A, dtype == NNSEMD_BF16, tiles, stride, grid, stream);
+        if (err != 0) return device_fail(h, err, "L1 distance launch");
+        CostArgs Cc = C;
+        Cc.pair_base = base;
+        Cc.num_pairs = grid;
+        nnsemd_status_t s = run_cost(h, Cc, max_m, max_n, true, oc, stream);
+        if (s != NNSEMD_OK) return s;
+    }
+    return NNSEMD_OK;
 }
 
 // FP32 points with d <= 7 take the point path; BF16 points (matrix-core
@@ -504,6 +616,7 @@ nnsemd_status_t nnsemd_destroy(nnsemd_handle_t h) {
         if (h->sg_quant) (void)hipFree(h->sg_quant);
         if (h->sg_ws) (void)hipFree(h->sg_ws);
         if (h->map_ws) (void)hipFree(h->map_ws);
+        if (h->ct_ws) (void)hipFree(h->ct_ws);
         if (h->map_plan) (void)hipFree(h->map_plan);
     }
     delete h;
@@ -688,6 +801,159 @@ nnsemd_status_t emd_approx_map(nnsemd_handle_t h, const void* X, const float* a,
     if ((s = run_pairs(h, A, d, m, n, oc, stream)) != NNSEMD_OK) return s;
     return run_map(h, ps, pd, pf, pcap, &st->nnz, static_cast<const float*>(Y), n, d, NNSEMD_MAP_SUPPLIERS, m, map,
                    stream);
+}
+
+nnsemd_status_t emd_approx_cost(nnsemd_handle_t h, const void* D, nnsemd_dtype_t dtype, const float* a, int64_t m,
+                                const float* b, int64_t n, const nnsemd_options_t* opts, double* cost,
+                                int32_t* plan_src, int32_t* plan_dst, double* plan_flow, int64_t plan_capacity,
+                                nnsemd_stats_t* stats, void* stream) {
+    if (h == nullptr) return NNSEMD_ERR_INVALID_ARG;
+    h->last_error.clear();
+    const nnsemd_options_t o = opts ? *opts : default_options();
+    nnsemd_status_t s = check_cost_options(h, dtype, o);
+    if (s != NNSEMD_OK) return s;
+    if (m < 0 || n < 0) return fail(h, NNSEMD_ERR_INVALID_ARG, "negative size");
+    if (cost == nullptr) return fail(h, NNSEMD_ERR_INVALID_ARG, "cost must not be NULL");
+    if ((m > 0 && a == nullptr) || (n > 0 && b == nullptr) || (m > 0 && n > 0 && D == nullptr))
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "NULL matrix or mass array");
+    const bool plan = plan_src != nullptr || plan_dst != nullptr || plan_flow != nullptr;
+    if (plan && (plan_src == nullptr || plan_dst == nullptr || plan_flow == nullptr))
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "plan arrays must be all given or all NULL");
+    if (plan && m + n > 0 && plan_capacity < m + n - 1)
+        return fail(h, NNSEMD_ERR_CAPACITY, "plan capacity below m + n - 1");
+    DeviceGuard g(h->device);
+    CostArgs A{};
+    A.num_pairs = 1;
+    A.D = D;
+    A.a = a;
+    A.b = b;
+    A.single_m = m;
+    A.single_n = n;
+    A.costs = cost;
+    A.plan_src = plan ? plan_src : nullptr;
+    A.plan_dst = plan ? plan_dst : nullptr;
+    A.plan_flow = plan ? plan_flow : nullptr;
+    A.single_plan_cap = plan_capacity;
+    A.stats = stats;
+    return run_cost(h, A, m, n, dtype == NNSEMD_F64, o, stream);
+}
+
+nnsemd_status_t emd_approx_cost_batched(nnsemd_handle_t h, int64_t num_pairs, const void* Dcat, const int64_t* d_off,
+                                        nnsemd_dtype_t dtype, const float* acat, const int64_t* a_off,
+                                        const float* bcat, const int64_t* b_off, int64_t max_m, int64_t max_n,
+                                        const nnsemd_options_t* opts, double* costs, int32_t* plan_src,
+                                        int32_t* plan_dst, double* plan_flow, const int64_t* plan_off,
+                                        nnsemd_stats_t* stats, void* stream) {
+    if (h == nullptr) return NNSEMD_ERR_INVALID_ARG;
+    h->last_error.clear();
+    const nnsemd_options_t o = opts ? *opts : default_options();
+    nnsemd_status_t s = check_cost_options(h, dtype, o);
+    if (s != NNSEMD_OK) return s;
+    if (num_pairs < 0 || max_m < 0 || max_n < 0) return fail(h, NNSEMD_ERR_INVALID_ARG, "negative count");
+    if (num_pairs == 0) return NNSEMD_OK;
+    if (num_pairs > 0x7fffffffLL - (1LL << 20)) return fail(h, NNSEMD_ERR_UNSUPPORTED, "too many pairs for one call");
+    if (costs == nullptr || Dcat == nullptr || d_off == nullptr || acat == nullptr || a_off == nullptr ||
+        bcat == nullptr || b_off == nullptr)
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "NULL required array");
+    const bool plan = plan_src != nullptr || plan_dst != nullptr || plan_flow != nullptr;
+    if (plan && (plan_src == nullptr || plan_dst == nullptr || plan_flow == nullptr || plan_off == nullptr))
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "plan arrays and plan_off must be all given or all NULL");
+    DeviceGuard g(h->device);
+    CostArgs A{};
+    A.num_pairs = num_pairs;
+    A.D = Dcat;
+    A.d_off = d_off;
+    A.a = acat;
+    A.a_off = a_off;
+    A.b = bcat;
+    A.b_off = b_off;
+    A.costs = costs;
+    A.plan_src = plan ? plan_src : nullptr;
+    A.plan_dst = plan ? plan_dst : nullptr;
+    A.plan_flow = plan ? plan_flow : nullptr;
+    A.plan_off = plan ? plan_off : nullptr;
+    A.stats = stats;
+    A.num_a_sets = num_pairs;
+    A.num_b_sets = num_pairs;
+    return run_cost(h, A, max_m, max_n, dtype == NNSEMD_F64, o, stream);
+}
+
+nnsemd_status_t nnsemd_colour_transfer(nnsemd_handle_t h, const uint8_t* ref_rgb, int64_t ref_pixels,
+                                       const uint8_t* src_rgb, int64_t src_pixels, int32_t k_ref, int32_t k_src,
+                                       int32_t iters, nnsemd_metric_t metric, const nnsemd_options_t* opts,
+                                       uint8_t* out_rgb, float* ref_palette, float* ref_mass, float* src_palette,
+                                       float* src_mass, int32_t* src_assign, double* cost, nnsemd_stats_t* stats,
+                                       void* stream) {
+    if (h == nullptr) return NNSEMD_ERR_INVALID_ARG;
+    h->last_error.clear();
+    const nnsemd_options_t o = opts ? *opts : default_options();
+    nnsemd_status_t s = check_common(h, 3, NNSEMD_F32, metric, o);
+    if (s != NNSEMD_OK) return s;
+    if (ref_rgb == nullptr || src_rgb == nullptr || out_rgb == nullptr)
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "NULL image");
+    if (ref_pixels < 1 || src_pixels < 1 || ref_pixels > 0x7fffffffLL || src_pixels > 0x7fffffffLL)
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "pixel counts must be in [1, 2^31)");
+    if (k_ref < 1 || k_src < 1 || k_ref > 1024 || k_src > 1024 || iters < 0 || iters > 1000)
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "need 1 <= k <= 1024 and 0 <= iters <= 1000");
+    if (kmeans_lds_bytes(std::max(k_ref, k_src)) + 8192 > h->max_lds)
+        return fail(h, NNSEMD_ERR_UNSUPPORTED, "palette does not fit in LDS");
+    DeviceGuard g(h->device);
+    // workspace: both clusterings, both palettes, plan, stats, map
+    Carver c;
+    const size_t oCr = c.take(24 * (size_t)k_ref), oSr = c.take(32 * (size_t)k_ref);
+    const size_t oAr = c.take(4 * (size_t)ref_pixels);
+    const size_t oCs = c.take(24 * (size_t)k_src), oSs = c.take(32 * (size_t)k_src);
+    const size_t oAs = c.take(4 * (size_t)src_pixels);
+    const size_t oXr = c.take(12 * (size_t)k_ref), oar = c.take(4 * (size_t)k_ref);
+    const size_t oYs = c.take(12 * (size_t)k_src), obs = c.take(4 * (size_t)k_src);
+    const int64_t cap = (int64_t)k_ref + k_src - 1;
+    const size_t opf = c.take(8 * (size_t)cap), ops = c.take(4 * (size_t)cap), opd = c.take(4 * (size_t)cap);
+    const size_t ost = c.take(sizeof(nnsemd_stats_t)), ocost = c.take(8), omap = c.take(24 * (size_t)k_src);
+    if ((s = grow(h, &h->ct_ws, &h->ct_bytes, align_up(c.off, 256), "colour transfer workspace")) != NNSEMD_OK)
+        return s;
+    char* b = h->ct_ws;
+    double* Cr = reinterpret_cast<double*>(b + oCr);
+    double* Cs = reinterpret_cast<double*>(b + oCs);
+    auto* Sr = reinterpret_cast<unsigned long long*>(b + oSr);
+    auto* Ss = reinterpret_cast<unsigned long long*>(b + oSs);
+    int32_t* Ar = reinterpret_cast<int32_t*>(b + oAr);
+    int32_t* As = src_assign ? src_assign : reinterpret_cast<int32_t*>(b + oAs);
+    float* Xr = ref_palette ? ref_palette : reinterpret_cast<float*>(b + oXr);
+    float* ar = ref_mass ? ref_mass : reinterpret_cast<float*>(b + oar);
+    float* Ys = src_palette ? src_palette : reinterpret_cast<float*>(b + oYs);
+    float* bs = src_mass ? src_mass : reinterpret_cast<float*>(b + obs);
+    double* pf = reinterpret_cast<double*>(b + opf);
+    int32_t* ps = reinterpret_cast<int32_t*>(b + ops);
+    int32_t* pd = reinterpret_cast<int32_t*>(b + opd);
+    nnsemd_stats_t* st = stats ? stats : reinterpret_cast<nnsemd_stats_t*>(b + ost);
+    double* cst = cost ? cost : reinterpret_cast<double*>(b + ocost);
+    double* T = reinterpret_cast<double*>(b + omap);
+    int err = launch_kmeans(ref_rgb, ref_pixels, k_ref, iters, Cr, Sr, Ar, Xr, ar, stream);
+    if (err == 0) err = launch_kmeans(src_rgb, src_pixels, k_src, iters, Cs, Ss, As, Ys, bs, stream);
+    if (err != 0) return device_fail(h, err, "palette reduction");
+    nnsemd_options_t oc = o;
+    oc.path = NNSEMD_PATH_ON_CHIP;
+    PairSolverArgs A{};
+    A.num_pairs = 1;
+    A.X = Xr;
+    A.a = ar;
+    A.Y = Ys;
+    A.b = bs;
+    A.single_m = k_ref;
+    A.single_n = k_src;
+    A.metric = metric;
+    A.costs = cst;
+    A.plan_src = ps;
+    A.plan_dst = pd;
+    A.plan_flow = pf;
+    A.single_plan_cap = cap;
+    A.stats = st;
+    if ((s = run_pairs(h, A, 3, k_ref, k_src, oc, stream)) != NNSEMD_OK) return s;
+    if ((s = run_map(h, ps, pd, pf, cap, &st->nnz, Xr, k_ref, 3, NNSEMD_MAP_CONSUMERS, k_src, T, stream)) != NNSEMD_OK)
+        return s;
+    err = launch_recolour(src_rgb, As, src_pixels, T, out_rgb, stream);
+    if (err != 0) return device_fail(h, err, "recolour");
+    return NNSEMD_OK;
 }
 
 nnsemd_status_t emd_barycentric_map(nnsemd_handle_t h, const int32_t* plan_src, const int32_t* plan_dst,

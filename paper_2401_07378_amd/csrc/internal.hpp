@@ -281,6 +281,47 @@ int launch_two_offsets(int64_t* off, int64_t m, void* stream);
 }  // namespace sg
 
 // ---------------------------------------------------------------------
+// Given ground-distance matrices (cost_solver.hip): one workgroup per pair.
+struct CostArgs {
+    int64_t num_pairs;
+    const void* D;          // FP32 or FP64 entries, pair p row-major m_p x n_p
+    const int64_t* d_off;   // num_pairs + 1 entry offsets; nullptr: single pair, or
+                            // pair p at (p - pair_base) * d_stride when d_stride > 0
+    int64_t d_stride;
+    int64_t pair_base;      // workgroup b solves pair pair_base + b (no order table)
+    const float* a;
+    const int64_t* a_off;   // supplier set offsets, or nullptr (single pair)
+    const float* b;
+    const int64_t* b_off;   // consumer set offsets, or nullptr
+    const int32_t* pair_x;  // nullable: pair p uses supplier set pair_x[p] (else p)
+    const int32_t* pair_y;  // nullable: consumer set pair_y[p] (else p)
+    int64_t num_a_sets;
+    int64_t num_b_sets;
+    int64_t single_m;
+    int64_t single_n;
+    int32_t max_m;          // LDS capacity of this launch
+    int32_t max_n;
+    int32_t protocol;
+    int32_t pad;
+    uint64_t seed;
+    int64_t max_rounds;
+    double* costs;
+    int32_t* plan_src;
+    int32_t* plan_dst;
+    double* plan_flow;
+    const int64_t* plan_off;
+    int64_t single_plan_cap;
+    nnsemd_stats_t* stats;
+    const int32_t* order;   // nullable: workgroup b solves pair order[b]
+};
+// blocks != nullptr: occupancy query only.
+int launch_cost_solver(const CostArgs& A, bool f64, int chunk_max, size_t lds, int grid, void* stream, int* blocks);
+// Exact FP64 L1 distance matrices of high-dimensional pairs (BF16 or FP32
+// points), in dimension order: pair pair_base + b of the doc arguments into
+// tiles + b * tile_stride (FP64, row-major m x n).
+int launch_l1_tiles(const DocArgs& A, bool bf16, double* tiles, int64_t tile_stride, int grid, void* stream);
+
+// ---------------------------------------------------------------------
 // Barycentric map of a plan (transport_map.hip): per-row buckets of plan
 // positions, so every row is summed in plan order.
 struct MapWork {
@@ -297,6 +338,17 @@ MapWork map_ws_carve(char* base, int64_t rows, int64_t cap);
 int launch_barycentric_map(const int32_t* src, const int32_t* dst, const double* flow, int64_t cap,
                            const int64_t* nnz, const float* P, int64_t p_rows, int d, int side, int64_t rows,
                            double* map, const MapWork& w, void* stream);
+
+// ---------------------------------------------------------------------
+// Colour transfer application (colour_transfer.hip).
+size_t kmeans_lds_bytes(int K);
+// K-means palette of P 8-bit RGB pixels (iters update steps, then the final
+// assignment): centroids C (K x 3, FP64), sums/counts S (K x 4), assignment,
+// palette points (K x 3 FP32) and masses (K FP32).
+int launch_kmeans(const uint8_t* px, int64_t P, int K, int iters, double* C, unsigned long long* S,
+                  int32_t* assign, float* pts, float* mass, void* stream);
+int launch_recolour(const uint8_t* px, const int32_t* assign, int64_t P, const double* T, uint8_t* out,
+                    void* stream);
 
 // Launch entry points (defined in pair_solver.hip).
 // Returns hipSuccess-compatible int (0 on success).

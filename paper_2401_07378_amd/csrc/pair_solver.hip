@@ -77,6 +77,34 @@ __device__ inline float search_gap_bound_l1(float b1) {
     return 4.f * (float)(D + 1) * kU32 * b1 + 1e-30f;
 }
 
+// Fractional bits of a finite FP32 value: the smallest q >= 0 with v a
+// multiple of 2^-q (0 for 0; a large value for subnormals, which never
+// qualify for the exact-key test below).
+__device__ inline int frac_bits(float v) {
+    const uint32_t u = __float_as_uint(v) & 0x7fffffffu;
+    if (u == 0u) return 0;
+    const int e = (int)(u >> 23);
+    if (e == 0) return 200;
+    const int tz = __builtin_ctz((u & 0x7fffffu) | 0x800000u);
+    const int q = 23 - tz - (e - 127);
+    return q > 0 ? q : 0;
+}
+
+// Exact-key test.  If every centred coordinate is a multiple of 2^-q with
+// magnitude <= R, every term of a Euclidean key (x^_t^2, 2 x^_t y^_t) is a
+// multiple of 2^-2q and every partial sum is at most 3 D R^2 in magnitude, so
+// all of them are FP32 numbers when 3 D R^2 4^q < 2^24: each FMA of the key
+// chain is then exact, the FP32 keys equal the exact ones (shifted by the
+// exact ||y^||^2), and the FP32 argmin with its smallest-slot tie rule is the
+// FP64 definition's.  L1 (uncentred): terms |x_t - y_t| <= 2R, sums <= 2DR,
+// exact when 2 D R 2^q < 2^24.  Integer-lattice inputs (pixel grids) pass.
+template <int D, bool L1>
+__device__ inline bool keys_exact(double q, double R) {
+    if (q > 40.0) return false;
+    const double s = exp2(q);
+    return L1 ? 2.0 * D * R * s < 16777216.0 : 3.0 * D * R * R * s * s < 16777216.0;
+}
+
 template <int D, int RS, bool L1>
 __device__ inline float key32(const float* __restrict__ rec, const float (&y)[D]) {
     if (L1) {
@@ -100,7 +128,8 @@ __device__ inline float key32(const float* __restrict__ rec, const float (&y)[D]
 template <int D, int RS, bool L1, int KC>
 __device__ inline void nns_pass(const Lds16& L, SharedCore& sh, const float* __restrict__ X,
                                 const float* __restrict__ Y, const float (&centre)[D], float rhat,
-                                int mact, int nact, int S, int qa, int G, int r) {
+                                int mact, int nact, int S, int qa, int G, int r, bool exact, int metric,
+                                int64_t& ties_nn) {
     int jj[KC];
     bool valid[KC];
     float y[KC][D];
@@ -177,6 +206,18 @@ __device__ inline void nns_pass(const Lds16& L, SharedCore& sh, const float* __r
     int pick[KC];
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
+        if (exact) {
+            // exact keys: the pick stands; the two nearest distances are
+            // b + ||y^||^2 exactly (FP64 holds the sum exactly)
+            flag[k] = false;
+            pick[k] = bs[k];
+            if (valid[k] && mact > 1) {
+                const double k1 = L1 ? (double)b1[k] : (double)b1[k] + (double)yn2[k];
+                const double k2 = L1 ? (double)b2[k] : (double)b2[k] + (double)yn2[k];
+                if (near_tie_dist(dist_of_key(k1, metric), dist_of_key(k2, metric))) ++ties_nn;
+            }
+            continue;
+        }
         // win: the proven search bound (see search_gap_bound) plus the window
         // in which the two nearest suppliers may still be a near tie.
         float win;
@@ -309,6 +350,7 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds16& L, S
     // index, mass, claimant count and bucket offset are compacted together.
     int mact = 0, nact = 0;
     float rhat = 0.f;
+    bool exact = false;  // every FP32 key is exact (keys_exact)
     if (status == NNSEMD_OK) {
         const int cs = (mi + T - 1) / T;
         const int cc = (ni + T - 1) / T;
@@ -329,6 +371,8 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds16& L, S
         mact = (int)(tot & 0xffffffffu);
         nact = (int)(tot >> 32);
         float rmax = 0.f;
+        int fq = 0;        // fractional bits of the (centred) coordinates
+        float amax = 0.f;  // their largest magnitude
 #pragma unroll
         for (int u = 0; u < CSMAX; ++u) {
             if (!(mv[u] > 0.0)) continue;
@@ -338,7 +382,11 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds16& L, S
             for (int q = 0; q < RS; ++q) r[q] = 0.f;
             if (L1) {
 #pragma unroll
-                for (int t = 0; t < D; ++t) r[t] = X[(size_t)i * D + t];
+                for (int t = 0; t < D; ++t) {
+                    r[t] = X[(size_t)i * D + t];
+                    fq = max(fq, frac_bits(r[t]));
+                    amax = fmaxf(amax, fabsf(r[t]));
+                }
             } else {
                 float h = 0.f;
 #pragma unroll
@@ -346,6 +394,8 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds16& L, S
                     float xc = X[(size_t)i * D + t] - centre[t];
                     r[t] = -2.f * xc;
                     h = fmaf(xc, xc, h);
+                    fq = max(fq, frac_bits(xc));
+                    amax = fmaxf(amax, fabsf(xc));
                 }
                 r[D] = h;
                 rmax = fmaxf(rmax, sqrtf(h));
@@ -356,12 +406,22 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds16& L, S
             L.scnt[ps] = 0;
             ++ps;
         }
-        for (int j = clo; j < chi; ++j)
-            if (L.cmass[j] > 0.0) L.cact[pc++] = j;
-        double rr[1] = {(double)rmax};
-        const int ro[1] = {2};
-        block_reduce<T, 1>(rr, ro, L.ckey);  // also orders the writes above
+        for (int j = clo; j < chi; ++j) {
+            if (L.cmass[j] > 0.0) {
+                L.cact[pc++] = j;
+#pragma unroll
+                for (int t = 0; t < D; ++t) {
+                    const float yc = L1 ? Y[(size_t)j * D + t] : Y[(size_t)j * D + t] - centre[t];
+                    fq = max(fq, frac_bits(yc));
+                    amax = fmaxf(amax, fabsf(yc));
+                }
+            }
+        }
+        double rr[3] = {(double)rmax, (double)fq, (double)amax};
+        const int ro[3] = {2, 2, 2};
+        block_reduce<T, 3>(rr, ro, L.ckey);  // also orders the writes above
         rhat = (float)rr[0] * (1.f + 1e-6f);
+        exact = keys_exact<D, L1>(rr[1], rr[2]);
         if (tid == 0) sh.nflag = 0;
         __syncthreads();
     }
@@ -396,13 +456,17 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds16& L, S
             const int G = T / S;
             for (int q0 = 0; q0 < nact; q0 += G * kc) {
                 if (kc == 4)
-                    nns_pass<D, RS, L1, 4>(L, sh, X, Y, centre, rhat, mact, nact, S, q0 + g, G, r);
+                    nns_pass<D, RS, L1, 4>(L, sh, X, Y, centre, rhat, mact, nact, S, q0 + g, G, r, exact, A.metric,
+                                           ties_nn);
                 else if (kc == 3)
-                    nns_pass<D, RS, L1, 3>(L, sh, X, Y, centre, rhat, mact, nact, S, q0 + g, G, r);
+                    nns_pass<D, RS, L1, 3>(L, sh, X, Y, centre, rhat, mact, nact, S, q0 + g, G, r, exact, A.metric,
+                                           ties_nn);
                 else if (kc == 2)
-                    nns_pass<D, RS, L1, 2>(L, sh, X, Y, centre, rhat, mact, nact, S, q0 + g, G, r);
+                    nns_pass<D, RS, L1, 2>(L, sh, X, Y, centre, rhat, mact, nact, S, q0 + g, G, r, exact, A.metric,
+                                           ties_nn);
                 else
-                    nns_pass<D, RS, L1, 1>(L, sh, X, Y, centre, rhat, mact, nact, S, q0 + g, G, r);
+                    nns_pass<D, RS, L1, 1>(L, sh, X, Y, centre, rhat, mact, nact, S, q0 + g, G, r, exact, A.metric,
+                                           ties_nn);
             }
         }
         __syncthreads();

@@ -25,6 +25,14 @@ Workloads (the suppliers X,a are searched by the consumers Y,b):
                      clipped to [0,1]^3, uniform masses, squared Euclidean.
   retrieval_3d       1 query vs C candidates of 256 points each, Gaussian
                      mixtures with 1..8 components, uniform masses.
+  lattice_hist_2d    N images on an s x s pixel grid (s = 28 or 32): every
+                     pixel is a point at its integer (row, col), its mass the
+                     normalised 8-bit intensity; pair p = (image p, image
+                     p + 1 mod N), L2.  Two image styles: sparse strokes
+                     (digit-like, most pixels 0) and smooth positive
+                     densities (sums of Gaussian bumps).
+  colour_images      seeded smooth RGB images (8-bit) for the colour
+                     transfer application.
 """
 from __future__ import annotations
 
@@ -38,6 +46,8 @@ SEEDS = {
     "documents_300d": 1003,
     "colour_transfer_3d": 1004,
     "retrieval_3d": 1005,
+    "lattice_hist_2d": 1006,
+    "colour_images": 1007,
 }
 
 
@@ -308,3 +318,73 @@ def random_doc_pair(seed: int, m: int, n: int, d: int, masses: str = "zipf", lat
     else:
         a, b = zipf_masses(r, m), zipf_masses(r, n)
     return X.reshape(m, d), a, Y.reshape(n, d), b
+
+
+def _stroke_image(r, side: int) -> np.ndarray:
+    """8-bit intensities of 1..3 thick random strokes (quadratic curves) on a
+    dark background, blurred one pixel: most pixels are exactly 0."""
+    img = np.zeros((side, side))
+    yy, xx = np.mgrid[0:side, 0:side].astype(np.float64)
+    for _ in range(int(r.integers(1, 4))):
+        p0, p1, p2 = r.uniform(0.15 * side, 0.85 * side, size=(3, 2))
+        width = r.uniform(0.9, 1.8)
+        for t in np.linspace(0.0, 1.0, 4 * side):
+            c = (1 - t) ** 2 * p0 + 2 * (1 - t) * t * p1 + t ** 2 * p2
+            img = np.maximum(img, np.exp(-((yy - c[0]) ** 2 + (xx - c[1]) ** 2) / (2 * width ** 2)))
+    q = np.floor(255.0 * img + 0.5)
+    q[q < 24] = 0.0  # background
+    return q
+
+
+def _smooth_image(r, side: int) -> np.ndarray:
+    """8-bit intensities of a smooth positive density: 2..6 Gaussian bumps of
+    random width and weight plus a floor, so every pixel has mass."""
+    yy, xx = np.mgrid[0:side, 0:side].astype(np.float64)
+    img = np.full((side, side), 0.05)
+    for _ in range(int(r.integers(2, 7))):
+        cy, cx = r.uniform(0, side, size=2)
+        w = r.uniform(0.05, 0.3) * side
+        img += r.uniform(0.2, 1.0) * np.exp(-((yy - cy) ** 2 + (xx - cx) ** 2) / (2 * w ** 2))
+    return np.floor(1.0 + 254.0 * img / img.max() + 0.5)
+
+
+def lattice_hist_2d(num_images: int = 1024, side: int = 32, style: str = "smooth",
+                    seed: int = SEEDS["lattice_hist_2d"]) -> PairSet:
+    """Pixel-grid histograms: image k (stream k of the seed) on a side x side
+    grid; points are the integer (row, col) of every pixel (FP32, exact), the
+    masses the 8-bit intensities normalised in FP64 then rounded to FP32;
+    pair p compares image p (suppliers) with image (p + 1) mod N."""
+    yy, xx = np.mgrid[0:side, 0:side]
+    grid = to_f32(np.stack([yy.ravel(), xx.ravel()], 1))
+    sets = []
+    for k in range(num_images):
+        r = rng_for(seed + (0 if style == "smooth" else 100), k)
+        img = _smooth_image(r, side) if style == "smooth" else _stroke_image(r, side)
+        w = img.ravel().astype(np.float64)
+        sets.append((grid, to_f32(w / w.sum())))
+    Xc, ac, xo = _concat(sets, 2)
+    pair_x = np.arange(num_images, dtype=np.int32)
+    pair_y = ((np.arange(num_images) + 1) % num_images).astype(np.int32)
+    return PairSet("lattice_hist_2d", 2, Xc, ac, xo, Xc, ac, xo, pair_x=pair_x, pair_y=pair_y, metric="l2",
+                   meta={"num_images": num_images, "side": side, "style": style, "seed": seed})
+
+
+def colour_image(k: int, height: int = 256, width: int = 256, seed: int = SEEDS["colour_images"]) -> np.ndarray:
+    """Seeded smooth RGB image (uint8, height x width x 3): each channel a sum
+    of a few random low-frequency waves and bumps, scaled to 0..255."""
+    r = rng_for(seed, k)
+    yy, xx = np.mgrid[0:height, 0:width].astype(np.float64)
+    yy /= height
+    xx /= width
+    out = np.zeros((height, width, 3))
+    for c in range(3):
+        f = np.zeros((height, width))
+        for _ in range(3):
+            fy, fx, ph = r.uniform(0.5, 3.0), r.uniform(0.5, 3.0), r.uniform(0, 2 * np.pi)
+            f += r.uniform(0.3, 1.0) * np.sin(2 * np.pi * (fy * yy + fx * xx) + ph)
+        for _ in range(2):
+            cy, cx, w = r.uniform(0, 1), r.uniform(0, 1), r.uniform(0.05, 0.3)
+            f += r.uniform(-1.0, 1.0) * np.exp(-((yy - cy) ** 2 + (xx - cx) ** 2) / (2 * w ** 2))
+        f = (f - f.min()) / max(f.max() - f.min(), 1e-12)
+        out[..., c] = f * r.uniform(0.6, 1.0) + r.uniform(0.0, 0.3)
+    return np.clip(np.floor(255.0 * out / max(out.max(), 1e-12) + 0.5), 0, 255).astype(np.uint8)

@@ -210,3 +210,52 @@ def test_documents_full_size_sampled():
         assert int(st["rounds"]) == ref["rounds"] and int(st["work"]) == ref["work"], p
         assert int(st["nnz"]) == ref["nnz"], p
         assert abs(float(g["costs"][p]) - ref["cost"]) <= 1e-12 * ref["cost"], p
+
+
+# -------------------------------------------------------------- L1 metric
+# L1 is not a contraction: each pair's distance matrix is summed exactly in
+# FP64 (dimension order, the definition's operations), then Algorithm 1 runs
+# on it; plans, counts and cost equal the oracle's.
+L1_CASES = [
+    (1, 40, 60, 300, "zipf", "greedy"),
+    (2, 500, 500, 300, "zipf", "greedy"),
+    (3, 1, 77, 300, "zipf", "greedy"),
+    (4, 77, 1, 50, "dirichlet", "random"),
+    (5, 130, 170, 33, "dirichlet", "greedy"),
+    (6, 96, 96, 1024, "uniform", "greedy"),
+]
+
+
+@pytest.mark.parametrize("case", L1_CASES, ids=lambda c: "-".join(map(str, c[1:])))
+def test_l1_high_dim_pairs(case):
+    seed, m, n, d, masses, protocol = case
+    Xb, a, Yb, b = W.random_doc_pair(890 + seed, m, n, d, masses=masses)
+    kw = dict(protocol=protocol, seed=9)
+    ref = oracle_pair(f32(Xb), a, f32(Yb), b, "l1", **kw)
+    assert_pair_matches(gpu_pair_bf16(Xb, a, Yb, b, "l1", **kw), ref, label=f"bf16-{case}")
+    assert_pair_matches(gpu_pair(f32(Xb).reshape(m, d), a, f32(Yb).reshape(n, d), b, "l1", **kw), ref,
+                        label=f"f32-{case}")
+
+
+def test_l1_high_dim_lattice_ties():
+    Xb, a, Yb, b = W.random_doc_pair(897, 150, 180, 40, masses="uniform", lattice=3)
+    ref = oracle_pair(f32(Xb), a, f32(Yb), b, "l1")
+    assert ref["near_ties_nn"] > 0
+    assert_pair_matches(gpu_pair_bf16(Xb, a, Yb, b, "l1"), ref, label="lattice")
+
+
+def test_l1_documents_batched_sampled():
+    """The document workload's shape (one 300-d query against ragged
+    candidates of 20..500 points, Zipf masses) under L1: 256 candidates in
+    one call, every pair against the oracle."""
+    ps = W.documents_300d(num_candidates=256)
+    ps.metric = "l1"
+    g = gpu_batched(ps, mode="bf16_mfma_refine", plan=True)
+    for p in range(ps.num_pairs):
+        X, a, Y, b = ps.pair(p)
+        ref = oracle_pair(X, a, Y, b, "l1")
+        lo = g["plan_off"][p]
+        k = int(g["stats"][p]["nnz"])
+        gp = {"cost": float(g["costs"][p]), "stats": g["stats"][p], "src": g["src"][lo:lo + k],
+              "dst": g["dst"][lo:lo + k], "flow": g["flow"][lo:lo + k]}
+        assert_pair_matches(gp, ref, label=f"cand{p}")

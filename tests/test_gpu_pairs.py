@@ -157,9 +157,8 @@ def test_host_side_errors():
     from paper_2401_07378_amd import binding
     X, a, Y, b = W.random_pair(98, 10, 10, 9)
     t = lambda v: torch.from_numpy(np.ascontiguousarray(v)).cuda()
-    with pytest.raises(binding.NNSEMDError) as e:
-        binding.emd_approx(t(X), t(a), t(Y), t(b), "l1")
-    assert e.value.status == -7  # L1 at d = 9: beyond the point path, not on the high-dimensional one
+    # L1 at d = 9 runs on the high-dimensional path (exact FP64 distances)
+    assert_pair_matches(gpu_pair(X, a, Y, b, "l1"), oracle_pair(X, a, Y, b, "l1"), label="l1-d9")
     with pytest.raises(binding.NNSEMDError) as e:
         binding.emd_approx(t(X), t(a), t(Y), t(b), path="multi")
     assert e.value.status == -7  # the multi-workgroup path is for d <= 7

@@ -518,3 +518,58 @@ def test_barycentric_dst_permutation_and_empty_rows():
     r = oracle.solve(X, a, Y, b)
     T = oracle.barycentric_dst(r["src"], r["dst"], r["flow"], X, 40)
     assert np.all(np.isnan(T[[4, 17]])) and not np.any(np.isnan(np.delete(T, [4, 17], axis=0)))
+
+
+# ------------------------------------------------------------ colour transfer
+def _gray(vals):
+    return np.repeat(np.asarray(vals, np.uint8)[:, None], 3, axis=1)
+
+
+def test_kmeans_hand_worked_lloyd():
+    """Gray pixels 0, 2, 10, 12 with K = 2: the start takes pixels 0 and 2
+    (colours 0 and 10); both iterations assign {0, 2} and {10, 12}, so the
+    centroids become 1 and 11 with two pixels each."""
+    C, n, asg = oracle.kmeans(_gray([0, 2, 10, 12]), 2, 3)
+    np.testing.assert_array_equal(C, [[1, 1, 1], [11, 11, 11]])
+    np.testing.assert_array_equal(n, [2, 2])
+    np.testing.assert_array_equal(asg, [0, 0, 1, 1])
+
+
+def test_kmeans_ties_and_empty_clusters():
+    """Pixel 5 is equidistant from centroids 0 and 10: it joins cluster 0.
+    A start with two equal colours leaves the second cluster empty; it keeps
+    its centroid and count 0."""
+    C, n, asg = oracle.kmeans(_gray([0, 10, 5]), 2, 0)
+    np.testing.assert_array_equal(asg, [0, 1, 0])
+    C, n, asg = oracle.kmeans(_gray([7, 7, 7, 7, 9, 9]), 3, 2)
+    assert list(n) == [4, 0, 2]
+    np.testing.assert_array_equal(C[1], [7, 7, 7])
+
+
+def test_kmeans_block_image_recovers_colours():
+    rng = np.random.default_rng(3)
+    cols = rng.integers(0, 256, size=(8, 3)).astype(np.uint8)
+    img = np.repeat(cols, 50, axis=0)  # eight blocks of 50 pixels
+    C, n, asg = oracle.kmeans(img, 8, 5)
+    np.testing.assert_array_equal(C, cols.astype(np.float64))
+    np.testing.assert_array_equal(n, np.full(8, 50))
+    np.testing.assert_array_equal(asg, np.repeat(np.arange(8), 50))
+
+
+def test_recolour_rounding_and_nan_rows():
+    px = np.array([[10, 20, 30], [40, 50, 60]], np.uint8)
+    T = np.array([[0.5, 1.0 / 255.0, np.nan], [2.0, -0.25, 0.0]])
+    out = oracle.recolour(px, np.array([0, 1], np.int32), T)
+    np.testing.assert_array_equal(out, [[128, 1, 30], [255, 0, 0]])  # 127.5 -> 128 (half to even)
+
+
+def test_colour_transfer_onto_itself_quantises():
+    """Reference = source: the palettes are equal, NNS-EMD is 0 in one round
+    (Theorem 2, identical sets) and the map sends every bin to its own colour,
+    so each pixel becomes its rounded centroid."""
+    img = W.colour_image(5, 48, 40).reshape(-1, 3)
+    out = oracle.colour_transfer(img, img, 16, 16, 4)
+    assert out["solve"]["cost"] == 0.0 and out["solve"]["rounds"] == 1
+    C, _, asg = oracle.kmeans(img, 16, 4)
+    want = np.clip(np.rint(255.0 * (C / 255.0).astype(np.float32).astype(np.float64)), 0, 255).astype(np.uint8)[asg]
+    np.testing.assert_array_equal(out["image"], want)
