@@ -349,6 +349,37 @@ nnsemd_status_t nnsemd_colour_transfer(nnsemd_handle_t h,
                                        double* cost, nnsemd_stats_t* stats,
                                        void* stream);
 
+/*
+ * emd_approx_batched_noalloc -- emd_approx_batched for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments and results as
+ * emd_approx_batched on the low-dimensional point path; its one scratch
+ * buffer, the longest-first schedule (one int32 per pair), lives in a fixed
+ * device array of 65536 entries (256 KiB on every GPU the library runs on,
+ * held until the process ends) instead of handle workspace, so the call
+ * allocates nothing.
+ * Limits: FP32 points with 1 <= d <= 7 (else UNSUPPORTED), num_pairs <=
+ * 65536 (else INVALID_ARG); other errors as emd_approx_batched.
+ * All calls on one GPU share that array (the schedule is rewritten in full
+ * by every call, nothing needs clearing): calls that overlap in time on the
+ * same GPU -- from other streams or host threads -- race on it and must be
+ * ordered by the caller.
+ */
+nnsemd_status_t emd_approx_batched_noalloc(nnsemd_handle_t h, int64_t num_pairs,
+                                           const void* Xcat, const float* acat,
+                                           const int64_t* x_off, int64_t num_x_sets,
+                                           const void* Ycat, const float* bcat,
+                                           const int64_t* y_off, int64_t num_y_sets,
+                                           const int32_t* pair_x, const int32_t* pair_y,
+                                           int64_t max_m, int64_t max_n,
+                                           int32_t d, nnsemd_dtype_t dtype, nnsemd_metric_t metric,
+                                           const nnsemd_options_t* opts,
+                                           double* costs,
+                                           int32_t* plan_src, int32_t* plan_dst, double* plan_flow,
+                                           const int64_t* plan_off,
+                                           nnsemd_stats_t* stats,
+                                           void* stream);
+
 /* ------------------------------------------------------------------------
  * Autotuning of the batched point path (FP32, 1 <= d <= 7).  The launch
  * configuration -- workgroup size (256 or 512) and the search split factor

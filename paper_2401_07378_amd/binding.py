@@ -33,7 +33,8 @@ STATS_BYTES = STATS_DTYPE.itemsize
 
 EXPORTS = ["nnsemd_create", "nnsemd_destroy", "nnsemd_status_string", "nnsemd_last_error",
            "emd_approx", "emd_approx_map", "emd_approx_batched", "emd_barycentric_map",
-           "emd_approx_cost", "emd_approx_cost_batched",
+           "emd_approx_cost", "emd_approx_cost_batched", "nnsemd_colour_transfer",
+           "emd_approx_batched_noalloc",
            "nnsemd_sg_num_params", "nnsemd_sg_embed", "nnsemd_sg_predict", "nnsemd_sg_loss_grad",
            "nnsemd_sg_train_step", "nnsemd_topk_smallest_f32", "nnsemd_topk_smallest_f64", "nnsemd_sg_retrieve",
            "nnsemd_autotune", "nnsemd_tuning_save", "nnsemd_tuning_load"]
@@ -87,6 +88,8 @@ def load_library():
         lib.emd_approx_batched.argtypes = [P, I64, P, P, P, I64, P, P, P, I64, P, P, I64, I64, I32, I32,
                                            I32, ctypes.POINTER(Options), P, P, P, P, P, P, P]
         lib.emd_approx_batched.restype = I32
+        lib.emd_approx_batched_noalloc.argtypes = lib.emd_approx_batched.argtypes
+        lib.emd_approx_batched_noalloc.restype = I32
         lib.emd_approx_map.argtypes = [P, P, P, I64, P, P, I64, I32, I32, I32, ctypes.POINTER(Options),
                                        P, P, P, P, P, I64, P, P]
         lib.emd_approx_map.restype = I32
@@ -97,6 +100,9 @@ def load_library():
         lib.emd_approx_cost_batched.argtypes = [P, I64, P, P, I32, P, P, P, P, I64, I64, ctypes.POINTER(Options),
                                                 P, P, P, P, P, P, P]
         lib.emd_approx_cost_batched.restype = I32
+        lib.nnsemd_colour_transfer.argtypes = [P, P, I64, P, I64, I32, I32, I32, I32, ctypes.POINTER(Options), P, P,
+                                               P, P, P, P, P, P, P]
+        lib.nnsemd_colour_transfer.restype = I32
         F32 = ctypes.c_float
         lib.nnsemd_sg_num_params.argtypes = []
         lib.nnsemd_sg_num_params.restype = I64
@@ -320,6 +326,39 @@ def emd_approx_cost_batched(Dcat, d_off, acat, a_off, bcat, b_off, *, max_m: int
     return {"costs": costs, "stats": stats, "plan_src": src, "plan_dst": dst, "plan_flow": flow}
 
 
+def colour_transfer(ref_rgb, src_rgb, k_ref: int = 256, k_src: int = 256, iters: int = 10, metric: str = "l2",
+                    protocol: str = "greedy", seed: int = 0, out: dict | None = None) -> dict:
+    """Colour transfer by NNS-EMD (uint8 device images of shape (P, 3) or
+    (H, W, 3)): k-means palettes, NNS-EMD reference -> source palette,
+    recoloured source through the per-consumer barycentric map.  Returns
+    device tensors: image (like src_rgb), palettes, masses, the source
+    assignment, cost and stats.  Asynchronous."""
+    import torch
+    lib = load_library()
+    dev = _dev_of(src_rgb)
+    h = handle(dev)
+    _require(ref_rgb, torch.uint8, "ref_rgb")
+    _require(src_rgb, torch.uint8, "src_rgb")
+    Pr, Ps = ref_rgb.numel() // 3, src_rgb.numel() // 3
+    o = out or {}
+    d = src_rgb.device
+    img = o.get("image") if o.get("image") is not None else torch.empty_like(src_rgb)
+    rp = torch.empty((k_ref, 3), dtype=torch.float32, device=d)
+    rm = torch.empty(k_ref, dtype=torch.float32, device=d)
+    sp = torch.empty((k_src, 3), dtype=torch.float32, device=d)
+    sm = torch.empty(k_src, dtype=torch.float32, device=d)
+    asg = torch.empty(Ps, dtype=torch.int32, device=d)
+    cost = torch.empty(1, dtype=torch.float64, device=d)
+    stats = torch.empty(STATS_BYTES, dtype=torch.uint8, device=d)
+    opts = _options(protocol, "fp32", 0, seed, 0)
+    st = lib.nnsemd_colour_transfer(h, _ptr(ref_rgb), Pr, _ptr(src_rgb), Ps, k_ref, k_src, iters, METRICS[metric],
+                                    ctypes.byref(opts), _ptr(img), _ptr(rp), _ptr(rm), _ptr(sp), _ptr(sm),
+                                    _ptr(asg), _ptr(cost), _ptr(stats), _stream(torch, dev))
+    _check(lib, h, st)
+    return {"image": img, "ref_palette": rp, "ref_mass": rm, "src_palette": sp, "src_mass": sm, "assign": asg,
+            "cost": cost, "stats": stats}
+
+
 MAP_SIDES = {"suppliers": 0, "consumers": 1}
 
 
@@ -363,12 +402,15 @@ def emd_approx_batched(Xcat, acat, x_off, Ycat, bcat, y_off, *, max_m: int, max_
                        pair_x=None, pair_y=None, num_pairs: int | None = None, metric: str = "l2",
                        plan_off=None, protocol: str = "greedy", mode: str = "fp32", seed: int = 0,
                        max_rounds: int = 0, threads: int = 0, schedule: str = "longest_first",
-                       out: dict | None = None) -> dict:
+                       out: dict | None = None, noalloc: bool = False) -> dict:
     """NNS-EMD of many ragged pairs in one persistent launch.  Offsets and
     pair tables are int64/int32 CUDA tensors; max_m/max_n are host bounds on
     the set sizes.  With plan_off (CUDA int64, num_pairs + 1) the plans are
     written too.  Returns device tensors costs (num_pairs,), stats
-    (num_pairs * STATS_BYTES uint8) and the plan buffers.  Asynchronous."""
+    (num_pairs * STATS_BYTES uint8) and the plan buffers.  Asynchronous.
+    noalloc: the entry point that allocates nothing (point path only).  Pass
+    every output in `out` (and plan_total with a plan) so that this binding
+    allocates nothing either."""
     import torch
     lib = load_library()
     dev = Xcat.device.index if Xcat.device.index is not None else torch.cuda.current_device()
@@ -405,7 +447,8 @@ def emd_approx_batched(Xcat, acat, x_off, Ycat, bcat, y_off, *, max_m: int, max_
         dst = o.get("plan_dst") if o.get("plan_dst") is not None else torch.empty(max(total, 1), dtype=torch.int32, device=Xcat.device)
         flow = o.get("plan_flow") if o.get("plan_flow") is not None else torch.empty(max(total, 1), dtype=torch.float64, device=Xcat.device)
     opts = _options(protocol, mode, max_rounds, seed, threads, schedule)
-    st = lib.emd_approx_batched(
+    fn = lib.emd_approx_batched_noalloc if noalloc else lib.emd_approx_batched
+    st = fn(
         h, num_pairs, _ptr(Xcat), _ptr(acat), _ptr(x_off), nx, _ptr(Ycat), _ptr(bcat), _ptr(y_off), ny,
         _ptr(pair_x), _ptr(pair_y), int(max_m), int(max_n), d,
         DTYPES["bf16" if mode == "bf16_mfma_refine" else "f32"], METRICS[metric], ctypes.byref(opts),

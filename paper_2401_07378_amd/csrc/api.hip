@@ -6,11 +6,26 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
 
 #include "internal.hpp"
+
+// Fixed device scratch of emd_approx_batched_noalloc: the longest-first
+// schedule (one int32 per pair) for callers that cannot allocate.  Each GPU
+// holds its own copy until the process ends.  Host code never uses this name
+// as an address: the device address of each GPU's copy is taken once per
+// device (nnsemd_create) and kept in g_scratch_dev.
+constexpr int kNoAllocMaxPairs = 65536;
+static __device__ __align__(256) int32_t scratch[kNoAllocMaxPairs];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int32_t* g_scratch_dev[kMaxDevices] = {};
+}  // namespace
 
 constexpr int nnsemd_tune_classes = 6;  // max side <= 128, 256, 512, 1024, 2048, 4096
 
@@ -45,6 +60,7 @@ struct nnsemd_handle {
     size_t map_plan_bytes = 0;
     char* ct_ws = nullptr;                       // colour transfer: palettes, assignments, plan, map
     size_t ct_bytes = 0;
+    int32_t* fixed_order = nullptr;              // this device's copy of `scratch` (no-alloc schedule)
 };
 
 namespace {
@@ -110,8 +126,10 @@ int tune_class(int64_t maxp) {
 
 // Common entry for one or many pairs of low-dimensional FP32 points.
 // forced_threads / forced_split > 0 bypass the options and the tuning table.
+// fixed_order != nullptr: the schedule goes there (no handle workspace).
 nnsemd_status_t run_pairs(nnsemd_handle_t h, PairSolverArgs& A, int d, int64_t max_m, int64_t max_n,
-                          const nnsemd_options_t& o, void* stream, int forced_threads = 0, int forced_split = 0) {
+                          const nnsemd_options_t& o, void* stream, int forced_threads = 0, int forced_split = 0,
+                          int32_t* fixed_order = nullptr) {
     if (d < 1 || d > 7) return fail(h, NNSEMD_ERR_UNSUPPORTED, "point path supports 1 <= d <= 7");
     int threads = o.threads > 0 ? o.threads : 256;
     int split = 2;
@@ -163,10 +181,17 @@ nnsemd_status_t run_pairs(nnsemd_handle_t h, PairSolverArgs& A, int d, int64_t m
     A.share_order = share ? 1 : 0;
     const int64_t grid = A.num_pairs;
     if (A.x_off != nullptr && A.num_pairs > 1 && o.schedule == NNSEMD_SCHEDULE_LONGEST_FIRST) {
-        nnsemd_status_t s = schedule(h, A.x_off, A.y_off, A.pair_x, A.pair_y, A.num_pairs, A.num_x_sets,
-                                     A.num_y_sets, stream);
-        if (s != NNSEMD_OK) return s;
-        A.order = h->order;
+        if (fixed_order != nullptr) {
+            err = launch_order(A.x_off, A.y_off, A.pair_x, A.pair_y, A.num_pairs, A.num_x_sets, A.num_y_sets,
+                               fixed_order, stream);
+            if (err != 0) return device_fail(h, err, "schedule launch");
+            A.order = fixed_order;
+        } else {
+            nnsemd_status_t s = schedule(h, A.x_off, A.y_off, A.pair_x, A.pair_y, A.num_pairs, A.num_x_sets,
+                                         A.num_y_sets, stream);
+            if (s != NNSEMD_OK) return s;
+            A.order = h->order;
+        }
     }
     err = launch_pair_solver(A, d, threads, chunk, coords, lds_bytes, (int)grid, stream);
     if (err != 0) return device_fail(h, err, "solver launch");
@@ -591,6 +616,19 @@ nnsemd_status_t nnsemd_create(nnsemd_handle_t* out, int32_t device) {
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
         delete h;
         return NNSEMD_ERR_DEVICE;
+    }
+    {
+        // the device address of this GPU's fixed scratch, taken once per device
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (device < kMaxDevices && g_scratch_dev[device] == nullptr) {
+            void* ptr = nullptr;
+            if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr) {
+                delete h;
+                return NNSEMD_ERR_DEVICE;
+            }
+            g_scratch_dev[device] = static_cast<int32_t*>(ptr);
+        }
+        h->fixed_order = device < kMaxDevices ? g_scratch_dev[device] : nullptr;
     }
     h->num_cus = prop.multiProcessorCount;
     h->max_lds = prop.sharedMemPerBlock;
@@ -1047,6 +1085,59 @@ nnsemd_status_t emd_approx_batched(nnsemd_handle_t h, int64_t num_pairs, const v
     A.plan_off = plan ? plan_off : nullptr;
     A.stats = stats;
     return run_pairs(h, A, d, max_m, max_n, o, stream);
+}
+
+nnsemd_status_t emd_approx_batched_noalloc(nnsemd_handle_t h, int64_t num_pairs, const void* Xcat,
+                                           const float* acat, const int64_t* x_off, int64_t num_x_sets,
+                                           const void* Ycat, const float* bcat, const int64_t* y_off,
+                                           int64_t num_y_sets, const int32_t* pair_x, const int32_t* pair_y,
+                                           int64_t max_m, int64_t max_n, int32_t d, nnsemd_dtype_t dtype,
+                                           nnsemd_metric_t metric, const nnsemd_options_t* opts, double* costs,
+                                           int32_t* plan_src, int32_t* plan_dst, double* plan_flow,
+                                           const int64_t* plan_off, nnsemd_stats_t* stats, void* stream) {
+    if (h == nullptr) return NNSEMD_ERR_INVALID_ARG;
+    h->last_error.clear();
+    const nnsemd_options_t o = opts ? *opts : default_options();
+    nnsemd_status_t s = check_common(h, d, dtype, metric, o);
+    if (s != NNSEMD_OK) return s;
+    if (use_doc_path(d, dtype))
+        return fail(h, NNSEMD_ERR_UNSUPPORTED, "the no-allocation call covers FP32 points with 1 <= d <= 7");
+    if (num_pairs < 0 || num_x_sets < 0 || num_y_sets < 0 || max_m < 0 || max_n < 0)
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "negative count");
+    if (num_pairs > kNoAllocMaxPairs)
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "the no-allocation call takes at most 65536 pairs");
+    if (num_pairs == 0) return NNSEMD_OK;
+    if (costs == nullptr || x_off == nullptr || y_off == nullptr || Xcat == nullptr || Ycat == nullptr ||
+        acat == nullptr || bcat == nullptr)
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "NULL required array");
+    if (num_x_sets == 0 || num_y_sets == 0) return fail(h, NNSEMD_ERR_INVALID_ARG, "no point sets");
+    if ((pair_x == nullptr && num_x_sets < num_pairs) || (pair_y == nullptr && num_y_sets < num_pairs))
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "fewer sets than pairs without a pair table");
+    const bool plan = plan_src != nullptr || plan_dst != nullptr || plan_flow != nullptr;
+    if (plan && (plan_src == nullptr || plan_dst == nullptr || plan_flow == nullptr || plan_off == nullptr))
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "plan arrays and plan_off must be all given or all NULL");
+    if (h->fixed_order == nullptr) return fail(h, NNSEMD_ERR_DEVICE, "fixed scratch not available on this device");
+    DeviceGuard g(h->device);
+    PairSolverArgs A{};
+    A.num_pairs = num_pairs;
+    A.X = static_cast<const float*>(Xcat);
+    A.a = acat;
+    A.x_off = x_off;
+    A.num_x_sets = num_x_sets;
+    A.Y = static_cast<const float*>(Ycat);
+    A.b = bcat;
+    A.y_off = y_off;
+    A.num_y_sets = num_y_sets;
+    A.pair_x = pair_x;
+    A.pair_y = pair_y;
+    A.metric = metric;
+    A.costs = costs;
+    A.plan_src = plan ? plan_src : nullptr;
+    A.plan_dst = plan ? plan_dst : nullptr;
+    A.plan_flow = plan ? plan_flow : nullptr;
+    A.plan_off = plan ? plan_off : nullptr;
+    A.stats = stats;
+    return run_pairs(h, A, d, max_m, max_n, o, stream, 0, 0, h->fixed_order);
 }
 
 nnsemd_status_t nnsemd_autotune(nnsemd_handle_t h, int32_t d, nnsemd_metric_t metric, int64_t max_m, int64_t max_n,

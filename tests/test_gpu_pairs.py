@@ -332,3 +332,36 @@ def test_near_tie_counts_hand_inputs(metric, far):
     g = gpu_pair(X, a, Y, b, metric)
     assert int(g["stats"]["near_ties_order"]) == 1
     assert_pair_matches(g, oracle_pair(X, a, Y, b, metric), label="order")
+
+
+# ------------------------------------------------- pixel-grid histograms
+@pytest.mark.parametrize("side,style", [(32, "smooth"), (28, "strokes")])
+@pytest.mark.parametrize("protocol", ["greedy", "random"])
+def test_lattice_histograms_batched(side, style, protocol):
+    """Pixel-grid histograms (integer coordinates, exact keys, dense exact
+    ties): 48 pairs in one launch with plans, every pair against the oracle."""
+    ps = W.lattice_hist_2d(48, side, style)
+    kw = dict(protocol=protocol, seed=5)
+    g = gpu_batched(ps, plan=True, **kw)
+    for p in range(ps.num_pairs):
+        X, a, Y, b = ps.pair(p)
+        ref = oracle_pair(X, a, Y, b, **kw)
+        lo = g["plan_off"][p]
+        k = int(g["stats"][p]["nnz"])
+        gp = {"cost": float(g["costs"][p]), "stats": g["stats"][p], "src": g["src"][lo:lo + k],
+              "dst": g["dst"][lo:lo + k], "flow": g["flow"][lo:lo + k]}
+        assert_pair_matches(gp, ref, label=f"{style}-pair{p}")
+        assert int(g["stats"][p]["rescored"]) == 0  # exact keys: nothing to re-score
+
+
+def test_lattice_histograms_full_sweep_size_sampled():
+    """16384 pairs of 32 x 32 images (the largest batch of the sweep) in one
+    launch, cost + stats; a seeded sample against the oracle."""
+    ps = W.lattice_hist_2d(16384, 32, "smooth")
+    g = gpu_batched(ps, plan=False)
+    assert np.all(g["stats"]["status"] == 0)
+    rng = np.random.default_rng(8)
+    for p in sorted(set(rng.choice(ps.num_pairs, 12, replace=False).tolist()) | {0, ps.num_pairs - 1}):
+        X, a, Y, b = ps.pair(p)
+        assert_pair_matches({"cost": float(g["costs"][p]), "stats": g["stats"][p]},
+                            oracle_pair(X, a, Y, b, with_plan=False), plan=False, label=f"pair{p}")

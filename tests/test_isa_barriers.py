@@ -63,7 +63,8 @@ def test_scanner_flags_the_bad_shape():
 
 
 @pytest.mark.skipif(not shutil.which(HIPCC) and not os.path.exists(HIPCC), reason="hipcc not available")
-@pytest.mark.parametrize("src", ["pair_solver.hip", "large_pair.hip", "doc_solver.hip", "surrogate.hip"])
+@pytest.mark.parametrize("src", ["pair_solver.hip", "large_pair.hip", "doc_solver.hip", "surrogate.hip",
+                                 "cost_solver.hip", "transport_map.hip", "colour_transfer.hip"])
 def test_solver_kernels_have_no_divergent_back_edge_into_a_barrier(tmp_path, src):
     out = tmp_path / (src + ".s")
     cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "--offload-device-only", "-S",
