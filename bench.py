@@ -714,9 +714,15 @@ def bench_documents(args, dev):
         same = (np.array([r["rounds"] for r in ref]) == st["rounds"][:S]) & \
                (np.array([r["work"] for r in ref]) == st["work"][:S]) & \
                (np.array([r["nnz"] for r in ref]) == st["nnz"][:S])
-        near_same = (np.array([r["near_ties_nn"] for r in ref]) == st["near_ties_nn"][:S]) & \
-                    (np.array([r["near_ties_order"] for r in ref]) == st["near_ties_order"][:S])
+        ref_nn = np.array([r["near_ties_nn"] for r in ref])
+        ref_ord = np.array([r["near_ties_order"] for r in ref])
+        near_same = (ref_nn == st["near_ties_nn"][:S]) & (ref_ord == st["near_ties_order"][:S])
+        bad = np.nonzero(~near_same)[0][:8]
+        mismatch = [[int(p), int(st["near_ties_nn"][p]), int(st["near_ties_order"][p]), int(ref_nn[p]),
+                     int(ref_ord[p])] for p in bad]
         parity = {"max_rel_err": float(rel.max()), "pairs_checked": S, "stats_identical": int(same.sum()),
+                  "oracle_near_ties_nn": int(ref_nn.sum()), "oracle_near_ties_order": int(ref_ord.sum()),
+                  "near_tie_mismatch_first": mismatch,
                   "rescored_consumers": int(st["rescored"].sum()),
                   "near_ties_nn": int(st["near_ties_nn"].sum()), "near_ties_order": int(st["near_ties_order"].sum()),
                   "near_ties_identical": int(near_same.sum()), "tolerance": 1e-3,

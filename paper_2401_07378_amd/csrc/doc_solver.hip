@@ -612,11 +612,11 @@ __device__ inline void rank_greedy_doc(const Lds& L, Shared& sh, int nact, const
         const int sl = L.cnn[j];
         if (e > L.soff[sl] - L.scnt[sl]) {
             const double kp = L.ckey[L.sorted[e - 1]], kj = L.ckey[j];
-            if (kp >= 0.0 && kj >= 0.0 && near_tie_dist(dist_of_key(kp, metric), dist_of_key(kj, metric)))
-                ++ties_order;
+            if (kp >= 0.0 && kj >= 0.0 && keys_near(kp, kj, metric)) ++ties_order;
         }
     }
     if (threadIdx.x == 0) sh.namb = 0;
+    __syncthreads();  // the serve walk overwrites the keys and picks read above
 }
 
 // Row ranges of pair p (status INVALID_ARG and empty sides if the tables or

@@ -327,6 +327,7 @@ __global__ __launch_bounds__(kLpScanThreads) void lp_setup(LPArgs A, int nblocks
         st->mact = status == NNSEMD_OK ? (int)(tot & 0xffffffffu) : 0;
         st->nact = status == NNSEMD_OK ? (int)(tot >> 32) : 0;
         st->nflag = 0;
+        st->nbig = 0;
         st->nnz = 0;
         st->work = 0;
         st->near = 0;
@@ -733,12 +734,26 @@ __global__ __launch_bounds__(kLpThreads) void lp_scatter(LPArgs A) {
 
 // ------------------------------------------------------------------ ties
 // Greedy protocol: near ties of neighbouring claimants in each supplier's
-// serve order, over the whole bucket (served or not).  One thread per
-// claimant finds its predecessor in (key, j) order -- the largest bucket
-// member below it -- by a scan of the bucket, and counts a near tie of the
-// two distances.  Keys are the exact FP64 keys the decide / re-score stored.
+// serve order, over the whole bucket (served or not), on the exact FP64 keys
+// the decide / re-score stored.  Buckets of up to kLpTiesSmall claimants:
+// one thread per claimant finds its predecessor in (key, j) order -- the
+// largest member below it -- by a scan of the bucket.  Larger buckets are
+// listed (by their rank-0 claimant) and sorted in LDS by lp_ties_big.
+constexpr int kLpTiesSmall = 64;
+constexpr int kLpTiesThreads = 1024;
+constexpr int kLpTiesSort = 4096;  // bucket sizes sorted in LDS
+constexpr int kLpTiesBlocks = 64;
+
+// Near tie of two keys (L2: of their square roots).  The key-space test
+// rejects every pair whose distances are more than (2e-6 + 1e-12) apart
+// relative, so the square roots are taken only for candidates.
+__device__ inline bool lp_keys_near(double k1, double k2, int metric) {
+    if (metric == NNSEMD_L2 && k2 - k1 > 2.1e-6 * k1 + 1e-24) return false;
+    return lp_near_tie(lp_dist(k1, metric), lp_dist(k2, metric));
+}
+
 __global__ __launch_bounds__(kLpThreads) void lp_ties(LPArgs A) {
-    const LPState* st = A.w.st;
+    LPState* st = A.w.st;
     if (!lp_live(st)) return;
     const int q = blockIdx.x * kLpThreads + threadIdx.x;
     const int nact = st->nact;
@@ -747,7 +762,9 @@ __global__ __launch_bounds__(kLpThreads) void lp_ties(LPArgs A) {
         const int j = A.w.cact[st->parity][q];
         const int s = A.w.cnn[j];
         const int c = A.w.scnt[s];
-        if (c > 1) {
+        if (c > kLpTiesSmall) {
+            if (A.w.sorted[j] == 0) A.w.big[atomicAdd(&st->nbig, 1)] = s;  // rank-0 claimant lists it
+        } else if (c > 1) {
             const int start = A.w.soff[s];
             const double k = A.w.ckey[j];
             double pk = -INFINITY;
@@ -760,12 +777,84 @@ __global__ __launch_bounds__(kLpThreads) void lp_ties(LPArgs A) {
                     any = true;
                 }
             }
-            hit = any && lp_near_tie(lp_dist(pk, A.metric), lp_dist(k, A.metric));
+            hit = any && lp_keys_near(pk, k, A.metric);
         }
     }
     const unsigned long long m = __ballot(hit != 0);
     if ((threadIdx.x & (kWave - 1)) == 0 && m != 0ull)
-        atomicAdd((unsigned long long*)&A.w.st->ties_order, (unsigned long long)__popcll(m));
+        atomicAdd((unsigned long long*)&st->ties_order, (unsigned long long)__popcll(m));
+}
+
+// Listed buckets: keys and consumer indices sorted by (key, j) with a
+// bitonic network in LDS (one workgroup per bucket, padded to a power of
+// two), then neighbours compared.  Buckets beyond kLpTiesSort fall back to
+// one thread per claimant scanning the bucket.
+__global__ __launch_bounds__(kLpTiesThreads) void lp_ties_big(LPArgs A) {
+    __shared__ double sk[kLpTiesSort];
+    __shared__ int sj[kLpTiesSort];
+    __shared__ int hits;
+    LPState* st = A.w.st;
+    if (!lp_live(st)) return;
+    const int nbig = st->nbig;
+    const int tid = threadIdx.x;
+    for (int b = blockIdx.x; b < nbig; b += gridDim.x) {
+        const int s = A.w.big[b];
+        const int c = A.w.scnt[s];
+        const int start = A.w.soff[s];
+        if (tid == 0) hits = 0;
+        int mine = 0;
+        if (c <= kLpTiesSort) {
+            int P = 1;
+            while (P < c) P <<= 1;
+            for (int e = tid; e < P; e += kLpTiesThreads) {
+                const int j = e < c ? A.w.list[start + e] : 0x7fffffff;
+                sk[e] = e < c ? A.w.ckey[j] : INFINITY;
+                sj[e] = j;
+            }
+            __syncthreads();
+            for (int size = 2; size <= P; size <<= 1) {
+                for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                    for (int e = tid; e < P; e += kLpTiesThreads) {
+                        const int o = e ^ stride;
+                        if (o > e) {
+                            const bool up = (e & size) == 0;
+                            const double ka = sk[e], kb = sk[o];
+                            const int ja = sj[e], jb = sj[o];
+                            const bool gt = ka > kb || (ka == kb && ja > jb);
+                            if (gt == up) {
+                                sk[e] = kb;
+                                sk[o] = ka;
+                                sj[e] = jb;
+                                sj[o] = ja;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            for (int e = tid + 1; e < c; e += kLpTiesThreads) mine += lp_keys_near(sk[e - 1], sk[e], A.metric);
+        } else {
+            for (int e = tid; e < c; e += kLpTiesThreads) {
+                const int j = A.w.list[start + e];
+                const double k = A.w.ckey[j];
+                double pk = -INFINITY;
+                bool any = false;
+                for (int f = start; f < start + c; ++f) {
+                    const int j2 = A.w.list[f];
+                    const double k2 = A.w.ckey[j2];
+                    if (k2 < k || (k2 == k && j2 < j)) {
+                        pk = fmax(pk, k2);
+                        any = true;
+                    }
+                }
+                mine += any && lp_keys_near(pk, k, A.metric);
+            }
+        }
+        if (mine) atomicAdd(&hits, mine);
+        __syncthreads();
+        if (tid == 0 && hits) atomicAdd((unsigned long long*)&st->ties_order, (unsigned long long)hits);
+        __syncthreads();
+    }
 }
 
 // ----------------------------------------------------------------- serve
@@ -966,6 +1055,7 @@ __device__ void lp_commit_round(const LPArgs& A, int nblocks, bool single, unsig
     st->work += (int64_t)st->mact * st->nact;
     st->near += st->nflag;
     st->nflag = 0;
+    st->nbig = 0;
     st->rounds += 1;
     st->mact = m2;
     st->nact = n2;
@@ -1161,7 +1251,10 @@ int lp_launch_round(const LPArgs& A, int d, int mact_ub, int nact_ub, void* stre
         }
         hipLaunchKernelGGL(lp_offsets, dim3(1), dim3(kLpScanThreads), 0, st, A);
         hipLaunchKernelGGL(lp_scatter, dim3(qblocks), dim3(kLpThreads), 0, st, A);
-        if (A.protocol == NNSEMD_GREEDY) hipLaunchKernelGGL(lp_ties, dim3(qblocks), dim3(kLpThreads), 0, st, A);
+        if (A.protocol == NNSEMD_GREEDY) {
+            hipLaunchKernelGGL(lp_ties, dim3(qblocks), dim3(kLpThreads), 0, st, A);
+            hipLaunchKernelGGL(lp_ties_big, dim3(kLpTiesBlocks), dim3(kLpTiesThreads), 0, st, A);
+        }
         hipLaunchKernelGGL(lp_serve<DD>, dim3(wblocks), dim3(kLpThreads), 0, st, A);
         if (cmblocks > 1) hipLaunchKernelGGL(lp_ccount, dim3(cmblocks), dim3(kLpThreads), 0, st, A);
         hipLaunchKernelGGL(lp_cwrite<DD>, dim3(cmblocks), dim3(kLpThreads), 0, st, A);

@@ -443,29 +443,34 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds16& L, S
         // ---- 1. NNS: FP32 scan, best + second best, near ties deferred;
         // each decided consumer also counts itself into its pick's bucket.
         // S lanes share one consumer (each scans every S-th supplier) when
-        // there are too few consumers to fill the workgroup; otherwise each
-        // lane takes KC (1 to 4, the fewest that cover the active consumers)
-        // so one record load feeds KC key chains.
+        // there are too few consumers to fill the workgroup.  Otherwise the
+        // active consumers are cut into 64-consumer slots and the slots
+        // dealt to the wavefronts as evenly as possible; a wavefront with k
+        // slots scans the records once with k consumers per lane (one record
+        // load feeds k key chains), so only the last slot has idle lanes.
         int S = 1;
         while (S < kWave && nact * S * A.split <= T) S <<= 1;
         while (S > 1 && S > mact) S >>= 1;
-        const int kc = S > 1 ? 1 : (nact > 3 * T ? 4 : (nact > 2 * T ? 3 : (nact > T ? 2 : 1)));
-        {
-            const int r = tid & (S - 1);
-            const int g = tid / S;
-            const int G = T / S;
-            for (int q0 = 0; q0 < nact; q0 += G * kc) {
-                if (kc == 4)
-                    nns_pass<D, RS, L1, 4>(L, sh, X, Y, centre, rhat, mact, nact, S, q0 + g, G, r, exact, A.metric,
+        if (S > 1) {
+            nns_pass<D, RS, L1, 1>(L, sh, X, Y, centre, rhat, mact, nact, S, tid / S, T / S, tid & (S - 1), exact,
+                                   A.metric, ties_nn);
+        } else {
+            const int nslots = (nact + kWave - 1) / kWave;
+            const int lo = wave * nslots / NW, hi = (wave + 1) * nslots / NW;
+            for (int u0 = lo; u0 < hi; u0 += 4) {
+                const int k = min(4, hi - u0);  // wavefront-uniform
+                const int qa = u0 * kWave + lane;
+                if (k == 4)
+                    nns_pass<D, RS, L1, 4>(L, sh, X, Y, centre, rhat, mact, nact, 1, qa, kWave, 0, exact, A.metric,
                                            ties_nn);
-                else if (kc == 3)
-                    nns_pass<D, RS, L1, 3>(L, sh, X, Y, centre, rhat, mact, nact, S, q0 + g, G, r, exact, A.metric,
+                else if (k == 3)
+                    nns_pass<D, RS, L1, 3>(L, sh, X, Y, centre, rhat, mact, nact, 1, qa, kWave, 0, exact, A.metric,
                                            ties_nn);
-                else if (kc == 2)
-                    nns_pass<D, RS, L1, 2>(L, sh, X, Y, centre, rhat, mact, nact, S, q0 + g, G, r, exact, A.metric,
+                else if (k == 2)
+                    nns_pass<D, RS, L1, 2>(L, sh, X, Y, centre, rhat, mact, nact, 1, qa, kWave, 0, exact, A.metric,
                                            ties_nn);
                 else
-                    nns_pass<D, RS, L1, 1>(L, sh, X, Y, centre, rhat, mact, nact, S, q0 + g, G, r, exact, A.metric,
+                    nns_pass<D, RS, L1, 1>(L, sh, X, Y, centre, rhat, mact, nact, 1, qa, kWave, 0, exact, A.metric,
                                            ties_nn);
             }
         }

@@ -121,6 +121,15 @@ __device__ inline bool near_tie_dist(double d1, double d2) {
     return d1 == 0.0 ? gap <= 1e-12 : gap <= 1e-6 * d1;
 }
 
+// Near tie of two keys k1 <= k2 (L2: of their square roots).  For L2 the
+// key-space test first rejects every pair whose distances are more than
+// (2e-6 + 1e-12) apart relative, so square roots are taken only for the few
+// candidates; the decision itself is always the one on distances.
+__device__ inline bool keys_near(double k1, double k2, int metric) {
+    if (metric == NNSEMD_L2 && k2 - k1 > 2.1e-6 * k1 + 1e-24) return false;
+    return near_tie_dist(dist_of_key(k1, metric), dist_of_key(k2, metric));
+}
+
 // Width, in FP32 key units, of the window past the proven search bound in
 // which two keys may still be a near tie.  Squared keys: the distances'
 // relative gap 1e-6 is a key gap of at most (2e-6 + 1e-12) of the smaller
@@ -326,7 +335,7 @@ __device__ inline void round_walk(const LT& L, int mact, int metric, double& cos
         const int isup = L.sidx[s];
         int pos = start;
         double sm = L.smass[s];
-        double prev = 0.0;  // distance of the previous claimant in the order
+        double prev = 0.0;  // key of the previous claimant in the order
         while (pos < end && sm > 0.0) {
             const int j = L.sorted[pos];
             const double cm = L.cmass[j];
@@ -334,11 +343,11 @@ __device__ inline void round_walk(const LT& L, int mact, int metric, double& cos
             sm = sm - f;
             L.cmass[j] = cm - f;
             if constexpr (COST) {
-                const double dj = dist_of_key(L.ckey[j], metric);
-                cost = cost + f * dj;
+                const double kj = L.ckey[j];
+                cost = cost + f * dist_of_key(kj, metric);
                 if (ties) {
-                    if (pos > start && near_tie_dist(prev, dj)) ++*ties_order;
-                    prev = dj;
+                    if (pos > start && keys_near(prev, kj, metric)) ++*ties_order;
+                    prev = kj;
                 }
             }
             L.ckey[j] = f;
@@ -349,9 +358,9 @@ __device__ inline void round_walk(const LT& L, int mact, int metric, double& cos
             const int j = L.sorted[e];
             if constexpr (COST) {
                 if (ties) {
-                    const double dj = dist_of_key(L.ckey[j], metric);
-                    if (e > start && near_tie_dist(prev, dj)) ++*ties_order;
-                    prev = dj;
+                    const double kj = L.ckey[j];
+                    if (e > start && keys_near(prev, kj, metric)) ++*ties_order;
+                    prev = kj;
                 }
             }
             L.ckey[j] = 0.0;

@@ -110,11 +110,10 @@ def test_unsupported_combinations_raise():
     import torch
     from paper_2401_07378_amd import binding
     from tests.gpu_helpers import to_dev, to_dev_bf16
-    Xb, a, Yb, b = W.random_doc_pair(882, 10, 10, 300)
+    Xb, a, Yb, b = W.random_doc_pair(883, 4097, 3, 16)
     with pytest.raises(binding.NNSEMDError) as e:
         binding.emd_approx(to_dev_bf16(Xb), to_dev(a), to_dev_bf16(Yb), to_dev(b), "l1", mode="bf16_mfma_refine")
-    assert e.value.status == -7
-    Xb, a, Yb, b = W.random_doc_pair(883, 4097, 3, 16)
+    assert e.value.status == -7  # L1 keeps sides <= 4096 as well
     with pytest.raises(binding.NNSEMDError) as e:
         binding.emd_approx(to_dev_bf16(Xb), to_dev(a), to_dev_bf16(Yb), to_dev(b), mode="bf16_mfma_refine")
     assert e.value.status == -7

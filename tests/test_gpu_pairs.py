@@ -60,12 +60,30 @@ def test_higher_point_dims(d):
 
 @pytest.mark.parametrize("seed", range(4))
 def test_lattice_ties(seed):
-    """Integer coordinates: FP32 keys are exact, ties are real and the
-    FP64 re-score path decides them by the smallest index."""
+    """Integer coordinates: every FP32 key is exact (the exact-key test
+    passes at ingest), ties are real, and the FP32 argmin's smallest-slot
+    rule decides them as the FP64 definition does, with nothing re-scored;
+    near ties are counted from the exact keys."""
     X, a, Y, b = W.random_pair(60 + seed, 200, 240, 2, masses="integer", lattice=6)
     g = gpu_pair(X, a, Y, b)
-    assert int(g["stats"]["rescored"]) > 0
-    assert_pair_matches(g, oracle_pair(X, a, Y, b), label=f"lattice{seed}")
+    ref = oracle_pair(X, a, Y, b)
+    assert int(g["stats"]["rescored"]) == 0 and ref["near_ties_nn"] > 0
+    assert_pair_matches(g, ref, label=f"lattice{seed}")
+
+
+@pytest.mark.parametrize("metric", ["l2", "sqeuclidean", "l1"])
+def test_exact_key_test_boundary(metric):
+    """Lattice coordinates scaled just below and just above the exact-key
+    limit (3 D R^2 4^q < 2^24; L1: 2 D R 2^q < 2^24): both sides of the
+    limit give the oracle's plan; only the exact side skips the re-score."""
+    X, a, Y, b = W.random_pair(65, 150, 170, 3, masses="integer", lattice=4)
+    for scale, exact in ((256.0, True), (8192.0, False)):
+        Xs = (X.astype(np.float64) * scale).astype(np.float32)
+        Ys = (Y.astype(np.float64) * scale).astype(np.float32)
+        g = gpu_pair(Xs, a, Ys, b, metric)
+        assert_pair_matches(g, oracle_pair(Xs, a, Ys, b, metric), label=f"{metric}-{scale}")
+        if exact:
+            assert int(g["stats"]["rescored"]) == 0
 
 
 def test_duplicate_points():
