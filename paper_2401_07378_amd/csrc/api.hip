@@ -264,7 +264,7 @@ nnsemd_status_t run_large(nnsemd_handle_t h, LPArgs& A, int d, void* stream) {
     const size_t o_cact0 = take(4 * ncap), o_cact1 = take(4 * ncap);
     const size_t o_cmass = take(8 * ncap), o_cnn = take(4 * ncap), o_ckey = take(8 * ncap);
     const size_t o_list = take(4 * ncap), o_sorted = take(4 * ncap), o_flag = take(4 * ncap);
-    const size_t o_big = take(4 * mcap);
+    const size_t o_tkey = take(8 * ncap), o_thead = take(4 * ncap), o_tnext = take(4 * ncap);
     const size_t o_part = take(16 * part_cap), o_blk = take(8 * blk_cap);
     const size_t o_cost = take(8 * mcap);
     const size_t o_wsum = want_map ? take(8 * mcap) : 0, o_bsum = want_map ? take(8 * mcap * d) : 0;
@@ -299,7 +299,9 @@ nnsemd_status_t run_large(nnsemd_handle_t h, LPArgs& A, int d, void* stream) {
     w.list = reinterpret_cast<int32_t*>(base + o_list);
     w.sorted = reinterpret_cast<int32_t*>(base + o_sorted);
     w.flagged = reinterpret_cast<int32_t*>(base + o_flag);
-    w.big = reinterpret_cast<int32_t*>(base + o_big);
+    w.tkey = reinterpret_cast<double*>(base + o_tkey);
+    w.thead = reinterpret_cast<int32_t*>(base + o_thead);
+    w.tnext = reinterpret_cast<int32_t*>(base + o_tnext);
     w.part = reinterpret_cast<float4*>(base + o_part);
     w.ncap = ncap;
     w.part_cap = part_cap;

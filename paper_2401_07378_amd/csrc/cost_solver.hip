@@ -32,6 +32,7 @@ __device__ inline bool bad_entry(TD v) {
 template <typename TD, int T, int CSMAX>
 __device__ void solve_cost_pair(const CostArgs& A, int64_t p, const Lds16& L, SharedCore& sh) {
     const int tid = threadIdx.x;
+    if (tid == 0) sh.tie_order = 0ull;  // ordered before use by the ingest's reductions
     int64_t m = A.single_m, n = A.single_n, a0 = 0, b0 = 0, d0 = 0;
     int status = NNSEMD_OK;
     if (A.a_off != nullptr) {
@@ -143,7 +144,7 @@ __device__ void solve_cost_pair(const CostArgs& A, int64_t p, const Lds16& L, Sh
     // ---- rounds
     const int64_t max_rounds = A.max_rounds > 0 ? A.max_rounds : (int64_t)mi + ni;
     int rounds = 0;
-    int64_t work = 0, nnz = 0, ties_nn = 0, ties_order = 0;
+    int64_t work = 0, nnz = 0, ties_nn = 0;
     double cost = 0.0;
     while (status == NNSEMD_OK && mact > 0 && nact > 0) {
         if (rounds >= max_rounds) {
@@ -208,21 +209,22 @@ __device__ void solve_cost_pair(const CostArgs& A, int64_t p, const Lds16& L, Sh
         }
         __syncthreads();
         round_buckets<T>(L, sh, mact, nact);
-        round_rank<T, CSMAX>(L, nact, A.protocol, A.seed, rounds);
         // keys are the distances themselves (metric code SQEUCLIDEAN: D = key)
-        round_walk<T>(L, mact, NNSEMD_SQEUCLIDEAN, cost, A.protocol == NNSEMD_GREEDY, &ties_order);
+        round_rank<T, CSMAX>(L, nact, A.protocol, A.seed, rounds, NNSEMD_SQEUCLIDEAN,
+                             A.protocol == NNSEMD_GREEDY ? &sh.tie_order : nullptr);
+        round_walk<T>(L, mact, NNSEMD_SQEUCLIDEAN, cost);
         round_compact<T, CSMAX, 0>(L, sh, mact, nact, nnz, want_plan ? A.plan_src : nullptr, A.plan_dst,
                                    A.plan_flow, plan_base);
         ++rounds;
     }
 
-    double fin[5] = {cost, 0.0, 0.0, (double)ties_nn, (double)ties_order};
-    const int fop[5] = {0, 0, 0, 0, 0};
+    double fin[4] = {cost, 0.0, 0.0, (double)ties_nn};
+    const int fop[4] = {0, 0, 0, 0};
     if (status == NNSEMD_OK || status == NNSEMD_ERR_NOT_CONVERGED) {
         for (int s = tid; s < mact; s += T) fin[1] += L.smass[s];
         for (int q = tid; q < nact; q += T) fin[2] += L.cmass[L.cact[q]];
     }
-    block_reduce<T, 5>(fin, fop, L.ckey);
+    block_reduce<T, 4>(fin, fop, L.ckey);  // its barriers also order the order-tie atomics
     if (tid == 0) {
         A.costs[p] = status == NNSEMD_OK ? fin[0] : NAN;
         if (A.stats != nullptr) {
@@ -235,7 +237,7 @@ __device__ void solve_cost_pair(const CostArgs& A, int64_t p, const Lds16& L, Sh
             st.residual_src = fin[1];
             st.residual_dst = fin[2];
             st.near_ties_nn = (int64_t)fin[3];
-            st.near_ties_order = (int64_t)fin[4];
+            st.near_ties_order = (int64_t)sh.tie_order;
             A.stats[p] = st;
         }
     }

@@ -104,7 +104,7 @@ struct LPState {
     int64_t nnz, work, near;
     int64_t ties_nn, ties_order;  // near-tie counters (see nnsemd_stats_t)
     int32_t rounds, done, parity, ticket;  // ticket: blocks of the round's last kernel that have finished
-    int32_t nbig, pad0;                    // suppliers whose bucket is sorted for the near-tie count
+    int32_t pad0, pad2;
     float centre[8];
     float rhat, pad1;
     double sum_a, sum_b;
@@ -123,7 +123,9 @@ struct LPWork {
     int32_t* list;       // claimant buckets
     int32_t* sorted;     // claimant buckets in serve order
     int32_t* flagged;    // near-tie consumers of the round
-    int32_t* big;        // suppliers (slots) with more than kLpTiesSmall claimants
+    double* tkey;        // near-tie bin tables, by bucket position: FP64 key,
+    int32_t* thead;      //   chain heads (-1 = empty; all -1 between rounds)
+    int32_t* tnext;      //   and chain links
     float4* part;        // per (supplier chunk, consumer) FP32 best/second/slot
     int64_t ncap;        // consumer capacity (row stride of part)
     int64_t part_cap;    // entries of part

@@ -201,6 +201,7 @@ __global__ __launch_bounds__(kLpThreads) void lp_ingest(LPArgs A) {
         }
     }
     if (i < A.n) {
+        A.w.thead[i] = -1;  // bin tables of the near-tie count start empty
         const float bv = A.b[i];
         if (!(bv >= 0.f) || !isfinite(bv)) v[2] = 1.0;
         v[1] = (double)bv;
@@ -327,7 +328,6 @@ __global__ __launch_bounds__(kLpScanThreads) void lp_setup(LPArgs A, int nblocks
         st->mact = status == NNSEMD_OK ? (int)(tot & 0xffffffffu) : 0;
         st->nact = status == NNSEMD_OK ? (int)(tot >> 32) : 0;
         st->nflag = 0;
-        st->nbig = 0;
         st->nnz = 0;
         st->work = 0;
         st->near = 0;
@@ -721,28 +721,37 @@ __global__ __launch_bounds__(kLpScanThreads) void lp_offsets(LPArgs A) {
     }
 }
 
-// --------------------------------------------------------------- scatter
-// Claimants into their buckets at the ranks the counting handed out.
-__global__ __launch_bounds__(kLpThreads) void lp_scatter(LPArgs A) {
-    const LPState* st = A.w.st;
-    if (!lp_live(st)) return;
-    const int q = blockIdx.x * kLpThreads + threadIdx.x;
-    if (q >= st->nact) return;
-    const int j = A.w.cact[st->parity][q];
-    A.w.list[A.w.soff[A.w.cnn[j]] + A.w.sorted[j]] = j;
-}
-
 // ------------------------------------------------------------------ ties
 // Greedy protocol: near ties of neighbouring claimants in each supplier's
 // serve order, over the whole bucket (served or not), on the exact FP64 keys
-// the decide / re-score stored.  Buckets of up to kLpTiesSmall claimants:
-// one thread per claimant finds its predecessor in (key, j) order -- the
-// largest member below it -- by a scan of the bucket.  Larger buckets are
-// listed (by their rank-0 claimant) and sorted in LDS by lp_ties_big.
-constexpr int kLpTiesSmall = 64;
-constexpr int kLpTiesThreads = 1024;
-constexpr int kLpTiesSort = 4096;  // bucket sizes sorted in LDS
-constexpr int kLpTiesBlocks = 64;
+// the decide / re-score stored.  The count over a bucket depends only on its
+// sorted keys, so any total order that sorts by key will do; (key, bucket
+// position) is used.  A claimant counts when its predecessor in that order
+// -- the largest member below it -- is a near tie of it.
+//
+// No sort: keys fall into bins of relative width 2^-18 .. 2^-17 (the FP64
+// bit pattern shifted right by 35; every key below 2^-30 in bin 0), wider
+// than any near-tie gap (2.1e-6 relative in squared keys, 1e-6 in distances,
+// and 1e-12 at distance zero lies inside bin 0).  So if the predecessor is a
+// near tie it lies in the claimant's bin or the one below, and the largest
+// member below the claimant within those two bins is then the predecessor
+// itself; if the two bins hold no member below it, the predecessor is at
+// least a whole bin away and not a near tie.  Each bucket keeps a chained
+// hash table of its members by bin, in its own span of bucket positions:
+// heads (thead, all -1 between rounds), links (tnext) and the keys by
+// position (tkey).  The scatter inserts, lp_ties queries, the serve clears
+// the heads of its bucket for the next round.
+constexpr double kLpTieBinFloor = 0x1p-30;
+
+__device__ inline uint64_t lp_tie_bin(double k) {
+    const uint64_t f = (uint64_t)__double_as_longlong(kLpTieBinFloor);
+    return k < kLpTieBinFloor ? 0ull : (((uint64_t)__double_as_longlong(k) - f) >> 35) + 1ull;
+}
+
+__device__ inline int lp_tie_slot(uint64_t bin, int c) {
+    const uint64_t h = (bin * 0x9E3779B97F4A7C15ull) >> 32;  // Fibonacci hashing
+    return (int)((h * (uint64_t)c) >> 32);
+}
 
 // Near tie of two keys (L2: of their square roots).  The key-space test
 // rejects every pair whose distances are more than (2e-6 + 1e-12) apart
@@ -752,109 +761,64 @@ __device__ inline bool lp_keys_near(double k1, double k2, int metric) {
     return lp_near_tie(lp_dist(k1, metric), lp_dist(k2, metric));
 }
 
+// --------------------------------------------------------------- scatter
+// Claimants into their buckets at the ranks the counting handed out; under
+// the greedy protocol each member of a bucket of two or more also enters
+// its bucket's bin table.
+__global__ __launch_bounds__(kLpThreads) void lp_scatter(LPArgs A) {
+    const LPState* st = A.w.st;
+    if (!lp_live(st)) return;
+    const int q = blockIdx.x * kLpThreads + threadIdx.x;
+    if (q >= st->nact) return;
+    const int j = A.w.cact[st->parity][q];
+    const int s = A.w.cnn[j];
+    const int start = A.w.soff[s];
+    const int e = start + A.w.sorted[j];
+    A.w.list[e] = j;
+    const int c = A.w.scnt[s];
+    if (A.protocol == NNSEMD_GREEDY && c > 1) {
+        const double k = A.w.ckey[j];
+        A.w.tkey[e] = k;
+        A.w.tnext[e] = atomicExch(&A.w.thead[start + lp_tie_slot(lp_tie_bin(k), c)], e);
+    }
+}
+
+// One thread per claimant: the largest member below it in its own bin and
+// the bin below (an equal key at a smaller position ends the search: the
+// predecessor then has the claimant's key), then the near-tie test.
 __global__ __launch_bounds__(kLpThreads) void lp_ties(LPArgs A) {
     LPState* st = A.w.st;
     if (!lp_live(st)) return;
     const int q = blockIdx.x * kLpThreads + threadIdx.x;
-    const int nact = st->nact;
     int hit = 0;
-    if (q < nact) {
+    if (q < st->nact) {
         const int j = A.w.cact[st->parity][q];
         const int s = A.w.cnn[j];
         const int c = A.w.scnt[s];
-        if (c > kLpTiesSmall) {
-            if (A.w.sorted[j] == 0) A.w.big[atomicAdd(&st->nbig, 1)] = s;  // rank-0 claimant lists it
-        } else if (c > 1) {
+        if (c > 1) {
             const int start = A.w.soff[s];
-            const double k = A.w.ckey[j];
-            double pk = -INFINITY;
-            bool any = false;
-            for (int e = start; e < start + c; ++e) {
-                const int j2 = A.w.list[e];
-                const double k2 = A.w.ckey[j2];
-                if (k2 < k || (k2 == k && j2 < j)) {
-                    pk = fmax(pk, k2);
-                    any = true;
+            const int e = start + A.w.sorted[j];
+            const double x = A.w.tkey[e];
+            const uint64_t bx = lp_tie_bin(x);
+            double pk = -1.0;  // keys are >= +0: -1 = no member below
+            for (int db = 0; db < 2 && pk != x; ++db) {
+                if (db == 1 && bx == 0ull) break;
+                const uint64_t bb = bx - (uint64_t)db;
+                for (int f = A.w.thead[start + lp_tie_slot(bb, c)]; f >= 0; f = A.w.tnext[f]) {
+                    const double y = A.w.tkey[f];
+                    if (f == e || lp_tie_bin(y) != bb) continue;
+                    if (y < x || (y == x && f < e)) {
+                        pk = fmax(pk, y);
+                        if (pk == x) break;
+                    }
                 }
             }
-            hit = any && lp_keys_near(pk, k, A.metric);
+            hit = pk >= 0.0 && lp_keys_near(pk, x, A.metric);
         }
     }
     const unsigned long long m = __ballot(hit != 0);
     if ((threadIdx.x & (kWave - 1)) == 0 && m != 0ull)
         atomicAdd((unsigned long long*)&st->ties_order, (unsigned long long)__popcll(m));
-}
-
-// Listed buckets: keys and consumer indices sorted by (key, j) with a
-// bitonic network in LDS (one workgroup per bucket, padded to a power of
-// two), then neighbours compared.  Buckets beyond kLpTiesSort fall back to
-// one thread per claimant scanning the bucket.
-__global__ __launch_bounds__(kLpTiesThreads) void lp_ties_big(LPArgs A) {
-    __shared__ double sk[kLpTiesSort];
-    __shared__ int sj[kLpTiesSort];
-    __shared__ int hits;
-    LPState* st = A.w.st;
-    if (!lp_live(st)) return;
-    const int nbig = st->nbig;
-    const int tid = threadIdx.x;
-    for (int b = blockIdx.x; b < nbig; b += gridDim.x) {
-        const int s = A.w.big[b];
-        const int c = A.w.scnt[s];
-        const int start = A.w.soff[s];
-        if (tid == 0) hits = 0;
-        int mine = 0;
-        if (c <= kLpTiesSort) {
-            int P = 1;
-            while (P < c) P <<= 1;
-            for (int e = tid; e < P; e += kLpTiesThreads) {
-                const int j = e < c ? A.w.list[start + e] : 0x7fffffff;
-                sk[e] = e < c ? A.w.ckey[j] : INFINITY;
-                sj[e] = j;
-            }
-            __syncthreads();
-            for (int size = 2; size <= P; size <<= 1) {
-                for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                    for (int e = tid; e < P; e += kLpTiesThreads) {
-                        const int o = e ^ stride;
-                        if (o > e) {
-                            const bool up = (e & size) == 0;
-                            const double ka = sk[e], kb = sk[o];
-                            const int ja = sj[e], jb = sj[o];
-                            const bool gt = ka > kb || (ka == kb && ja > jb);
-                            if (gt == up) {
-                                sk[e] = kb;
-                                sk[o] = ka;
-                                sj[e] = jb;
-                                sj[o] = ja;
-                            }
-                        }
-                    }
-                    __syncthreads();
-                }
-            }
-            for (int e = tid + 1; e < c; e += kLpTiesThreads) mine += lp_keys_near(sk[e - 1], sk[e], A.metric);
-        } else {
-            for (int e = tid; e < c; e += kLpTiesThreads) {
-                const int j = A.w.list[start + e];
-                const double k = A.w.ckey[j];
-                double pk = -INFINITY;
-                bool any = false;
-                for (int f = start; f < start + c; ++f) {
-                    const int j2 = A.w.list[f];
-                    const double k2 = A.w.ckey[j2];
-                    if (k2 < k || (k2 == k && j2 < j)) {
-                        pk = fmax(pk, k2);
-                        any = true;
-                    }
-                }
-                mine += any && lp_keys_near(pk, k, A.metric);
-            }
-        }
-        if (mine) atomicAdd(&hits, mine);
-        __syncthreads();
-        if (tid == 0 && hits) atomicAdd((unsigned long long*)&st->ties_order, (unsigned long long)hits);
-        __syncthreads();
-    }
 }
 
 // ----------------------------------------------------------------- serve
@@ -979,6 +943,8 @@ __global__ __launch_bounds__(kLpThreads) void lp_serve(LPArgs A) {
             pos += __popcll(m);
         }
     }
+    if (greedy && c > 1)  // the bin table of this bucket, empty again for the next round
+        for (int e = start + lane; e < end; e += kWave) A.w.thead[e] = -1;
     if (lane == 0) {
         for (int q = start; q < start + served; ++q) {
             const int j = A.w.sorted[q];
@@ -1055,7 +1021,6 @@ __device__ void lp_commit_round(const LPArgs& A, int nblocks, bool single, unsig
     st->work += (int64_t)st->mact * st->nact;
     st->near += st->nflag;
     st->nflag = 0;
-    st->nbig = 0;
     st->rounds += 1;
     st->mact = m2;
     st->nact = n2;
@@ -1251,10 +1216,7 @@ int lp_launch_round(const LPArgs& A, int d, int mact_ub, int nact_ub, void* stre
         }
         hipLaunchKernelGGL(lp_offsets, dim3(1), dim3(kLpScanThreads), 0, st, A);
         hipLaunchKernelGGL(lp_scatter, dim3(qblocks), dim3(kLpThreads), 0, st, A);
-        if (A.protocol == NNSEMD_GREEDY) {
-            hipLaunchKernelGGL(lp_ties, dim3(qblocks), dim3(kLpThreads), 0, st, A);
-            hipLaunchKernelGGL(lp_ties_big, dim3(kLpTiesBlocks), dim3(kLpTiesThreads), 0, st, A);
-        }
+        if (A.protocol == NNSEMD_GREEDY) hipLaunchKernelGGL(lp_ties, dim3(qblocks), dim3(kLpThreads), 0, st, A);
         hipLaunchKernelGGL(lp_serve<DD>, dim3(wblocks), dim3(kLpThreads), 0, st, A);
         if (cmblocks > 1) hipLaunchKernelGGL(lp_ccount, dim3(cmblocks), dim3(kLpThreads), 0, st, A);
         hipLaunchKernelGGL(lp_cwrite<DD>, dim3(cmblocks), dim3(kLpThreads), 0, st, A);

@@ -128,8 +128,7 @@ __device__ inline float key32(const float* __restrict__ rec, const float (&y)[D]
 template <int D, int RS, bool L1, int KC>
 __device__ inline void nns_pass(const Lds16& L, SharedCore& sh, const float* __restrict__ X,
                                 const float* __restrict__ Y, const float (&centre)[D], float rhat,
-                                int mact, int nact, int S, int qa, int G, int r, bool exact, int metric,
-                                int64_t& ties_nn) {
+                                int mact, int nact, int S, int qa, int G, int r, bool exact, int metric) {
     int jj[KC];
     bool valid[KC];
     float y[KC][D];
@@ -214,7 +213,7 @@ __device__ inline void nns_pass(const Lds16& L, SharedCore& sh, const float* __r
             if (valid[k] && mact > 1) {
                 const double k1 = L1 ? (double)b1[k] : (double)b1[k] + (double)yn2[k];
                 const double k2 = L1 ? (double)b2[k] : (double)b2[k] + (double)yn2[k];
-                if (near_tie_dist(dist_of_key(k1, metric), dist_of_key(k2, metric))) ++ties_nn;
+                if (near_tie_dist(dist_of_key(k1, metric), dist_of_key(k2, metric))) atomicAdd(&sh.tie_nn, 1ull);
             }
             continue;
         }
@@ -256,6 +255,10 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds16& L, S
     const int wave = tid / kWave;
 
     NNSEMD_PH_DECL
+    if (tid == 0) {  // the ingest's block reductions order these before any use
+        sh.tie_nn = 0ull;
+        sh.tie_order = 0ull;
+    }
     // ---------------------------------------------------------- pair geometry
     int64_t x0 = 0, y0 = 0, m = A.single_m, n = A.single_n;
     int status = NNSEMD_OK;
@@ -431,7 +434,6 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds16& L, S
     const int64_t max_rounds = A.max_rounds > 0 ? A.max_rounds : (int64_t)mi + ni;
     int rounds = 0;
     int64_t work = 0, nnz = 0, near = 0;
-    int64_t ties_nn = 0, ties_order = 0;  // this thread's near-tie counts
     double cost = 0.0;  // this thread's part of R
     while (status == NNSEMD_OK && mact > 0 && nact > 0) {
         if (rounds >= max_rounds) {
@@ -452,8 +454,7 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds16& L, S
         while (S < kWave && nact * S * A.split <= T) S <<= 1;
         while (S > 1 && S > mact) S >>= 1;
         if (S > 1) {
-            nns_pass<D, RS, L1, 1>(L, sh, X, Y, centre, rhat, mact, nact, S, tid / S, T / S, tid & (S - 1), exact,
-                                   A.metric, ties_nn);
+            nns_pass<D, RS, L1, 1>(L, sh, X, Y, centre, rhat, mact, nact, S, tid / S, T / S, tid & (S - 1), exact, A.metric);
         } else {
             const int nslots = (nact + kWave - 1) / kWave;
             const int lo = wave * nslots / NW, hi = (wave + 1) * nslots / NW;
@@ -461,17 +462,13 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds16& L, S
                 const int k = min(4, hi - u0);  // wavefront-uniform
                 const int qa = u0 * kWave + lane;
                 if (k == 4)
-                    nns_pass<D, RS, L1, 4>(L, sh, X, Y, centre, rhat, mact, nact, 1, qa, kWave, 0, exact, A.metric,
-                                           ties_nn);
+                    nns_pass<D, RS, L1, 4>(L, sh, X, Y, centre, rhat, mact, nact, 1, qa, kWave, 0, exact, A.metric);
                 else if (k == 3)
-                    nns_pass<D, RS, L1, 3>(L, sh, X, Y, centre, rhat, mact, nact, 1, qa, kWave, 0, exact, A.metric,
-                                           ties_nn);
+                    nns_pass<D, RS, L1, 3>(L, sh, X, Y, centre, rhat, mact, nact, 1, qa, kWave, 0, exact, A.metric);
                 else if (k == 2)
-                    nns_pass<D, RS, L1, 2>(L, sh, X, Y, centre, rhat, mact, nact, 1, qa, kWave, 0, exact, A.metric,
-                                           ties_nn);
+                    nns_pass<D, RS, L1, 2>(L, sh, X, Y, centre, rhat, mact, nact, 1, qa, kWave, 0, exact, A.metric);
                 else
-                    nns_pass<D, RS, L1, 1>(L, sh, X, Y, centre, rhat, mact, nact, 1, qa, kWave, 0, exact, A.metric,
-                                           ties_nn);
+                    nns_pass<D, RS, L1, 1>(L, sh, X, Y, centre, rhat, mact, nact, 1, qa, kWave, 0, exact, A.metric);
             }
         }
         __syncthreads();
@@ -512,7 +509,7 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds16& L, S
                     L.ckey[j] = best;
                     cnt_add(L.scnt, bsl);
                     if (mact > 1 && near_tie_dist(dist_of_key(best, A.metric), dist_of_key(sec, A.metric)))
-                        ++ties_nn;
+                        atomicAdd(&sh.tie_nn, 1ull);
                 }
             }
             near += nf;
@@ -524,9 +521,10 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds16& L, S
         round_buckets<T>(L, sh, mact, nact);
         NNSEMD_PH(3)
         // ---- 3. flow & cost: claimant order, then the serve walk
-        round_rank<T, CSMAX>(L, nact, A.protocol, A.seed, rounds);
+        round_rank<T, CSMAX>(L, nact, A.protocol, A.seed, rounds, A.metric,
+                             A.protocol == NNSEMD_GREEDY ? &sh.tie_order : nullptr);
         NNSEMD_PH(5)
-        round_walk<T>(L, mact, A.metric, cost, A.protocol == NNSEMD_GREEDY, &ties_order);
+        round_walk<T>(L, mact, A.metric, cost);
         NNSEMD_PH(6)
         // ---- 4. weights update: plan append + compaction
         round_compact<T, CSMAX, RS>(L, sh, mact, nact, nnz, want_plan ? A.plan_src : nullptr, A.plan_dst,
@@ -536,13 +534,13 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds16& L, S
     }
 
     // ---------------------------------------------------------- results
-    double fin[5] = {cost, 0.0, 0.0, (double)ties_nn, (double)ties_order};
-    const int fop[5] = {0, 0, 0, 0, 0};
+    double fin[3] = {cost, 0.0, 0.0};
+    const int fop[3] = {0, 0, 0};
     if (status == NNSEMD_OK || status == NNSEMD_ERR_NOT_CONVERGED) {
         for (int s = tid; s < mact; s += T) fin[1] += L.smass[s];
         for (int q = tid; q < nact; q += T) fin[2] += L.cmass[L.cact[q]];
     }
-    block_reduce<T, 5>(fin, fop, L.ckey);
+    block_reduce<T, 3>(fin, fop, L.ckey);  // its barriers also order the counters' atomics
     NNSEMD_PH(8)
     NNSEMD_PH_FLUSH(A.phase_cycles)
     if (tid == 0) {
@@ -556,8 +554,8 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds16& L, S
             st.rescored = near;
             st.residual_src = fin[1];
             st.residual_dst = fin[2];
-            st.near_ties_nn = (int64_t)fin[3];
-            st.near_ties_order = (int64_t)fin[4];
+            st.near_ties_nn = (int64_t)sh.tie_nn;
+            st.near_ties_order = (int64_t)sh.tie_order;
             A.stats[p] = st;
         }
     }
@@ -569,10 +567,13 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds16& L, S
 // used here: its back-edge merges with the thread-0-only result write, and
 // the structurized code lets lanes 1-63 of wave 0 pass the following
 // barrier without the fetch, re-solving the same pair forever.)
-// Up to four claimants per thread the kernel is held to 128 VGPRs (four
-// waves per SIMD, no spills): small pairs keep four workgroups per CU.
+// Register budget, up to four claimants per thread, chosen so that no
+// variant spills: 128 VGPRs for d <= 3 (four waves per SIMD, so small
+// pairs keep four workgroups per CU), 168 for d = 4, 5 and 256 for d = 6, 7,
+// whose larger LDS records hold a 1024-point pair to two or three
+// workgroups per CU anyway.
 template <int D, int T, int CSMAX, bool L1, bool CL>
-__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(CSMAX <= 4 ? 4 : 1)))
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(CSMAX <= 4 ? (D <= 3 ? 4 : (D <= 5 ? 3 : 2)) : 1)))
 void pair_solver_kernel(PairSolverArgs A) {
     extern __shared__ __align__(16) char lds_dyn[];
     __shared__ SharedCore sh;

@@ -66,6 +66,8 @@ static_assert(sizeof(double) * kMaxWaves * kMaxReduce == kPairRedBytes, "reducti
 // Shared carries one, the compact point path lends its FP64 key array.
 struct SharedCore {
     unsigned long long scan[kMaxWaves];
+    unsigned long long tie_nn;     // near-tie counters of the pair (LDS atomics: hits are rare,
+    unsigned long long tie_order;  // and no register is held across the rounds for them)
     int32_t nflag;  // near-tie consumers of the search
     int32_t namb;   // claimants whose serve order needs exact keys (high-dimensional path)
 };
@@ -260,9 +262,13 @@ __device__ inline void round_buckets(const LT& L, SharedCore& sh, int mact, int 
 // it and writes itself to that rank; no dependent chains.  When the serve
 // order shares the buckets' storage (compact layout), every rank is taken
 // first (at most CS claimants per thread, kept in registers) and written
-// after a barrier.
+// after a barrier.  With `ties_order` (greedy order, exact FP64 keys) the
+// same scan keeps the largest key below the claimant's -- its neighbour's
+// in the serve order over the whole bucket -- and counts the pair when the
+// two distances are a near tie.
 template <typename LT>
-__device__ inline int claimant_place(const LT& L, int j, int protocol, uint64_t seed, int rounds) {
+__device__ inline int claimant_place(const LT& L, int j, int protocol, uint64_t seed, int rounds, int metric,
+                                     unsigned long long* ties_order) {
     const int sl = L.cnn[j];
     const int c = L.scnt[sl];
     const int end = L.soff[sl];
@@ -271,12 +277,16 @@ __device__ inline int claimant_place(const LT& L, int j, int protocol, uint64_t 
     if (c > 1) {
         if (protocol == NNSEMD_GREEDY) {
             const double k = L.ckey[j];
+            double pk = -1.0;  // keys are >= +0: -1 = no predecessor
 #pragma unroll 4
             for (int e = start; e < end; ++e) {
                 const int j2 = L.list[e];
                 const double k2 = L.ckey[j2];
-                rank += (k2 < k) || (k2 == k && j2 < j);
+                const bool below = (k2 < k) || (k2 == k && j2 < j);
+                rank += below;
+                if (below && k2 > pk) pk = k2;
             }
+            if (ties_order != nullptr && pk >= 0.0 && keys_near(pk, k, metric)) atomicAdd(ties_order, 1ull);
         } else {
             const uint64_t k = rp_key(seed, rounds, j);
 #pragma unroll 4
@@ -291,7 +301,8 @@ __device__ inline int claimant_place(const LT& L, int j, int protocol, uint64_t 
 }
 
 template <int T, int CS = 1, typename LT>
-__device__ inline void round_rank(const LT& L, int nact, int protocol, uint64_t seed, int rounds) {
+__device__ inline void round_rank(const LT& L, int nact, int protocol, uint64_t seed, int rounds, int metric = 0,
+                                  unsigned long long* ties_order = nullptr) {
     if (L.sorted == L.list) {
         int pos[CS], jv[CS];
 #pragma unroll
@@ -301,7 +312,7 @@ __device__ inline void round_rank(const LT& L, int nact, int protocol, uint64_t 
             jv[u] = 0;
             if (q < nact) {
                 jv[u] = L.cact[q];
-                pos[u] = claimant_place(L, jv[u], protocol, seed, rounds);
+                pos[u] = claimant_place(L, jv[u], protocol, seed, rounds, metric, ties_order);
             }
         }
         __syncthreads();
@@ -311,7 +322,7 @@ __device__ inline void round_rank(const LT& L, int nact, int protocol, uint64_t 
     } else {
         for (int q = threadIdx.x; q < nact; q += T) {
             const int j = L.cact[q];
-            L.sorted[claimant_place(L, j, protocol, seed, rounds)] = j;
+            L.sorted[claimant_place(L, j, protocol, seed, rounds, metric, ties_order)] = j;
         }
     }
     __syncthreads();
@@ -321,12 +332,10 @@ __device__ inline void round_rank(const LT& L, int nact, int protocol, uint64_t 
 // claimants while it still holds mass.  A served claimant records the local
 // index of its supplier (for the plan) and its flow in place of its key; an
 // unserved one gets flow 0.  With COST (the keys are the exact FP64 keys),
-// `cost` accumulates this thread's part of R, and with `ties` (greedy order)
-// `ties_order` counts neighbouring claimants whose distances are a near tie;
-// without COST, R and the tie count are left to the caller.
+// `cost` accumulates this thread's part of R; without it, R is left to the
+// caller.
 template <int T, bool COST = true, typename LT>
-__device__ inline void round_walk(const LT& L, int mact, int metric, double& cost, bool ties = false,
-                                  int64_t* ties_order = nullptr) {
+__device__ inline void round_walk(const LT& L, int mact, int metric, double& cost) {
     for (int s = threadIdx.x; s < mact; s += T) {
         const int c = L.scnt[s];
         if (c == 0) continue;
@@ -335,36 +344,18 @@ __device__ inline void round_walk(const LT& L, int mact, int metric, double& cos
         const int isup = L.sidx[s];
         int pos = start;
         double sm = L.smass[s];
-        double prev = 0.0;  // key of the previous claimant in the order
         while (pos < end && sm > 0.0) {
             const int j = L.sorted[pos];
             const double cm = L.cmass[j];
             const double f = sm < cm ? sm : cm;
             sm = sm - f;
             L.cmass[j] = cm - f;
-            if constexpr (COST) {
-                const double kj = L.ckey[j];
-                cost = cost + f * dist_of_key(kj, metric);
-                if (ties) {
-                    if (pos > start && keys_near(prev, kj, metric)) ++*ties_order;
-                    prev = kj;
-                }
-            }
+            if constexpr (COST) cost = cost + f * dist_of_key(L.ckey[j], metric);
             L.ckey[j] = f;
             L.cnn[j] = isup;
             ++pos;
         }
-        for (int e = pos; e < end; ++e) {
-            const int j = L.sorted[e];
-            if constexpr (COST) {
-                if (ties) {
-                    const double kj = L.ckey[j];
-                    if (e > start && keys_near(prev, kj, metric)) ++*ties_order;
-                    prev = kj;
-                }
-            }
-            L.ckey[j] = 0.0;
-        }
+        for (int e = pos; e < end; ++e) L.ckey[L.sorted[e]] = 0.0;
         L.smass[s] = sm;
     }
     __syncthreads();
