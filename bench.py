@@ -301,7 +301,7 @@ def main():
                                "Dirichlet(1) masses, L2, one launch, cost+plan+stats",
                    "num_pairs": P, "plan": want_plan, "graph": use_graph,
                    "threads": args.threads or (tuning["threads"] if tuning else 256),
-                   "search_split": tuning["split"] if tuning else 2, "autotuned": tuning is not None,
+                   "search_split": tuning["split"] if tuning else 1, "autotuned": tuning is not None,
                    "schedule": args.schedule, "seed": ps.meta["seed"],
                    "rounds_mean": float(st["rounds"].mean())},
         "roofline": roofline,

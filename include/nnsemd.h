@@ -383,9 +383,10 @@ nnsemd_status_t emd_approx_batched_noalloc(nnsemd_handle_t h, int64_t num_pairs,
 /* ------------------------------------------------------------------------
  * Autotuning of the batched point path (FP32, 1 <= d <= 7).  The launch
  * configuration -- workgroup size (256 or 512) and the search split factor
- * (lanes share a consumer while active consumers x lanes x split <= workgroup
- * size, i.e. how early the search spreads one consumer over several lanes as
- * the active sets shrink) -- is timed with HIP events on synthetic ragged
+ * (each active consumer gets the largest power-of-two number of lanes, at
+ * most 64, with active consumers x lanes x split <= workgroup size, i.e. how
+ * early the search spreads one consumer over several lanes as the active
+ * sets shrink; split 1 fills the workgroup) -- is timed with HIP events on synthetic ragged
  * pairs shaped like the caller's (sides uniform in [max/8, max], uniform
  * coordinates, exponential masses) and the fastest is recorded in the handle
  * for (d, metric, size class of max(max_m, max_n)).  Later calls with
@@ -396,16 +397,18 @@ typedef struct {
     int32_t threads;  /* chosen workgroup size */
     int32_t split;    /* chosen search split factor (1, 2 or 4) */
     float ms_best;    /* its time per launch on the synthetic batch */
-    float ms_default; /* time of the default (256, 2) */
+    float ms_default; /* time of the default (256, 1) */
 } nnsemd_tuning_t;
 
 nnsemd_status_t nnsemd_autotune(nnsemd_handle_t h, int32_t d, nnsemd_metric_t metric, int64_t max_m, int64_t max_n,
                                 int64_t num_pairs, nnsemd_tuning_t* result, void* stream);
 
-/* The handle's tuning table as text ("nnsemd-tuning 1", then one line
+/* The handle's tuning table as text ("nnsemd-tuning 2", then one line
  * "d metric class threads split ms" per entry), and back. */
 nnsemd_status_t nnsemd_tuning_save(nnsemd_handle_t h, const char* path);
 nnsemd_status_t nnsemd_tuning_load(nnsemd_handle_t h, const char* path);
+/* Forget every recorded configuration: later calls use the default (256, 1). */
+nnsemd_status_t nnsemd_tuning_clear(nnsemd_handle_t h);
 
 /* ------------------------------------------------------------------------
  * Learned surrogate for retrieval (not part of the paper, which treats

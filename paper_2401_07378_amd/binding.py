@@ -37,7 +37,8 @@ EXPORTS = ["nnsemd_create", "nnsemd_destroy", "nnsemd_status_string", "nnsemd_la
            "emd_approx_batched_noalloc",
            "nnsemd_sg_num_params", "nnsemd_sg_embed", "nnsemd_sg_predict", "nnsemd_sg_loss_grad",
            "nnsemd_sg_train_step", "nnsemd_topk_smallest_f32", "nnsemd_topk_smallest_f64", "nnsemd_sg_retrieve",
-           "nnsemd_autotune", "nnsemd_tuning_save", "nnsemd_tuning_load"]
+           "nnsemd_autotune", "nnsemd_tuning_save", "nnsemd_tuning_load",
+           "nnsemd_tuning_clear"]
 SG_HIDDEN = 256
 
 
@@ -116,7 +117,8 @@ def load_library():
         lib.nnsemd_autotune.argtypes = [P, I32, I32, I64, I64, I64, ctypes.POINTER(Tuning), P]
         lib.nnsemd_tuning_save.argtypes = [P, ctypes.c_char_p]
         lib.nnsemd_tuning_load.argtypes = [P, ctypes.c_char_p]
-        for fn in ("nnsemd_autotune", "nnsemd_tuning_save", "nnsemd_tuning_load"):
+        lib.nnsemd_tuning_clear.argtypes = [P]
+        for fn in ("nnsemd_autotune", "nnsemd_tuning_save", "nnsemd_tuning_load", "nnsemd_tuning_clear"):
             getattr(lib, fn).restype = I32
         for fn in ("nnsemd_sg_embed", "nnsemd_sg_predict", "nnsemd_sg_loss_grad", "nnsemd_sg_train_step",
                    "nnsemd_topk_smallest_f32", "nnsemd_topk_smallest_f64", "nnsemd_sg_retrieve"):
@@ -597,3 +599,10 @@ def tuning_load(path: str, device: int = 0):
     lib = load_library()
     h = handle(device)
     _check(lib, h, lib.nnsemd_tuning_load(h, path.encode()))
+
+
+def tuning_reset(device: int = 0):
+    """Forget every recorded launch configuration (back to the default)."""
+    lib = load_library()
+    h = handle(device)
+    _check(lib, h, lib.nnsemd_tuning_clear(h))

@@ -48,7 +48,7 @@ struct nnsemd_handle {
     // Autotuned launch configuration of the batched point path, by
     // dimension (1..7), metric and size class of max(max_m, max_n).
     struct Tune {
-        int32_t valid = 0, threads = 256, split = 2;
+        int32_t valid = 0, threads = 256, split = 1;
         float ms = 0.f;
     } tune[8][3][nnsemd_tune_classes];
     char* sg_quant = nullptr;                    // BF16 weight copies of the surrogate
@@ -132,7 +132,7 @@ nnsemd_status_t run_pairs(nnsemd_handle_t h, PairSolverArgs& A, int d, int64_t m
                           int32_t* fixed_order = nullptr) {
     if (d < 1 || d > 7) return fail(h, NNSEMD_ERR_UNSUPPORTED, "point path supports 1 <= d <= 7");
     int threads = o.threads > 0 ? o.threads : 256;
-    int split = 2;
+    int split = 1;
     const auto& tn = h->tune[d][A.metric][tune_class(std::max<int64_t>(max_m, max_n))];
     if (o.threads == 0 && tn.valid) {
         threads = tn.threads;
@@ -1195,7 +1195,7 @@ nnsemd_status_t nnsemd_autotune(nnsemd_handle_t h, int32_t d, nnsemd_metric_t me
     hipEvent_t e0 = nullptr, e1 = nullptr;
     nnsemd_status_t status = NNSEMD_OK;
     float best_ms = -1.f, default_ms = -1.f;
-    int best_t = 256, best_s = 2;
+    int best_t = 256, best_s = 1;
     bool ok = hipMemcpyAsync(base + oX, X.data(), 4 * X.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
               hipMemcpyAsync(base + oa, a.data(), 4 * a.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
               hipMemcpyAsync(base + oY, Y.data(), 4 * Y.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
@@ -1241,7 +1241,7 @@ nnsemd_status_t nnsemd_autotune(nnsemd_handle_t h, int32_t d, nnsemd_metric_t me
                 break;
             }
             ms /= 3.f;
-            if (threads_c[ti] == 256 && split_c[si] == 2) default_ms = ms;
+            if (threads_c[ti] == 256 && split_c[si] == 1) default_ms = ms;
             if (best_ms < 0.f || ms < best_ms) {
                 best_ms = ms;
                 best_t = threads_c[ti];
@@ -1273,7 +1273,7 @@ nnsemd_status_t nnsemd_tuning_save(nnsemd_handle_t h, const char* path) {
     if (h == nullptr || path == nullptr) return NNSEMD_ERR_INVALID_ARG;
     FILE* f = std::fopen(path, "w");
     if (f == nullptr) return fail(h, NNSEMD_ERR_INVALID_ARG, "cannot open the tuning file for writing");
-    std::fprintf(f, "nnsemd-tuning 1\n");
+    std::fprintf(f, "nnsemd-tuning 2\n");
     for (int d = 1; d <= 7; ++d)
         for (int m = 0; m < 3; ++m)
             for (int c = 0; c < nnsemd_tune_classes; ++c) {
@@ -1284,14 +1284,22 @@ nnsemd_status_t nnsemd_tuning_save(nnsemd_handle_t h, const char* path) {
     return ok ? NNSEMD_OK : fail(h, NNSEMD_ERR_INVALID_ARG, "writing the tuning file failed");
 }
 
+nnsemd_status_t nnsemd_tuning_clear(nnsemd_handle_t h) {
+    if (h == nullptr) return NNSEMD_ERR_INVALID_ARG;
+    for (auto& per_d : h->tune)
+        for (auto& per_metric : per_d)
+            for (auto& tn : per_metric) tn.valid = 0;
+    return NNSEMD_OK;
+}
+
 nnsemd_status_t nnsemd_tuning_load(nnsemd_handle_t h, const char* path) {
     if (h == nullptr || path == nullptr) return NNSEMD_ERR_INVALID_ARG;
     FILE* f = std::fopen(path, "r");
     if (f == nullptr) return fail(h, NNSEMD_ERR_INVALID_ARG, "cannot open the tuning file");
     int version = 0;
     nnsemd_status_t s = NNSEMD_OK;
-    if (std::fscanf(f, "nnsemd-tuning %d", &version) != 1 || version != 1) {
-        s = fail(h, NNSEMD_ERR_INVALID_ARG, "not a tuning file (version 1)");
+    if (std::fscanf(f, "nnsemd-tuning %d", &version) != 1 || version != 2) {
+        s = fail(h, NNSEMD_ERR_INVALID_ARG, "not a tuning file (version 2)");
     } else {
         int d, m, c, t, sp;
         double ms;

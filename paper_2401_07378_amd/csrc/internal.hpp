@@ -46,7 +46,7 @@ struct PairSolverArgs {
     nnsemd_stats_t* stats;
     const int32_t* order;  // nullable: workgroup b solves pair order[b]
     unsigned long long* phase_cycles;  // profiling builds only: 9 per-phase cycle totals
-    int32_t split;         // search: lanes per consumer grow while nact * lanes * split <= threads
+    int32_t split;         // search: lanes per consumer = largest power of two with nact * lanes * split <= threads
     int32_t share_order;   // LDS layout: the serve order written over the claimant buckets
 };
 

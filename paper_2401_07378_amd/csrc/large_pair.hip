@@ -346,6 +346,23 @@ __global__ __launch_bounds__(kLpScanThreads) void lp_setup(LPArgs A, int nblocks
 }
 
 // ---------------------------------------------------------------- search
+// FP32 search key of one record: L1 sums |x_t - y_t| in dimension order;
+// the Euclidean metrics run the FMA chain ||x^||^2 + sum_t (-2 x^_t) y^_t.
+template <int D, int RS, bool L1>
+__device__ inline float lp_key(const float (&rec)[RS], const float (&y)[D]) {
+    float key;
+    if (L1) {
+        key = 0.f;
+#pragma unroll
+        for (int t = 0; t < D; ++t) key += fabsf(rec[t] - y[t]);
+    } else {
+        key = rec[D];
+#pragma unroll
+        for (int t = D - 1; t >= 0; --t) key = fmaf(rec[t], y[t], key);
+    }
+    return key;
+}
+
 template <int D, bool L1, int KC>
 __global__ __launch_bounds__(kLpThreads) void lp_search(LPArgs A, int split) {
     constexpr int RS = record_stride(D);
@@ -373,6 +390,19 @@ __global__ __launch_bounds__(kLpThreads) void lp_search(LPArgs A, int split) {
         b2[k] = INFINITY;
         bs[k] = 0x7fffffff;
     }
+    // Blocks of kLpUnroll records: two keys at a time update (b1, b2) as
+    // b2 <- min(b2, med3(b1, ka, kb)), b1 <- min(b1, ka, kb) (the two smallest
+    // of the multiset); only the block in which b1 last fell strictly is
+    // remembered, and its records are scanned again at the end (from the
+    // global records, the same FP32 values) for the first slot holding b1.
+    // Records past the last full block (the chunk's tail) keep their slot
+    // directly; they come after every block, so a fall there is the last.
+    int blk[KC], bsr[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        blk[k] = -1;
+        bsr[k] = -1;
+    }
     for (int t0 = s_lo; t0 < s_hi; t0 += kLpTile) {
         const int cnt = min(kLpTile, s_hi - t0);
         const float4* src = reinterpret_cast<const float4*>(srec + (size_t)t0 * RS);
@@ -394,26 +424,21 @@ __global__ __launch_bounds__(kLpThreads) void lp_search(LPArgs A, int split) {
                     rec[u][4 * q + 3] = v.w;
                 }
             }
+            float b1o[KC];
 #pragma unroll
-            for (int u = 0; u < kLpUnroll; ++u) {
+            for (int k = 0; k < KC; ++k) b1o[k] = b1[k];
+#pragma unroll
+            for (int u = 0; u < kLpUnroll; u += 2) {
 #pragma unroll
                 for (int k = 0; k < KC; ++k) {
-                    float key;
-                    if (L1) {
-                        key = 0.f;
-#pragma unroll
-                        for (int t = 0; t < D; ++t) key += fabsf(rec[u][t] - y[k][t]);
-                    } else {
-                        key = rec[u][D];
-#pragma unroll
-                        for (int t = D - 1; t >= 0; --t) key = fmaf(rec[u][t], y[k][t], key);
-                    }
-                    const bool lt = key < b1[k];
-                    bs[k] = lt ? t0 + s0 + u : bs[k];
-                    b2[k] = __builtin_amdgcn_fmed3f(b1[k], key, b2[k]);
-                    b1[k] = fminf(b1[k], key);
+                    const float ka = lp_key<D, RS, L1>(rec[u], y[k]);
+                    const float kb = lp_key<D, RS, L1>(rec[u + 1], y[k]);
+                    b2[k] = fminf(b2[k], __builtin_amdgcn_fmed3f(b1[k], ka, kb));
+                    b1[k] = fminf(b1[k], fminf(ka, kb));
                 }
             }
+#pragma unroll
+            for (int k = 0; k < KC; ++k) blk[k] = b1[k] < b1o[k] ? t0 + s0 : blk[k];
         }
         for (int s = full; s < cnt; ++s) {
             float rec[RS];
@@ -421,23 +446,38 @@ __global__ __launch_bounds__(kLpThreads) void lp_search(LPArgs A, int split) {
             for (int q = 0; q < RS; ++q) rec[q] = tile[(size_t)s * RS + q];
 #pragma unroll
             for (int k = 0; k < KC; ++k) {
-                float key;
-                if (L1) {
-                    key = 0.f;
-#pragma unroll
-                    for (int t = 0; t < D; ++t) key += fabsf(rec[t] - y[k][t]);
-                } else {
-                    key = rec[D];
-#pragma unroll
-                    for (int t = D - 1; t >= 0; --t) key = fmaf(rec[t], y[k][t], key);
-                }
+                const float key = lp_key<D, RS, L1>(rec, y[k]);
                 const bool lt = key < b1[k];
-                bs[k] = lt ? t0 + s : bs[k];
+                bsr[k] = lt ? t0 + s : bsr[k];
                 b2[k] = __builtin_amdgcn_fmed3f(b1[k], key, b2[k]);
                 b1[k] = fminf(b1[k], key);
             }
         }
         __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        bs[k] = bsr[k];
+        if (bsr[k] < 0 && blk[k] >= 0) {
+            int u = kLpUnroll - 1;
+#pragma unroll
+            for (int v = kLpUnroll - 2; v >= 0; --v) {
+                float rv[RS];
+                const float4* p = reinterpret_cast<const float4*>(srec + (size_t)(blk[k] + v) * RS);
+#pragma unroll
+                for (int q = 0; q < RS / 4; ++q) {
+                    const float4 w = p[q];
+                    rv[4 * q] = w.x;
+                    rv[4 * q + 1] = w.y;
+                    rv[4 * q + 2] = w.z;
+                    rv[4 * q + 3] = w.w;
+                }
+                u = lp_key<D, RS, L1>(rv, y[k]) == b1[k] ? v : u;
+            }
+            bs[k] = blk[k] + u;
+        } else if (bsr[k] < 0) {
+            bs[k] = 0x7fffffff;
+        }
     }
 #pragma unroll
     for (int k = 0; k < KC; ++k) {

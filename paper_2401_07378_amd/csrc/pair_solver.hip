@@ -34,7 +34,10 @@ namespace {
 
 using namespace rc;
 
-constexpr int kUnroll = 8;  // supplier records in flight per step of the search
+// supplier records in flight per step of the search: 8, or 4 for the
+// 512-thread kernels held to 80 VGPRs (six wavefronts per SIMD)
+template <int CSMAX>
+constexpr int search_unroll() { return CSMAX <= 2 ? 4 : 8; }
 
 // Exact FP64 key in the definition's operation order (dimension order, no
 // fused multiply-add): squared Euclidean, or L1.
@@ -125,7 +128,7 @@ __device__ inline float key32(const float* __restrict__ rec, const float (&y)[D]
 // Per consumer: FP32 best and second-best keys; if they are closer than the
 // rounding bound the consumer is queued for the FP64 re-score, otherwise its
 // pick and the exact FP64 key of the pick are stored.
-template <int D, int RS, bool L1, int KC>
+template <int D, int RS, bool L1, int KC, int UN>
 __device__ inline void nns_pass(const Lds16& L, SharedCore& sh, const float* __restrict__ X,
                                 const float* __restrict__ Y, const float (&centre)[D], float rhat,
                                 int mact, int nact, int S, int qa, int G, int r, bool exact, int metric) {
@@ -157,22 +160,48 @@ __device__ inline void nns_pass(const Lds16& L, SharedCore& sh, const float* __r
         b2[k] = INFINITY;
         bs[k] = 0x7fffffff;
     }
-    const int stride = S * kUnroll;
+    // Full blocks of UN records.  Two keys at a time update the pair
+    // (b1, b2): b2 <- min(b2, med3(b1, ka, kb)) and b1 <- min(b1, ka, kb)
+    // give the two smallest of {b1, b2, ka, kb} (as a multiset, so equal
+    // keys leave b2 = b1).  Only the block in which b1 last fell strictly
+    // is remembered; its records are scanned again afterwards for the first
+    // slot holding b1, which is the smallest slot with the smallest key.
+    const int stride = S * UN;
     const int full = (mact / stride) * stride;
+    int blk[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) blk[k] = -1;
     for (int s0 = r; s0 < full; s0 += stride) {
-        float rec[kUnroll][RS];
+        float rec[UN][RS];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) load_rec<RS>(L.srec, s0 + u * S, rec[u]);
+        for (int u = 0; u < UN; ++u) load_rec<RS>(L.srec, s0 + u * S, rec[u]);
+        float b1o[KC];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
+        for (int k = 0; k < KC; ++k) b1o[k] = b1[k];
+#pragma unroll
+        for (int u = 0; u < UN; u += 2) {
 #pragma unroll
             for (int k = 0; k < KC; ++k) {
-                const float key = key32<D, RS, L1>(rec[u], y[k]);
-                const bool lt = key < b1[k];
-                bs[k] = lt ? s0 + u * S : bs[k];
-                b2[k] = __builtin_amdgcn_fmed3f(b1[k], key, b2[k]);
-                b1[k] = fminf(b1[k], key);
+                const float ka = key32<D, RS, L1>(rec[u], y[k]);
+                const float kb = key32<D, RS, L1>(rec[u + 1], y[k]);
+                b2[k] = fminf(b2[k], __builtin_amdgcn_fmed3f(b1[k], ka, kb));
+                b1[k] = fminf(b1[k], fminf(ka, kb));
             }
+        }
+#pragma unroll
+        for (int k = 0; k < KC; ++k) blk[k] = b1[k] < b1o[k] ? s0 : blk[k];
+    }
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        if (blk[k] >= 0) {
+            int u = UN - 1;
+#pragma unroll
+            for (int v = UN - 2; v >= 0; --v) {
+                float rv[RS];
+                load_rec<RS>(L.srec, blk[k] + v * S, rv);
+                u = key32<D, RS, L1>(rv, y[k]) == b1[k] ? v : u;
+            }
+            bs[k] = blk[k] + u * S;
         }
     }
     for (int s = full + r; s < mact; s += S) {
@@ -450,25 +479,29 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds16& L, S
         // dealt to the wavefronts as evenly as possible; a wavefront with k
         // slots scans the records once with k consumers per lane (one record
         // load feeds k key chains), so only the last slot has idle lanes.
+        // S is the largest power of two (at most 64 and at most mact) with
+        // nact * S * split <= T, so every active consumer gets its S lanes.
+        constexpr int UN = search_unroll<CSMAX>();
         int S = 1;
-        while (S < kWave && nact * S * A.split <= T) S <<= 1;
-        while (S > 1 && S > mact) S >>= 1;
+        while ((S << 1) <= kWave && (S << 1) <= mact && nact * (S << 1) * A.split <= T) S <<= 1;
         if (S > 1) {
-            nns_pass<D, RS, L1, 1>(L, sh, X, Y, centre, rhat, mact, nact, S, tid / S, T / S, tid & (S - 1), exact, A.metric);
+            nns_pass<D, RS, L1, 1, UN>(L, sh, X, Y, centre, rhat, mact, nact, S, tid / S, T / S, tid & (S - 1), exact, A.metric);
         } else {
             const int nslots = (nact + kWave - 1) / kWave;
             const int lo = wave * nslots / NW, hi = (wave + 1) * nslots / NW;
-            for (int u0 = lo; u0 < hi; u0 += 4) {
-                const int k = min(4, hi - u0);  // wavefront-uniform
+            // a wavefront holds at most CSMAX slots (nact <= CSMAX * T)
+            constexpr int KMAX = CSMAX < 4 ? CSMAX : 4;
+            for (int u0 = lo; u0 < hi; u0 += KMAX) {
+                const int k = min(KMAX, hi - u0);  // wavefront-uniform
                 const int qa = u0 * kWave + lane;
-                if (k == 4)
-                    nns_pass<D, RS, L1, 4>(L, sh, X, Y, centre, rhat, mact, nact, 1, qa, kWave, 0, exact, A.metric);
-                else if (k == 3)
-                    nns_pass<D, RS, L1, 3>(L, sh, X, Y, centre, rhat, mact, nact, 1, qa, kWave, 0, exact, A.metric);
-                else if (k == 2)
-                    nns_pass<D, RS, L1, 2>(L, sh, X, Y, centre, rhat, mact, nact, 1, qa, kWave, 0, exact, A.metric);
+                if (KMAX >= 4 && k == 4)
+                    nns_pass<D, RS, L1, KMAX, UN>(L, sh, X, Y, centre, rhat, mact, nact, 1, qa, kWave, 0, exact, A.metric);
+                else if (KMAX >= 3 && k == 3)
+                    nns_pass<D, RS, L1, KMAX >= 3 ? 3 : 1, UN>(L, sh, X, Y, centre, rhat, mact, nact, 1, qa, kWave, 0, exact, A.metric);
+                else if (KMAX >= 2 && k == 2)
+                    nns_pass<D, RS, L1, KMAX >= 2 ? 2 : 1, UN>(L, sh, X, Y, centre, rhat, mact, nact, 1, qa, kWave, 0, exact, A.metric);
                 else
-                    nns_pass<D, RS, L1, 1>(L, sh, X, Y, centre, rhat, mact, nact, 1, qa, kWave, 0, exact, A.metric);
+                    nns_pass<D, RS, L1, 1, UN>(L, sh, X, Y, centre, rhat, mact, nact, 1, qa, kWave, 0, exact, A.metric);
             }
         }
         __syncthreads();
@@ -573,7 +606,7 @@ __device__ void solve_pair(const PairSolverArgs& A, int64_t p, const Lds16& L, S
 // whose larger LDS records hold a 1024-point pair to two or three
 // workgroups per CU anyway.
 template <int D, int T, int CSMAX, bool L1, bool CL>
-__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(CSMAX <= 4 ? (D <= 3 ? 4 : (D <= 5 ? 3 : 2)) : 1)))
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(CSMAX <= 2 && D <= 3 ? 6 : (CSMAX <= 4 ? (D <= 3 ? 4 : (D <= 5 ? 3 : 2)) : 1))))
 void pair_solver_kernel(PairSolverArgs A) {
     extern __shared__ __align__(16) char lds_dyn[];
     __shared__ SharedCore sh;
