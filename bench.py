@@ -61,6 +61,12 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def issued_per_eval(d):
+    """VALU instructions the point-path search loop issues per evaluation
+    (counted in the gfx950 assembly of the unrolled block)."""
+    return d + 1.6875
+
+
 def measured_traffic(per_launch_algorithmic_bytes):
     """HBM bytes per launch from the committed rocprofv3 counter summary,
     or None when the kernel source changed since the counters were taken."""
@@ -235,10 +241,13 @@ def main():
                 "work_evals": work,
                 "ops_per_eval": 2 * d + 2, "algorithmic_bytes": alg_bytes,
                 "hbm_gbs_algorithmic": alg_bytes / (ms / 1e3) / 1e9,
-                # the kernel issues d + 4 VALU instructions per evaluation
-                # (d FMAs, compare, select, med3, min): the issue-based share
-                "issued_ops_per_eval": d + 4,
-                "issue_frac": work * (d + 4) / (ms / 1e3) / PEAK_VALU_LANE_OPS}
+                # the search loop issues d + 1.6875 VALU instructions per
+                # evaluation (per block of 8 records x 4 consumers: 32 d FMAs,
+                # 16 med3 and 24 min3 for the best two keys, 14 for the
+                # block's slot bookkeeping): the share of the VALU issue
+                # slots that went to evaluations
+                "issued_ops_per_eval": issued_per_eval(d),
+                "issue_frac": work * issued_per_eval(d) / (ms / 1e3) / PEAK_VALU_LANE_OPS}
 
     single = None
     if not args.no_single_pair:
