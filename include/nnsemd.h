@@ -89,8 +89,16 @@ typedef enum { NNSEMD_SCHEDULE_LONGEST_FIRST = 0, NNSEMD_SCHEDULE_AS_GIVEN = 1 }
 
 /* Which implementation solves a single pair: automatic (on-chip whenever the
  * pair fits one workgroup's LDS), the on-chip one-workgroup path, or the
- * multi-workgroup path (any size; its host thread waits for the result). */
-typedef enum { NNSEMD_PATH_AUTO = 0, NNSEMD_PATH_ON_CHIP = 1, NNSEMD_PATH_MULTI = 2 } nnsemd_path_t;
+ * multi-workgroup path (any size; its host thread waits for the result).
+ * The multi-workgroup path hands the last rounds, once both active sets fit
+ * one workgroup's LDS, to a single-workgroup finish; MULTI_NO_TAIL runs
+ * every round grid-wide (same results; for tests and comparisons). */
+typedef enum {
+    NNSEMD_PATH_AUTO = 0,
+    NNSEMD_PATH_ON_CHIP = 1,
+    NNSEMD_PATH_MULTI = 2,
+    NNSEMD_PATH_MULTI_NO_TAIL = 3
+} nnsemd_path_t;
 
 typedef struct {
     int32_t protocol;   /* nnsemd_protocol_t, default NNSEMD_GREEDY */

@@ -151,7 +151,7 @@ def _ptr(t):
 
 
 SCHEDULES = {"longest_first": 0, "as_given": 1}
-PATHS = {"auto": 0, "on_chip": 1, "multi": 2}
+PATHS = {"auto": 0, "on_chip": 1, "multi": 2, "multi_no_tail": 3}
 
 
 def _options(protocol, mode, max_rounds, seed, threads, schedule="longest_first", path="auto"):

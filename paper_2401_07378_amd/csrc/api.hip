@@ -323,6 +323,11 @@ nnsemd_status_t run_large(nnsemd_handle_t h, LPArgs& A, int d, void* stream) {
         if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
         if (e != hipSuccess) return device_fail(h, (int)e, "round state readback");
         if (h->lp_host->done || h->lp_host->status != NNSEMD_OK) break;
+        if (h->lp_host->tail) {  // both active sets fit one workgroup: it runs the rest
+            err = lp_launch_tail(A, d, stream);
+            if (err != 0) return device_fail(h, err, "single-workgroup finish");
+            break;
+        }
         if (launched > A.max_rounds + kChunk) break;  // unreachable: the device caps the rounds
         mact_ub = h->lp_host->mact;
         nact_ub = h->lp_host->nact;
@@ -590,7 +595,8 @@ nnsemd_status_t check_common(nnsemd_handle_t h, int32_t d, nnsemd_dtype_t dtype,
         return fail(h, NNSEMD_ERR_INVALID_ARG, "bad protocol");
     if (o.schedule != NNSEMD_SCHEDULE_LONGEST_FIRST && o.schedule != NNSEMD_SCHEDULE_AS_GIVEN)
         return fail(h, NNSEMD_ERR_INVALID_ARG, "bad schedule");
-    if (o.path != NNSEMD_PATH_AUTO && o.path != NNSEMD_PATH_ON_CHIP && o.path != NNSEMD_PATH_MULTI)
+    if (o.path != NNSEMD_PATH_AUTO && o.path != NNSEMD_PATH_ON_CHIP && o.path != NNSEMD_PATH_MULTI &&
+        o.path != NNSEMD_PATH_MULTI_NO_TAIL)
         return fail(h, NNSEMD_ERR_INVALID_ARG, "bad path");
     if (o.reserved != 0) return fail(h, NNSEMD_ERR_INVALID_ARG, "reserved option field must be 0");
     if (o.mode != NNSEMD_MODE_FP32 && o.mode != NNSEMD_MODE_BF16_MFMA_REFINE)
@@ -702,7 +708,7 @@ nnsemd_status_t emd_approx(nnsemd_handle_t h, const void* X, const float* a, int
         return fail(h, NNSEMD_ERR_CAPACITY, "plan capacity below m + n - 1");
     DeviceGuard g(h->device);
     if (use_doc_path(d, dtype)) {
-        if (o.path == NNSEMD_PATH_MULTI)
+        if (o.path == NNSEMD_PATH_MULTI || o.path == NNSEMD_PATH_MULTI_NO_TAIL)
             return fail(h, NNSEMD_ERR_UNSUPPORTED, "multi-workgroup path supports FP32 points with d <= 7");
         DocArgs A{};
         A.num_pairs = 1;
@@ -722,7 +728,8 @@ nnsemd_status_t emd_approx(nnsemd_handle_t h, const void* X, const float* a, int
         A.stats = stats;
         return run_docs(h, A, m, n, dtype, o, stream);
     }
-    const bool multi = o.path == NNSEMD_PATH_MULTI || (o.path == NNSEMD_PATH_AUTO && !fits_on_chip(h, m, n, d, o.threads));
+    const bool multi = o.path == NNSEMD_PATH_MULTI || o.path == NNSEMD_PATH_MULTI_NO_TAIL ||
+                       (o.path == NNSEMD_PATH_AUTO && !fits_on_chip(h, m, n, d, o.threads));
     if (multi) {
         LPArgs L{};
         L.m = m;
@@ -740,6 +747,7 @@ nnsemd_status_t emd_approx(nnsemd_handle_t h, const void* X, const float* a, int
         L.plan_dst = plan ? plan_dst : nullptr;
         L.plan_flow = plan ? plan_flow : nullptr;
         L.stats = stats;
+        L.tail_cap = o.path == NNSEMD_PATH_MULTI_NO_TAIL ? 0 : lp_tail_capacity(d, h->max_lds);
         return run_large(h, L, d, stream);
     }
     PairSolverArgs A{};
@@ -782,7 +790,8 @@ nnsemd_status_t emd_approx_map(nnsemd_handle_t h, const void* X, const float* a,
     if (use_doc_path(d, dtype))
         return fail(h, NNSEMD_ERR_UNSUPPORTED, "the transport map is computed for FP32 points with d <= 7");
     DeviceGuard g(h->device);
-    if (o.path == NNSEMD_PATH_MULTI || (o.path == NNSEMD_PATH_AUTO && !fits_on_chip(h, m, n, d, o.threads))) {
+    if (o.path == NNSEMD_PATH_MULTI || o.path == NNSEMD_PATH_MULTI_NO_TAIL ||
+        (o.path == NNSEMD_PATH_AUTO && !fits_on_chip(h, m, n, d, o.threads))) {
         // the multi-workgroup path accumulates the map while it serves
         LPArgs L{};
         L.m = m;
@@ -801,6 +810,7 @@ nnsemd_status_t emd_approx_map(nnsemd_handle_t h, const void* X, const float* a,
         L.plan_flow = plan ? plan_flow : nullptr;
         L.stats = stats;
         L.map = map;
+        L.tail_cap = o.path == NNSEMD_PATH_MULTI_NO_TAIL ? 0 : lp_tail_capacity(d, h->max_lds);
         return run_large(h, L, d, stream);
     }
     // On-chip solve into the caller's plan (or the handle's), then the map of

@@ -212,8 +212,8 @@ __device__ void solve_cost_pair(const CostArgs& A, int64_t p, const Lds16& L, Sh
         // keys are the distances themselves (metric code SQEUCLIDEAN: D = key)
         round_rank<T, CSMAX>(L, nact, A.protocol, A.seed, rounds, NNSEMD_SQEUCLIDEAN,
                              A.protocol == NNSEMD_GREEDY ? &sh.tie_order : nullptr);
-        round_walk<T>(L, mact, NNSEMD_SQEUCLIDEAN, cost);
-        round_compact<T, CSMAX, 0>(L, sh, mact, nact, nnz, want_plan ? A.plan_src : nullptr, A.plan_dst,
+        round_walk<T, true, true>(L, mact, NNSEMD_SQEUCLIDEAN, cost);
+        round_compact<T, CSMAX, 0, true>(L, sh, mact, nact, nnz, want_plan ? A.plan_src : nullptr, A.plan_dst,
                                    A.plan_flow, plan_base);
         ++rounds;
     }

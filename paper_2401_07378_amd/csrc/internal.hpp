@@ -104,7 +104,7 @@ struct LPState {
     int64_t nnz, work, near;
     int64_t ties_nn, ties_order;  // near-tie counters (see nnsemd_stats_t)
     int32_t rounds, done, parity, ticket;  // ticket: blocks of the round's last kernel that have finished
-    int32_t pad0, pad2;
+    int32_t tail, pad2;  // tail: both active sets fit the single-workgroup finish
     float centre[8];
     float rhat, pad1;
     double sum_a, sum_b;
@@ -148,6 +148,8 @@ struct LPArgs {
     int32_t metric, protocol;
     uint64_t seed;
     int64_t max_rounds;
+    int32_t tail_cap;  // active points per side at which the single-workgroup finish takes over (0: never)
+    int32_t tail_pad;
     double* cost;
     int32_t* plan_src;
     int32_t* plan_dst;
@@ -160,6 +162,10 @@ struct LPArgs {
 int lp_launch_init(const LPArgs& A, int d, void* stream);
 int lp_launch_round(const LPArgs& A, int d, int mact_ub, int nact_ub, void* stream);
 int lp_launch_finish(const LPArgs& A, int d, void* stream);
+// The single-workgroup finish: its largest capacity per side that fits
+// max_lds bytes of LDS (0 if none), and its launch.
+int lp_tail_capacity(int d, size_t max_lds);
+int lp_launch_tail(const LPArgs& A, int d, void* stream);
 
 // ---------------------------------------------------------------------
 // High-dimensional path (doc_solver.hip): one workgroup per pair, the key

@@ -27,6 +27,8 @@
 #include <stdint.h>
 
 #include "internal.hpp"
+#include "point_search.hpp"
+#include "round_common.hpp"
 
 namespace nnsemd {
 namespace {
@@ -37,7 +39,9 @@ constexpr int kLpScanThreads = 1024;
 constexpr int kLpTile = 1024;   // supplier records per LDS tile in the search
 constexpr int kLpUnroll = 8;
 
-__device__ inline bool lp_live(const LPState* st) { return st->status == NNSEMD_OK && !st->done; }
+// The round kernels run while the pair is unfinished and the
+// single-workgroup finish has not taken over.
+__device__ inline bool lp_live(const LPState* st) { return st->status == NNSEMD_OK && !st->done && !st->tail; }
 
 template <int D, bool L1>
 __device__ inline double lp_key64(const float* __restrict__ x, const float* __restrict__ y) {
@@ -337,6 +341,7 @@ __global__ __launch_bounds__(kLpScanThreads) void lp_setup(LPArgs A, int nblocks
         st->ticket = 0;
         st->parity = 1;
         st->done = (st->mact == 0 || st->nact == 0) ? 1 : 0;
+        st->tail = (!st->done && st->mact <= A.tail_cap && st->nact <= A.tail_cap) ? 1 : 0;
         st->rhat = __uint_as_float(rbits) * (1.f + 1e-6f);
 #pragma unroll
         for (int t = 0; t < D; ++t) st->centre[t] = centre[t];
@@ -1071,6 +1076,8 @@ __device__ void lp_commit_round(const LPArgs& A, int nblocks, bool single, unsig
     } else if (A.max_rounds > 0 && st->rounds >= A.max_rounds) {
         st->status = NNSEMD_ERR_NOT_CONVERGED;
         st->done = 1;
+    } else if (m2 <= A.tail_cap && n2 <= A.tail_cap) {
+        st->tail = 1;
     }
 }
 
@@ -1193,6 +1200,145 @@ __global__ __launch_bounds__(kLpScanThreads) void lp_finish(LPArgs A) {
     }
 }
 
+// ----------------------------------------------------------------- tail
+// Single-workgroup finish.  Once both active sets fit (tail_cap points per
+// side), the remaining rounds run in one workgroup with the pair in LDS, as
+// on the one-workgroup path, instead of nine grid-wide launches per round.
+// The suppliers keep their slots (ascending supplier index, so ties still go
+// to the smallest index) and records; the consumers are renumbered 0..nact-1
+// in ascending index order (the greedy order's tie rule is unchanged) and
+// mapped back to the caller's indices for the random order, the plan and the
+// map.  Costs and the map sums go to the same per-supplier accumulators, in
+// the same serve order, as on the grid-wide rounds.
+constexpr int kLpTailThreads = 512;
+constexpr int kLpTailChunk = 4;  // points per thread and side: capacity 2048
+
+__host__ __device__ inline size_t lp_tail_lds(int cap, int rs) {
+    return align_up(pair_lds_layout(cap, cap, rs, 0, false, false).total, 16) + sizeof(int32_t) * (size_t)cap;
+}
+
+template <int D, bool L1>
+__global__ __launch_bounds__(kLpTailThreads) void lp_tail(LPArgs A) {
+#pragma clang fp contract(off)
+    constexpr int RS = record_stride(D);
+    constexpr int T = kLpTailThreads;
+    extern __shared__ __align__(16) char lds_dyn[];
+    __shared__ rc::SharedCore sh;
+    LPState* st = A.w.st;
+    if (!(st->status == NNSEMD_OK && !st->done && st->tail)) return;  // uniform
+    const int cap = A.tail_cap;
+    rc::Lds L = rc::carve(lds_dyn, cap, cap, RS);
+    int32_t* jmap = reinterpret_cast<int32_t*>(lds_dyn + align_up(pair_lds_layout(cap, cap, RS, 0, false, false).total, 16));
+    L.jmap = jmap;
+    const int tid = threadIdx.x;
+    const int par = st->parity;
+    const int nact0 = st->nact;
+    int mact = st->mact, nact = nact0;
+    float centre[D];
+#pragma unroll
+    for (int t = 0; t < D; ++t) centre[t] = st->centre[t];
+    const float rhat = st->rhat;
+    // consumer coordinates gathered by tail-local index (the partial-result
+    // buffer is free from here on)
+    float* Yt = reinterpret_cast<float*>(A.w.part);
+    if (tid == 0) {
+        sh.tie_nn = 0ull;
+        sh.tie_order = 0ull;
+        sh.nflag = 0;
+    }
+    for (int s = tid; s < mact; s += T) {
+        const float4* src = reinterpret_cast<const float4*>(A.w.srec[par] + (size_t)s * RS);
+        float4* dst = reinterpret_cast<float4*>(L.srec + (size_t)s * RS);
+#pragma unroll
+        for (int q = 0; q < RS / 4; ++q) dst[q] = src[q];
+        L.sidx[s] = A.w.sidx[par][s];
+        L.smass[s] = A.w.smass[par][s];
+        L.scnt[s] = 0;
+    }
+    for (int q = tid; q < nact; q += T) {
+        const int j = A.w.cact[par][q];
+        jmap[q] = j;
+        L.cact[q] = q;
+        L.cmass[q] = A.w.cmass[j];
+#pragma unroll
+        for (int t = 0; t < D; ++t) Yt[(size_t)q * D + t] = A.Y[(int64_t)j * D + t];
+    }
+    __syncthreads();
+    const int64_t max_rounds = A.max_rounds;
+    int status = NNSEMD_OK;
+    int64_t rounds = st->rounds;
+    int64_t work = 0, nnz = 0, near = 0;
+    const int64_t plan_base = st->nnz;
+    while (mact > 0 && nact > 0) {
+        if (max_rounds > 0 && rounds >= max_rounds) {
+            status = NNSEMD_ERR_NOT_CONVERGED;
+            break;
+        }
+        work += (int64_t)mact * nact;
+        near += ps::search_round<D, T, kLpTailChunk, L1>(L, sh, A.X, Yt, centre, rhat, mact, nact, 1, false,
+                                                          A.metric);
+        rc::round_buckets<T>(L, sh, mact, nact);
+        rc::round_rank<T, kLpTailChunk>(L, nact, A.protocol, A.seed, (int)rounds, A.metric,
+                                        A.protocol == NNSEMD_GREEDY ? &sh.tie_order : nullptr);
+        // serve walk (the grid-wide rounds' operations and accumulators)
+        for (int s = tid; s < mact; s += T) {
+            const int c = L.scnt[s];
+            if (c == 0) continue;
+            const int end = L.soff[s];
+            const int isup = L.sidx[s];
+            int pos = end - c;
+            double sm = L.smass[s];
+            double acc = A.w.costacc[isup];
+            while (pos < end && sm > 0.0) {
+                const int q = L.sorted[pos];
+                const double cm = L.cmass[q];
+                const double f = sm < cm ? sm : cm;
+                sm = sm - f;
+                L.cmass[q] = cm - f;
+                const double key = L.ckey[q];
+                acc = acc + f * (A.metric == NNSEMD_L2 ? sqrt(key) : key);
+                if (A.w.wsum != nullptr) {
+                    A.w.wsum[isup] = A.w.wsum[isup] + f;
+#pragma unroll
+                    for (int t = 0; t < D; ++t)
+                        A.w.bsum[(int64_t)isup * D + t] =
+                            A.w.bsum[(int64_t)isup * D + t] + f * (double)Yt[(size_t)q * D + t];
+                }
+                L.ckey[q] = -f;  // negated flow: unserved claimants keep their keys
+                L.cnn[q] = isup;
+                ++pos;
+            }
+            L.smass[s] = sm;
+            A.w.costacc[isup] = acc;
+        }
+        __syncthreads();
+        rc::round_compact<T, kLpTailChunk, RS, true>(L, sh, mact, nact, nnz, A.plan_src, A.plan_dst, A.plan_flow,
+                                               plan_base);
+        ++rounds;
+    }
+    // hand the state back to the finish: survivors in slots 0.. of the
+    // current buffers, consumer masses by the caller's index
+    for (int s = tid; s < mact; s += T) {
+        A.w.sidx[par][s] = L.sidx[s];
+        A.w.smass[par][s] = L.smass[s];
+    }
+    for (int q = tid; q < nact; q += T) A.w.cact[par][q] = jmap[L.cact[q]];
+    for (int q = tid; q < nact0; q += T) A.w.cmass[jmap[q]] = L.cmass[q];
+    __syncthreads();
+    if (tid == 0) {
+        st->status = status;
+        st->rounds = (int32_t)rounds;
+        st->nnz += nnz;
+        st->work += work;
+        st->near += near;
+        st->ties_nn += (int64_t)sh.tie_nn;
+        st->ties_order += (int64_t)sh.tie_order;
+        st->mact = mact;
+        st->nact = nact;
+        st->done = 1;
+    }
+}
+
 #define NNSEMD_LP_DISPATCH(D_, EXPR)                   \
     switch (D_) {                                      \
         case 1: { constexpr int DD = 1; EXPR; } break; \
@@ -1261,6 +1407,42 @@ int lp_launch_round(const LPArgs& A, int d, int mact_ub, int nact_ub, void* stre
         if (cmblocks > 1) hipLaunchKernelGGL(lp_ccount, dim3(cmblocks), dim3(kLpThreads), 0, st, A);
         hipLaunchKernelGGL(lp_cwrite<DD>, dim3(cmblocks), dim3(kLpThreads), 0, st, A);
     })
+    return (int)hipGetLastError();
+}
+
+template <int D, bool L1>
+int launch_tail_typed(const LPArgs& A, size_t lds, hipStream_t st) {
+    hipError_t e = hipFuncSetAttribute((const void*)lp_tail<D, L1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return (int)e;
+    hipLaunchKernelGGL((lp_tail<D, L1>), dim3(1), dim3(kLpTailThreads), lds, st, A);
+    return (int)hipGetLastError();
+}
+
+template <int D>
+int launch_tail_metric(const LPArgs& A, bool l1, size_t lds, hipStream_t st) {
+    return l1 ? launch_tail_typed<D, true>(A, lds, st) : launch_tail_typed<D, false>(A, lds, st);
+}
+
+// Hand-over point: both active sets at most 512 points.  The workgroup
+// could hold 2048 a side, but the on-chip claimant order costs O(c) per
+// claimant of a bucket of c, and the colour-transfer pair's late rounds
+// have buckets of hundreds to thousands of claimants (one supplier left
+// among many consumers): handing over at 2048 took that pair from 63.0 to
+// 68.1 ms, at 1024 to 62.0 ms, at 512 to 61.0 ms.
+constexpr int kLpTailHandOver = 512;
+
+int lp_tail_capacity(int d, size_t max_lds) {
+    const int rs = record_stride(d);
+    for (int cap = kLpTailHandOver; cap >= 64; cap /= 2)
+        if (lp_tail_lds(cap, rs) + 8192 <= max_lds) return cap;
+    return 0;
+}
+
+int lp_launch_tail(const LPArgs& A, int d, void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    const bool l1 = A.metric == NNSEMD_L1;
+    const size_t lds = lp_tail_lds(A.tail_cap, record_stride(d));
+    NNSEMD_LP_DISPATCH(d, { return launch_tail_metric<DD>(A, l1, lds, st); })
     return (int)hipGetLastError();
 }
 

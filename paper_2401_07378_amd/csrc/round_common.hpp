@@ -53,6 +53,7 @@ struct LdsT {
     I* sorted;      // [N] claimant buckets in serve order (the list's storage when compact)
     float* xl;      // [M * cd] supplier coordinates by local index (coordinate variant only)
     float* yl;      // [N * cd] consumer coordinates by local index (coordinate variant only)
+    const int32_t* jmap;  // [N] caller's consumer index of each local one (null: the same)
 };
 using Lds = LdsT<int32_t>;
 using Lds16 = LdsT<uint16_t>;
@@ -91,6 +92,7 @@ __device__ inline LdsT<I> carve_t(char* base, const PairLdsLayout& L) {
     s.sorted = reinterpret_cast<I*>(base + L.sorted);
     s.xl = reinterpret_cast<float*>(base + L.xl);
     s.yl = reinterpret_cast<float*>(base + L.yl);
+    s.jmap = nullptr;
     return s;
 }
 
@@ -288,11 +290,12 @@ __device__ inline int claimant_place(const LT& L, int j, int protocol, uint64_t 
             }
             if (ties_order != nullptr && pk >= 0.0 && keys_near(pk, k, metric)) atomicAdd(ties_order, 1ull);
         } else {
-            const uint64_t k = rp_key(seed, rounds, j);
+            // the random order is drawn for the caller's consumer indices
+            const uint64_t k = rp_key(seed, rounds, L.jmap != nullptr ? L.jmap[j] : j);
 #pragma unroll 4
             for (int e = start; e < end; ++e) {
                 const int j2 = L.list[e];
-                const uint64_t k2 = rp_key(seed, rounds, j2);
+                const uint64_t k2 = rp_key(seed, rounds, L.jmap != nullptr ? L.jmap[j2] : j2);
                 rank += (k2 < k) || (k2 == k && j2 < j);
             }
         }
@@ -331,10 +334,13 @@ __device__ inline void round_rank(const LT& L, int nact, int protocol, uint64_t 
 // ---- flow & cost: one lane per claimed supplier walks its ordered
 // claimants while it still holds mass.  A served claimant records the local
 // index of its supplier (for the plan) and its flow in place of its key; an
-// unserved one gets flow 0.  With COST (the keys are the exact FP64 keys),
-// `cost` accumulates this thread's part of R; without it, R is left to the
-// caller.
-template <int T, bool COST = true, typename LT>
+// unserved one gets flow 0.  With NEGF (every key is >= +0 when the walk
+// starts) the flow is stored negated and unserved claimants keep their keys,
+// so the walk never visits the unserved part of a bucket (one serve can
+// exhaust a supplier with thousands of claimants); round_compact must then be
+// told the same.  With COST (the keys are the exact FP64 keys), `cost`
+// accumulates this thread's part of R; without it, R is left to the caller.
+template <int T, bool COST = true, bool NEGF = false, typename LT>
 __device__ inline void round_walk(const LT& L, int mact, int metric, double& cost) {
     for (int s = threadIdx.x; s < mact; s += T) {
         const int c = L.scnt[s];
@@ -351,11 +357,12 @@ __device__ inline void round_walk(const LT& L, int mact, int metric, double& cos
             sm = sm - f;
             L.cmass[j] = cm - f;
             if constexpr (COST) cost = cost + f * dist_of_key(L.ckey[j], metric);
-            L.ckey[j] = f;
+            L.ckey[j] = NEGF ? -f : f;
             L.cnn[j] = isup;
             ++pos;
         }
-        for (int e = pos; e < end; ++e) L.ckey[L.sorted[e]] = 0.0;
+        if constexpr (!NEGF)
+            for (int e = pos; e < end; ++e) L.ckey[L.sorted[e]] = 0.0;
         L.smass[s] = sm;
     }
     __syncthreads();
@@ -363,7 +370,7 @@ __device__ inline void round_walk(const LT& L, int mact, int metric, double& cos
 
 // ---- weights update: plan append + compaction of the active sets (and of
 // the RS-float search records when RS > 0), one scan for all three streams.
-template <int T, int CSMAX, int RS, typename LT>
+template <int T, int CSMAX, int RS, bool NEGF = false, typename LT>
 __device__ inline void round_compact(const LT& L, SharedCore& sh, int& mact, int& nact, int64_t& nnz,
                                      int32_t* plan_src, int32_t* plan_dst, double* plan_flow, int64_t plan_base) {
     constexpr int RSA = RS > 0 ? RS : 4;
@@ -383,10 +390,11 @@ __device__ inline void round_compact(const LT& L, SharedCore& sh, int& mact, int
             const int k = plo + u;
             pj[u] = k < phi ? (int)L.sorted[k] : 0;
             pf[u] = k < phi ? L.ckey[pj[u]] : 0.0;
+            if constexpr (NEGF) pf[u] = pf[u] < 0.0 ? -pf[u] : 0.0;
             kp += pf[u] > 0.0;
         }
     } else {
-        for (int k = plo; k < phi; ++k) kp += L.ckey[L.sorted[k]] > 0.0;
+        for (int k = plo; k < phi; ++k) kp += NEGF ? L.ckey[L.sorted[k]] < 0.0 : L.ckey[L.sorted[k]] > 0.0;
     }
     const int cs = (mact + T - 1) / T;
     const int slo = min(tid * cs, mact);
@@ -430,7 +438,7 @@ __device__ inline void round_compact(const LT& L, SharedCore& sh, int& mact, int
                     const int j = pj[u];
                     const int64_t e = plan_base + nnz + wp;
                     plan_src[e] = L.cnn[j];
-                    plan_dst[e] = j;
+                    plan_dst[e] = L.jmap != nullptr ? L.jmap[j] : j;
                     plan_flow[e] = pf[u];
                     ++wp;
                 }
@@ -438,11 +446,11 @@ __device__ inline void round_compact(const LT& L, SharedCore& sh, int& mact, int
         } else {
             for (int k = plo; k < phi; ++k) {
                 const int j = L.sorted[k];
-                const double f = L.ckey[j];
+                const double f = NEGF ? -L.ckey[j] : L.ckey[j];
                 if (f > 0.0) {
                     const int64_t e = plan_base + nnz + wp;
                     plan_src[e] = L.cnn[j];
-                    plan_dst[e] = j;
+                    plan_dst[e] = L.jmap != nullptr ? L.jmap[j] : j;
                     plan_flow[e] = f;
                     ++wp;
                 }

@@ -3,7 +3,9 @@ barycentric transport map with the FP64 oracle.
 
 Small and medium pairs are forced onto the multi-workgroup path and compared
 in full: plan bit-identical, rounds/work/nnz equal, cost to 1e-12, map
-bit-identical to the oracle's map of its own plan.  The full 65536 x 65536
+bit-identical to the oracle's map of its own plan.  Every case runs twice:
+with the single-workgroup finish (pairs whose active sets both fit it start
+there; larger ones hand over once they fit) and with every round grid-wide.  The full 65536 x 65536
 colour-transfer pair is compared in full with a stored oracle run (hashes of
 the plan and map) and checked on properties that hold at any size.
 """
@@ -29,16 +31,37 @@ CASES = [
     (8, 5000, 4500, 3, "dirichlet", "l2", "greedy"),
     (9, 3000, 3000, 3, "uniform", "sqeuclidean", "greedy"),
     (10, 12000, 9000, 3, "dirichlet", "l2", "greedy"),
+    # hand-over to the single-workgroup finish under the random order, L1
+    # and at d = 7
+    (11, 3000, 2800, 3, "dirichlet", "l2", "random"),
+    (12, 2600, 3100, 2, "integer", "l1", "greedy"),
+    (13, 2500, 2300, 7, "uniform", "l2", "greedy"),
 ]
 
 
+@pytest.mark.parametrize("path", ["multi", "multi_no_tail"])
 @pytest.mark.parametrize("case", CASES, ids=lambda c: "-".join(map(str, c[1:])))
-def test_multi_path_matches_oracle(case):
+def test_multi_path_matches_oracle(case, path):
     seed, m, n, d, masses, metric, protocol = case
     X, a, Y, b = W.random_pair(700 + seed, m, n, d, masses=masses)
     kw = dict(protocol=protocol, seed=99)
-    g = gpu_pair(X, a, Y, b, metric, path="multi", **kw)
-    assert_pair_matches(g, oracle_pair(X, a, Y, b, metric, **kw), label=str(case))
+    g = gpu_pair(X, a, Y, b, metric, path=path, **kw)
+    assert_pair_matches(g, oracle_pair(X, a, Y, b, metric, **kw), label=f"{case} {path}")
+
+
+@pytest.mark.parametrize("path", ["multi", "multi_no_tail"])
+def test_multi_path_map_across_the_hand_over(path):
+    """A pair that starts grid-wide and finishes in one workgroup: the map
+    (per-supplier sums accumulated in serve order on both sides of the
+    hand-over) is bit-identical to the oracle's map of its own plan."""
+    X, a, Y, b = W.random_pair(760, 2900, 2900, 3)
+    g = gpu_pair_map(X, a, Y, b, "sqeuclidean", path=path)
+    ref = oracle_pair(X, a, Y, b, "sqeuclidean")
+    assert_pair_matches(g, ref, label=f"map {path}")
+    want = oracle.barycentric(ref["src"], ref["dst"], ref["flow"], Y, len(a))
+    got = g["map"]
+    assert np.array_equal(np.isnan(got), np.isnan(want))
+    assert np.array_equal(got[~np.isnan(got)], want[~np.isnan(want)])
 
 
 @pytest.mark.parametrize("seed", range(3))
@@ -78,13 +101,14 @@ def test_barycentric_map_zero_mass_rows_are_nan():
     assert not np.any(np.isnan(np.delete(g["map"], [3, 9], axis=0)))
 
 
-def test_multi_path_status_codes():
+@pytest.mark.parametrize("path", ["multi", "multi_no_tail"])
+def test_multi_path_status_codes(path):
     X, a, Y, b = W.random_pair(750, 40, 50, 3)
     Xn = X.copy()
     Xn[5, 2] = np.nan
-    assert int(gpu_pair(Xn, a, Y, b, path="multi")["stats"]["status"]) == -1
-    assert int(gpu_pair(X, a * 2, Y, b, path="multi")["stats"]["status"]) == -2
-    g = gpu_pair(X, a, Y, b, path="multi", max_rounds=2)
+    assert int(gpu_pair(Xn, a, Y, b, path=path)["stats"]["status"]) == -1
+    assert int(gpu_pair(X, a * 2, Y, b, path=path)["stats"]["status"]) == -2
+    g = gpu_pair(X, a, Y, b, path=path, max_rounds=2)
     assert int(g["stats"]["status"]) == -6
     ref = oracle_pair(X, a, Y, b, max_rounds=2)
     assert ref["status"] == -6
@@ -92,8 +116,24 @@ def test_multi_path_status_codes():
     np.testing.assert_array_equal(g["flow"], ref["flow"])
 
 
-def test_multi_path_empty():
-    g = gpu_pair(np.zeros((0, 3)), np.zeros(0), np.zeros((0, 3)), np.zeros(0), path="multi")
+def test_round_cap_inside_the_single_workgroup_finish():
+    """The round cap reached after the hand-over: status NOT_CONVERGED, the
+    plan so far equal to the oracle's capped run."""
+    X, a, Y, b = W.random_pair(751, 2700, 2700, 3)
+    full = oracle_pair(X, a, Y, b, with_plan=False)
+    cap = full["rounds"] - 3
+    g = gpu_pair(X, a, Y, b, path="multi", max_rounds=cap)
+    ref = oracle_pair(X, a, Y, b, max_rounds=cap)
+    assert ref["status"] == -6 and int(g["stats"]["status"]) == -6
+    assert int(g["stats"]["rounds"]) == ref["rounds"] == cap
+    np.testing.assert_array_equal(g["src"], ref["src"])
+    np.testing.assert_array_equal(g["dst"], ref["dst"])
+    np.testing.assert_array_equal(g["flow"], ref["flow"])
+
+
+@pytest.mark.parametrize("path", ["multi", "multi_no_tail"])
+def test_multi_path_empty(path):
+    g = gpu_pair(np.zeros((0, 3)), np.zeros(0), np.zeros((0, 3)), np.zeros(0), path=path)
     assert int(g["stats"]["status"]) == 0 and g["cost"] == 0.0
 
 
