@@ -38,7 +38,7 @@ PEAK_BF16_MFMA = 2.5e15
 PEAK_HBM = 8.0e12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pair_solver_batched_hist_3d_traffic.json")
 SOURCES = [os.path.join(ROOT, "paper_2401_07378_amd", "csrc", f)
-           for f in ("pair_solver.hip", "round_common.hpp", "internal.hpp")]
+           for f in ("pair_solver.hip", "point_search.hpp", "round_common.hpp", "internal.hpp")]
 
 
 def log(msg):
