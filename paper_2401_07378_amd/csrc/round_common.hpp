@@ -154,6 +154,30 @@ __device__ inline uint64_t rp_key(uint64_t seed, int64_t round, int32_t j) {
     return z ^ (z >> 31);
 }
 
+// One DPP move of a 64-bit value (both halves); lanes without a source, or
+// in rows the row mask leaves out, read 0.
+template <int CTRL, int ROWS>
+__device__ inline unsigned long long dpp_u64(unsigned long long x) {
+    const int lo = (int)(unsigned)(x & 0xffffffffull), hi = (int)(unsigned)(x >> 32);
+    const unsigned rlo = (unsigned)__builtin_amdgcn_update_dpp(0, lo, CTRL, ROWS, 0xf, false);
+    const unsigned rhi = (unsigned)__builtin_amdgcn_update_dpp(0, hi, CTRL, ROWS, 0xf, false);
+    return ((unsigned long long)rhi << 32) | rlo;
+}
+
+// Inclusive scan over the 64 lanes of a wavefront with DPP moves: shifts by
+// 1, 2, 4, 8 within 16-lane rows, then lane 15's total added to rows 1 and
+// 3 and lane 31's to rows 2 and 3.  No LDS traffic (a shuffle is an LDS
+// permute).  Every lane of the wavefront must be active.
+__device__ inline unsigned long long wave_incl_scan_u64(unsigned long long x) {
+    x += dpp_u64<0x111, 0xf>(x);  // row_shr:1
+    x += dpp_u64<0x112, 0xf>(x);  // row_shr:2
+    x += dpp_u64<0x114, 0xf>(x);  // row_shr:4
+    x += dpp_u64<0x118, 0xf>(x);  // row_shr:8
+    x += dpp_u64<0x142, 0xa>(x);  // row_bcast:15
+    x += dpp_u64<0x143, 0xc>(x);  // row_bcast:31
+    return x;
+}
+
 // Exclusive block scan of one 64-bit value per thread; *total = block sum.
 template <int T>
 __device__ inline unsigned long long block_scan_u64(unsigned long long v, unsigned long long* total,
@@ -161,12 +185,7 @@ __device__ inline unsigned long long block_scan_u64(unsigned long long v, unsign
     static_assert(T / kWave <= kMaxWaves, "workgroup too large for the scan scratch");
     const int lane = threadIdx.x & (kWave - 1);
     const int w = threadIdx.x / kWave;
-    unsigned long long x = v;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        unsigned long long y = __shfl_up(x, o);
-        if (lane >= o) x += y;
-    }
+    unsigned long long x = wave_incl_scan_u64(v);
     if (lane == kWave - 1) sh.scan[w] = x;
     __syncthreads();
     unsigned long long off = 0, tot = 0;
