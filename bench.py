@@ -91,7 +91,7 @@ def main():
                     help="batched_hist_3d: launch eagerly instead of replaying a captured graph of one step")
     ap.add_argument("--schedule", default="longest_first", choices=["longest_first", "as_given"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true", help="batched_hist_3d, retrieval_3d: skip the launch autotuner")
+    ap.add_argument("--no-autotune", action="store_true", help="batched_hist_3d, documents_300d, retrieval_3d: skip the launch autotuner")
     ap.add_argument("--no-single-pair", action="store_true")
     ap.add_argument("--single-pair-sample", type=int, default=512)
     ap.add_argument("--workload", default="batched_hist_3d",
@@ -652,6 +652,10 @@ def bench_documents(args, dev):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / steps
 
+    doc_tuning = None
+    if not args.no_autotune:
+        doc_tuning = binding.autotune_docs(d, max_m, max_n, num_pairs=1024)
+        log(f"autotuned launch form: {doc_tuning}")
     out = buffers()
     log(f"timing {args.steps} steps (BF16 matrix-core path)")
     ms = timed(Xb, Yb, "bf16_mfma_refine", out, args.steps)
@@ -701,7 +705,9 @@ def bench_documents(args, dev):
     # call is bound by HBM; the matrix-core rate is reported beside it.
     roofline = {"bound": "hbm", "achieved": alg_bytes / (ms / 1e3) / 1e9, "peak": PEAK_HBM / 1e9,
                 "unit": "GB/s", "frac": alg_bytes / (ms / 1e3) / PEAK_HBM, "traffic": None,
-                "kernel": "doc_tile_kernel + doc_pair_kernel<bf16, mfma, 256, 4, split> (one call)",
+                "kernel": ("doc_pair_kernel<bf16, mfma, 256, 4, fused> (one call)"
+                           if doc_tuning is not None and doc_tuning["form"] == "fused" else
+                           "doc_tile_kernel + doc_pair_kernel<bf16, mfma, 256, 4, split> (one call)"),
                 "algorithmic_bytes": alg_bytes, "mfma_flops_per_launch": flops,
                 "mfma_tflops": flops / (ms / 1e3) / 1e12, "mfma_frac": flops / (ms / 1e3) / PEAK_BF16_MFMA,
                 "work_evals": work}
@@ -745,7 +751,8 @@ def bench_documents(args, dev):
             "config": {"workload": "documents_300d: 1 query vs 8192 candidates, sizes U{20..500}, 300-d "
                                    "N(0,1)/sqrt(300) stored BF16, Zipf(1.1) masses, L2, cost+plan+stats",
                        "num_pairs": P, "plan": want_plan, "seed": ps.meta["seed"],
-                       "rounds_mean": float(st["rounds"].mean())},
+                       "rounds_mean": float(st["rounds"].mean()),
+                       "launch_form": doc_tuning if doc_tuning is not None else {"form": "split", "autotuned": False}},
             "roofline": roofline, "cpu_baseline": cpu, "single_pair_fp32": single,
             "batched_fp32_vector": {"value": P / (ms_v / 1e3), "unit": "pairs/s", "ms_per_step": ms_v},
             "parity": parity}

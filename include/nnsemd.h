@@ -415,8 +415,34 @@ nnsemd_status_t nnsemd_autotune(nnsemd_handle_t h, int32_t d, nnsemd_metric_t me
  * "d metric class threads split ms" per entry), and back. */
 nnsemd_status_t nnsemd_tuning_save(nnsemd_handle_t h, const char* path);
 nnsemd_status_t nnsemd_tuning_load(nnsemd_handle_t h, const char* path);
-/* Forget every recorded configuration: later calls use the default (256, 1). */
+/* Forget every recorded configuration (both tables): later calls use the
+ * defaults. */
 nnsemd_status_t nnsemd_tuning_clear(nnsemd_handle_t h);
+
+/* Autotuning of the high-dimensional BF16 matrix-core path (Sec. III-D
+ * batching with the distance tile of the blueprint's matrix-core form).
+ * Two launch forms compute the same plans and costs: the split form (a key
+ * tile kernel with 16-consumer stripes whose BF16 fragments stay in
+ * registers, then the rounds kernel) and the fused form (32 x 32 blocked
+ * tiles computed by the rounds kernel itself).  The split form exists for
+ * d <= 320 and sides <= 1024.  Both are timed with HIP events on synthetic
+ * ragged BF16 pairs shaped like the caller's (sides uniform in
+ * [max/8, max], N(0, 1/d) coordinates, exponential masses) and the faster
+ * is recorded for (d class: <= 64, <= 128, <= 320, larger; size class of
+ * max(max_m, max_n)).  Later BF16 calls use it.  The call synchronises
+ * stream.  1 <= d <= 4096, 1 <= max_m, max_n <= 4096,
+ * 1 <= num_pairs <= 65536. */
+typedef struct {
+    int32_t split;    /* 1: split form chosen, 0: fused form */
+    float ms_split;   /* split form per launch on the synthetic batch (-1: not available) */
+    float ms_fused;   /* fused form per launch */
+} nnsemd_doc_tuning_t;
+
+nnsemd_status_t nnsemd_autotune_docs(nnsemd_handle_t h, int32_t d, int64_t max_m, int64_t max_n, int64_t num_pairs,
+                                     nnsemd_doc_tuning_t* result, void* stream);
+/* Record a launch form by hand for the (d class, size class of max_side)
+ * entry: split 1 = split form where it exists, 0 = fused form. */
+nnsemd_status_t nnsemd_tuning_set_docs(nnsemd_handle_t h, int32_t d, int64_t max_side, int32_t split);
 
 /* ------------------------------------------------------------------------
  * Learned surrogate for retrieval (not part of the paper, which treats

@@ -38,7 +38,7 @@ EXPORTS = ["nnsemd_create", "nnsemd_destroy", "nnsemd_status_string", "nnsemd_la
            "nnsemd_sg_num_params", "nnsemd_sg_embed", "nnsemd_sg_predict", "nnsemd_sg_loss_grad",
            "nnsemd_sg_train_step", "nnsemd_topk_smallest_f32", "nnsemd_topk_smallest_f64", "nnsemd_sg_retrieve",
            "nnsemd_autotune", "nnsemd_tuning_save", "nnsemd_tuning_load",
-           "nnsemd_tuning_clear"]
+           "nnsemd_tuning_clear", "nnsemd_autotune_docs", "nnsemd_tuning_set_docs"]
 SG_HIDDEN = 256
 
 
@@ -58,6 +58,10 @@ class Options(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("threads", ctypes.c_int32), ("split", ctypes.c_int32),
                 ("ms_best", ctypes.c_float), ("ms_default", ctypes.c_float)]
+
+
+class DocTuning(ctypes.Structure):
+    _fields_ = [("split", ctypes.c_int32), ("ms_split", ctypes.c_float), ("ms_fused", ctypes.c_float)]
 
 
 _lock = threading.Lock()
@@ -118,7 +122,10 @@ def load_library():
         lib.nnsemd_tuning_save.argtypes = [P, ctypes.c_char_p]
         lib.nnsemd_tuning_load.argtypes = [P, ctypes.c_char_p]
         lib.nnsemd_tuning_clear.argtypes = [P]
-        for fn in ("nnsemd_autotune", "nnsemd_tuning_save", "nnsemd_tuning_load", "nnsemd_tuning_clear"):
+        lib.nnsemd_autotune_docs.argtypes = [P, I32, I64, I64, I64, ctypes.POINTER(DocTuning), P]
+        lib.nnsemd_tuning_set_docs.argtypes = [P, I32, I64, I32]
+        for fn in ("nnsemd_autotune", "nnsemd_tuning_save", "nnsemd_tuning_load", "nnsemd_tuning_clear",
+                   "nnsemd_autotune_docs", "nnsemd_tuning_set_docs"):
             getattr(lib, fn).restype = I32
         for fn in ("nnsemd_sg_embed", "nnsemd_sg_predict", "nnsemd_sg_loss_grad", "nnsemd_sg_train_step",
                    "nnsemd_topk_smallest_f32", "nnsemd_topk_smallest_f64", "nnsemd_sg_retrieve"):
@@ -587,6 +594,29 @@ def autotune(d: int, metric: str, max_m: int, max_n: int, num_pairs: int = 1024,
                              _stream(torch, device))
     _check(lib, h, st)
     return {"threads": t.threads, "split": t.split, "ms_best": t.ms_best, "ms_default": t.ms_default}
+
+
+def autotune_docs(d: int, max_m: int, max_n: int, num_pairs: int = 1024, device: int = 0) -> dict:
+    """Time the BF16 high-dimensional path's launch forms (split key-tile
+    kernel, or tiles fused into the rounds kernel) on synthetic pairs of this
+    shape and record the faster in the device's handle."""
+    import torch
+    lib = load_library()
+    h = handle(device)
+    t = DocTuning()
+    st = lib.nnsemd_autotune_docs(h, d, max_m, max_n, num_pairs, ctypes.byref(t), _stream(torch, device))
+    _check(lib, h, st)
+    return {"form": "split" if t.split else "fused", "ms_split": t.ms_split, "ms_fused": t.ms_fused}
+
+
+def tuning_set_docs(d: int, max_side: int, form: str, device: int = 0):
+    """Record the BF16 high-dimensional path's launch form ("split" or
+    "fused") by hand for the (d, max side) class."""
+    lib = load_library()
+    h = handle(device)
+    if form not in ("split", "fused"):
+        raise ValueError("form is 'split' or 'fused'")
+    _check(lib, h, lib.nnsemd_tuning_set_docs(h, d, max_side, 1 if form == "split" else 0))
 
 
 def tuning_save(path: str, device: int = 0):

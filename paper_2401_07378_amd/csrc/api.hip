@@ -61,6 +61,12 @@ struct nnsemd_handle {
     char* ct_ws = nullptr;                       // colour transfer: palettes, assignments, plan, map
     size_t ct_bytes = 0;
     int32_t* fixed_order = nullptr;              // this device's copy of `scratch` (no-alloc schedule)
+    // Autotuned launch form of the BF16 high-dimensional path, by d class
+    // (<= 64, <= 128, <= 320, larger) and size class of max(max_m, max_n).
+    struct DocTune {
+        int32_t valid = 0, split = 1;
+        float ms_split = -1.f, ms_fused = -1.f;
+    } doc_tune[4][nnsemd_tune_classes];
 };
 
 namespace {
@@ -355,8 +361,11 @@ constexpr int kDocMaxDim = 65536;
 nnsemd_status_t run_docs_l1(nnsemd_handle_t h, DocArgs& A, int64_t max_m, int64_t max_n, nnsemd_dtype_t dtype,
                             const nnsemd_options_t& o, void* stream);
 
+int doc_dim_class(int64_t d) { return d <= 64 ? 0 : (d <= 128 ? 1 : (d <= 320 ? 2 : 3)); }
+
+// force_split: -1 = the tuned (or default split) form, 0 = fused, 1 = split where it exists.
 nnsemd_status_t run_docs(nnsemd_handle_t h, DocArgs& A, int64_t max_m, int64_t max_n, nnsemd_dtype_t dtype,
-                         const nnsemd_options_t& o, void* stream) {
+                         const nnsemd_options_t& o, void* stream, int force_split = -1) {
     if (A.metric == NNSEMD_L1) return run_docs_l1(h, A, max_m, max_n, dtype, o, stream);
     if (A.d > kDocMaxDim) return fail(h, NNSEMD_ERR_UNSUPPORTED, "d above 65536");
     if (o.threads != 0 && o.threads != 256)
@@ -373,8 +382,15 @@ nnsemd_status_t run_docs(nnsemd_handle_t h, DocArgs& A, int64_t max_m, int64_t m
     A.seed = o.seed;
     A.max_rounds = o.max_rounds;
     const bool mfma = dtype == NNSEMD_BF16;
+    bool split = doc_split_form(A.d, mfma, chunk);
+    if (force_split == 0) {
+        split = false;
+    } else if (force_split < 0 && split) {
+        const auto& dt = h->doc_tune[doc_dim_class(A.d)][tune_class(std::max<int64_t>(max_m, max_n))];
+        if (dt.valid && !dt.split) split = false;
+    }
     int blocks = 0;
-    int err = launch_doc_solver(A, mfma, chunk, lds, 0, stream, &blocks);
+    int err = launch_doc_solver(A, mfma, chunk, lds, 0, stream, &blocks, split);
     if (err != 0) return device_fail(h, err, "occupancy query");
     if (blocks < 1) return fail(h, NNSEMD_ERR_UNSUPPORTED, "pair workgroup does not fit on a compute unit");
     const int64_t slot = (int64_t)doc_slot_bytes(mcap, ncap);
@@ -399,7 +415,7 @@ nnsemd_status_t run_docs(nnsemd_handle_t h, DocArgs& A, int64_t max_m, int64_t m
         A.order = h->order;
     }
     A.xnorm = nullptr;
-    if (doc_split_form(A.d, mfma, chunk) && A.num_pairs > 0) {
+    if (split && A.num_pairs > 0) {
         const int64_t sets = A.x_off != nullptr ? A.num_x_sets : 1;
         const size_t xb = sizeof(double) * (size_t)std::max<int64_t>(sets, 1) * (size_t)mcap;
         if (h->doc_xnorm_bytes < xb) {
@@ -417,7 +433,7 @@ nnsemd_status_t run_docs(nnsemd_handle_t h, DocArgs& A, int64_t max_m, int64_t m
     for (int64_t base = 0; base < A.num_pairs; base += per_launch) {
         A.pair_base = base;
         const int grid = (int)std::min<int64_t>(per_launch, A.num_pairs - base);
-        err = launch_doc_solver(A, mfma, chunk, lds, grid, stream, nullptr);
+        err = launch_doc_solver(A, mfma, chunk, lds, grid, stream, nullptr, split);
         if (err != 0) return device_fail(h, err, "high-dimensional solver launch");
     }
     return NNSEMD_OK;
@@ -1299,6 +1315,145 @@ nnsemd_status_t nnsemd_tuning_clear(nnsemd_handle_t h) {
     for (auto& per_d : h->tune)
         for (auto& per_metric : per_d)
             for (auto& tn : per_metric) tn.valid = 0;
+    for (auto& per_d : h->doc_tune)
+        for (auto& dt : per_d) dt.valid = 0;
+    return NNSEMD_OK;
+}
+
+nnsemd_status_t nnsemd_tuning_set_docs(nnsemd_handle_t h, int32_t d, int64_t max_side, int32_t split) {
+    if (h == nullptr) return NNSEMD_ERR_INVALID_ARG;
+    h->last_error.clear();
+    if (d < 1 || max_side < 1 || (split != 0 && split != 1))
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "need d >= 1, max_side >= 1 and split 0 or 1");
+    auto& dt = h->doc_tune[doc_dim_class(d)][tune_class(max_side)];
+    dt.valid = 1;
+    dt.split = split;
+    dt.ms_split = dt.ms_fused = -1.f;
+    return NNSEMD_OK;
+}
+
+nnsemd_status_t nnsemd_autotune_docs(nnsemd_handle_t h, int32_t d, int64_t max_m, int64_t max_n, int64_t num_pairs,
+                                     nnsemd_doc_tuning_t* result, void* stream) {
+    if (h == nullptr) return NNSEMD_ERR_INVALID_ARG;
+    h->last_error.clear();
+    if (d < 1 || d > 4096) return fail(h, NNSEMD_ERR_INVALID_ARG, "need 1 <= d <= 4096");
+    if (max_m < 1 || max_n < 1 || max_m > 4096 || max_n > 4096 || num_pairs < 1 || num_pairs > 65536)
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "need 1 <= max_m, max_n <= 4096 and 1 <= num_pairs <= 65536");
+    DeviceGuard g(h->device);
+    hipStream_t st = (hipStream_t)stream;
+    // Synthetic BF16 pairs shaped like the caller's: sides uniform in
+    // [max/8, max], N(0, 1/d) coordinates rounded to BF16, normalised
+    // exponential masses.
+    std::vector<int64_t> xo(num_pairs + 1, 0), yo(num_pairs + 1, 0);
+    uint64_t rs = 0xD1B54A32D192ED03ull ^ (uint64_t)(d * 977 + max_m * 3 + max_n);
+    auto next = [&rs]() {
+        rs += 0x9E3779B97F4A7C15ull;
+        uint64_t z = rs;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    auto unif = [&next]() { return ((double)(next() >> 11) + 0.5) * 0x1.0p-53; };
+    for (int64_t p = 0; p < num_pairs; ++p) {
+        const int64_t lm = std::max<int64_t>(1, max_m / 8), ln = std::max<int64_t>(1, max_n / 8);
+        xo[p + 1] = xo[p] + lm + (int64_t)(unif() * (double)(max_m - lm + 1));
+        yo[p + 1] = yo[p] + ln + (int64_t)(unif() * (double)(max_n - ln + 1));
+    }
+    const double sd = 1.0 / std::sqrt((double)d);
+    auto points = [&](const std::vector<int64_t>& off, std::vector<uint16_t>& P, std::vector<float>& w) {
+        P.resize((size_t)off.back() * d);
+        w.resize((size_t)off.back());
+        for (auto& v : P) {  // Box-Muller, then round to nearest even BF16
+            const double g = std::sqrt(-2.0 * std::log(unif())) * std::cos(6.283185307179586 * unif());
+            const float f = (float)(g * sd);
+            uint32_t u;
+            std::memcpy(&u, &f, 4);
+            u += 0x7fffu + ((u >> 16) & 1u);
+            v = (uint16_t)(u >> 16);
+        }
+        for (size_t s = 0; s + 1 < off.size(); ++s) {
+            double sum = 0.0;
+            for (int64_t i = off[s]; i < off[s + 1]; ++i) sum += (w[i] = (float)-std::log(unif()));
+            for (int64_t i = off[s]; i < off[s + 1]; ++i) w[i] = (float)(w[i] / sum);
+        }
+    };
+    std::vector<uint16_t> X, Y;
+    std::vector<float> a, b;
+    points(xo, X, a);
+    points(yo, Y, b);
+    Carver c;
+    const size_t oX = c.take(2 * X.size()), oa = c.take(4 * a.size()), oY = c.take(2 * Y.size()),
+                 ob = c.take(4 * b.size()), oxo = c.take(8 * xo.size()), oyo = c.take(8 * yo.size()),
+                 oc = c.take(8 * (size_t)num_pairs);
+    char* base = nullptr;
+    if (hipMalloc((void**)&base, align_up(c.off, 256)) != hipSuccess)
+        return fail(h, NNSEMD_ERR_OUT_OF_MEMORY, "autotuning inputs");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    nnsemd_status_t status = NNSEMD_OK;
+    bool ok = hipMemcpyAsync(base + oX, X.data(), 2 * X.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
+              hipMemcpyAsync(base + oa, a.data(), 4 * a.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
+              hipMemcpyAsync(base + oY, Y.data(), 2 * Y.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
+              hipMemcpyAsync(base + ob, b.data(), 4 * b.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
+              hipMemcpyAsync(base + oxo, xo.data(), 8 * xo.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
+              hipMemcpyAsync(base + oyo, yo.data(), 8 * yo.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
+              hipStreamSynchronize(st) == hipSuccess && hipEventCreate(&e0) == hipSuccess &&
+              hipEventCreate(&e1) == hipSuccess;
+    if (!ok) status = fail(h, NNSEMD_ERR_DEVICE, "autotuning set-up");
+    float ms_form[2] = {-1.f, -1.f};  // fused, split
+    const int mcap = (int)max_m, ncap = (int)max_n;
+    const int chunk = (std::max(mcap, ncap) + 255) / 256;
+    const bool split_exists = doc_split_form(d, true, chunk);
+    for (int form = 0; form < 2 && status == NNSEMD_OK; ++form) {
+        if (form == 1 && !split_exists) break;
+        DocArgs A{};
+        A.num_pairs = num_pairs;
+        A.X = base + oX;
+        A.a = reinterpret_cast<const float*>(base + oa);
+        A.x_off = reinterpret_cast<const int64_t*>(base + oxo);
+        A.num_x_sets = num_pairs;
+        A.Y = base + oY;
+        A.b = reinterpret_cast<const float*>(base + ob);
+        A.y_off = reinterpret_cast<const int64_t*>(base + oyo);
+        A.num_y_sets = num_pairs;
+        A.d = d;
+        A.metric = NNSEMD_L2;
+        A.costs = reinterpret_cast<double*>(base + oc);
+        const nnsemd_options_t o = default_options();
+        DocArgs Aw = A;
+        nnsemd_status_t s = run_docs(h, Aw, max_m, max_n, NNSEMD_BF16, o, stream, form);
+        if (s != NNSEMD_OK) {
+            status = s;
+            break;
+        }
+        float ms = 0.f;
+        bool good = hipEventRecord(e0, st) == hipSuccess;
+        for (int r = 0; r < 3 && good; ++r) {
+            DocArgs Ar = A;
+            good = run_docs(h, Ar, max_m, max_n, NNSEMD_BF16, o, stream, form) == NNSEMD_OK;
+        }
+        good = good && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+               hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+        if (!good) {
+            status = fail(h, NNSEMD_ERR_DEVICE, "autotuning launch");
+            break;
+        }
+        ms_form[form] = ms / 3.f;
+    }
+    (void)hipStreamSynchronize(st);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(base);
+    if (status != NNSEMD_OK) return status;
+    auto& dt = h->doc_tune[doc_dim_class(d)][tune_class(std::max(max_m, max_n))];
+    dt.valid = 1;
+    dt.split = ms_form[1] >= 0.f && ms_form[1] <= ms_form[0] ? 1 : 0;
+    dt.ms_split = ms_form[1];
+    dt.ms_fused = ms_form[0];
+    if (result != nullptr) {
+        result->split = dt.split;
+        result->ms_split = dt.ms_split;
+        result->ms_fused = dt.ms_fused;
+    }
     return NNSEMD_OK;
 }
 

@@ -1264,10 +1264,10 @@ int launch_doc_xnorm(const DocArgs& A, void* stream) {
 }
 
 int launch_doc_solver(const DocArgs& A, bool bf16_mfma, int chunk_max, size_t lds, int grid, void* stream,
-                      int* blocks) {
+                      int* blocks, bool allow_split) {
     const bool run = blocks == nullptr;
     hipStream_t st = (hipStream_t)stream;
-    const bool split = doc_split_form(A.d, bf16_mfma, chunk_max);
+    const bool split = allow_split && doc_split_form(A.d, bf16_mfma, chunk_max);
     if (bf16_mfma) {
         if (chunk_max <= 4 && split) return doc_launch_typed<uint16_t, true, 4, true>(A, lds, grid, st, run, blocks);
         if (chunk_max <= 4) return doc_launch_typed<uint16_t, true, 4, false>(A, lds, grid, st, run, blocks);

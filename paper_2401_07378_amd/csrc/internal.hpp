@@ -228,8 +228,9 @@ __host__ __device__ inline size_t doc_slot_bytes(int max_m, int max_n) {
     return doc_aux_offset(max_m, max_n) + align_up(4 * ((size_t)max_m + 4 * (size_t)max_n) + 16, 256);
 }
 // blocks == nullptr: launch; else query resident workgroups per CU.
+// allow_split = false takes the fused form even where the split one exists.
 int launch_doc_solver(const DocArgs& A, bool bf16_mfma, int chunk_max, size_t lds, int grid, void* stream,
-                      int* blocks);
+                      int* blocks, bool allow_split = true);
 
 // ---------------------------------------------------------------------
 // Deep-sets EMD surrogate (surrogate.hip).  Flat FP32 parameter layout:

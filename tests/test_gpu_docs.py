@@ -180,6 +180,35 @@ def test_document_batch_several_supplier_sets():
             assert gb["costs"][p] == g["costs"][p], p
 
 
+def test_document_autotuner_keeps_results():
+    """Both launch forms of the BF16 path (split key-tile kernel, tiles fused
+    into the rounds kernel) give the same plans and costs; the autotuner times
+    them and records one, and results stay the same."""
+    from paper_2401_07378_amd import binding
+    ps = _small_docs(40, seed=893)
+    m_sizes, n_sizes = ps.sizes()
+    side = int(max(m_sizes.max(), n_sizes.max()))
+    binding.tuning_reset()
+    try:
+        split = gpu_batched(ps, plan=True, mode="bf16_mfma_refine")
+        binding.tuning_set_docs(300, side, "fused")
+        fused = gpu_batched(ps, plan=True, mode="bf16_mfma_refine")
+        t = binding.autotune_docs(300, int(m_sizes.max()), int(n_sizes.max()), num_pairs=256)
+        assert t["form"] in ("split", "fused") and t["ms_fused"] > 0 and t["ms_split"] > 0
+        tuned = gpu_batched(ps, plan=True, mode="bf16_mfma_refine")
+        # The forms round their FP32 keys in different orders, so each flags
+        # its own near ties for the FP64 re-score; every result and every
+        # other counter is the same.
+        for other in (fused, tuned):
+            for k in ("costs", "src", "dst", "flow"):
+                np.testing.assert_array_equal(other[k], split[k])
+            for f in split["stats"].dtype.names:
+                if f != "rescored":
+                    np.testing.assert_array_equal(other["stats"][f], split["stats"][f], err_msg=f)
+    finally:
+        binding.tuning_reset()
+
+
 def test_document_batch_as_given_schedule_same_bits():
     ps = _small_docs(32, seed=891)
     g1 = gpu_batched(ps, mode="bf16_mfma_refine")
