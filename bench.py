@@ -668,8 +668,11 @@ def bench_documents(args, dev):
     out_v = buffers()
     vsteps = max(1, min(args.steps, 5))
     ms_v = timed(Xf, Yf, "fp32", out_v, vsteps)
-    same_bits = bool(np.array_equal(out_v["costs"].cpu().numpy()[:P], costs))
-    log(f"batched FP32 vector path {ms_v:.3f} ms/step; identical costs: {same_bits}")
+    # The FP32 vector path recomputes every served distance in FP64; the BF16
+    # split form takes them from its keys within 1e-5 (plans identical).
+    vcosts = out_v["costs"].cpu().numpy()[:P]
+    v_rel = float(np.max(np.abs(vcosts - costs) / np.maximum(np.abs(vcosts), 1e-300)))
+    log(f"batched FP32 vector path {ms_v:.3f} ms/step; max rel cost difference {v_rel:.3g}")
 
     single = None
     if not args.no_single_pair:
@@ -707,7 +710,7 @@ def bench_documents(args, dev):
                 "unit": "GB/s", "frac": alg_bytes / (ms / 1e3) / PEAK_HBM, "traffic": None,
                 "kernel": ("doc_pair_kernel<bf16, mfma, 256, 4, fused> (one call)"
                            if doc_tuning is not None and doc_tuning["form"] == "fused" else
-                           "doc_tile_kernel + doc_pair_kernel<bf16, mfma, 256, 4, split> (one call)"),
+                           "doc_tile_shared_kernel + doc_pair_kernel<bf16, mfma, 256, 4, split> (one call)"),
                 "algorithmic_bytes": alg_bytes, "mfma_flops_per_launch": flops,
                 "mfma_tflops": flops / (ms / 1e3) / 1e12, "mfma_frac": flops / (ms / 1e3) / PEAK_BF16_MFMA,
                 "work_evals": work}
@@ -741,7 +744,7 @@ def bench_documents(args, dev):
                   "rescored_consumers": int(st["rescored"].sum()),
                   "near_ties_nn": int(st["near_ties_nn"].sum()), "near_ties_order": int(st["near_ties_order"].sum()),
                   "near_ties_identical": int(near_same.sum()), "tolerance": 1e-3,
-                  "fp32_vector_path_identical_costs": same_bits}
+                  "fp32_vector_path_max_rel_cost_diff": v_rel}
         log(f"oracle {cpu['value']:.1f} pairs/s; max rel err {rel.max():.3g}")
 
     line = {"metric": "EMD pairs/sec at stated rel. error vs FP64 oracle; batched/MFMA vs plain FP32",
@@ -754,7 +757,8 @@ def bench_documents(args, dev):
                        "rounds_mean": float(st["rounds"].mean()),
                        "launch_form": doc_tuning if doc_tuning is not None else {"form": "split", "autotuned": False}},
             "roofline": roofline, "cpu_baseline": cpu, "single_pair_fp32": single,
-            "batched_fp32_vector": {"value": P / (ms_v / 1e3), "unit": "pairs/s", "ms_per_step": ms_v},
+            "batched_fp32_vector": {"value": P / (ms_v / 1e3), "unit": "pairs/s", "ms_per_step": ms_v,
+                                   "max_rel_cost_diff": v_rel},
             "parity": parity}
     print(json.dumps(line), flush=True)
 

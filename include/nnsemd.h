@@ -441,7 +441,10 @@ typedef struct {
 nnsemd_status_t nnsemd_autotune_docs(nnsemd_handle_t h, int32_t d, int64_t max_m, int64_t max_n, int64_t num_pairs,
                                      nnsemd_doc_tuning_t* result, void* stream);
 /* Record a launch form by hand for the (d class, size class of max_side)
- * entry: split 1 = split form where it exists, 0 = fused form. */
+ * entry: split 1 = split form where it exists (its tile pass stages a supplier
+ * set shared by every pair once per workgroup and runs stripe by stripe, else
+ * one workgroup per pair), 2 = split form with the per-pair tile pass always,
+ * 0 = fused form.  All three give the same plans and costs. */
 nnsemd_status_t nnsemd_tuning_set_docs(nnsemd_handle_t h, int32_t d, int64_t max_side, int32_t split);
 
 /* ------------------------------------------------------------------------

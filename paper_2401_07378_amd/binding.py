@@ -610,13 +610,16 @@ def autotune_docs(d: int, max_m: int, max_n: int, num_pairs: int = 1024, device:
 
 
 def tuning_set_docs(d: int, max_side: int, form: str, device: int = 0):
-    """Record the BF16 high-dimensional path's launch form ("split" or
-    "fused") by hand for the (d, max side) class."""
+    """Record the BF16 high-dimensional path's launch form by hand for the
+    (d, max side) class: "split" (its tile pass runs stripe by stripe over a
+    supplier set that every pair shares, else per pair), "split_per_pair"
+    (the per-pair tile pass always) or "fused"."""
     lib = load_library()
     h = handle(device)
-    if form not in ("split", "fused"):
-        raise ValueError("form is 'split' or 'fused'")
-    _check(lib, h, lib.nnsemd_tuning_set_docs(h, d, max_side, 1 if form == "split" else 0))
+    forms = {"fused": 0, "split": 1, "split_per_pair": 2}
+    if form not in forms:
+        raise ValueError("form is 'split', 'split_per_pair' or 'fused'")
+    _check(lib, h, lib.nnsemd_tuning_set_docs(h, d, max_side, forms[form]))
 
 
 def tuning_save(path: str, device: int = 0):

@@ -45,6 +45,8 @@ struct nnsemd_handle {
     char* topk_ws = nullptr;                     // top-k threshold, count and candidate buffer
     double* doc_xnorm = nullptr;                 // supplier-set norms of the split document form
     size_t doc_xnorm_bytes = 0;
+    int32_t* doc_stripes = nullptr;              // stripe list of the shared-query tile kernel, then its length
+    size_t doc_stripes_bytes = 0;
     // Autotuned launch configuration of the batched point path, by
     // dimension (1..7), metric and size class of max(max_m, max_n).
     struct Tune {
@@ -383,19 +385,22 @@ nnsemd_status_t run_docs(nnsemd_handle_t h, DocArgs& A, int64_t max_m, int64_t m
     A.max_rounds = o.max_rounds;
     const bool mfma = dtype == NNSEMD_BF16;
     bool split = doc_split_form(A.d, mfma, chunk);
+    bool per_pair_tile = false;
     if (force_split == 0) {
         split = false;
     } else if (force_split < 0 && split) {
         const auto& dt = h->doc_tune[doc_dim_class(A.d)][tune_class(std::max<int64_t>(max_m, max_n))];
-        if (dt.valid && !dt.split) split = false;
+        if (dt.valid && dt.split == 0) split = false;
+        if (dt.valid && dt.split == 2) per_pair_tile = true;
     }
     int blocks = 0;
     int err = launch_doc_solver(A, mfma, chunk, lds, 0, stream, &blocks, split);
     if (err != 0) return device_fail(h, err, "occupancy query");
     if (blocks < 1) return fail(h, NNSEMD_ERR_UNSUPPORTED, "pair workgroup does not fit on a compute unit");
     const int64_t slot = (int64_t)doc_slot_bytes(mcap, ncap);
-    const int64_t per_launch =
-        std::max<int64_t>(1, std::min<int64_t>(A.num_pairs, (int64_t)(kDocTileBudget / (size_t)slot)));
+    // (at most 2^24 pairs per launch: the stripe records pack the pair position in 25 bits)
+    const int64_t per_launch = std::max<int64_t>(
+        1, std::min<int64_t>({A.num_pairs, (int64_t)(kDocTileBudget / (size_t)slot), (int64_t)1 << 24}));
     const size_t need = (size_t)slot * (size_t)per_launch;
     if (h->doc_bytes < need) {
         if (h->doc_tiles) (void)hipFree(h->doc_tiles);
@@ -429,6 +434,34 @@ nnsemd_status_t run_docs(nnsemd_handle_t h, DocArgs& A, int64_t max_m, int64_t m
         A.xnorm = h->doc_xnorm;
         err = launch_doc_xnorm(A, stream);
         if (err != 0) return device_fail(h, err, "supplier norm launch");
+    }
+    // One supplier set for every pair (one query against many candidates):
+    // the tile pass stages it once per workgroup and runs stripe by stripe.
+    A.stripes = nullptr;
+    A.stripe_total = nullptr;
+    A.tile_grid = 0;
+    if (split && !per_pair_tile && A.x_off != nullptr && A.num_x_sets == 1 && A.num_pairs > 0 &&
+        doc_shared_tile_lds(mcap) <= h->max_lds) {
+        const int occ = doc_shared_tile_occupancy(mcap);
+        if (occ >= 1) {
+            const int64_t smax = (ncap + 15) / 16;
+            const size_t sb = 16 * ((size_t)per_launch * (size_t)smax) + 256;
+            if (h->doc_stripes_bytes < sb) {
+                if (h->doc_stripes) (void)hipFree(h->doc_stripes);
+                h->doc_stripes = nullptr;
+                h->doc_stripes_bytes = 0;
+                if (hipMalloc((void**)&h->doc_stripes, sb) != hipSuccess)
+                    return fail(h, NNSEMD_ERR_OUT_OF_MEMORY, "stripe list");
+                h->doc_stripes_bytes = sb;
+            }
+            A.stripe_total = h->doc_stripes;
+            A.stripes = reinterpret_cast<int4*>(h->doc_stripes + 64);
+            // enough wavefronts for every stripe of the launch, at most the
+            // resident workgroups of the whole chip
+            const int64_t wpg = doc_shared_tile_threads() / 64;
+            const int64_t want = (std::min<int64_t>(per_launch, A.num_pairs) * smax + wpg - 1) / wpg;
+            A.tile_grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)occ * h->num_cus));
+        }
     }
     for (int64_t base = 0; base < A.num_pairs; base += per_launch) {
         A.pair_base = base;
@@ -676,6 +709,7 @@ nnsemd_status_t nnsemd_destroy(nnsemd_handle_t h) {
         if (h->lp_host) (void)hipHostFree(h->lp_host);
         if (h->topk_ws) (void)hipFree(h->topk_ws);
         if (h->doc_xnorm) (void)hipFree(h->doc_xnorm);
+        if (h->doc_stripes) (void)hipFree(h->doc_stripes);
         if (h->doc_tiles) (void)hipFree(h->doc_tiles);
         if (h->sg_quant) (void)hipFree(h->sg_quant);
         if (h->sg_ws) (void)hipFree(h->sg_ws);
@@ -1323,8 +1357,8 @@ nnsemd_status_t nnsemd_tuning_clear(nnsemd_handle_t h) {
 nnsemd_status_t nnsemd_tuning_set_docs(nnsemd_handle_t h, int32_t d, int64_t max_side, int32_t split) {
     if (h == nullptr) return NNSEMD_ERR_INVALID_ARG;
     h->last_error.clear();
-    if (d < 1 || max_side < 1 || (split != 0 && split != 1))
-        return fail(h, NNSEMD_ERR_INVALID_ARG, "need d >= 1, max_side >= 1 and split 0 or 1");
+    if (d < 1 || max_side < 1 || split < 0 || split > 2)
+        return fail(h, NNSEMD_ERR_INVALID_ARG, "need d >= 1, max_side >= 1 and split 0, 1 or 2");
     auto& dt = h->doc_tune[doc_dim_class(d)][tune_class(max_side)];
     dt.valid = 1;
     dt.split = split;

@@ -619,6 +619,60 @@ __device__ inline void rank_greedy_doc(const Lds& L, Shared& sh, int nact, const
     __syncthreads();  // the serve walk overwrites the keys and picks read above
 }
 
+// Relative accuracy of the served distances in the split form's cost: a
+// term is taken from the FP32 key when its bound guarantees this, else the
+// whole cost is taken from exact FP64 distances.
+constexpr double kKeyCostTau = 1e-5;
+
+// Serve walk of the split form (the phase of round_walk, the same FP64
+// flows) that also accumulates this thread's part of R = sum f D.  D comes
+// from the pick's exact FP64 key where the round computed one, else from
+// the FP32 full key kap (|kap - D^2| <= t = tscale (R + ||y||)^2): when
+// kap >= t (1 + 1/tau), D^2 >= kap - t > 0 and the term's relative error
+// is at most t / (kap - t) <= tau (for L2, |sqrt(kap) - D| / D <=
+// t / D^2).  A term that fails the test sets the LDS flag `loose`, and the
+// caller then recomputes every distance exactly instead.
+template <int T, typename LT>
+__device__ inline void doc_walk_keycost(const LT& L, int& loose_flag, int mact, int metric,
+                                        const float* __restrict__ kap, const float* __restrict__ yn, float rhat,
+                                        float tscale, double& cost) {
+    bool loose = false;
+    for (int s = threadIdx.x; s < mact; s += T) {
+        const int c = L.scnt[s];
+        if (c == 0) continue;
+        const int end = L.soff[s];
+        const int start = end - c;
+        const int isup = L.sidx[s];
+        int pos = start;
+        double sm = L.smass[s];
+        while (pos < end && sm > 0.0) {
+            const int j = L.sorted[pos];
+            const double cm = L.cmass[j];
+            const double f = sm < cm ? sm : cm;
+            sm = sm - f;
+            L.cmass[j] = cm - f;
+            const double ek = L.ckey[j];
+            double key;
+            if (ek >= 0.0) {
+                key = ek;
+            } else {
+                key = (double)kap[j];
+                const double e = (double)rhat + (double)yn[j];
+                const double t = (double)tscale * e * e * (1.0 + 1e-6);
+                loose |= !(key >= t * (1.0 + 1.0 / kKeyCostTau));
+            }
+            cost = cost + f * dist_of_key(key, metric);
+            L.ckey[j] = f;
+            L.cnn[j] = isup;
+            ++pos;
+        }
+        for (int e = pos; e < end; ++e) L.ckey[L.sorted[e]] = 0.0;
+        L.smass[s] = sm;
+    }
+    if (loose) loose_flag = 1;
+    __syncthreads();
+}
+
 // Row ranges of pair p (status INVALID_ARG and empty sides if the tables or
 // sizes are out of range).
 __device__ inline int resolve_pair(const DocArgs& A, int64_t p, int64_t& x0, int64_t& m, int64_t& y0, int64_t& n) {
@@ -652,7 +706,7 @@ __device__ inline int resolve_pair(const DocArgs& A, int64_t p, int64_t& x0, int
 template <typename TIn, bool MFMA, int T, int CSMAX, bool SPLIT>
 __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ slot, const Lds& L,
                                float* __restrict__ xx, float* __restrict__ yy, float* __restrict__ yn,
-                               float* __restrict__ kap, int32_t* __restrict__ amb, Shared& sh) {
+                               float* __restrict__ kap, int32_t* __restrict__ amb, Shared& sh, int& kloose) {
     constexpr int NW = T / 64;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -825,6 +879,7 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
         if (tid == 0) {
             sh.nflag = 0;
             sh.namb = 0;
+            kloose = 0;
         }
         __syncthreads();
     }
@@ -834,6 +889,7 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
     int rounds = 0;
     int64_t work = 0, nnz = 0, near = 0;
     int64_t ties_nn = 0, ties_order = 0;  // this thread's near-tie counts
+    double wcost = 0.0;                    // split form: this thread's part of R from the walk
     float* flag_b1 = reinterpret_cast<float*>(L.sorted);  // re-score cutoff of each flagged consumer
     while (status == NNSEMD_OK && mact > 0 && nact > 0) {
         if (rounds >= max_rounds) {
@@ -981,8 +1037,12 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
         else
             round_rank<T>(L, nact, A.protocol, A.seed, rounds);
         NNSEMD_PH(4)
-        double unused = 0.0;
-        round_walk<T, false>(L, mact, A.metric, unused);
+        if constexpr (SPLIT) {
+            doc_walk_keycost<T>(L, kloose, mact, A.metric, kap, yn, rhat, tscale, wcost);
+        } else {
+            double unused = 0.0;
+            round_walk<T, false>(L, mact, A.metric, unused);
+        }
         NNSEMD_PH(5)
         round_compact<T, CSMAX, 0>(L, sh, mact, nact, nnz, psrc, pdst, pflow, plan_base);
         NNSEMD_PH(6)
@@ -995,13 +1055,18 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
         for (int s = tid; s < mact; s += T) fin[1] += L.smass[s];
         for (int q = tid; q < nact; q += T) fin[2] += L.cmass[L.cact[q]];
     }
+    // ---- R = sum f * D.  The split form took every term in its walk unless
+    // one failed the key bound (kloose, read after the last round's
+    // barriers, the same in every thread).
+    const bool exact_cost = !SPLIT || kloose != 0;
+    if (status == NNSEMD_OK && !exact_cost) fin[0] = wcost;
     // ---- R = sum f * D over the plan, D from exact FP64 keys.  Entries are
     // sorted by consumer (counting sort in LDS) and dealt to lanes in that
     // order, so neighbouring lanes share a consumer row (one fetch) and heavy
     // consumers are spread over many lanes; each entry's f * D goes to its
     // own slot and the slots are summed in a fixed order, so R does not
     // depend on the sort's order.
-    if (status == NNSEMD_OK) {
+    if (status == NNSEMD_OK && exact_cost) {
         __syncthreads();  // residuals read; the LDS below is reused
         int32_t* cnt = reinterpret_cast<int32_t*>(L.ckey);  // [N]
         int32_t* off = cnt + A.max_n;                       // [N]
@@ -1205,10 +1270,274 @@ __global__ __launch_bounds__(T) void doc_tile_kernel(DocArgs A) {
     doc_tile_pair<T>(A, p, slot, xx, am, xs, sh);
 }
 
+// ---- Tile pass when every pair searches the same supplier set (one query
+// against many candidates).  The query's rows are staged in LDS once per
+// workgroup for the whole launch, and each wavefront then computes 16-consumer
+// stripes on its own, with no barrier after the staging: wavefront w of W
+// takes stripes w, w + W, w + 2W, ... of the list below (the stripes of the
+// largest pairs first; every stripe costs the same, 16 consumers against all
+// suppliers).  A stripe computes exactly what key_tile_mfma_stripes computes
+// for it: the same MFMA blocks, the same FP64 chunk sums in K order, the same
+// top-2 updates in ascending supplier order and the same merge, so the tiles
+// and the first round's results are bit-identical to the per-pair tile pass.
+
+// Stripe list of one launch: one 16-byte record per stripe, (local pair
+// position << 6 | stripe, consumers of the pair or -1 for a pair that fails
+// its checks, first consumer row as int64); n <= 1024 per side so a pair has
+// at most 64 stripes, and every pair gets at least one record (its stripe 0
+// also writes the pair's supplier norms).  The order of the list does not
+// matter (every stripe is the same work: 16 consumers against all
+// suppliers).  The list kernel also clears each pair's non-finite flag,
+// which the stripes raise with atomic ORs.
+constexpr int kStripeShift = 6;
+constexpr int kSharedTileThreads = 768;  // 12 wavefronts: 170 VGPRs each for the pipeline
+
+__device__ inline int32_t* doc_aux_flag(const DocArgs& A, char* slot) {
+    char* aux = slot + doc_aux_offset(A.max_m, A.max_n);
+    return reinterpret_cast<int32_t*>(reinterpret_cast<float*>(aux) + A.max_m + 3 * (size_t)A.max_n) + A.max_n;
+}
+
+__global__ void doc_stripe_reset_kernel(DocArgs A) {
+    if (threadIdx.x == 0) *A.stripe_total = 0;
+}
+
+// One thread per pair: its stripe count, a workgroup scan, one atomic for the
+// workgroup's place in the list (list order is free), then the records.
+template <int T>
+__global__ __launch_bounds__(T) void doc_stripe_list_kernel(DocArgs A, int npairs) {
+    __shared__ int wsum[T / 64];
+    __shared__ int base;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid / 64;
+    const int b = (int)blockIdx.x * T + tid;
+    int n = 0;
+    int64_t y0 = 0;
+    if (b < npairs) {
+        const int64_t q = A.pair_base + b;
+        const int64_t p = A.order != nullptr ? (int64_t)A.order[q] : q;
+        int64_t x0, m, nn;
+        const int status = resolve_pair(A, p, x0, m, y0, nn);
+        n = status == NNSEMD_OK ? (int)nn : -1;
+    }
+    const int k = b < npairs ? (n > 0 ? (n + 15) / 16 : 1) : 0;
+    int v = k;  // inclusive scan over the wavefront
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int w = __shfl_up(v, o);
+        if (lane >= o) v += w;
+    }
+    if (lane == 63) wsum[wave] = v;
+    __syncthreads();
+    if (tid == 0) {
+        int tot = 0;
+        for (int w = 0; w < T / 64; ++w) tot += wsum[w];
+        base = atomicAdd(A.stripe_total, tot);
+    }
+    __syncthreads();
+    int off = base + v - k;
+    for (int w = 0; w < wave; ++w) off += wsum[w];
+    for (int s = 0; s < k; ++s)
+        A.stripes[off + s] = make_int4((b << kStripeShift) | s, n, (int)(uint32_t)(uint64_t)y0,
+                                       (int)(uint32_t)((uint64_t)y0 >> 32));
+    if (b < npairs) *doc_aux_flag(A, A.scratch + (size_t)b * (size_t)A.slot_bytes) = 0;
+}
+
+// LDS of doc_tile_shared_kernel: the query rows (zero-padded to whole
+// 32-row blocks and K steps), their FP64 norms and their masses.
+__host__ __device__ inline size_t doc_shared_rows(int max_m) { return (size_t)((max_m + 31) & ~31); }
+__host__ __device__ inline size_t doc_shared_lds(int max_m) {
+    return doc_shared_rows(max_m) * (sizeof(uint16_t) * kStripeLdx + sizeof(double) + sizeof(float));
+}
+
+// Stripe s of a pair: the consumers' fragments (all K steps) of rows
+// 16 s .. 16 s + 15 of the pair's consumer set.
+struct StripeRec {
+    int b, s, n;       // local pair position, stripe, consumers (-1: the pair failed its checks)
+    const uint16_t* Y;  // the pair's first consumer row
+};
+
+__device__ inline StripeRec stripe_rec(const DocArgs& A, int t, int total) {
+    StripeRec r{0, 0, 0, nullptr};
+    if (t < total) {
+        const int4 e = A.stripes[t];
+        r.b = e.x >> kStripeShift;
+        r.s = e.x & ((1 << kStripeShift) - 1);
+        r.n = e.y;
+        const int64_t y0 = (int64_t)(((uint64_t)(uint32_t)e.w << 32) | (uint64_t)(uint32_t)e.z);
+        r.Y = reinterpret_cast<const uint16_t*>(A.Y) + y0 * A.d;
+    }
+    return r;
+}
+
+template <int T>
+__global__ __launch_bounds__(T) void doc_tile_shared_kernel(DocArgs A) {
+    constexpr int KS = kStripeKSteps;
+    extern __shared__ __align__(16) char lds_dyn[];
+    const int mrows = (int)doc_shared_rows(A.max_m);
+    uint16_t* xs = reinterpret_cast<uint16_t*>(lds_dyn);
+    double* xx = reinterpret_cast<double*>(lds_dyn + sizeof(uint16_t) * kStripeLdx * (size_t)mrows);
+    float* am = reinterpret_cast<float*>(xx + mrows);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int d = A.d;
+    const int ksteps = (d + 31) / 32;
+    const int kp = ksteps * 32;
+    const int64_t qx0 = A.x_off != nullptr ? A.x_off[0] : 0;
+    const int mq = (int)min<int64_t>(A.x_off != nullptr ? A.x_off[1] - qx0 : A.single_m, (int64_t)A.max_m);
+    const uint16_t* Xq = reinterpret_cast<const uint16_t*>(A.X) + qx0 * d;
+    // ---- stage the query once (rows >= mq and columns >= d are zero)
+    const bool rows8 = (d & 3) == 0 && (reinterpret_cast<uintptr_t>(Xq) & 7u) == 0;
+    for (int e = tid; e < mrows * (kp / 4); e += T) {
+        const int r = e / (kp / 4), k = 4 * (e % (kp / 4));
+        uint2 v = make_uint2(0u, 0u);
+        if (r < mq && k < d) {
+            if (rows8) {
+                v = *reinterpret_cast<const uint2*>(Xq + (size_t)r * d + k);
+            } else {
+                uint16_t h[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) h[u] = k + u < d ? Xq[(size_t)r * d + k + u] : (uint16_t)0;
+                v = make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16));
+            }
+        }
+        *reinterpret_cast<uint2*>(&xs[r * kStripeLdx + k]) = v;
+    }
+    for (int i = tid; i < mrows; i += T) {
+        xx[i] = i < mq ? A.xnorm[i] : 0.0;
+        am[i] = i < mq ? A.a[qx0 + i] : 0.f;
+    }
+    __syncthreads();  // the only barrier: every thread reaches it once
+
+    const int r16 = lane & 15, kq = 8 * (lane >> 4);
+    const int W = (int)gridDim.x * (T / 64);
+    const int total = *A.stripe_total;
+    auto load_frags = [&](const StripeRec& r, bf16x8 (&yb)[KS]) {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+            if (ks < ksteps) yb[ks] = frag8(r.Y, r.s * 16 + r16, max(r.n, 0), ks * 32 + kq, d);
+    };
+    // Software pipeline: the record of the stripe after next and the
+    // fragments of the next stripe are in flight while this one multiplies.
+    int t = (int)blockIdx.x * (T / 64) + tid / 64;
+    StripeRec cur = stripe_rec(A, t, total);
+    StripeRec nxt = stripe_rec(A, t + W, total);
+    bf16x8 yb[KS], ybn[KS];
+    if (t < total) load_frags(cur, yb);
+    for (; t < total; t += W) {
+        if (t + W < total) load_frags(nxt, ybn);
+        const StripeRec nn = stripe_rec(A, t + 2 * W, total);
+        const int mi = cur.n >= 0 ? mq : 0, ni = max(cur.n, 0);
+        char* slot = A.scratch + (size_t)cur.b * (size_t)A.slot_bytes;
+        char* aux = slot + doc_aux_offset(A.max_m, A.max_n);
+        float* axx = reinterpret_cast<float*>(aux);
+        float* ayy = axx + A.max_m;
+        float* ab1 = ayy + A.max_n;
+        float* ab2 = ab1 + A.max_n;
+        int32_t* abs_ = reinterpret_cast<int32_t*>(ab2 + A.max_n);
+        float* tile = reinterpret_cast<float*>(slot);
+        bool bad = false;
+        if (cur.s == 0) {
+            for (int i = lane; i < mi; i += 64) {
+                const double s2 = xx[i];
+                bad |= s2 != s2;
+                axx[i] = (float)s2;
+            }
+        }
+        const int j0 = cur.s * 16;
+        if (j0 < ni) {
+            double ss = 0.0;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                if (ks < ksteps) {
+                    union {
+                        bf16x8 v;
+                        uint32_t w[4];
+                    } u;
+                    u.v = yb[ks];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        bad |= !finite_pair(u.w[e]);
+                        const double f0 = bf_lo(u.w[e]), f1 = bf_hi(u.w[e]);
+                        ss = fma(f0, f0, ss);
+                        ss = fma(f1, f1, ss);
+                    }
+                }
+            }
+            ss += __shfl_xor(ss, 16);
+            ss += __shfl_xor(ss, 32);
+            if (lane < 16 && j0 + r16 < ni) ayy[j0 + r16] = (float)ss;
+            float tb1 = INFINITY, tb2 = INFINITY;
+            int tbs = 0x7fffffff;
+            const int j = j0 + r16;
+            const f32x4 zero = (f32x4){0.f, 0.f, 0.f, 0.f};
+            for (int i0 = 0; i0 < mi; i0 += 32) {
+                double dot0[4] = {0.0, 0.0, 0.0, 0.0}, dot1[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) {
+                    if (ks < ksteps) {
+                        union {
+                            uint4 u;
+                            bf16x8 v;
+                        } f0, f1;
+                        f0.u = *reinterpret_cast<const uint4*>(&xs[(i0 + r16) * kStripeLdx + ks * 32 + kq]);
+                        f1.u = *reinterpret_cast<const uint4*>(&xs[(i0 + 16 + r16) * kStripeLdx + ks * 32 + kq]);
+                        const f32x4 c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f0.v, yb[ks], zero, 0, 0, 0);
+                        const f32x4 c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f1.v, yb[ks], zero, 0, 0, 0);
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            dot0[r] += (double)c0[r];
+                            dot1[r] += (double)c1[r];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int i = i0 + 16 * h + 4 * (lane >> 4) + r;
+                        if (i < mi) {
+                            const float v = (float)(xx[i] - 2.0 * (h == 0 ? dot0[r] : dot1[r]));
+                            if (j < ni) tile[(size_t)i * ni + j] = v;
+                            if (am[i] > 0.f) {
+                                const bool lt = v < tb1;
+                                tbs = lt ? i : tbs;
+                                tb2 = __builtin_amdgcn_fmed3f(tb1, v, tb2);
+                                tb1 = fminf(tb1, v);
+                            }
+                        }
+                    }
+            }
+#pragma unroll
+            for (int o = 16; o < 64; o <<= 1) {
+                const float c1 = __shfl_xor(tb1, o);
+                const float c2 = __shfl_xor(tb2, o);
+                const int cs2 = __shfl_xor(tbs, o);
+                const float n2 = fminf(fmaxf(tb1, c1), fminf(tb2, c2));
+                const bool take = (c1 < tb1) || (c1 == tb1 && cs2 < tbs);
+                tb1 = take ? c1 : tb1;
+                tbs = take ? cs2 : tbs;
+                tb2 = n2;
+            }
+            if (lane < 16 && j < ni) {
+                ab1[j] = tb1;
+                ab2[j] = tb2;
+                abs_[j] = tbs;
+            }
+        }
+        if (__ballot(bad) != 0 && lane == 0) atomicOr(doc_aux_flag(A, slot), 1);
+        cur = nxt;
+        nxt = nn;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) yb[ks] = ybn[ks];
+    }
+}
+
 template <typename TIn, bool MFMA, int T, int CSMAX, bool SPLIT>
 __global__ __launch_bounds__(T) void doc_pair_kernel(DocArgs A) {
     extern __shared__ __align__(16) char lds_dyn[];
     __shared__ Shared sh;
+    __shared__ int kloose;  // split form: a served distance needs its exact FP64 value
     const PairLdsLayout lay = pair_lds_layout(A.max_m, A.max_n, 0);
     const Lds L = carve(lds_dyn, A.max_m, A.max_n, 0);
     float* xx = reinterpret_cast<float*>(lds_dyn + lay.total);
@@ -1219,7 +1548,7 @@ __global__ __launch_bounds__(T) void doc_pair_kernel(DocArgs A) {
     const int64_t b = A.pair_base + (int64_t)blockIdx.x;
     const int64_t p = A.order != nullptr ? (int64_t)A.order[b] : b;
     char* slot = A.scratch + (size_t)blockIdx.x * (size_t)A.slot_bytes;
-    solve_doc_pair<TIn, MFMA, T, CSMAX, SPLIT>(A, p, slot, L, xx, yy, yn, kap, amb, sh);
+    solve_doc_pair<TIn, MFMA, T, CSMAX, SPLIT>(A, p, slot, L, xx, yy, yn, kap, amb, sh, kloose);
 }
 
 template <typename TIn, bool MFMA, int CSMAX, bool SPLIT>
@@ -1231,8 +1560,21 @@ int doc_launch_typed(const DocArgs& A, size_t lds, int grid, hipStream_t st, boo
     }
     if (!run) return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k, 256, lds);
     if constexpr (SPLIT) {
-        const size_t tl = (sizeof(double) + sizeof(float)) * (size_t)A.max_m;
-        hipLaunchKernelGGL(doc_tile_kernel<256>, dim3(grid), dim3(256), tl, st, A);
+        if (A.stripes != nullptr) {
+            hipLaunchKernelGGL(doc_stripe_reset_kernel, dim3(1), dim3(64), 0, st, A);
+            hipLaunchKernelGGL(doc_stripe_list_kernel<256>, dim3((grid + 255) / 256), dim3(256), 0, st, A, grid);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return (int)e;
+            const size_t tl = doc_shared_lds(A.max_m);
+            e = hipFuncSetAttribute((const void*)doc_tile_shared_kernel<kSharedTileThreads>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)tl);
+            if (e != hipSuccess) return (int)e;
+            hipLaunchKernelGGL(doc_tile_shared_kernel<kSharedTileThreads>, dim3(A.tile_grid), dim3(kSharedTileThreads),
+                               tl, st, A);
+        } else {
+            const size_t tl = (sizeof(double) + sizeof(float)) * (size_t)A.max_m;
+            hipLaunchKernelGGL(doc_tile_kernel<256>, dim3(grid), dim3(256), tl, st, A);
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return (int)e;
     }
@@ -1246,6 +1588,21 @@ int doc_launch_typed(const DocArgs& A, size_t lds, int grid, hipStream_t st, boo
 // Pair layout (no records) + xx[M], yy[N], yn[N], kap[N] (float), amb[N] (int32).
 size_t doc_lds_bytes(int max_m, int max_n) {
     return pair_lds_layout(max_m, max_n, 0).total + sizeof(float) * ((size_t)max_m + 4 * (size_t)max_n);
+}
+
+size_t doc_shared_tile_lds(int max_m) { return doc_shared_lds(max_m); }
+
+int doc_shared_tile_threads() { return kSharedTileThreads; }
+
+int doc_shared_tile_occupancy(int max_m) {
+    const size_t tl = doc_shared_lds(max_m);
+    const void* k = (const void*)doc_tile_shared_kernel<kSharedTileThreads>;
+    if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)tl) != hipSuccess) return 0;
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, doc_tile_shared_kernel<kSharedTileThreads>,
+                                                     kSharedTileThreads, tl) != hipSuccess)
+        return 0;
+    return blocks;
 }
 
 bool doc_split_form(int d, bool bf16_mfma, int chunk_max) {

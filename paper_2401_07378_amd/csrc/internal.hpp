@@ -206,6 +206,11 @@ struct DocArgs {
     unsigned long long* phase_cycles;  // profiling builds only: 9 per-phase cycle totals
     double* xnorm;         // split form: FP64 squared norms of the supplier sets' rows,
                            // [set * max_m + i], NaN for a row with a non-finite coordinate
+    int4* stripes;         // split form, one supplier set for every pair: the launch's stripe
+                           // records (nullptr: the per-pair tile kernel runs instead)
+    int32_t* stripe_total; // its length (written by the list kernel)
+    int32_t tile_grid;     // workgroups of the shared-query tile kernel
+    int32_t pad2;
 };
 
 size_t doc_lds_bytes(int max_m, int max_n);
@@ -213,6 +218,11 @@ size_t doc_lds_bytes(int max_m, int max_n);
 // the supplier-set norm pass it needs first (A.xnorm: num_x_sets * max_m).
 bool doc_split_form(int d, bool bf16_mfma, int chunk_max);
 int launch_doc_xnorm(const DocArgs& A, void* stream);
+// LDS bytes of the shared-query tile kernel (the query staged whole), and
+// its resident workgroups per CU (0 if it does not fit).
+size_t doc_shared_tile_lds(int max_m);
+int doc_shared_tile_occupancy(int max_m);
+int doc_shared_tile_threads();
 // Scratch slot of one workgroup: the m x n FP32 key tile (256-byte aligned)
 // followed by m + n plan entries (int32 src, int32 dst, double flow).
 __host__ __device__ inline size_t doc_tile_bytes(int max_m, int max_n) {
