@@ -14,11 +14,14 @@
 // with R = max ||x|| (R ||y|| <= (R + ||y||)^2 / 4):
 //   unsplit form (FP32 norms, FP32 accumulation over all d products):
 //     tscale = 4 (d + 2) u;
-//   split form (BF16, d <= 320: every MFMA sums 32 products from a zero
-//     accumulator, at most 31 roundings, and the 10 chunk sums and the norms
-//     are added in FP64): 2 * 62u R ||y|| + FP64 terms + the final rounding to
-//     FP32 <= 33u (R + ||y||)^2, with ||y||^2 rounded once more for the full
-//     key: tscale = 36u.
+//   split form (BF16, d <= 320): every MFMA sums 32 products from a zero
+//     accumulator (at most 31 roundings, each at most 2u of the chunk's sum
+//     of |x_k y_k|), and the 10 chunk results are added in FP32 in K order
+//     (9 roundings of at most u sum |x_k y_k|), so the dot product is within
+//     71u ||x|| ||y|| and -2 x.y within 142u R ||y|| <= 35.5u (R + ||y||)^2;
+//     the key fma(-2, dot, fl(||x||^2)) adds two roundings (<= 2u (R +
+//     ||y||)^2) and the full key fl(key + fl(||y||^2)) two more: 39.5u,
+//     tscale = 44u.
 //  * Search: a consumer whose two best FP32 keys are closer than 2t (twice
 //    the worst disagreement of two keys) is re-scored in FP64 on the
 //    suppliers whose FP32 key lies within 2t of the best, in the
@@ -27,10 +30,12 @@
 //  * Serve order (greedy protocol): claimants of one supplier are ordered by
 //    their full FP32 keys (tile + ||y||^2), each within t_j; two claimants
 //    closer than t_a + t_b get exact FP64 keys and are compared on those.
-//  * Cost: R = sum f * D over the plan, with every D recomputed in FP64 from
-//    the inputs after the rounds (all lanes busy, one pass).
+//  * Cost: R = sum f * D over the plan.  The split form takes D from the
+//    pick's exact key, or from its FP32 key when the bound makes that term
+//    accurate to 1e-5 relative (else every D of the pair is recomputed in
+//    FP64); the other forms recompute every D in FP64 after the rounds.
 // The plan is thus the one of the FP64 definition, and R agrees with the
-// sequential FP64 sum up to the summation order.
+// sequential FP64 sum up to the summation order (split form: within 1e-5).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -246,8 +251,8 @@ __device__ inline bf16x8 frag8(const uint16_t* __restrict__ base, int r, int row
 // k = 8(l/16)..+8; B lane l holds column l%16, the same k; C lane l
 // register r is row 4(l/16)+r, column l%16.
 template <int T>
-__device__ void key_tile_mfma(const uint16_t* __restrict__ X, const uint16_t* __restrict__ Y, int m, int n, int d,
-                              const float* __restrict__ xx, float* __restrict__ tile) {
+__device__ void key_tile_mfma(const uint16_t* __restrict__ X, const uint16_t* __restrict__ Y, int m, int n, int ld,
+                              int d, const float* __restrict__ xx, float* __restrict__ tile) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x / 64;
     const int tm = (m + 31) / 32, tn = (n + 31) / 32;
@@ -290,7 +295,7 @@ __device__ void key_tile_mfma(const uint16_t* __restrict__ X, const uint16_t* __
                 for (int r = 0; r < 4; ++r) {
                     const int i = i0 + 16 * a + 4 * (lane >> 4) + r;
                     const int j = j0 + 16 * b + r16;
-                    if (i < m && j < n) tile[(size_t)i * n + j] = xx[i] - 2.f * acc[a][b][r];
+                    if (i < m && j < n) tile[(size_t)i * ld + j] = xx[i] - 2.f * acc[a][b][r];
                 }
     }
 }
@@ -298,6 +303,85 @@ __device__ void key_tile_mfma(const uint16_t* __restrict__ X, const uint16_t* __
 // K steps of 32 whose consumer fragments stay in registers in
 // key_tile_mfma_stripes (d <= 320); larger d takes key_tile_mfma.
 constexpr int kStripeKSteps = 10;
+
+// Stripe epilogue shared by both split-form tile passes.  The MFMAs of a
+// stripe run transposed (C^T = Y X^T: the consumers' fragments are the A
+// operand), so lane l holds consumers jg .. jg + 3 (jg = j0 + 4 (l / 16))
+// against supplier i0 + l % 16 (first block half) and i0 + 16 + l % 16
+// (second half).  Each half is one 16-byte store of four consecutive keys
+// of tile row i (rows padded to a multiple of 4 columns), and the running
+// best / second-best / best-index of the four consumers take the suppliers
+// in ascending order.
+struct StripeTop {
+    float b1[4], b2[4];
+    int bs[4];
+};
+
+__device__ inline void stripe_top_init(StripeTop& tp) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        tp.b1[r] = INFINITY;
+        tp.b2[r] = INFINITY;
+        tp.bs[r] = 0x7fffffff;
+    }
+}
+
+__device__ inline void stripe_block_epilogue(const float (&dot0)[4], const float (&dot1)[4], int i0, int m, int jg,
+                                             int n, int ld, const double* __restrict__ xx,
+                                             const float* __restrict__ amass, float* __restrict__ tile,
+                                             StripeTop& tp) {
+    const int r16 = threadIdx.x & 15;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int i = i0 + 16 * h + r16;
+        if (i < m) {
+            const float xf = (float)xx[i];
+            float v[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[r] = fmaf(-2.f, h == 0 ? dot0[r] : dot1[r], xf);
+            if (jg < n) *reinterpret_cast<float4*>(tile + (size_t)i * ld + jg) = make_float4(v[0], v[1], v[2], v[3]);
+            if (amass[i] > 0.f) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const bool lt = v[r] < tp.b1[r];
+                    tp.bs[r] = lt ? i : tp.bs[r];
+                    tp.b2[r] = __builtin_amdgcn_fmed3f(tp.b1[r], v[r], tp.b2[r]);
+                    tp.b1[r] = fminf(tp.b1[r], v[r]);
+                }
+            }
+        }
+    }
+}
+
+// Merge of the 16 lanes that hold the same four consumers (smallest key,
+// ties to the smallest index; the second-best of the multiset); lane
+// 16 g then writes consumers jg .. jg + 3.
+__device__ inline void stripe_top_finish(StripeTop& tp, int jg, int n, float* __restrict__ b1,
+                                         float* __restrict__ b2, int32_t* __restrict__ bs) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+            const float c1 = __shfl_xor(tp.b1[r], o);
+            const float c2 = __shfl_xor(tp.b2[r], o);
+            const int cs2 = __shfl_xor(tp.bs[r], o);
+            const float n2 = fminf(fmaxf(tp.b1[r], c1), fminf(tp.b2[r], c2));
+            const bool take = (c1 < tp.b1[r]) || (c1 == tp.b1[r] && cs2 < tp.bs[r]);
+            tp.b1[r] = take ? c1 : tp.b1[r];
+            tp.bs[r] = take ? cs2 : tp.bs[r];
+            tp.b2[r] = n2;
+        }
+    }
+    if ((threadIdx.x & 15) == 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (jg + r < n) {
+                b1[jg + r] = tp.b1[r];
+                b2[jg + r] = tp.b2[r];
+                bs[jg + r] = tp.bs[r];
+            }
+    }
+}
 
 // Key tile with matrix cores for the split form, consumer-stationary: the
 // four wavefronts each own a stripe of 16 consumers (their BF16 fragments
@@ -314,7 +398,7 @@ constexpr int kStripeLdx = kStripeKSteps * 32 + 8;
 
 template <int T>
 __device__ void key_tile_mfma_stripes(const uint16_t* __restrict__ X, const uint16_t* __restrict__ Y, int m, int n,
-                                      int d, const double* __restrict__ xx, float* __restrict__ tile,
+                                      int ld, int d, const double* __restrict__ xx, float* __restrict__ tile,
                                       float* __restrict__ yy, bool& bad, const float* __restrict__ amass,
                                       float* __restrict__ r1b1, float* __restrict__ r1b2, int32_t* __restrict__ r1bs,
                                       uint16_t* __restrict__ xs
@@ -355,8 +439,8 @@ __device__ void key_tile_mfma_stripes(const uint16_t* __restrict__ X, const uint
         const bool mine = cs < tn;
         const int j0 = cs * 16;
         bf16x8 yb[KS];
-        float tb1 = INFINITY, tb2 = INFINITY;
-        int tbs = 0x7fffffff;
+        StripeTop tp;
+        stripe_top_init(tp);
         if (mine) {
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks)
@@ -411,8 +495,8 @@ __device__ void key_tile_mfma_stripes(const uint16_t* __restrict__ X, const uint
 #endif
             if (!mine) continue;
             // each K step from a zero accumulator (at most 31 roundings),
-            // the chunk sums added in FP64
-            double dot0[4] = {0.0, 0.0, 0.0, 0.0}, dot1[4] = {0.0, 0.0, 0.0, 0.0};
+            // the chunk results added in FP32 in K order
+            float dot0[4] = {0.f, 0.f, 0.f, 0.f}, dot1[4] = {0.f, 0.f, 0.f, 0.f};
             const f32x4 zero = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
@@ -423,65 +507,31 @@ __device__ void key_tile_mfma_stripes(const uint16_t* __restrict__ X, const uint
                     } f0, f1;
                     f0.u = *reinterpret_cast<const uint4*>(&xs[r16 * kStripeLdx + ks * 32 + kq]);
                     f1.u = *reinterpret_cast<const uint4*>(&xs[(16 + r16) * kStripeLdx + ks * 32 + kq]);
-                    const f32x4 c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f0.v, yb[ks], zero, 0, 0, 0);
-                    const f32x4 c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f1.v, yb[ks], zero, 0, 0, 0);
+                    const f32x4 c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yb[ks], f0.v, zero, 0, 0, 0);
+                    const f32x4 c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yb[ks], f1.v, zero, 0, 0, 0);
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        dot0[r] += (double)c0[r];
-                        dot1[r] += (double)c1[r];
+                        dot0[r] += c0[r];
+                        dot1[r] += c1[r];
                     }
                 }
             }
 #ifdef NNSEMD_PHASE_TILE
             NNSEMD_PH(3)
 #endif
-            const int j = j0 + r16;
-            // rows of this lane in ascending order: acc0's four, then acc1's
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int i = i0 + 16 * h + 4 * (lane >> 4) + r;
-                    if (i < m) {
-                        const float v = (float)(xx[i] - 2.0 * (h == 0 ? dot0[r] : dot1[r]));
-                        if (j < n) tile[(size_t)i * n + j] = v;
-                        if (amass[i] > 0.f) {
-                            const bool lt = v < tb1;
-                            tbs = lt ? i : tbs;
-                            tb2 = __builtin_amdgcn_fmed3f(tb1, v, tb2);
-                            tb1 = fminf(tb1, v);
-                        }
-                    }
-                }
+            stripe_block_epilogue(dot0, dot1, i0, m, j0 + 4 * (lane >> 4), n, ld, xx, amass, tile, tp);
 #ifdef NNSEMD_PHASE_TILE
             NNSEMD_PH(4)
 #endif
         }
-        if (mine) {
-#pragma unroll
-            for (int o = 16; o < 64; o <<= 1) {
-                const float c1 = __shfl_xor(tb1, o);
-                const float c2 = __shfl_xor(tb2, o);
-                const int cs2 = __shfl_xor(tbs, o);
-                const float n2 = fminf(fmaxf(tb1, c1), fminf(tb2, c2));
-                const bool take = (c1 < tb1) || (c1 == tb1 && cs2 < tbs);
-                tb1 = take ? c1 : tb1;
-                tbs = take ? cs2 : tbs;
-                tb2 = n2;
-            }
-            if (lane < 16 && j0 + r16 < n) {
-                r1b1[j0 + r16] = tb1;
-                r1b2[j0 + r16] = tb2;
-                r1bs[j0 + r16] = tbs;
-            }
-        }
+        if (mine) stripe_top_finish(tp, j0 + 4 * (lane >> 4), n, r1b1, r1b2, r1bs);
     }
 }
 
 // Key tile on the vector ALUs (FP32 inputs): each lane owns a 4 x 4 block
 // of (i, j) and walks the d products with 16-byte loads when rows allow it.
 template <int T>
-__device__ void key_tile_valu(const float* __restrict__ X, const float* __restrict__ Y, int m, int n, int d,
+__device__ void key_tile_valu(const float* __restrict__ X, const float* __restrict__ Y, int m, int n, int ld, int d,
                               const float* __restrict__ xx, float* __restrict__ tile) {
     const int bm = (m + 3) / 4, bn = (n + 3) / 4;
     const bool vec = (d & 3) == 0 && ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y)) & 15u) == 0;
@@ -535,7 +585,7 @@ __device__ void key_tile_valu(const float* __restrict__ X, const float* __restri
         for (int u = 0; u < 4; ++u)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                if (i0 + u < m && j0 + v < n) tile[(size_t)(i0 + u) * n + j0 + v] = xx[i0 + u] - 2.f * acc[u][v];
+                if (i0 + u < m && j0 + v < n) tile[(size_t)(i0 + u) * ld + j0 + v] = xx[i0 + u] - 2.f * acc[u][v];
     }
 }
 
@@ -747,6 +797,7 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
     const TIn* __restrict__ X = reinterpret_cast<const TIn*>(A.X) + x0 * d;
     const TIn* __restrict__ Y = reinterpret_cast<const TIn*>(A.Y) + y0 * d;
     const int mi = (int)m, ni = (int)n;
+    const int ldt = doc_tile_ld(ni);  // tile row stride (columns padded to a multiple of 4)
 
     // ---- ingest: masses, validity, norms (16 lanes per row)
     double red[4] = {0.0, 0.0, 0.0, 0.0};  // sum a, sum b, bad, max ||x||^2
@@ -827,16 +878,16 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
     }
     const float rhat = sqrtf((float)red[3]) * infl;
     // Key error bound t = tscale (R + ||y||)^2; the search gap threshold is 2t.
-    const float tscale = SPLIT ? 36.f * kU32 : 4.f * (float)(d + 2) * kU32;
+    const float tscale = SPLIT ? 44.f * kU32 : 4.f * (float)(d + 2) * kU32;
 
     NNSEMD_PH(0)
     // ---- key tile
     if (!SPLIT && status == NNSEMD_OK) {
         if constexpr (MFMA) {
-            key_tile_mfma<T>(reinterpret_cast<const uint16_t*>(X), reinterpret_cast<const uint16_t*>(Y), mi, ni, d, xx,
+            key_tile_mfma<T>(reinterpret_cast<const uint16_t*>(X), reinterpret_cast<const uint16_t*>(Y), mi, ni, ldt, d, xx,
                              tile);
         } else {
-            key_tile_valu<T>(reinterpret_cast<const float*>(X), reinterpret_cast<const float*>(Y), mi, ni, d, xx,
+            key_tile_valu<T>(reinterpret_cast<const float*>(X), reinterpret_cast<const float*>(Y), mi, ni, ldt, d, xx,
                              tile);
         }
     }
@@ -939,7 +990,7 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
             for (int s0 = r; s0 < full; s0 += stride) {
                 float kk[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) kk[u] = tile[(size_t)L.sidx[s0 + u * S] * ni + j];
+                for (int u = 0; u < U; ++u) kk[u] = tile[(size_t)L.sidx[s0 + u * S] * ldt + j];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const bool lt = kk[u] < b1;
@@ -949,7 +1000,7 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
                 }
             }
             for (int s = full + r; s < mact; s += S) {
-                const float k = tile[(size_t)L.sidx[s] * ni + j];
+                const float k = tile[(size_t)L.sidx[s] * ldt + j];
                 const bool lt = k < b1;
                 bs = lt ? s : bs;
                 b2 = __builtin_amdgcn_fmed3f(b1, k, b2);
@@ -997,7 +1048,7 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
                 int bsl = 0x7fffffff;
                 for (int s = lane; s < mact; s += 64) {
                     const int i = L.sidx[s];
-                    if (tile[(size_t)i * ni + j] > lim) continue;
+                    if (tile[(size_t)i * ldt + j] > lim) continue;
                     const double k = dkey64<TIn>(X + (size_t)i * d, Y + (size_t)j * d, d);
                     if (k < best) {
                         sec = best;
@@ -1021,7 +1072,7 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
                 if (lane == 0) {
                     L.cnn[j] = bsl;
                     L.ckey[j] = best;
-                    kap[j] = tile[(size_t)L.sidx[bsl] * ni + j] + yy[j];
+                    kap[j] = tile[(size_t)L.sidx[bsl] * ldt + j] + yy[j];
                     atomicAdd(&L.scnt[bsl], 1);
                     if (mact > 1 && near_tie_dist(dist_of_key(best, A.metric), dist_of_key(sec, A.metric)))
                         ++ties_nn;
@@ -1220,10 +1271,12 @@ __device__ void doc_tile_pair(const DocArgs& A, int64_t p, char* __restrict__ sl
     __syncthreads();
 #ifdef NNSEMD_PHASE_TILE
     NNSEMD_PH(0)
-    key_tile_mfma_stripes<T>(X, Y, mi, ni, d, xx, reinterpret_cast<float*>(slot), ayy, bad, am, ab1, ab2, abs_, xs,
+    key_tile_mfma_stripes<T>(X, Y, mi, ni, doc_tile_ld(ni), d, xx, reinterpret_cast<float*>(slot), ayy, bad, am, ab1,
+                             ab2, abs_, xs,
                              ph, ph_t);
 #else
-    key_tile_mfma_stripes<T>(X, Y, mi, ni, d, xx, reinterpret_cast<float*>(slot), ayy, bad, am, ab1, ab2, abs_, xs);
+    key_tile_mfma_stripes<T>(X, Y, mi, ni, doc_tile_ld(ni), d, xx, reinterpret_cast<float*>(slot), ayy, bad, am, ab1,
+                             ab2, abs_, xs);
 #endif
     double bd[1] = {bad ? 1.0 : 0.0};
     const int bop[1] = {2};
@@ -1277,7 +1330,7 @@ __global__ __launch_bounds__(T) void doc_tile_kernel(DocArgs A) {
 // takes stripes w, w + W, w + 2W, ... of the list below (the stripes of the
 // largest pairs first; every stripe costs the same, 16 consumers against all
 // suppliers).  A stripe computes exactly what key_tile_mfma_stripes computes
-// for it: the same MFMA blocks, the same FP64 chunk sums in K order, the same
+// for it: the same MFMA blocks, the same FP32 chunk sums in K order, the same
 // top-2 updates in ascending supplier order and the same merge, so the tiles
 // and the first round's results are bit-identical to the per-pair tile pass.
 
@@ -1467,12 +1520,13 @@ __global__ __launch_bounds__(T) void doc_tile_shared_kernel(DocArgs A) {
             ss += __shfl_xor(ss, 16);
             ss += __shfl_xor(ss, 32);
             if (lane < 16 && j0 + r16 < ni) ayy[j0 + r16] = (float)ss;
-            float tb1 = INFINITY, tb2 = INFINITY;
-            int tbs = 0x7fffffff;
-            const int j = j0 + r16;
+            StripeTop tp;
+            stripe_top_init(tp);
+            const int jg = j0 + 4 * (lane >> 4);
+            const int ldt = doc_tile_ld(ni);
             const f32x4 zero = (f32x4){0.f, 0.f, 0.f, 0.f};
             for (int i0 = 0; i0 < mi; i0 += 32) {
-                double dot0[4] = {0.0, 0.0, 0.0, 0.0}, dot1[4] = {0.0, 0.0, 0.0, 0.0};
+                float dot0[4] = {0.f, 0.f, 0.f, 0.f}, dot1[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int ks = 0; ks < KS; ++ks) {
                     if (ks < ksteps) {
@@ -1482,48 +1536,18 @@ __global__ __launch_bounds__(T) void doc_tile_shared_kernel(DocArgs A) {
                         } f0, f1;
                         f0.u = *reinterpret_cast<const uint4*>(&xs[(i0 + r16) * kStripeLdx + ks * 32 + kq]);
                         f1.u = *reinterpret_cast<const uint4*>(&xs[(i0 + 16 + r16) * kStripeLdx + ks * 32 + kq]);
-                        const f32x4 c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f0.v, yb[ks], zero, 0, 0, 0);
-                        const f32x4 c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f1.v, yb[ks], zero, 0, 0, 0);
+                        const f32x4 c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yb[ks], f0.v, zero, 0, 0, 0);
+                        const f32x4 c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yb[ks], f1.v, zero, 0, 0, 0);
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
-                            dot0[r] += (double)c0[r];
-                            dot1[r] += (double)c1[r];
+                            dot0[r] += c0[r];
+                            dot1[r] += c1[r];
                         }
                     }
                 }
-#pragma unroll
-                for (int h = 0; h < 2; ++h)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int i = i0 + 16 * h + 4 * (lane >> 4) + r;
-                        if (i < mi) {
-                            const float v = (float)(xx[i] - 2.0 * (h == 0 ? dot0[r] : dot1[r]));
-                            if (j < ni) tile[(size_t)i * ni + j] = v;
-                            if (am[i] > 0.f) {
-                                const bool lt = v < tb1;
-                                tbs = lt ? i : tbs;
-                                tb2 = __builtin_amdgcn_fmed3f(tb1, v, tb2);
-                                tb1 = fminf(tb1, v);
-                            }
-                        }
-                    }
+                stripe_block_epilogue(dot0, dot1, i0, mi, jg, ni, ldt, xx, am, tile, tp);
             }
-#pragma unroll
-            for (int o = 16; o < 64; o <<= 1) {
-                const float c1 = __shfl_xor(tb1, o);
-                const float c2 = __shfl_xor(tb2, o);
-                const int cs2 = __shfl_xor(tbs, o);
-                const float n2 = fminf(fmaxf(tb1, c1), fminf(tb2, c2));
-                const bool take = (c1 < tb1) || (c1 == tb1 && cs2 < tbs);
-                tb1 = take ? c1 : tb1;
-                tbs = take ? cs2 : tbs;
-                tb2 = n2;
-            }
-            if (lane < 16 && j < ni) {
-                ab1[j] = tb1;
-                ab2[j] = tb2;
-                abs_[j] = tbs;
-            }
+            stripe_top_finish(tp, jg, ni, ab1, ab2, abs_);
         }
         if (__ballot(bad) != 0 && lane == 0) atomicOr(doc_aux_flag(A, slot), 1);
         cur = nxt;

@@ -223,10 +223,13 @@ int launch_doc_xnorm(const DocArgs& A, void* stream);
 size_t doc_shared_tile_lds(int max_m);
 int doc_shared_tile_occupancy(int max_m);
 int doc_shared_tile_threads();
-// Scratch slot of one workgroup: the m x n FP32 key tile (256-byte aligned)
+// Scratch slot of one workgroup: the m x n FP32 key tile (256-byte aligned,
+// rows of doc_tile_ld(n) columns)
 // followed by m + n plan entries (int32 src, int32 dst, double flow).
+// Tile row stride: the columns padded to a multiple of 4 (16-byte rows).
+__host__ __device__ inline int doc_tile_ld(int n) { return (n + 3) & ~3; }
 __host__ __device__ inline size_t doc_tile_bytes(int max_m, int max_n) {
-    return align_up(sizeof(float) * (size_t)max_m * (size_t)max_n, 256);
+    return align_up(sizeof(float) * (size_t)max_m * (size_t)doc_tile_ld(max_n), 256);
 }
 // After the plan area, the results of the separate tile kernel: xx[M],
 // yy[N], first-round best b1[N], second best b2[N] (FP32), best local index
