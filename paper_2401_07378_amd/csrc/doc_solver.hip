@@ -309,7 +309,7 @@ constexpr int kStripeKSteps = 10;
 // operand), so lane l holds consumers jg .. jg + 3 (jg = j0 + 4 (l / 16))
 // against supplier i0 + l % 16 (first block half) and i0 + 16 + l % 16
 // (second half).  Each half is one 16-byte store of four consecutive keys
-// of tile row i (rows padded to a multiple of 4 columns), and the running
+// of tile row i (rows padded to a multiple of 16 columns), and the running
 // best / second-best / best-index of the four consumers take the suppliers
 // in ascending order.
 struct StripeTop {
@@ -779,7 +779,7 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
     const TIn* __restrict__ X = reinterpret_cast<const TIn*>(A.X) + x0 * d;
     const TIn* __restrict__ Y = reinterpret_cast<const TIn*>(A.Y) + y0 * d;
     const int mi = (int)m, ni = (int)n;
-    const int ldt = doc_tile_ld(ni);  // tile row stride (columns padded to a multiple of 4)
+    const int ldt = doc_tile_ld(ni);  // tile row stride (columns padded to a multiple of 16)
 
     // ---- ingest: masses, validity, norms (16 lanes per row)
     double red[4] = {0.0, 0.0, 0.0, 0.0};  // sum a, sum b, bad, max ||x||^2

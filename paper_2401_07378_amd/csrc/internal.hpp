@@ -226,8 +226,9 @@ int doc_shared_tile_threads();
 // Scratch slot of one workgroup: the m x n FP32 key tile (256-byte aligned,
 // rows of doc_tile_ld(n) columns)
 // followed by m + n plan entries (int32 src, int32 dst, double flow).
-// Tile row stride: the columns padded to a multiple of 4 (16-byte rows).
-__host__ __device__ inline int doc_tile_ld(int n) { return (n + 3) & ~3; }
+// Tile row stride: the columns padded to a multiple of 16, so that the
+// 64-byte row segment of one 16-consumer stripe is one aligned 64-byte block.
+__host__ __device__ inline int doc_tile_ld(int n) { return (n + 15) & ~15; }
 __host__ __device__ inline size_t doc_tile_bytes(int max_m, int max_n) {
     return align_up(sizeof(float) * (size_t)max_m * (size_t)doc_tile_ld(max_n), 256);
 }
