@@ -1317,16 +1317,16 @@ __global__ __launch_bounds__(T) void doc_tile_kernel(DocArgs A) {
 // top-2 updates in ascending supplier order and the same merge, so the tiles
 // and the first round's results are bit-identical to the per-pair tile pass.
 
-// Stripe list of one launch: one 16-byte record per stripe, (local pair
-// position << 6 | stripe, consumers of the pair or -1 for a pair that fails
-// its checks, first consumer row as int64); n <= 1024 per side so a pair has
-// at most 64 stripes, and every pair gets at least one record (its stripe 0
-// also writes the pair's supplier norms).  The order of the list does not
-// matter (every stripe is the same work: 16 consumers against all
-// suppliers).  The list kernel also clears each pair's non-finite flag,
-// which the stripes raise with atomic ORs.
+// Stripe list of one launch: one 16-byte record per pair of 16-consumer
+// stripes, (local pair position << 6 | stripe pair, consumers of the pair or
+// -1 for a pair that fails its checks, first consumer row as int64); n <=
+// 1024 per side so a pair has at most 32 records, and every pair gets at
+// least one (its first record also writes the pair's supplier norms).  The
+// order of the list does not matter (every record is nearly the same work:
+// 32 consumers against all suppliers).  The list kernel also clears each
+// pair's non-finite flag, which the stripes raise with atomic ORs.
 constexpr int kStripeShift = 6;
-constexpr int kSharedTileThreads = 768;  // 12 wavefronts: 170 VGPRs each for the pipeline
+constexpr int kSharedTileThreads = 768;  // 12 wavefronts: up to 170 VGPRs each
 
 __device__ inline int32_t* doc_aux_flag(const DocArgs& A, char* slot) {
     char* aux = slot + doc_aux_offset(A.max_m, A.max_n);
@@ -1356,7 +1356,7 @@ __global__ __launch_bounds__(T) void doc_stripe_list_kernel(DocArgs A, int npair
         const int status = resolve_pair(A, p, x0, m, y0, nn);
         n = status == NNSEMD_OK ? (int)nn : -1;
     }
-    const int k = b < npairs ? (n > 0 ? (n + 15) / 16 : 1) : 0;
+    const int k = b < npairs ? (n > 0 ? (n + 31) / 32 : 1) : 0;
     int v = k;  // inclusive scan over the wavefront
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -1448,20 +1448,45 @@ __global__ __launch_bounds__(T) void doc_tile_shared_kernel(DocArgs A) {
     const int r16 = lane & 15, kq = 8 * (lane >> 4);
     const int W = (int)gridDim.x * (T / 64);
     const int total = *A.stripe_total;
-    auto load_frags = [&](const StripeRec& r, bf16x8 (&yb)[KS]) {
+    // A record covers the stripes 2 sp and 2 sp + 1 of a pair (consumers
+    // 32 sp .. 32 sp + 31): both take the same supplier fragments from LDS,
+    // and their 64-byte row segments are the two halves of one 128-byte
+    // block.  A second stripe beyond the pair's consumers multiplies zero
+    // fragments and stores nothing.
+    auto load_frags = [&](const StripeRec& r, int h, bf16x8 (&yb)[KS]) {
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks)
-            if (ks < ksteps) yb[ks] = frag8(r.Y, r.s * 16 + r16, max(r.n, 0), ks * 32 + kq, d);
+            if (ks < ksteps) yb[ks] = frag8(r.Y, r.s * 32 + 16 * h + r16, max(r.n, 0), ks * 32 + kq, d);
     };
-    // Software pipeline: the record of the stripe after next and the
-    // fragments of the next stripe are in flight while this one multiplies.
+    auto norm_of = [&](const bf16x8 (&yb)[KS], bool& bad) {
+        double ss = 0.0;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            if (ks < ksteps) {
+                union {
+                    bf16x8 v;
+                    uint32_t w[4];
+                } u;
+                u.v = yb[ks];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    bad |= !finite_pair(u.w[e]);
+                    const double f0 = bf_lo(u.w[e]), f1 = bf_hi(u.w[e]);
+                    ss = fma(f0, f0, ss);
+                    ss = fma(f1, f1, ss);
+                }
+            }
+        }
+        ss += __shfl_xor(ss, 16);
+        ss += __shfl_xor(ss, 32);
+        return ss;
+    };
+    // The record of the stripe pair after next is loaded while this one
+    // multiplies.
     int t = (int)blockIdx.x * (T / 64) + tid / 64;
     StripeRec cur = stripe_rec(A, t, total);
     StripeRec nxt = stripe_rec(A, t + W, total);
-    bf16x8 yb[KS], ybn[KS];
-    if (t < total) load_frags(cur, yb);
     for (; t < total; t += W) {
-        if (t + W < total) load_frags(nxt, ybn);
         const StripeRec nn = stripe_rec(A, t + 2 * W, total);
         const int mi = cur.n >= 0 ? mq : 0, ni = max(cur.n, 0);
         char* slot = A.scratch + (size_t)cur.b * (size_t)A.slot_bytes;
@@ -1480,36 +1505,23 @@ __global__ __launch_bounds__(T) void doc_tile_shared_kernel(DocArgs A) {
                 axx[i] = (float)s2;
             }
         }
-        const int j0 = cur.s * 16;
+        const int j0 = cur.s * 32;
         if (j0 < ni) {
-            double ss = 0.0;
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
-                if (ks < ksteps) {
-                    union {
-                        bf16x8 v;
-                        uint32_t w[4];
-                    } u;
-                    u.v = yb[ks];
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        bad |= !finite_pair(u.w[e]);
-                        const double f0 = bf_lo(u.w[e]), f1 = bf_hi(u.w[e]);
-                        ss = fma(f0, f0, ss);
-                        ss = fma(f1, f1, ss);
-                    }
-                }
-            }
-            ss += __shfl_xor(ss, 16);
-            ss += __shfl_xor(ss, 32);
-            if (lane < 16 && j0 + r16 < ni) ayy[j0 + r16] = (float)ss;
-            StripeTop tp;
-            stripe_top_init(tp);
+            bf16x8 ya[KS], yb[KS];
+            load_frags(cur, 0, ya);
+            load_frags(cur, 1, yb);
+            const double ssa = norm_of(ya, bad), ssb = norm_of(yb, bad);
+            if (lane < 16 && j0 + r16 < ni) ayy[j0 + r16] = (float)ssa;
+            if (lane < 16 && j0 + 16 + r16 < ni) ayy[j0 + 16 + r16] = (float)ssb;
+            StripeTop ta, tb;
+            stripe_top_init(ta);
+            stripe_top_init(tb);
             const int jg = j0 + 4 * (lane >> 4);
             const int ldt = doc_tile_ld(ni);
             const f32x4 zero = (f32x4){0.f, 0.f, 0.f, 0.f};
             for (int i0 = 0; i0 < mi; i0 += 32) {
-                float dot0[4] = {0.f, 0.f, 0.f, 0.f}, dot1[4] = {0.f, 0.f, 0.f, 0.f};
+                float a0[4] = {0.f, 0.f, 0.f, 0.f}, a1[4] = {0.f, 0.f, 0.f, 0.f};
+                float b0[4] = {0.f, 0.f, 0.f, 0.f}, b1[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int ks = 0; ks < KS; ++ks) {
                     if (ks < ksteps) {
@@ -1519,24 +1531,28 @@ __global__ __launch_bounds__(T) void doc_tile_shared_kernel(DocArgs A) {
                         } f0, f1;
                         f0.u = *reinterpret_cast<const uint4*>(&xs[(i0 + r16) * kStripeLdx + ks * 32 + kq]);
                         f1.u = *reinterpret_cast<const uint4*>(&xs[(i0 + 16 + r16) * kStripeLdx + ks * 32 + kq]);
-                        const f32x4 c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yb[ks], f0.v, zero, 0, 0, 0);
-                        const f32x4 c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yb[ks], f1.v, zero, 0, 0, 0);
+                        const f32x4 ca0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ya[ks], f0.v, zero, 0, 0, 0);
+                        const f32x4 ca1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ya[ks], f1.v, zero, 0, 0, 0);
+                        const f32x4 cb0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yb[ks], f0.v, zero, 0, 0, 0);
+                        const f32x4 cb1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yb[ks], f1.v, zero, 0, 0, 0);
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
-                            dot0[r] += c0[r];
-                            dot1[r] += c1[r];
+                            a0[r] += ca0[r];
+                            a1[r] += ca1[r];
+                            b0[r] += cb0[r];
+                            b1[r] += cb1[r];
                         }
                     }
                 }
-                stripe_block_epilogue(dot0, dot1, i0, mi, jg, ni, ldt, xx, am, tile, tp);
+                stripe_block_epilogue(a0, a1, i0, mi, jg, ni, ldt, xx, am, tile, ta);
+                stripe_block_epilogue(b0, b1, i0, mi, jg + 16, ni, ldt, xx, am, tile, tb);
             }
-            stripe_top_finish(tp, jg, ni, ab1, ab2, abs_);
+            stripe_top_finish(ta, jg, ni, ab1, ab2, abs_);
+            stripe_top_finish(tb, jg + 16, ni, ab1, ab2, abs_);
         }
         if (__ballot(bad) != 0 && lane == 0) atomicOr(doc_aux_flag(A, slot), 1);
         cur = nxt;
         nxt = nn;
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) yb[ks] = ybn[ks];
     }
 }
 
