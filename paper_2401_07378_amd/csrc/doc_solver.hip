@@ -1386,10 +1386,10 @@ __host__ __device__ inline size_t doc_shared_lds(int max_m) {
     return doc_shared_rows(max_m) * (sizeof(uint16_t) * kStripeLdx + sizeof(double) + sizeof(float));
 }
 
-// Stripe s of a pair: the consumers' fragments (all K steps) of rows
-// 16 s .. 16 s + 15 of the pair's consumer set.
+// Record s of a pair: its stripes 2 s and 2 s + 1, the consumers
+// 32 s .. 32 s + 31 of the pair's consumer set.
 struct StripeRec {
-    int b, s, n;       // local pair position, stripe, consumers (-1: the pair failed its checks)
+    int b, s, n;       // local pair position, stripe pair, consumers (-1: the pair failed its checks)
     const uint16_t* Y;  // the pair's first consumer row
 };
 
