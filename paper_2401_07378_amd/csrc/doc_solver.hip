@@ -1396,7 +1396,9 @@ struct StripeRec {
 __device__ inline StripeRec stripe_rec(const DocArgs& A, int t, int total) {
     StripeRec r{0, 0, 0, nullptr};
     if (t < total) {
-        const int4 e = A.stripes[t];
+        // the list from its end: the pairs scheduled first have their tiles
+        // written last, so the rounds kernel finds more of them in the caches
+        const int4 e = A.stripes[total - 1 - t];
         r.b = e.x >> kStripeShift;
         r.s = e.x & ((1 << kStripeShift) - 1);
         r.n = e.y;
