@@ -286,6 +286,62 @@ def test_shared_query_tile_pass_same_bits():
     assert np.all(gq["stats"]["status"] == -1)
 
 
+def test_shared_query_two_launches_and_bad_entries():
+    """A query of 224 points against 5000 candidates, one of them 1024
+    points long, so the key-tile scratch (4 GiB) takes the batch in two
+    launches.  Two pair-table entries name a supplier set that does not
+    exist and one candidate is empty.  The shared-query tile pass gives the
+    same bits as the per-pair one on every pair; sampled pairs from both
+    launches, the long one and the empty one match the oracle."""
+    from paper_2401_07378_amd import binding
+    d = 300
+    r = W.rng_for(895, 0)
+    qb = W.f32_to_bf16_bits(W.to_f32(r.standard_normal((224, d)) / np.sqrt(d)))
+    qa = W.zipf_masses(r, 224)
+    sizes = r.integers(20, 41, 5000)
+    sizes[2700] = 1024
+    sizes[4321] = 0
+    yb = W.f32_to_bf16_bits(W.to_f32(r.standard_normal((int(sizes.sum()), d)) / np.sqrt(d)))
+    yo = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    ya = np.concatenate([W.zipf_masses(r, int(k)) if k > 0 else np.zeros(0, np.float32) for k in sizes])
+    ya = ya.astype(np.float32)
+    px = np.zeros(5000, np.int32)
+    px[[17, 4800]] = 1  # no supplier set 1
+    ps = W.PairSet("two_launches", d, W.bf16_bits_to_f32(qb).reshape(-1, d), qa.astype(np.float32),
+                   np.array([0, 224], np.int64), W.bf16_bits_to_f32(yb).reshape(-1, d), ya, yo,
+                   pair_x=px, pair_y=np.arange(5000, dtype=np.int32), metric="l2", dtype="bf16",
+                   X_bits=qb.reshape(-1, d), Y_bits=yb.reshape(-1, d))
+    import torch
+    from tests.gpu_helpers import to_dev, to_dev_bf16
+
+    def run():
+        r = binding.emd_approx_batched(to_dev_bf16(ps.X_bits), to_dev(ps.a), to_dev(ps.x_off),
+                                       to_dev_bf16(ps.Y_bits), to_dev(ps.b), to_dev(ps.y_off),
+                                       pair_x=to_dev(px), pair_y=to_dev(ps.pair_y), num_pairs=5000,
+                                       max_m=224, max_n=1024, metric="l2", mode="bf16_mfma_refine")
+        torch.cuda.synchronize()
+        return {"costs": r["costs"][:5000].cpu().numpy(), "stats": binding.stats_numpy(r["stats"])[:5000]}
+
+    binding.tuning_reset()
+    try:
+        shared = run()
+        binding.tuning_set_docs(d, 1024, "split_per_pair")
+        per_pair = run()
+    finally:
+        binding.tuning_reset()
+    np.testing.assert_array_equal(shared["costs"], per_pair["costs"])
+    np.testing.assert_array_equal(shared["stats"], per_pair["stats"])
+    st = shared["stats"]
+    assert int(st["status"][17]) == -1 and int(st["status"][4800]) == -1
+    assert int(st["status"][4321]) == -2  # empty candidate against a non-empty query: masses differ
+    for p in (0, 1, 2699, 2700, 4321, 4680, 4681, 4999):
+        X, a = ps.X, ps.a
+        Y, b = ps.Y[yo[p]:yo[p + 1]], ps.b[yo[p]:yo[p + 1]]
+        ref = oracle_pair(X, a, Y, b)
+        gp = {"cost": float(shared["costs"][p]), "stats": st[p]}
+        assert_pair_matches(gp, ref, rel=BF16_COST_REL, plan=False, label=f"pair{p}")
+
+
 def test_document_batch_as_given_schedule_same_bits():
     ps = _small_docs(32, seed=891)
     g1 = gpu_batched(ps, mode="bf16_mfma_refine")
