@@ -966,7 +966,7 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
             const int j = L.cact[valid ? q : 0];
             float b1 = INFINITY, b2 = INFINITY;
             int bs = 0x7fffffff;
-            constexpr int U = 8;
+            constexpr int U = 16;
             const int stride = S * U;
             const int full = (mact / stride) * stride;
             for (int s0 = r; s0 < full; s0 += stride) {
