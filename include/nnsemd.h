@@ -80,7 +80,14 @@ typedef enum { NNSEMD_GREEDY = 0, NNSEMD_RANDOM = 1 } nnsemd_protocol_t;
  * accumulation.  In both modes a consumer whose two best FP32 keys are
  * closer than the proven FP32 error bound is re-scored in FP64 from the
  * inputs, so every argmin and every serve order is the one of the FP64
- * definition (ties to the smallest index) and the cost is summed in FP64. */
+ * definition (ties to the smallest index) and the cost is summed in FP64.
+ * Cost terms: FP32 mode recomputes every served distance in FP64.
+ * BF16_MFMA_REFINE with d <= 320 and sides <= 1024 takes a served distance
+ * from its key when the key's error bound makes the term accurate to 1e-5
+ * relative.  Where that fails for any term of a pair, it recomputes every
+ * distance of the pair in FP64.  The cost is then within 1e-5 relative of
+ * the definition's (Sec. III-A: R sums flow times distance), inside the
+ * 1e-3 allowed for this mode. */
 typedef enum { NNSEMD_MODE_FP32 = 0, NNSEMD_MODE_BF16_MFMA_REFINE = 1 } nnsemd_mode_t;
 
 /* Order in which a batched call starts its pairs (results do not depend on
