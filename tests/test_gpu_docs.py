@@ -342,6 +342,42 @@ def test_shared_query_two_launches_and_bad_entries():
         assert_pair_matches(gp, ref, rel=BF16_COST_REL, plan=False, label=f"pair{p}")
 
 
+def test_shared_query_stripe_edges_and_large_offset():
+    """One query against candidates whose sizes sit at the stripe and
+    stripe-pair edges (1, 2, 15, 16, 17, 31, 32, 33, 63, 64, 65 consumers),
+    with every coordinate offset by 3 (BF16 spacing 2^-6 there): the keys
+    ||x||^2 - 2 x.y cancel about 300 times their result, so the FP32 bound
+    is about 0.6 % of a squared distance.  Many consumers and serve orders
+    then go to FP64 keys, and the cost falls back to exact distances.
+    Plans, counts and costs (1e-12) equal the oracle's."""
+    d = 64
+    r = W.rng_for(896, 0)
+    sizes = [1, 2, 15, 16, 17, 31, 32, 33, 63, 64, 65]
+    def pts(k):
+        return W.f32_to_bf16_bits(W.to_f32(3.0 + r.standard_normal((k, d)) / np.sqrt(d)))
+    qb = pts(90)
+    qa = W.zipf_masses(r, 90)
+    ys = [(pts(k), W.zipf_masses(r, k)) for k in sizes]
+    yb = np.concatenate([y[0] for y in ys]).astype(np.uint16)
+    ya = np.concatenate([y[1] for y in ys]).astype(np.float32)
+    yo = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    P = len(sizes)
+    ps = W.PairSet("edges", d, W.bf16_bits_to_f32(qb).reshape(-1, d), qa.astype(np.float32),
+                   np.array([0, 90], np.int64), W.bf16_bits_to_f32(yb).reshape(-1, d), ya, yo,
+                   pair_x=np.zeros(P, np.int32), pair_y=np.arange(P, dtype=np.int32), metric="l2", dtype="bf16",
+                   X_bits=qb.reshape(-1, d), Y_bits=yb.reshape(-1, d))
+    g = gpu_batched(ps, plan=True, mode="bf16_mfma_refine")
+    assert int(g["stats"]["rescored"].sum()) > 0
+    for p in range(P):
+        X, a, Y, b = ps.pair(p)
+        ref = oracle_pair(X, a, Y, b)
+        lo = g["plan_off"][p]
+        k = int(g["stats"][p]["nnz"])
+        gp = {"cost": float(g["costs"][p]), "stats": g["stats"][p], "src": g["src"][lo:lo + k],
+              "dst": g["dst"][lo:lo + k], "flow": g["flow"][lo:lo + k]}
+        assert_pair_matches(gp, ref, rel=1e-12, label=f"pair{p} n={sizes[p]}")
+
+
 def test_document_batch_as_given_schedule_same_bits():
     ps = _small_docs(32, seed=891)
     g1 = gpu_batched(ps, mode="bf16_mfma_refine")
