@@ -1131,7 +1131,7 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
         // D to FP64 accuracy, not in the definition's operation order: 300
         // terms in any order stay within 1e-13 relative.)
         {
-            constexpr int G = 16, E = 2, NG = T / G;
+            constexpr int G = 16, E = SPLIT ? 1 : 2, NG = T / G;  // (split form: rare, kept light)
             const int gl = tid & (G - 1);
             for (int q0 = tid / G; q0 < ne; q0 += E * NG) {
                 const TIn* xr[E];
