@@ -597,7 +597,7 @@ __device__ void key_tile_valu(const float* __restrict__ X, const float* __restri
 // may be a near tie carries exact keys, and the near ties of neighbouring
 // claimants are counted on those (ties_order).
 template <int T, typename TIn>
-__device__ inline void rank_greedy_doc(const Lds& L, Shared& sh, int nact, const float* __restrict__ kap,
+__device__ inline void rank_greedy_doc(const Lds16& L, Shared& sh, int nact, const float* __restrict__ kap,
                                        const float* __restrict__ yn, float rhat, float tscale,
                                        int32_t* __restrict__ amb, const TIn* __restrict__ X,
                                        const TIn* __restrict__ Y, int d, int metric, int64_t& near,
@@ -736,7 +736,7 @@ __device__ inline int resolve_pair(const DocArgs& A, int64_t p, int64_t& x0, int
 // SPLIT: the key tile, the norms, the coordinates' finiteness and the first
 // round's search were done by doc_tile_kernel into this workgroup's slot.
 template <typename TIn, bool MFMA, int T, int CSMAX, bool SPLIT>
-__device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ slot, const Lds& L,
+__device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ slot, const Lds16& L,
                                float* __restrict__ xx, float* __restrict__ yy, float* __restrict__ yn,
                                float* __restrict__ kap, int32_t* __restrict__ amb, Shared& sh, int& kloose) {
     constexpr int NW = T / 64;
@@ -923,7 +923,7 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
     int64_t work = 0, nnz = 0, near = 0;
     int64_t ties_nn = 0, ties_order = 0;  // this thread's near-tie counts
     double wcost = 0.0;                    // split form: this thread's part of R from the walk
-    float* flag_b1 = reinterpret_cast<float*>(L.sorted);  // re-score cutoff of each flagged consumer
+    float* flag_b1 = reinterpret_cast<float*>(amb);  // re-score cutoff of each flagged consumer (amb is free until the order)
     while (status == NNSEMD_OK && mact > 0 && nact > 0) {
         if (rounds >= max_rounds) {
             status = NNSEMD_ERR_NOT_CONVERGED;
@@ -949,7 +949,7 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
                     L.cnn[j] = bs;
                     kap[j] = b1 + yy[j];
                     L.ckey[j] = -1.0;  // exact key not known
-                    atomicAdd(&L.scnt[bs], 1);
+                    cnt_add(L.scnt, bs);
                 }
             }
         } else {
@@ -1010,7 +1010,7 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
                     L.cnn[j] = bs;
                     kap[j] = b1 + yy[j];
                     L.ckey[j] = -1.0;  // exact key not known
-                    atomicAdd(&L.scnt[bs], 1);
+                    cnt_add(L.scnt, bs);
                 }
             }
         }
@@ -1055,7 +1055,7 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
                     L.cnn[j] = bsl;
                     L.ckey[j] = best;
                     kap[j] = tile[(size_t)L.sidx[bsl] * ldt + j] + yy[j];
-                    atomicAdd(&L.scnt[bsl], 1);
+                    cnt_add(L.scnt, bsl);
                     if (mact > 1 && near_tie_dist(dist_of_key(best, A.metric), dist_of_key(sec, A.metric)))
                         ++ties_nn;
                 }
@@ -1104,7 +1104,7 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
         __syncthreads();  // residuals read; the LDS below is reused
         int32_t* cnt = reinterpret_cast<int32_t*>(L.ckey);  // [N]
         int32_t* off = cnt + A.max_n;                       // [N]
-        int32_t* ent = L.sidx;                              // [m + n] (sidx .. sorted are contiguous)
+        int32_t* ent = reinterpret_cast<int32_t*>(L.sidx);  // [m + n] (sidx .. sorted are contiguous)
         double* contrib = L.smass;                          // [m + n] (smass, cmass are contiguous)
         const int ne = (int)nnz;
         for (int j = tid; j < ni; j += T) cnt[j] = 0;
@@ -1558,15 +1558,16 @@ __global__ __launch_bounds__(T) void doc_tile_shared_kernel(DocArgs A) {
     }
 }
 
-// The split form runs at five wavefronts per SIMD (96 VGPRs; its LDS also
-// allows five pairs per CU): 1.59 -> 1.43 ms on the document batch against four.
+// The split form runs at six wavefronts per SIMD (80 VGPRs, a few spilled),
+// which its compact LDS layout (16-bit indices) also allows: six 162 x 500
+// pairs per CU.
 template <typename TIn, bool MFMA, int T, int CSMAX, bool SPLIT>
-__global__ __launch_bounds__(T, SPLIT ? 5 : 1) void doc_pair_kernel(DocArgs A) {
+__global__ __launch_bounds__(T, SPLIT ? 6 : 1) void doc_pair_kernel(DocArgs A) {
     extern __shared__ __align__(16) char lds_dyn[];
     __shared__ Shared sh;
     __shared__ int kloose;  // split form: a served distance needs its exact FP64 value
-    const PairLdsLayout lay = pair_lds_layout(A.max_m, A.max_n, 0);
-    const Lds L = carve(lds_dyn, A.max_m, A.max_n, 0);
+    const PairLdsLayout lay = pair_lds_layout(A.max_m, A.max_n, 0, 0, true, false);
+    const Lds16 L = carve16(lds_dyn, A.max_m, A.max_n, 0, 0, false);
     float* xx = reinterpret_cast<float*>(lds_dyn + lay.total);
     float* yy = xx + A.max_m;
     float* yn = yy + A.max_n;
@@ -1612,9 +1613,11 @@ int doc_launch_typed(const DocArgs& A, size_t lds, int grid, hipStream_t st, boo
 
 }  // namespace
 
-// Pair layout (no records) + xx[M], yy[N], yn[N], kap[N] (float), amb[N] (int32).
+// Compact pair layout (16-bit indices, no records, its own serve-order
+// array) + xx[M], yy[N], yn[N], kap[N] (float), amb[N] (int32).
 size_t doc_lds_bytes(int max_m, int max_n) {
-    return pair_lds_layout(max_m, max_n, 0).total + sizeof(float) * ((size_t)max_m + 4 * (size_t)max_n);
+    return pair_lds_layout(max_m, max_n, 0, 0, true, false).total +
+           sizeof(float) * ((size_t)max_m + 4 * (size_t)max_n);
 }
 
 size_t doc_shared_tile_lds(int max_m) { return doc_shared_lds(max_m); }
