@@ -376,7 +376,7 @@ nnsemd_status_t run_docs(nnsemd_handle_t h, DocArgs& A, int64_t max_m, int64_t m
         return fail(h, NNSEMD_ERR_UNSUPPORTED, "high-dimensional path supports up to 4096 points per side");
     const int mcap = (int)std::max<int64_t>(max_m, 1), ncap = (int)std::max<int64_t>(max_n, 1);
     const int chunk = (std::max(mcap, ncap) + 255) / 256;
-    const size_t lds = doc_lds_bytes(mcap, ncap);
+    const size_t lds = doc_lds_bytes(mcap, ncap, dtype != NNSEMD_BF16);
     if (lds + 8192 > h->max_lds) return fail(h, NNSEMD_ERR_UNSUPPORTED, "pair does not fit in LDS");
     A.max_m = mcap;
     A.max_n = ncap;

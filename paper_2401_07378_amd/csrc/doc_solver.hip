@@ -528,64 +528,64 @@ __device__ void key_tile_mfma_stripes(const uint16_t* __restrict__ X, const uint
     }
 }
 
-// Key tile on the vector ALUs (FP32 inputs): each lane owns a 4 x 4 block
-// of (i, j) and walks the d products with 16-byte loads when rows allow it.
+// Key tile on the vector ALUs (FP32 inputs), blocked through LDS: the
+// workgroup computes 64 x 64 blocks of (i, j); each K chunk of 16 of both
+// row panels is staged in LDS (transposed, zero-padded), and each thread
+// accumulates a 4 x 4 block with FMAs.  Any accumulation order is covered by
+// the FP32 bound of the unsplit form.  stage: LDS, 2 x 16 x kValuLd floats,
+// 16-byte aligned.
+constexpr int kValuBK = 16;
+constexpr int kValuLd = 68;  // 64 rows + padding (keeps the float4 reads aligned)
+constexpr size_t kValuStageBytes = sizeof(float) * 2 * kValuBK * kValuLd;
+
 template <int T>
 __device__ void key_tile_valu(const float* __restrict__ X, const float* __restrict__ Y, int m, int n, int ld, int d,
-                              const float* __restrict__ xx, float* __restrict__ tile) {
-    const int bm = (m + 3) / 4, bn = (n + 3) / 4;
-    const bool vec = (d & 3) == 0 && ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y)) & 15u) == 0;
-    for (int e = threadIdx.x; e < bm * bn; e += T) {
-        const int i0 = (e / bn) * 4, j0 = (e % bn) * 4;
-        const float* xr[4];
-        const float* yr[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            xr[u] = X + (size_t)min(i0 + u, m - 1) * d;  // clamped rows are computed, not stored
-            yr[u] = Y + (size_t)min(j0 + u, n - 1) * d;
-        }
+                              const float* __restrict__ xx, float* __restrict__ tile, float* __restrict__ stage) {
+    static_assert(T == 256, "16 x 16 threads of 4 x 4 outputs");
+    float* xs = stage;                      // [kValuBK][kValuLd]: X panel, k-major
+    float* ys = stage + kValuBK * kValuLd;  // [kValuBK][kValuLd]: Y panel
+    const int tid = threadIdx.x;
+    const int ty = tid / 16, tx = tid % 16;
+    const int bm = (m + 63) / 64, bn = (n + 63) / 64;
+    for (int blk = 0; blk < bm * bn; ++blk) {
+        const int i0 = (blk / bn) * 64, j0 = (blk % bn) * 64;
         float acc[4][4];
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc[u][v] = 0.f;
-        int k = 0;
-        if (vec) {
-            for (; k < d; k += 4) {
-                float4 xv[4], yv[4];
+        for (int k0 = 0; k0 < d; k0 += kValuBK) {
+            __syncthreads();  // the previous chunk has been read
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    xv[u] = *reinterpret_cast<const float4*>(xr[u] + k);
-                    yv[u] = *reinterpret_cast<const float4*>(yr[u] + k);
-                }
+            for (int q = 0; q < 64 * kValuBK / T; ++q) {
+                const int e = tid + q * T;
+                const int r = e / kValuBK, k = e % kValuBK;
+                const bool kin = k0 + k < d;
+                xs[k * kValuLd + r] = (i0 + r < m && kin) ? X[(size_t)(i0 + r) * d + k0 + k] : 0.f;
+                ys[k * kValuLd + r] = (j0 + r < n && kin) ? Y[(size_t)(j0 + r) * d + k0 + k] : 0.f;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < kValuBK; ++k) {
+                const float4 a = *reinterpret_cast<const float4*>(&xs[k * kValuLd + 4 * ty]);
+                const float4 b = *reinterpret_cast<const float4*>(&ys[k * kValuLd + 4 * tx]);
+                const float av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        acc[u][v] = fmaf(xv[u].x, yv[v].x, acc[u][v]);
-                        acc[u][v] = fmaf(xv[u].y, yv[v].y, acc[u][v]);
-                        acc[u][v] = fmaf(xv[u].z, yv[v].z, acc[u][v]);
-                        acc[u][v] = fmaf(xv[u].w, yv[v].w, acc[u][v]);
-                    }
+                    for (int v = 0; v < 4; ++v) acc[u][v] = fmaf(av[u], bv[v], acc[u][v]);
             }
         }
-        for (; k < d; ++k) {
-            float xs[4], ys[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                xs[u] = xr[u][k];
-                ys[u] = yr[u][k];
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + 4 * ty + u;
+            if (i >= m) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int j = j0 + 4 * tx + v;
+                if (j < n) tile[(size_t)i * ld + j] = xx[i] - 2.f * acc[u][v];
             }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[u][v] = fmaf(xs[u], ys[v], acc[u][v]);
         }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-                if (i0 + u < m && j0 + v < n) tile[(size_t)(i0 + u) * ld + j0 + v] = xx[i0 + u] - 2.f * acc[u][v];
     }
 }
 
@@ -738,7 +738,8 @@ __device__ inline int resolve_pair(const DocArgs& A, int64_t p, int64_t& x0, int
 template <typename TIn, bool MFMA, int T, int CSMAX, bool SPLIT>
 __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ slot, const Lds16& L,
                                float* __restrict__ xx, float* __restrict__ yy, float* __restrict__ yn,
-                               float* __restrict__ kap, int32_t* __restrict__ amb, Shared& sh, int& kloose) {
+                               float* __restrict__ kap, int32_t* __restrict__ amb, Shared& sh, int& kloose,
+                               float* __restrict__ vstage) {
     constexpr int NW = T / 64;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -870,7 +871,7 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
                              tile);
         } else {
             key_tile_valu<T>(reinterpret_cast<const float*>(X), reinterpret_cast<const float*>(Y), mi, ni, ldt, d, xx,
-                             tile);
+                             tile, vstage);
         }
     }
     __syncthreads();
@@ -1573,10 +1574,12 @@ __global__ __launch_bounds__(T, SPLIT ? 6 : 1) void doc_pair_kernel(DocArgs A) {
     float* yn = yy + A.max_n;
     float* kap = yn + A.max_n;
     int32_t* amb = reinterpret_cast<int32_t*>(kap + A.max_n);
+    // FP32 vector tile: its LDS staging panels after the pair's arrays
+    float* vstage = reinterpret_cast<float*>(align_up(reinterpret_cast<uintptr_t>(amb + A.max_n), 16));
     const int64_t b = A.pair_base + (int64_t)blockIdx.x;
     const int64_t p = A.order != nullptr ? (int64_t)A.order[b] : b;
     char* slot = A.scratch + (size_t)blockIdx.x * (size_t)A.slot_bytes;
-    solve_doc_pair<TIn, MFMA, T, CSMAX, SPLIT>(A, p, slot, L, xx, yy, yn, kap, amb, sh, kloose);
+    solve_doc_pair<TIn, MFMA, T, CSMAX, SPLIT>(A, p, slot, L, xx, yy, yn, kap, amb, sh, kloose, vstage);
 }
 
 template <typename TIn, bool MFMA, int CSMAX, bool SPLIT>
@@ -1614,10 +1617,11 @@ int doc_launch_typed(const DocArgs& A, size_t lds, int grid, hipStream_t st, boo
 }  // namespace
 
 // Compact pair layout (16-bit indices, no records, its own serve-order
-// array) + xx[M], yy[N], yn[N], kap[N] (float), amb[N] (int32).
-size_t doc_lds_bytes(int max_m, int max_n) {
+// array) + xx[M], yy[N], yn[N], kap[N] (float), amb[N] (int32), and for FP32
+// points the staging panels of the vector tile (16-byte aligned).
+size_t doc_lds_bytes(int max_m, int max_n, bool fp32_points) {
     return pair_lds_layout(max_m, max_n, 0, 0, true, false).total +
-           sizeof(float) * ((size_t)max_m + 4 * (size_t)max_n);
+           sizeof(float) * ((size_t)max_m + 4 * (size_t)max_n) + (fp32_points ? kValuStageBytes + 16 : 0);
 }
 
 size_t doc_shared_tile_lds(int max_m) { return doc_shared_lds(max_m); }

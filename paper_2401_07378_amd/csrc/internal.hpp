@@ -213,7 +213,7 @@ struct DocArgs {
     int32_t pad2;
 };
 
-size_t doc_lds_bytes(int max_m, int max_n);
+size_t doc_lds_bytes(int max_m, int max_n, bool fp32_points);
 // Whether a launch takes the split form (tile kernel + rounds kernel), and
 // the supplier-set norm pass it needs first (A.xnorm: num_x_sets * max_m).
 bool doc_split_form(int d, bool bf16_mfma, int chunk_max);
