@@ -528,8 +528,73 @@ __device__ void key_tile_mfma_stripes(const uint16_t* __restrict__ X, const uint
     }
 }
 
-// Key tile on the vector ALUs (FP32 inputs), blocked through LDS: the
-// workgroup computes 64 x 64 blocks of (i, j); each K chunk of 16 of both
+// Key tile on the vector ALUs (FP32 inputs) for launches of few pairs: each
+// lane owns a 4 x 4 block of (i, j) and walks the d products with 16-byte
+// loads from global memory when rows allow it, with no barrier (a pair that
+// has a CU to itself is bound by latency, not by the L2).
+template <int T>
+__device__ void key_tile_valu_direct(const float* __restrict__ X, const float* __restrict__ Y, int m, int n, int ld, int d,
+                              const float* __restrict__ xx, float* __restrict__ tile) {
+    const int bm = (m + 3) / 4, bn = (n + 3) / 4;
+    const bool vec = (d & 3) == 0 && ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y)) & 15u) == 0;
+    for (int e = threadIdx.x; e < bm * bn; e += T) {
+        const int i0 = (e / bn) * 4, j0 = (e % bn) * 4;
+        const float* xr[4];
+        const float* yr[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            xr[u] = X + (size_t)min(i0 + u, m - 1) * d;  // clamped rows are computed, not stored
+            yr[u] = Y + (size_t)min(j0 + u, n - 1) * d;
+        }
+        float acc[4][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[u][v] = 0.f;
+        int k = 0;
+        if (vec) {
+            for (; k < d; k += 4) {
+                float4 xv[4], yv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    xv[u] = *reinterpret_cast<const float4*>(xr[u] + k);
+                    yv[u] = *reinterpret_cast<const float4*>(yr[u] + k);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        acc[u][v] = fmaf(xv[u].x, yv[v].x, acc[u][v]);
+                        acc[u][v] = fmaf(xv[u].y, yv[v].y, acc[u][v]);
+                        acc[u][v] = fmaf(xv[u].z, yv[v].z, acc[u][v]);
+                        acc[u][v] = fmaf(xv[u].w, yv[v].w, acc[u][v]);
+                    }
+            }
+        }
+        for (; k < d; ++k) {
+            float xs[4], ys[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                xs[u] = xr[u][k];
+                ys[u] = yr[u][k];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] = fmaf(xs[u], ys[v], acc[u][v]);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                if (i0 + u < m && j0 + v < n) tile[(size_t)(i0 + u) * ld + j0 + v] = xx[i0 + u] - 2.f * acc[u][v];
+    }
+}
+
+// Key tile on the vector ALUs (FP32 inputs) for batches, blocked through LDS
+// (the direct form re-reads every operand through the L2, which the whole
+// chip then contends for): the workgroup computes 64 x 64 blocks of (i, j);
+// each K chunk of 16 of both
 // row panels is staged in LDS (transposed, zero-padded), and each thread
 // accumulates a 4 x 4 block with FMAs.  Any accumulation order is covered by
 // the FP32 bound of the unsplit form.  stage: LDS, 2 x 16 x kValuLd floats,
@@ -537,6 +602,7 @@ __device__ void key_tile_mfma_stripes(const uint16_t* __restrict__ X, const uint
 constexpr int kValuBK = 16;
 constexpr int kValuLd = 68;  // 64 rows + padding (keeps the float4 reads aligned)
 constexpr size_t kValuStageBytes = sizeof(float) * 2 * kValuBK * kValuLd;
+constexpr unsigned kValuBlockedMinPairs = 256;  // launches of at least one pair per CU
 
 template <int T>
 __device__ void key_tile_valu(const float* __restrict__ X, const float* __restrict__ Y, int m, int n, int ld, int d,
@@ -870,8 +936,12 @@ __device__ void solve_doc_pair(const DocArgs& A, int64_t p, char* __restrict__ s
             key_tile_mfma<T>(reinterpret_cast<const uint16_t*>(X), reinterpret_cast<const uint16_t*>(Y), mi, ni, ldt, d, xx,
                              tile);
         } else {
-            key_tile_valu<T>(reinterpret_cast<const float*>(X), reinterpret_cast<const float*>(Y), mi, ni, ldt, d, xx,
-                             tile, vstage);
+            if (gridDim.x >= kValuBlockedMinPairs)
+                key_tile_valu<T>(reinterpret_cast<const float*>(X), reinterpret_cast<const float*>(Y), mi, ni, ldt, d,
+                                 xx, tile, vstage);
+            else
+                key_tile_valu_direct<T>(reinterpret_cast<const float*>(X), reinterpret_cast<const float*>(Y), mi, ni,
+                                        ldt, d, xx, tile);
         }
     }
     __syncthreads();
