@@ -1629,11 +1629,12 @@ __global__ __launch_bounds__(T) void doc_tile_shared_kernel(DocArgs A) {
     }
 }
 
-// The split form runs at six wavefronts per SIMD (80 VGPRs, a few spilled),
-// which its compact LDS layout (16-bit indices) also allows: six 162 x 500
-// pairs per CU.
+// The split form runs at five wavefronts per SIMD (94 VGPRs, no spills; at
+// six the 80-VGPR limit spills 30 registers, whose scratch traffic costs as
+// much as the extra wavefront gains).  Its compact LDS layout (16-bit
+// indices) fits five 162 x 500 pairs per CU.
 template <typename TIn, bool MFMA, int T, int CSMAX, bool SPLIT>
-__global__ __launch_bounds__(T, SPLIT ? 6 : 1) void doc_pair_kernel(DocArgs A) {
+__global__ __launch_bounds__(T, SPLIT ? 5 : 1) void doc_pair_kernel(DocArgs A) {
     extern __shared__ __align__(16) char lds_dyn[];
     __shared__ Shared sh;
     __shared__ int kloose;  // split form: a served distance needs its exact FP64 value
