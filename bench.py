@@ -61,6 +61,32 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+DOC_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "doc_pair_kernel_documents_300d_traffic.json")
+DOC_SOURCES = [os.path.join(ROOT, "paper_2401_07378_amd", "csrc", f)
+               for f in ("doc_solver.hip", "round_common.hpp", "internal.hpp")]
+
+
+def doc_kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in DOC_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_doc_traffic():
+    """HBM bytes per document call (split form, every kernel of the call)
+    from the committed rocprofv3 counter summary, or None when a document
+    kernel source changed since the counters were taken."""
+    if not os.path.exists(DOC_TRAFFIC_FILE):
+        return None
+    with open(DOC_TRAFFIC_FILE) as f:
+        t = json.load(f)
+    if t.get("source_hash") != doc_kernel_source_hash():
+        return None
+    return t.get("bytes_per_call")
+
+
 def issued_per_eval(d):
     """VALU instructions the point-path search loop issues per evaluation
     (counted in the gfx950 assembly of the unrolled block)."""
@@ -706,10 +732,12 @@ def bench_documents(args, dev):
     # One query of m points against the candidates: about m flops per byte
     # of candidate rows, below the BF16 ridge (2.5e15 / 8e12 = 312), so the
     # call is bound by HBM; the matrix-core rate is reported beside it.
+    fused = doc_tuning is not None and doc_tuning["form"] == "fused"
     roofline = {"bound": "hbm", "achieved": alg_bytes / (ms / 1e3) / 1e9, "peak": PEAK_HBM / 1e9,
-                "unit": "GB/s", "frac": alg_bytes / (ms / 1e3) / PEAK_HBM, "traffic": None,
+                "unit": "GB/s", "frac": alg_bytes / (ms / 1e3) / PEAK_HBM,
+                "traffic": None if fused else measured_doc_traffic(),
                 "kernel": ("doc_pair_kernel<bf16, mfma, 256, 4, fused> (one call)"
-                           if doc_tuning is not None and doc_tuning["form"] == "fused" else
+                           if fused else
                            "doc_tile_shared_kernel + doc_pair_kernel<bf16, mfma, 256, 4, split> (one call)"),
                 "algorithmic_bytes": alg_bytes, "mfma_flops_per_launch": flops,
                 "mfma_tflops": flops / (ms / 1e3) / 1e12, "mfma_frac": flops / (ms / 1e3) / PEAK_BF16_MFMA,
