@@ -1663,6 +1663,11 @@ int doc_launch_typed(const DocArgs& A, size_t lds, int grid, hipStream_t st, boo
     if (!run) return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k, 256, lds);
     if constexpr (SPLIT) {
         if (A.stripes != nullptr) {
+            // the records' pair positions and stripe-pair numbers must fit
+            // their packed fields (the split form caps each side at 1024)
+            if ((A.max_n + 31) / 32 > (1 << kStripeShift) || grid > (1 << (31 - kStripeShift)) ||
+                A.tile_grid < 1)
+                return (int)hipErrorInvalidValue;
             hipLaunchKernelGGL(doc_stripe_reset_kernel, dim3(1), dim3(64), 0, st, A);
             hipLaunchKernelGGL(doc_stripe_list_kernel<256>, dim3((grid + 255) / 256), dim3(256), 0, st, A, grid);
             hipError_t e = hipGetLastError();
