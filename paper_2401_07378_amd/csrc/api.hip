@@ -444,8 +444,9 @@ nnsemd_status_t run_docs(nnsemd_handle_t h, DocArgs& A, int64_t max_m, int64_t m
         doc_shared_tile_lds(mcap) <= h->max_lds) {
         const int occ = doc_shared_tile_occupancy(mcap);
         if (occ >= 1) {
-            const int64_t smax = (ncap + 15) / 16;
-            const size_t sb = 16 * ((size_t)per_launch * (size_t)smax) + 256;
+            // one 16-byte record per 32 consumers of a pair (at least one)
+            const int64_t rmax = (ncap + 31) / 32;
+            const size_t sb = 16 * ((size_t)per_launch * (size_t)rmax) + 256;
             if (h->doc_stripes_bytes < sb) {
                 if (h->doc_stripes) (void)hipFree(h->doc_stripes);
                 h->doc_stripes = nullptr;
@@ -456,10 +457,10 @@ nnsemd_status_t run_docs(nnsemd_handle_t h, DocArgs& A, int64_t max_m, int64_t m
             }
             A.stripe_total = h->doc_stripes;
             A.stripes = reinterpret_cast<int4*>(h->doc_stripes + 64);
-            // enough wavefronts for every stripe of the launch, at most the
+            // a wavefront for every record of the launch, at most the
             // resident workgroups of the whole chip
             const int64_t wpg = doc_shared_tile_threads() / 64;
-            const int64_t want = (std::min<int64_t>(per_launch, A.num_pairs) * smax + wpg - 1) / wpg;
+            const int64_t want = (std::min<int64_t>(per_launch, A.num_pairs) * rmax + wpg - 1) / wpg;
             A.tile_grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)occ * h->num_cus));
         }
     }
