@@ -417,6 +417,47 @@ def test_shared_query_tile_pass_dimensions(d):
         assert_pair_matches(gp, ref, rel=BF16_COST_REL, label=f"d{d} pair{p}")
 
 
+@pytest.mark.parametrize("sizes", [[1], [1024], [32, 33]])
+def test_shared_query_smallest_launches(sizes):
+    """Shared-query launches at the edges of the record list: one pair of
+    one point (one record, one workgroup), one pair of 1024 points (32
+    records, the largest stripe-pair number the records hold) and two pairs
+    on either side of a record boundary.  Same bits as the per-pair pass,
+    and the oracle's plans."""
+    from paper_2401_07378_amd import binding
+    d = 64
+    r = W.rng_for(905 + len(sizes) + sizes[0], 0)
+    qb = W.f32_to_bf16_bits(W.to_f32(r.standard_normal((50, d)) / np.sqrt(d)))
+    qa = W.zipf_masses(r, 50)
+    sizes = np.array(sizes, np.int64)
+    yb = W.f32_to_bf16_bits(W.to_f32(r.standard_normal((int(sizes.sum()), d)) / np.sqrt(d)))
+    ya = np.concatenate([W.zipf_masses(r, int(k)) for k in sizes]).astype(np.float32)
+    yo = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    P = len(sizes)
+    ps = W.PairSet("edges", d, W.bf16_bits_to_f32(qb).reshape(-1, d), qa.astype(np.float32),
+                   np.array([0, 50], np.int64), W.bf16_bits_to_f32(yb).reshape(-1, d), ya, yo,
+                   pair_x=np.zeros(P, np.int32), pair_y=np.arange(P, dtype=np.int32), metric="l2", dtype="bf16",
+                   X_bits=qb.reshape(-1, d), Y_bits=yb.reshape(-1, d))
+    side = int(max(50, sizes.max()))
+    binding.tuning_reset()
+    try:
+        shared = gpu_batched(ps, plan=True, mode="bf16_mfma_refine")
+        binding.tuning_set_docs(d, side, "split_per_pair")
+        per_pair = gpu_batched(ps, plan=True, mode="bf16_mfma_refine")
+    finally:
+        binding.tuning_reset()
+    for k in ("costs", "src", "dst", "flow", "stats"):
+        np.testing.assert_array_equal(shared[k], per_pair[k], err_msg=k)
+    for p in range(P):
+        X, a, Y, b = ps.pair(p)
+        ref = oracle_pair(X, a, Y, b)
+        lo = shared["plan_off"][p]
+        k = int(shared["stats"][p]["nnz"])
+        gp = {"cost": float(shared["costs"][p]), "stats": shared["stats"][p], "src": shared["src"][lo:lo + k],
+              "dst": shared["dst"][lo:lo + k], "flow": shared["flow"][lo:lo + k]}
+        assert_pair_matches(gp, ref, rel=BF16_COST_REL, label=f"sizes{list(sizes)} pair{p}")
+
+
 def test_document_batch_as_given_schedule_same_bits():
     ps = _small_docs(32, seed=891)
     g1 = gpu_batched(ps, mode="bf16_mfma_refine")
